@@ -1,0 +1,214 @@
+#!/usr/bin/env python
+"""Throughput of the split-step Crank-Nicolson spin-1 step on one MI355X.
+
+Headline workload: 512 x 512 real-time run (Dresselhaus gamma = 1, Rabi 0.2,
+Omega = 0.9, c0 = 200, c2 = +5, dx = 0.05, dt = 1e-4) started from the
+imaginary-time state of the same parameters plus seeded complex noise of 1e-3;
+a step is one whole SSCN step (local substep, x sweep, y sweep).  Timed in
+FP64 (the headline value) and in FP32 bulk.  Also timed: 4096 x 4096
+imaginary-time steps (Rashba gamma = 0.75, Omega = 0.95, c0 = 1000, c2 = -20,
+dx = 0.02), the grid whose state (805 MB in FP64) does not fit in the caches,
+which gives the honest HBM roofline fraction.  All inputs are seeded and
+synthetic.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_BPS = 8.0e12  # MI355X HBM3E, vendor figure
+METRIC = "3-comp grid-point-steps/s FP64 vs FP32 (%HBM roofline); p50/p99 solve latency"
+UNIT = "3-comp grid-point-steps/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_per_complex(prec):
+    return 16 if prec == "fp64" else 8
+
+
+def kernel_roofline(timing, npts, prec):
+    """Roofline of the dominant sweep kernel: algorithmic bytes per launch
+    (read + write of the 3 components, 6 s bytes per point) / mean launch time."""
+    per_launch = 6 * bytes_per_complex(prec) * npts
+    rows = {}
+    for kind in ("x_sweep", "y_sweep"):
+        t = timing[kind]
+        if t["launches"]:
+            avg_s = t["ms"] / t["launches"] / 1e3
+            rows[kind] = {"avg_us": avg_s * 1e6, "achieved_GBps": per_launch / avg_s / 1e9,
+                          "frac": per_launch / avg_s / HBM_PEAK_BPS, "total_ms": t["ms"]}
+    dom = max(rows, key=lambda k: rows[k]["total_ms"])
+    d = rows[dom]
+    return {"bound": "hbm", "kernel": dom, "achieved": round(d["achieved_GBps"], 1), "peak": HBM_PEAK_BPS / 1e9,
+            "unit": "GB/s", "frac": round(d["frac"], 4), "traffic": None,
+            "bytes_per_launch": per_launch,
+            "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in rows.items()}}
+
+
+def time_steps(solver, t, nsteps, imag, torch):
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    (solver.step_imag if imag else solver.step_real)(t, nsteps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    solver.sync()
+    return e0.elapsed_time(e1)
+
+
+def kernel_timing(solver, t, nsteps, imag):
+    solver.timing(True)
+    (solver.step_imag if imag else solver.step_real)(t, nsteps)
+    res = solver.timing_read()
+    solver.timing(False)
+    return res
+
+
+def c2_initial_state(torch, binding, inputs):
+    """Imaginary-time state of the headline parameters (dt = 0.1 dx^2, stop at
+    |dE|/E < 1e-10 over 100 steps or 20000 steps), plus 1e-3 noise (seed 3)."""
+    p = inputs.config_c2()
+    q = dict(p, dt=0.1 * p["dx"] * p["dx"])
+    psi = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], seed=2, phase_noise=0.1)
+    s = binding.Solver(q, "fp64")
+    t = torch.from_numpy(psi).to("cuda")
+    e_prev, steps = None, 0
+    while steps < 20000:
+        s.step_imag(t, 100)
+        steps += 100
+        e = s.observables(t)["energy"]
+        if e_prev is not None and abs(e - e_prev) < 1e-10 * abs(e):
+            break
+        e_prev = e
+    log(f"[bench] C2 initial state: {steps} imaginary-time steps, E = {e:.10f}")
+    out = inputs.add_noise(t.cpu().numpy(), p["dx"], p["dy"], 1e-3, seed=3)
+    s.close()
+    return p, out
+
+
+def cpu_baseline(p, psi0, seconds):
+    import oracle
+    t0 = time.perf_counter()
+    psi = oracle.step(p, psi0, 1, False)
+    t1 = time.perf_counter() - t0
+    n = max(1, int(seconds / max(t1, 1e-6)))
+    t0 = time.perf_counter()
+    oracle.step(p, psi, n, False)
+    dt = time.perf_counter() - t0
+    return {"value": p["nx"] * p["ny"] * n / dt, "unit": UNIT, "cores": oracle.get_threads(), "kind": "oracle",
+            "sample": f"{n} real-time FP64 steps of the {p['nx']}x{p['ny']} workload (block-Thomas oracle, "
+                      f"{dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000, help="timed SSCN steps of the headline workload")
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--c3-steps", type=int, default=100, help="timed steps of the 4096^2 grid (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample length (0 = skip)")
+    ap.add_argument("--timing-steps", type=int, default=500, help="steps of the per-kernel timing pass")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (each condensate runs on "
+              f"one device and this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2105_10517_amd import binding, inputs
+    binding.load()
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+
+    p, psi0 = c2_initial_state(torch, binding, inputs)
+    npts = p["nx"] * p["ny"]
+    results = {}
+    for prec in ("fp64", "fp32"):
+        s = binding.Solver(p, prec)
+        t = torch.from_numpy(psi0).to("cuda").to(s.dtype)
+        s.step_real(t, args.warmup)
+        ms = time_steps(s, t, args.steps, False, torch)
+        norm = s.observables(t)["norm_total"]
+        tim = kernel_timing(s, t, args.timing_steps, False)
+        roof = kernel_roofline(tim, npts, prec)
+        val = npts * args.steps / (ms / 1e3)
+        step_bytes = 12 * bytes_per_complex(prec) * npts
+        results[prec] = {"value": val, "ms_per_step": ms / args.steps, "roofline": roof,
+                         "step_frac": step_bytes / (ms / args.steps / 1e3) / HBM_PEAK_BPS,
+                         "norm_drift": norm - 1.0, "plan": s.plan(False)}
+        log(f"[bench] 512^2 real {prec}: {val:.3e} pt-steps/s, {ms / args.steps * 1e3:.2f} us/step, "
+            f"dominant {roof['kernel']} {roof['achieved']:.0f} GB/s ({roof['frac'] * 100:.1f}% of HBM peak), "
+            f"norm drift {norm - 1:.2e}")
+        s.close()
+        del t
+        torch.cuda.empty_cache()
+
+    c3 = {}
+    if args.c3_steps > 0:
+        q = inputs.config_c3(4096)
+        psi3 = inputs.gaussian(4096, 4096, q["dx"], q["dy"], seed=4, full_phase=True)
+        n3 = 4096 * 4096
+        for prec in ("fp64", "fp32"):
+            s = binding.Solver(q, prec)
+            t = torch.from_numpy(psi3).to("cuda").to(s.dtype)
+            s.step_imag(t, 5)
+            ms = time_steps(s, t, args.c3_steps, True, torch)
+            tim = kernel_timing(s, t, max(10, args.c3_steps // 5), True)
+            roof = kernel_roofline(tim, n3, prec)
+            val = n3 * args.c3_steps / (ms / 1e3)
+            step_bytes = 12 * bytes_per_complex(prec) * n3
+            c3[prec] = {"value": val, "ms_per_step": ms / args.c3_steps, "roofline": roof,
+                        "step_frac": step_bytes / (ms / args.c3_steps / 1e3) / HBM_PEAK_BPS}
+            log(f"[bench] 4096^2 imag {prec}: {val:.3e} pt-steps/s, {ms / args.c3_steps:.3f} ms/step, "
+                f"step {c3[prec]['step_frac'] * 100:.1f}% of the 12 s B/pt-step roofline, dominant "
+                f"{roof['kernel']} {roof['frac'] * 100:.1f}%")
+            s.close()
+            del t
+            torch.cuda.empty_cache()
+        del psi3
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        cpu = cpu_baseline(p, psi0, args.cpu_seconds)
+        log(f"[bench] CPU oracle baseline: {cpu['value']:.3e} pt-steps/s on {cpu['cores']} threads")
+
+    r = results["fp64"]
+    line = {
+        "metric": METRIC, "value": r["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "512x512 real-time SSCN step, Dresselhaus gamma=1, Rabi=0.2, Omega=0.9, c0=200, "
+                               "c2=+5, dx=0.05, dt=1e-4, from the imaginary-time state + 1e-3 noise",
+                   "nx": 512, "ny": 512, "mode": "real", "precision": "fp64"},
+        "roofline": r["roofline"],
+        "step_roofline_frac": round(r["step_frac"], 4),
+        "cpu_baseline": cpu,
+        "fp32": {"value": results["fp32"]["value"], "ms_per_step": results["fp32"]["ms_per_step"],
+                 "dtype": "f32 bulk, f64 reductions", "roofline": results["fp32"]["roofline"],
+                 "step_roofline_frac": round(results["fp32"]["step_frac"], 4),
+                 "norm_drift": results["fp32"]["norm_drift"]},
+        "norm_drift_fp64": r["norm_drift"],
+        "c3_4096": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "roofline": v["roofline"],
+                        "step_roofline_frac": round(v["step_frac"], 4)} for k, v in c3.items()},
+        "plan": {"x_points_per_thread": r["plan"]["x_points_per_thread"], "y_solver": r["plan"]["y_solver"],
+                 "y_halo": r["plan"]["y_halo"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,179 @@
+/*
+ * gp_spin1.h -- C ABI of the MI355X (gfx950) split-step Crank-Nicolson (SSCN)
+ * solver for the quasi-2D rotating spin-1 Gross-Pitaevskii equation with
+ * Rashba or Dresselhaus spin-orbit (SO) coupling and Rabi coupling.
+ *
+ * The equations are Eqs. (S.1)-(S.3) of the Supplementary Material of
+ * arXiv:2105.10517 (Muruganandam, Balaz, Adhikari):
+ *   i d_t psi_{+-1} = [H + c2 (rho_{+-1} - rho_{-+1} + rho_0)] psi_{+-1}
+ *                     + c2 psi_0^2 psi_{-+1}^* + R/sqrt2 psi_0 + gamma f_{+-1}
+ *   i d_t psi_0     = [H + c2 (rho_{+1} + rho_{-1})] psi_0
+ *                     + 2 c2 psi_{+1} psi_{-1} psi_0^* + R/sqrt2 (psi_{+1} + psi_{-1}) + gamma f_0
+ *   H = -1/2 grad^2 + V + c0 rho - Omega L_z,   V = (x^2 + y^2)/2,
+ *   gamma f = gamma (eta p_y Sigma_x - p_x Sigma_y)   (eta = +1 Rashba, -1 Dresselhaus),
+ * with Sigma_x, Sigma_y the spin-1 matrices of Eq. (S.5), lengths in l0, time
+ * in 1/omega.  The paper's solution method is the SSCN scheme in imaginary time
+ * (stationary states) and in real time (dynamics).
+ *
+ * One time step (Lie splitting) is
+ *   1. local substep   psi <- exp(-i dt H_loc) psi      (real time)
+ *                      psi <- exp(-dt H_loc) psi        (imaginary time)
+ *      H_loc = (V + c0 rho) I + c2 F.Sigma + R Sigma_x, F = psi^+ Sigma psi,
+ *      frozen at the substep input;
+ *   2. x sweep  (I + a H_x) psi' = (I - a H_x) psi,  H_x = -1/2 d_x^2 - i Omega y d_x + i gamma Sigma_y d_x;
+ *   3. y sweep  (I + a H_y) psi' = (I - a H_y) psi,  H_y = -1/2 d_y^2 + i Omega x d_y - i eta gamma Sigma_x d_y;
+ *   4. imaginary time only: psi <- psi / sqrt(dx dy sum |psi|^2)
+ *      (normalisation condition stated after Eq. (S.5));
+ * with a = i dt/2 in real time and a = dt/2 in imaginary time, 3-point
+ * second differences, central first differences and psi = 0 on the ghost
+ * points just outside the grid.
+ *
+ * Wave-function layout (every entry point): psi[3][ny][nx], C-contiguous,
+ * x fastest, components ordered m = +1, 0, -1, interleaved complex
+ * (complex128 for GP_FP64, complex64 for GP_FP32).  Grid: x_i = x0 + i dx,
+ * y_j = y0 + j dy.  psi lives in caller-owned device memory; the library
+ * borrows it for the duration of a call and never frees it.
+ *
+ * Status: every function returns a gp_status (0 = success).  No exception
+ * crosses this boundary.  A handle is not thread-safe: use one handle per
+ * stream.  Device work is enqueued on the stream given at creation; the step
+ * and substep calls return without waiting, gp_spin1_observables and
+ * gp_spin1_sync wait for the stream.
+ */
+#ifndef GP_SPIN1_H
+#define GP_SPIN1_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GP_OK = 0,
+    GP_EINVAL = -1,        /* bad argument: non-finite value, n < 3, d <= 0, dt <= 0, |eta| != 1, NULL */
+    GP_EUNSTABLE = -2,     /* the requested propagation fails the create-time stability checks */
+    GP_ENOMEM = -3,        /* a device allocation failed */
+    GP_EHIP = -4,          /* a HIP runtime call failed; gp_spin1_last_error has the message */
+    GP_ENONFINITE = -5,    /* a NaN or Inf was met in a norm or an observable */
+    GP_EUNSUPPORTED = -6   /* a size or option this build does not handle */
+} gp_status;
+
+typedef enum { GP_FP64 = 0, GP_FP32 = 1 } gp_precision; /* FP32: bulk in FP32, reductions in FP64 */
+
+/* Choice of the y-sweep line solver (the x sweep always uses whole rows). */
+typedef enum {
+    GP_YSOLVER_AUTO = 0,   /* windowed scan when its truncation bound holds, else per-column Thomas */
+    GP_YSOLVER_WINDOW = 1, /* windowed partitioned scan over column tiles (2 HBM passes per step) */
+    GP_YSOLVER_THOMAS = 2  /* exact per-thread Thomas down whole columns (one thread per column) */
+} gp_ysolver;
+
+typedef struct {
+    int32_t nx, ny;    /* grid points, each >= 3; nx <= 8192 (one row is held on chip)        */
+    double dx, dy;     /* grid steps, > 0 (lengths in l0)                                      */
+    double x0, y0;     /* coordinate of index 0; NaN selects the default -n*d/2                */
+    double dt;         /* time step, > 0 (same meaning in imaginary and real time)             */
+    double c0, c2;     /* density and spin-exchange couplings of Eq. (S.4)                     */
+    double gamma;      /* SO strength gamma                                                    */
+    int32_t eta;       /* +1 Rashba, -1 Dresselhaus (term gamma (eta p_y Sigma_x - p_x Sigma_y)) */
+    double rabi;       /* Rabi coupling R                                                      */
+    double omega;      /* rotation frequency Omega (in units of the trap frequency)            */
+    int32_t precision; /* gp_precision                                                         */
+    int32_t y_solver;  /* gp_ysolver                                                           */
+} gp_spin1_params;
+
+/* Observables of one wave function (all FP64, rectangle-rule quadrature
+ * dx dy sum):
+ *   norm[m] = int rho_m, norm_total, magnetization = norm[+1] - norm[-1]
+ *   (conditions after Eq. (S.5));
+ *   energy = e_kin + e_trap + e_int + e_rot + e_so + e_rabi, the terms of the
+ *   Eq. (S.6) functional (e_kin from forward differences over the ghost-padded
+ *   grid, i.e. <psi| -grad^2/2 |psi>; e_int = 1/2 int (c0 rho^2 + c2 |F|^2));
+ *   lz = <L_z> summed over components;
+ *   mu[m] = Re <psi_m | (H psi)_m> / norm[m] with (H psi) the right-hand sides
+ *   of Eqs. (S.1)-(S.2), mu_total = sum_m Re <psi_m|(H psi)_m> / norm_total. */
+typedef struct {
+    double norm[3], norm_total, magnetization;
+    double energy, e_kin, e_trap, e_int, e_rot, e_so, e_rabi, lz;
+    double mu[3], mu_total;
+} gp_spin1_obs;
+
+/* What gp_spin1_create chose for one propagation mode (introspection). */
+typedef struct {
+    int32_t x_points_per_thread; /* K of the x kernel: each thread holds K consecutive points   */
+    int32_t x_threads_per_row;   /* threads cooperating on one row                               */
+    int32_t x_rows_per_block;
+    int32_t y_solver;            /* GP_YSOLVER_WINDOW or GP_YSOLVER_THOMAS                        */
+    int32_t y_halo;              /* rows of overlap on each side of a y window                   */
+    int32_t y_rows_out;          /* rows written per y window                                    */
+    int32_t y_tile_cols, y_segments, y_rows_per_thread;
+    int32_t pivots_x, pivots_y;  /* tabulated Thomas pivots per line before the constant limit  */
+    double decay_x, decay_y;     /* largest |a m| or |c'| of the converged pivots per direction  */
+    int32_t stable;              /* 1 if the mode passed the stability checks                    */
+} gp_spin1_plan;
+
+typedef struct gp_spin1 gp_spin1_t;
+
+/* Create a solver handle.  p is copied.  hip_stream is a hipStream_t (NULL =
+ * the default stream).  Validates p (GP_EINVAL), tabulates the Thomas pivots
+ * of every x line (row j, Sigma_y eigenvalue) and y line (column i, Sigma_x
+ * eigenvalue) for both propagation modes, and allocates small device tables
+ * and reduction scratch.  *out is set only on success. */
+int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out);
+int gp_spin1_destroy(gp_spin1_t* h);
+
+/* nsteps >= 0 imaginary-time SSCN steps on psi (device), renormalised to unit
+ * norm after each step.  GP_EUNSTABLE if the imaginary-time Cayley bound
+ * (dt/4)(|Omega| L_max + |gamma|)^2 < 1 or the diagonal dominance of the line
+ * systems fails.  Asynchronous; a non-finite norm is reported by the next
+ * gp_spin1_sync or gp_spin1_observables as GP_ENONFINITE. */
+int gp_spin1_step_imag(gp_spin1_t* h, void* psi_dev, int64_t nsteps);
+
+/* nsteps >= 0 real-time SSCN steps on psi (device); no renormalisation.
+ * GP_EUNSTABLE if the line systems lose diagonal dominance.  Asynchronous. */
+int gp_spin1_step_real(gp_spin1_t* h, void* psi_dev, int64_t nsteps);
+
+/* One substep alone (diagnostics and per-kernel parity checks):
+ * which = 0 local substep, 1 x sweep, 2 y sweep, 3 renormalise to unit norm;
+ * imag != 0 selects the imaginary-time form.  Asynchronous. */
+int gp_spin1_substep(gp_spin1_t* h, void* psi_dev, int32_t which, int32_t imag);
+
+/* Observables of psi (device).  Blocks until out_host is written.  If dens_dev
+ * is not NULL it receives rho_m = |psi_m|^2 as a real [3][ny][nx] array of the
+ * handle's precision (device).  GP_ENONFINITE if any sum is not finite. */
+int gp_spin1_observables(gp_spin1_t* h, const void* psi_dev, gp_spin1_obs* out_host, void* dens_dev);
+
+/* Wait for the handle's stream; returns GP_ENONFINITE if an imaginary-time
+ * norm was not finite since the last check (and clears the flag). */
+int gp_spin1_sync(gp_spin1_t* h);
+
+/* Plan chosen for imag != 0 (imaginary time) or imag == 0 (real time). */
+int gp_spin1_get_plan(const gp_spin1_t* h, int32_t imag, gp_spin1_plan* out);
+
+/* The same plan computed on the host alone, without a handle or any device
+ * call: validates p (GP_EINVAL / GP_EUNSUPPORTED as gp_spin1_create) and
+ * reports the pivot tables, decay factors, y solver and stability flag that
+ * gp_spin1_create would choose. */
+int gp_spin1_plan_query(const gp_spin1_params* p, int32_t imag, gp_spin1_plan* out);
+
+/* Per-kernel timing (diagnostics).  While enabled, the step calls bracket
+ * every kernel launch with HIP events on the handle's stream; gp_spin1_timing_read
+ * waits for the stream and returns, per kernel kind, the number of launches
+ * and their summed duration in milliseconds since the last enable (which
+ * resets the counters).  Kinds: 0 x sweep (with the fused local substep),
+ * 1 y sweep, 2 norm finalize, 3 final renormalisation. */
+typedef struct {
+    int64_t launches[4];
+    double ms[4];
+} gp_spin1_timing;
+int gp_spin1_timing_enable(gp_spin1_t* h, int32_t enable);
+int gp_spin1_timing_read(gp_spin1_t* h, gp_spin1_timing* out);
+
+const char* gp_spin1_strerror(int status);
+const char* gp_spin1_last_error(const gp_spin1_t* h); /* per-handle message of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_SPIN1_H */

@@ -1,0 +1,221 @@
+"""ctypes binding of the C ABI declared in include/gp_spin1.h.
+
+Argument marshalling only: every step of the SSCN path runs in the HIP
+kernels of libgp_spin1.so.  PyTorch supplies the device memory (a complex128
+or complex64 tensor of shape (3, ny, nx)) and the stream; the library borrows
+the tensor's storage for the duration of each call.
+
+The library is loaded on first use and a missing build raises
+``LibraryNotBuilt``: there is no fallback of any kind.
+"""
+import ctypes
+import math
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libgp_spin1.so")
+
+GP_OK, GP_EINVAL, GP_EUNSTABLE, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+GP_FP64, GP_FP32 = 0, 1
+GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS = 0, 1, 2
+SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
+
+# Every entry point the header declares (checked by the CPU test suite).
+EXPORTS = ("gp_spin1_create", "gp_spin1_destroy", "gp_spin1_step_imag", "gp_spin1_step_real",
+           "gp_spin1_substep", "gp_spin1_observables", "gp_spin1_sync", "gp_spin1_get_plan",
+           "gp_spin1_plan_query", "gp_spin1_timing_enable", "gp_spin1_timing_read",
+           "gp_spin1_strerror", "gp_spin1_last_error")
+
+
+class LibraryNotBuilt(RuntimeError):
+    pass
+
+
+class GPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("dt", ctypes.c_double),
+                ("c0", ctypes.c_double), ("c2", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("eta", ctypes.c_int32), ("rabi", ctypes.c_double), ("omega", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("y_solver", ctypes.c_int32)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double * 3), ("norm_total", ctypes.c_double),
+                ("magnetization", ctypes.c_double), ("energy", ctypes.c_double),
+                ("e_kin", ctypes.c_double), ("e_trap", ctypes.c_double), ("e_int", ctypes.c_double),
+                ("e_rot", ctypes.c_double), ("e_so", ctypes.c_double), ("e_rabi", ctypes.c_double),
+                ("lz", ctypes.c_double), ("mu", ctypes.c_double * 3), ("mu_total", ctypes.c_double)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 4), ("ms", ctypes.c_double * 4)]
+
+
+TIMING_KINDS = ("x_sweep", "y_sweep", "norm_finalize", "renormalise")
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("x_points_per_thread", ctypes.c_int32), ("x_threads_per_row", ctypes.c_int32),
+                ("x_rows_per_block", ctypes.c_int32), ("y_solver", ctypes.c_int32),
+                ("y_halo", ctypes.c_int32), ("y_rows_out", ctypes.c_int32),
+                ("y_tile_cols", ctypes.c_int32), ("y_segments", ctypes.c_int32),
+                ("y_rows_per_thread", ctypes.c_int32), ("pivots_x", ctypes.c_int32),
+                ("pivots_y", ctypes.c_int32), ("decay_x", ctypes.c_double), ("decay_y", ctypes.c_double),
+                ("stable", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libgp_spin1.so (built in-tree by ``paper_2105_10517_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise LibraryNotBuilt(f"{LIBPATH} is missing: run `python -m paper_2105_10517_amd.build`")
+    lib = ctypes.CDLL(LIBPATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "gp_spin1_create": [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)],
+        "gp_spin1_destroy": [vp],
+        "gp_spin1_step_imag": [vp, vp, i64],
+        "gp_spin1_step_real": [vp, vp, i64],
+        "gp_spin1_substep": [vp, vp, i32, i32],
+        "gp_spin1_observables": [vp, vp, ctypes.POINTER(Obs), vp],
+        "gp_spin1_sync": [vp],
+        "gp_spin1_get_plan": [vp, i32, ctypes.POINTER(Plan)],
+        "gp_spin1_plan_query": [ctypes.POINTER(Params), i32, ctypes.POINTER(Plan)],
+        "gp_spin1_timing_enable": [vp, i32],
+        "gp_spin1_timing_read": [vp, ctypes.POINTER(Timing)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.gp_spin1_strerror.argtypes = [ctypes.c_int]
+    lib.gp_spin1_strerror.restype = ctypes.c_char_p
+    lib.gp_spin1_last_error.argtypes = [vp]
+    lib.gp_spin1_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto") -> Params:
+    """Params from a plain mapping (keys nx, ny, dx, dy, x0, y0, dt, c0, c2,
+    gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2)."""
+    prec = {"fp64": GP_FP64, "fp32": GP_FP32}[precision]
+    ys = {"auto": GP_YSOLVER_AUTO, "window": GP_YSOLVER_WINDOW, "thomas": GP_YSOLVER_THOMAS}[y_solver]
+    return Params(int(p["nx"]), int(p["ny"]), float(p["dx"]), float(p.get("dy", p["dx"])),
+                  float(p.get("x0", math.nan)), float(p.get("y0", math.nan)), float(p["dt"]),
+                  float(p.get("c0", 0.0)), float(p.get("c2", 0.0)), float(p.get("gamma", 0.0)),
+                  int(p.get("eta", 1)), float(p.get("rabi", 0.0)), float(p.get("omega", 0.0)), prec, ys)
+
+
+def _obs_dict(o: Obs) -> dict:
+    return {"norm": list(o.norm), "norm_total": o.norm_total, "magnetization": o.magnetization,
+            "energy": o.energy, "e_kin": o.e_kin, "e_trap": o.e_trap, "e_int": o.e_int, "e_rot": o.e_rot,
+            "e_so": o.e_so, "e_rabi": o.e_rabi, "lz": o.lz, "mu": list(o.mu), "mu_total": o.mu_total}
+
+
+def plan_query(p: dict, imag: bool, precision: str = "fp64", y_solver: str = "auto") -> dict:
+    """Host-only plan (no GPU needed): pivot table lengths, decay factors,
+    y solver and stability flag for these parameters."""
+    lib = load()
+    pl = Plan()
+    pp = make_params(p, precision, y_solver)
+    rc = lib.gp_spin1_plan_query(ctypes.byref(pp), int(bool(imag)), ctypes.byref(pl))
+    if rc != GP_OK:
+        raise GPError(rc, "gp_spin1_plan_query: " + lib.gp_spin1_strerror(rc).decode())
+    return {k: getattr(pl, k) for k, _ in Plan._fields_}
+
+
+class Solver:
+    """One condensate on one stream: a handle of the C ABI."""
+
+    def __init__(self, p: dict, precision: str = "fp64", y_solver: str = "auto", stream=None):
+        import torch
+        self._lib = load()
+        self.precision = precision
+        self.params = dict(p)
+        self.nx, self.ny = int(p["nx"]), int(p["ny"])
+        self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
+        self.real_dtype = torch.float64 if precision == "fp64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self._h = ctypes.c_void_p()
+        pp = make_params(p, precision, y_solver)
+        rc = self._lib.gp_spin1_create(ctypes.byref(pp), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
+        if rc != GP_OK:
+            raise GPError(rc, "gp_spin1_create: " + self._lib.gp_spin1_strerror(rc).decode())
+
+    def _check(self, rc, what):
+        if rc != GP_OK:
+            msg = self._lib.gp_spin1_last_error(self._h).decode()
+            raise GPError(rc, f"{what}: {self._lib.gp_spin1_strerror(rc).decode()}: {msg}")
+
+    def _psi(self, psi):
+        if psi.dtype != self.dtype or tuple(psi.shape) != (3, self.ny, self.nx) or not psi.is_contiguous() \
+                or not psi.is_cuda:
+            raise ValueError(f"psi must be a contiguous CUDA {self.dtype} tensor of shape (3, {self.ny}, {self.nx})")
+        return ctypes.c_void_p(psi.data_ptr())
+
+    def step_imag(self, psi, nsteps: int):
+        self._check(self._lib.gp_spin1_step_imag(self._h, self._psi(psi), int(nsteps)), "step_imag")
+
+    def step_real(self, psi, nsteps: int):
+        self._check(self._lib.gp_spin1_step_real(self._h, self._psi(psi), int(nsteps)), "step_real")
+
+    def substep(self, psi, which: int, imag: bool):
+        self._check(self._lib.gp_spin1_substep(self._h, self._psi(psi), int(which), int(bool(imag))), "substep")
+
+    def observables(self, psi, dens=None) -> dict:
+        o = Obs()
+        dp = None
+        if dens is not None:
+            if dens.dtype != self.real_dtype or tuple(dens.shape) != (3, self.ny, self.nx) or not dens.is_contiguous():
+                raise ValueError("dens must be a contiguous real tensor of shape (3, ny, nx) in the solver precision")
+            dp = ctypes.c_void_p(dens.data_ptr())
+        self._check(self._lib.gp_spin1_observables(self._h, self._psi(psi), ctypes.byref(o), dp), "observables")
+        return _obs_dict(o)
+
+    def sync(self):
+        self._check(self._lib.gp_spin1_sync(self._h), "sync")
+
+    def plan(self, imag: bool) -> dict:
+        pl = Plan()
+        self._check(self._lib.gp_spin1_get_plan(self._h, int(bool(imag)), ctypes.byref(pl)), "get_plan")
+        return {k: getattr(pl, k) for k, _ in Plan._fields_}
+
+    def timing(self, enable: bool):
+        self._check(self._lib.gp_spin1_timing_enable(self._h, int(bool(enable))), "timing_enable")
+
+    def timing_read(self) -> dict:
+        t = Timing()
+        self._check(self._lib.gp_spin1_timing_read(self._h, ctypes.byref(t)), "timing_read")
+        return {k: {"launches": int(t.launches[i]), "ms": float(t.ms[i])} for i, k in enumerate(TIMING_KINDS)}
+
+    def close(self):
+        if self._h:
+            self._lib.gp_spin1_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,682 @@
+// gfx950 kernels of the SSCN step.
+//
+//   k_x_scan     local substep (+ pending renormalisation) fused into the x
+//                Crank-Nicolson sweep; one row per thread group, K consecutive
+//                points per thread in registers, exact partitioned Thomas
+//                (local recurrences + wave/LDS scans of the block carries).
+//   k_y_window   y sweep over column tiles: TW columns x (S segments of KY
+//                rows); exact partitioned Thomas inside the tile, windows
+//                overlapping by h rows so that the truncated carries at the
+//                window ends decay below the rounding level before the rows
+//                that are written.  Norm partials fused into the store.
+//   k_y_thomas   exact per-thread Thomas down whole columns (one thread per
+//                column, forward eliminations stored in place).
+//   k_local, k_scale, k_set_scale, k_norm_finalize, k_obs, k_obs_finalize.
+#include "gp_kernels.hpp"
+#include "gp_scan.hpp"
+
+namespace gp {
+
+// ---------------------------------------------------------------------------
+// Partitioned Thomas on one line held as K consecutive values per thread.
+// Works in place on u[]; n is the line length, i0 the first index of this
+// thread's block.  Every thread of the block must call it (barriers).
+// ---------------------------------------------------------------------------
+template <typename T, int K>
+__device__ inline void row_line_solve(cx<T> (&u)[K], const LineSet<T>& ls, int line, int i0, int n, int lane,
+                                      int w, int nw, cx<T>* shA, cx<T>* shB) {
+    using C = cx<T>;
+    const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], b = ls.b;
+    const Piv<T> lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
+    // neighbours of the block ends (ghost zeros beyond the row)
+    C left = shfl_up_c(u[K - 1], 1), right = shfl_down_c(u[0], 1);
+    if (lane == 63) shA[w] = u[K - 1];
+    if (lane == 0) shB[w] = u[0];
+    __syncthreads();
+    if (lane == 0) left = (w > 0) ? shA[w - 1] : zero_c<C>();
+    if (lane == 63) right = (w + 1 < nw) ? shB[w + 1] : zero_c<C>();
+    __syncthreads();
+    C r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const C um = (k == 0) ? left : u[k - 1];
+        const C up = (k == K - 1) ? right : u[k + 1];
+        // r = 2u - (a u_{k-1} + b u_k + e u_{k+1})
+        C t = cmul(b, u[k]);
+        t = cfma(um, a, t);
+        t = cfma(up, e, t);
+        r[k] = (i0 + k < n) ? csub(cscale(u[k], (T)2), t) : zero_c<C>();
+    }
+    // forward elimination over the block from a zero carry
+    C E = zero_c<C>(), P = one_c<C>();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = i0 + k;
+        if (i < n) {
+            const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+            E = csub(mul_m(pv, r[k]), cmul(pv.am, E));
+            P = cmul(mk<T>(-pv.am.x, -pv.am.y), P);
+        } else {
+            E = zero_c<C>();
+            P = zero_c<C>();
+        }
+        u[k] = E;
+    }
+    const C din = row_scan_fwd(P, E, lane, w, nw, shA, shB);
+    {
+        C Q = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            if (i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                Q = cmul(mk<T>(-pv.am.x, -pv.am.y), Q);
+                u[k] = cfma(din, Q, u[k]);
+            }
+        }
+    }
+    // back substitution over the block from a zero carry
+    C G = zero_c<C>(), R = one_c<C>();
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) {
+        const int i = i0 + k;
+        if (i < n) {
+            const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+            G = csub(u[k], cmul(pv.cp, G));
+            R = cmul(mk<T>(-pv.cp.x, -pv.cp.y), R);
+        } else {
+            G = zero_c<C>();
+            R = zero_c<C>();
+        }
+        u[k] = G;
+    }
+    const C xin = row_scan_bwd(R, G, lane, w, nw, shA, shB);
+    {
+        C Sx = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            if (i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                Sx = cmul(mk<T>(-pv.cp.x, -pv.cp.y), Sx);
+                u[k] = cfma(xin, Sx, u[k]);
+            }
+        }
+    }
+}
+
+template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
+__global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
+                                               LineSet<T> ls, const double* __restrict__ scale, int G, int R) {
+    using C = cx<T>;
+    __shared__ C shA[16 * 16];
+    __shared__ C shB[16 * 16];
+    const int tid = threadIdx.x;
+    const int r = tid / G, t = tid - r * G;
+    const int lane = t & 63, w = t >> 6, nw = G >> 6;
+    const int j = blockIdx.x * R + r;
+    const bool row_ok = j < ph.ny;
+    const int nx = ph.nx;
+    const size_t plane = (size_t)ph.nx * ph.ny;
+    const int i0 = t * K;
+    const size_t rowoff = (size_t)(row_ok ? j : 0) * nx;
+    const C* rowp = src + rowoff;
+    C* rowq = dst + rowoff;
+    C v[3][K];
+    if (row_ok && i0 + K <= nx) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[m][k] = rowp[m * plane + i0 + k];
+    } else {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                v[m][k] = (row_ok && i0 + k < nx) ? rowp[m * plane + i0 + k] : zero_c<C>();
+    }
+    if (SCALE) {
+        const T s = (T)(*scale);
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[m][k] = cscale(v[m][k], s);
+    }
+    if (LOCAL) {
+        const T y = (T)(ph.y0 + (row_ok ? j : 0) * ph.dy);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T x = (T)(ph.x0 + (i0 + k) * ph.dx);
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], (T)0.5 * (x * x + y * y), (T)ph.dt, (T)ph.c0,
+                                   (T)ph.c2, (T)ph.rabi);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    const int jl = row_ok ? j : 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+        row_line_solve<T, K>(v[q], ls, jl * 3 + q, i0, nx, lane, w, nw, shA + 16 * r, shB + 16 * r);
+#pragma unroll
+    for (int k = 0; k < K; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    if (row_ok && i0 + K <= nx) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) rowq[m * plane + i0 + k] = v[m][k];
+    } else if (row_ok) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (i0 + k < nx) rowq[m * plane + i0 + k] = v[m][k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of one double (all threads call; result valid in thread 0).
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nw; ++k) s += sh[k];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------------------
+// y sweep, windowed partitioned Thomas over column tiles.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, int KY, int TW, int S, bool NORM>
+__global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
+                                                   LineSet<T> ls, int L, int h, int ncs,
+                                                   double* __restrict__ partials) {
+    using C = cx<T>;
+    __shared__ C shP[TW * S];
+    __shared__ C shE[TW * S];
+    __shared__ double shr[16];
+    const int tid = threadIdx.x;
+    const int c = tid % TW, s = tid / TW;
+    const int cs = blockIdx.x % ncs, rt = blockIdx.x / ncs;
+    const int i = cs * TW + c;
+    const bool col_ok = i < ph.nx;
+    const int nx = ph.nx, ny = ph.ny;
+    const size_t plane = (size_t)nx * ny;
+    const int j0 = rt * L;
+    const int g0 = j0 - h + s * KY;  // first row of this thread
+    C v[3][KY];
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        const bool ok = col_ok && g >= 0 && g < ny;
+        const size_t o = (size_t)(ok ? g : 0) * nx + (col_ok ? i : 0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? src[m * plane + o] : zero_c<C>();
+    }
+#pragma unroll
+    for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    const int il = col_ok ? i : 0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        C (&u)[KY] = v[q];
+        const int line = il * 3 + q;
+        const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], b = ls.b;
+        const Piv<T> lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
+        // segment-end neighbours through shared memory (zeros outside the window)
+        shP[tid] = u[KY - 1];
+        shE[tid] = u[0];
+        __syncthreads();
+        const C up = (s > 0) ? shP[tid - TW] : zero_c<C>();
+        const C dn = (s + 1 < S) ? shE[tid + TW] : zero_c<C>();
+        __syncthreads();
+        C r[KY];
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            const int g = g0 + k;
+            const C um = (k == 0) ? up : u[k - 1];
+            const C uq = (k == KY - 1) ? dn : u[k + 1];
+            C t = cmul(b, u[k]);
+            t = cfma(um, a, t);
+            t = cfma(uq, e, t);
+            r[k] = (g >= 0 && g < ny) ? csub(cscale(u[k], (T)2), t) : zero_c<C>();
+        }
+        C E = zero_c<C>(), P = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            const int g = g0 + k;
+            if (g >= 0 && g < ny) {
+                const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
+                E = csub(mul_m(pv, r[k]), cmul(pv.am, E));
+                P = cmul(mk<T>(-pv.am.x, -pv.am.y), P);
+            } else {
+                E = zero_c<C>();
+                P = zero_c<C>();
+            }
+            u[k] = E;
+        }
+        const C din = seg_scan<C, TW, S, false>(P, E, c, s, shP, shE);
+        {
+            C Q = one_c<C>();
+#pragma unroll
+            for (int k = 0; k < KY; ++k) {
+                const int g = g0 + k;
+                if (g >= 0 && g < ny) {
+                    const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
+                    Q = cmul(mk<T>(-pv.am.x, -pv.am.y), Q);
+                    u[k] = cfma(din, Q, u[k]);
+                }
+            }
+        }
+        C G = zero_c<C>(), R = one_c<C>();
+#pragma unroll
+        for (int k = KY - 1; k >= 0; --k) {
+            const int g = g0 + k;
+            if (g >= 0 && g < ny) {
+                const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
+                G = csub(u[k], cmul(pv.cp, G));
+                R = cmul(mk<T>(-pv.cp.x, -pv.cp.y), R);
+            } else {
+                G = zero_c<C>();
+                R = zero_c<C>();
+            }
+            u[k] = G;
+        }
+        const C xin = seg_scan<C, TW, S, true>(R, G, c, s, shP, shE);
+        {
+            C Sx = one_c<C>();
+#pragma unroll
+            for (int k = KY - 1; k >= 0; --k) {
+                const int g = g0 + k;
+                if (g >= 0 && g < ny) {
+                    const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
+                    Sx = cmul(mk<T>(-pv.cp.x, -pv.cp.y), Sx);
+                    u[k] = cfma(xin, Sx, u[k]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    double acc = 0;
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        if (col_ok && g >= j0 && g < j0 + L && g < ny) {
+            const size_t o = (size_t)g * nx + i;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                dst[m * plane + o] = v[m][k];
+                if (NORM) acc += (double)cnorm2(v[m][k]);
+            }
+        }
+    }
+    if (NORM) {
+        const double tot = block_sum(acc, shr);
+        if (tid == 0) partials[blockIdx.x] = tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y sweep, exact per-thread Thomas down whole columns.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, bool NORM>
+__global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
+                                                 LineSet<T> ls, double* __restrict__ partials) {
+    using C = cx<T>;
+    __shared__ double shr[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = ph.nx, ny = ph.ny;
+    const size_t plane = (size_t)nx * ny;
+    double acc = 0;
+    if (i < nx) {
+        C a[3], e[3];
+        Piv<T> lim[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            a[q] = ls.ae[2 * (i * 3 + q)];
+            e[q] = ls.ae[2 * (i * 3 + q) + 1];
+            lim[q] = ls.piv[(size_t)(i * 3 + q) * (ls.K + 1) + ls.K];
+        }
+        auto load_sx = [&](int g, C (&o)[3]) {
+            if (g < ny) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) o[m] = src[m * plane + (size_t)g * nx + i];
+                to_sx<C, T>(o[0], o[1], o[2]);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) o[m] = zero_c<C>();
+            }
+        };
+        C prev[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()}, cur[3], nxt[3], d[3];
+        load_sx(0, cur);
+        C carry[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
+        for (int g = 0; g < ny; ++g) {
+            load_sx(g + 1, nxt);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                C t = cmul(ls.b, cur[q]);
+                t = cfma(prev[q], a[q], t);
+                t = cfma(nxt[q], e[q], t);
+                const C rr = csub(cscale(cur[q], (T)2), t);
+                const Piv<T> pv = (g < ls.K) ? piv_at(ls, i * 3 + q, g) : lim[q];
+                d[q] = csub(mul_m(pv, rr), cmul(pv.am, carry[q]));
+                carry[q] = d[q];
+                prev[q] = cur[q];
+                cur[q] = nxt[q];
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) dst[m * plane + (size_t)g * nx + i] = d[m];
+        }
+        C x[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
+        for (int g = ny - 1; g >= 0; --g) {
+            C o[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) o[m] = dst[m * plane + (size_t)g * nx + i];
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const Piv<T> pv = (g < ls.K) ? piv_at(ls, i * 3 + q, g) : lim[q];
+                x[q] = csub(o[q], cmul(pv.cp, x[q]));
+                o[q] = x[q];
+            }
+            from_sx<C, T>(o[0], o[1], o[2]);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                dst[m * plane + (size_t)g * nx + i] = o[m];
+                if (NORM) acc += (double)cnorm2(o[m]);
+            }
+        }
+    }
+    if (NORM) {
+        const double tot = block_sum(acc, shr);
+        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG>
+__global__ __launch_bounds__(256) void k_local(cx<T>* __restrict__ psi, Phys ph) {
+    const size_t plane = (size_t)ph.nx * ph.ny;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane; idx += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx % ph.nx), j = (int)(idx / ph.nx);
+        const T x = (T)(ph.x0 + i * ph.dx), y = (T)(ph.y0 + j * ph.dy);
+        cx<T> p = psi[idx], z = psi[plane + idx], m = psi[2 * plane + idx];
+        local_substep<T, IMAG>(p, z, m, (T)0.5 * (x * x + y * y), (T)ph.dt, (T)ph.c0, (T)ph.c2, (T)ph.rabi);
+        psi[idx] = p; psi[plane + idx] = z; psi[2 * plane + idx] = m;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale(cx<T>* __restrict__ psi, size_t n, const double* __restrict__ scale) {
+    const T s = (T)(*scale);
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x)
+        psi[idx] = cscale(psi[idx], s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_norm_partials(const cx<T>* __restrict__ psi, size_t n, double* __restrict__ partials) {
+    __shared__ double shr[16];
+    double acc = 0;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x)
+        acc += (double)cnorm2(psi[idx]);
+    const double tot = block_sum(acc, shr);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+__global__ void k_set_scale(double* scale, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *scale = v;
+}
+
+// Sum the per-block partial norms in a fixed order; scale = 1/sqrt(dx dy sum).
+__global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict__ partials, int n, double dxdy,
+                                                      double* __restrict__ scale, int* __restrict__ flag) {
+    __shared__ double shr[16];
+    double acc = 0;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) acc += partials[k];
+    const double tot = block_sum(acc, shr);
+    if (threadIdx.x == 0) {
+        const double nn = tot * dxdy;
+        if (nn > 0.0 && isfinite(nn)) {
+            *scale = 1.0 / sqrt(nn);
+        } else {
+            *scale = 1.0;
+            *flag = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Observables: per-point contributions accumulated in FP64.
+// q: 0-2 rho_m, 3 kinetic, 4 trap, 5 interaction, 6 rotation (-Omega <Lz>),
+//    7 SO, 8 Rabi, 9 <Lz>, 10-12 Re conj(psi_m) (H psi)_m.
+// ---------------------------------------------------------------------------
+struct ObsArgs {
+    double c0, c2, rabi, gamma, omega;
+    int eta;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_obs(const cx<T>* __restrict__ psi, Phys ph, ObsArgs oa,
+                                            T* __restrict__ dens, double* __restrict__ partials) {
+    __shared__ double shr[16];
+    const int nx = ph.nx, ny = ph.ny;
+    const size_t plane = (size_t)nx * ny;
+    const double idx2 = 1.0 / (ph.dx * ph.dx), idy2 = 1.0 / (ph.dy * ph.dy);
+    const double i2dx = 0.5 / ph.dx, i2dy = 0.5 / ph.dy;
+    const double s2 = 1.4142135623730950488, is2 = 0.70710678118654752440;
+    double acc[kObsCount];
+#pragma unroll
+    for (int q = 0; q < kObsCount; ++q) acc[q] = 0;
+    auto ld = [&](int m, int j, int i) -> double2 {
+        if (i < 0 || i >= nx || j < 0 || j >= ny) return make_double2(0.0, 0.0);
+        const cx<T> z = psi[m * plane + (size_t)j * nx + i];
+        return make_double2((double)z.x, (double)z.y);
+    };
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane; idx += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx % nx), j = (int)(idx / nx);
+        const double x = ph.x0 + i * ph.dx, y = ph.y0 + j * ph.dy;
+        double2 v[3], dxv[3], dyv[3], lap[3];
+        for (int m = 0; m < 3; ++m) {
+            v[m] = ld(m, j, i);
+            const double2 xe = ld(m, j, i + 1), xw = ld(m, j, i - 1), yn = ld(m, j + 1, i), ys = ld(m, j - 1, i);
+            dxv[m] = cscale(csub(xe, xw), i2dx);
+            dyv[m] = cscale(csub(yn, ys), i2dy);
+            lap[m] = cadd(cscale(csub(cadd(xe, xw), cscale(v[m], 2.0)), idx2),
+                          cscale(csub(cadd(yn, ys), cscale(v[m], 2.0)), idy2));
+            // kinetic: forward differences (plus the ghost-side difference at i = 0, j = 0)
+            const double2 gx = csub(xe, v[m]), gy = csub(yn, v[m]);
+            double k = cnorm2(gx) * idx2 + cnorm2(gy) * idy2;
+            if (i == 0) k += cnorm2(v[m]) * idx2;
+            if (j == 0) k += cnorm2(v[m]) * idy2;
+            acc[3] += 0.5 * k;
+        }
+        const double rp = cnorm2(v[0]), r0 = cnorm2(v[1]), rm = cnorm2(v[2]);
+        const double rho = rp + r0 + rm;
+        const double V = 0.5 * (x * x + y * y);
+        acc[0] += rp; acc[1] += r0; acc[2] += rm;
+        acc[4] += V * rho;
+        // spin density
+        const double Fz = rp - rm;
+        const double2 Fp = cscale(cadd(cmulc(v[1], v[0]), cmulc(v[2], v[1])), s2);  // Fx + i Fy
+        const double F2 = Fz * Fz + cnorm2(Fp);
+        acc[5] += 0.5 * (oa.c0 * rho * rho + oa.c2 * F2);
+        acc[8] += oa.rabi * Fp.x;
+        // H_loc psi with B = c2 F + R e_x, plus the scalar part
+        const double2 Bp = make_double2(oa.c2 * Fp.x + oa.rabi, oa.c2 * Fp.y), Bm = cconj(Bp);
+        const double Bz = oa.c2 * Fz;
+        double2 Hv[3];
+        Hv[0] = cadd(cscale(v[0], Bz), cscale(cmul(Bm, v[1]), is2));
+        Hv[1] = cscale(cadd(cmul(Bp, v[0]), cmul(Bm, v[2])), is2);
+        Hv[2] = csub(cscale(cmul(Bp, v[1]), is2), cscale(v[2], Bz));
+        // SO: i gamma Sigma_y D_x psi - i eta gamma Sigma_x D_y psi
+        //   Sigma_y w = i (-w0, w+ - w-, w0)/sqrt2 ; Sigma_x w = (w0, w+ + w-, w0)/sqrt2
+        const double g = oa.gamma * is2, ge = oa.gamma * oa.eta * is2;
+        double2 so[3];
+        // i * i (-dx0) g = g dx0 ; i * i (dx+ - dx-) g = -g (dx+ - dx-) ; i*i dx0 g = -g dx0
+        so[0] = csub(cscale(dxv[1], g), cscale(ctimes_i(dyv[1]), ge));
+        so[1] = csub(cscale(csub(dxv[0], dxv[2]), -g), cscale(ctimes_i(cadd(dyv[0], dyv[2])), ge));
+        so[2] = csub(cscale(dxv[1], -g), cscale(ctimes_i(dyv[1]), ge));
+        for (int m = 0; m < 3; ++m) {
+            // L_z psi = -i (x D_y - y D_x) psi
+            const double2 lz = ctimes_mi(csub(cscale(dyv[m], x), cscale(dxv[m], y)));
+            const double lzr = cmulc(lz, v[m]).x;  // Re conj(v) Lz v
+            acc[9] += lzr;
+            acc[6] += -oa.omega * lzr;
+            acc[7] += cmulc(so[m], v[m]).x;
+            double2 hm = cadd(cscale(lap[m], -0.5), cscale(v[m], V + oa.c0 * rho));
+            hm = cadd(hm, Hv[m]);
+            hm = csub(hm, cscale(lz, oa.omega));
+            hm = cadd(hm, so[m]);
+            acc[10 + m] += cmulc(hm, v[m]).x;
+        }
+        if (dens) {
+            dens[idx] = (T)rp; dens[plane + idx] = (T)r0; dens[2 * plane + idx] = (T)rm;
+        }
+    }
+    for (int q = 0; q < kObsCount; ++q) {
+        const double tot = block_sum(acc[q], shr);
+        if (threadIdx.x == 0) partials[(size_t)blockIdx.x * kObsCount + q] = tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_obs_finalize(const double* __restrict__ partials, int nblk,
+                                                     double* __restrict__ out) {
+    __shared__ double shr[16];
+    for (int q = 0; q < kObsCount; ++q) {
+        double acc = 0;
+        for (int k = threadIdx.x; k < nblk; k += blockDim.x) acc += partials[(size_t)k * kObsCount + q];
+        const double tot = block_sum(acc, shr);
+        if (threadIdx.x == 0) out[q] = tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, bool LOCAL, bool SCALE>
+static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph, const LineSet<T>& ls,
+                             const double* scale, int G, int R, hipStream_t st) {
+    const int nblk = (ph.ny + R - 1) / R;
+    const dim3 grid(nblk), block(G * R);
+    if (G * R > 512) return hipErrorInvalidValue;
+    switch (K) {
+        case 1: k_x_scan<T, IMAG, 1, LOCAL, SCALE, 256><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 2: k_x_scan<T, IMAG, 2, LOCAL, SCALE, 256><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 4: k_x_scan<T, IMAG, 4, LOCAL, SCALE, 256><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 8: k_x_scan<T, IMAG, 8, LOCAL, SCALE, 512><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 16: k_x_scan<T, IMAG, 16, LOCAL, SCALE, 512><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_x(const XLaunch<T>& a, hipStream_t st) {
+    if (a.imag) {
+        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
+        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
+    }
+    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
+    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
+}
+
+template <typename T, bool IMAG, bool NORM>
+static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st) {
+    constexpr int KY = YCfg<T>::KY, TW = YCfg<T>::TW, S = YCfg<T>::S;
+    const int ncs = (a.ph.nx + TW - 1) / TW;
+    const int nrt = (a.ph.ny + a.L - 1) / a.L;
+    k_y_window<T, IMAG, KY, TW, S, NORM><<<dim3(ncs * nrt), dim3(TW * S), 0, st>>>(a.src, a.dst, a.ph, a.ls, a.L, a.h,
+                                                                                  ncs, a.partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+int y_blocks(const YLaunch<T>& a) {
+    if (a.window) {
+        const int ncs = (a.ph.nx + YCfg<T>::TW - 1) / YCfg<T>::TW;
+        return ncs * ((a.ph.ny + a.L - 1) / a.L);
+    }
+    return (a.ph.nx + 255) / 256;
+}
+
+template <typename T>
+hipError_t launch_y(const YLaunch<T>& a, hipStream_t st) {
+    if (a.window) {
+        if (a.imag) return a.norm ? launch_yw<T, true, true>(a, st) : launch_yw<T, true, false>(a, st);
+        return a.norm ? launch_yw<T, false, true>(a, st) : launch_yw<T, false, false>(a, st);
+    }
+    const dim3 grid((a.ph.nx + 255) / 256), block(256);
+    if (a.imag) {
+        if (a.norm) k_y_thomas<T, true, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
+        else k_y_thomas<T, true, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
+    } else {
+        if (a.norm) k_y_thomas<T, false, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
+        else k_y_thomas<T, false, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_local(cx<T>* psi, const Phys& ph, bool imag, hipStream_t st) {
+    const size_t n = (size_t)ph.nx * ph.ny;
+    const int nblk = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
+    if (imag) k_local<T, true><<<nblk, 256, 0, st>>>(psi, ph);
+    else k_local<T, false><<<nblk, 256, 0, st>>>(psi, ph);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale(cx<T>* psi, size_t n, const double* scale, hipStream_t st) {
+    const int nblk = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    k_scale<T><<<nblk, 256, 0, st>>>(psi, n, scale);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_norm_partials(const cx<T>* psi, size_t n, double* partials, int nblk, hipStream_t st) {
+    k_norm_partials<T><<<nblk, 256, 0, st>>>(psi, n, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_scale(double* scale, double v, hipStream_t st) {
+    k_set_scale<<<1, 64, 0, st>>>(scale, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, double* scale, int* flag, hipStream_t st) {
+    k_norm_finalize<<<1, 256, 0, st>>>(partials, n, dxdy, scale, flag);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_obs(const cx<T>* psi, const Phys& ph, const ObsLaunch& o, T* dens, double* partials, int nblk,
+                      hipStream_t st) {
+    ObsArgs oa{o.c0, o.c2, o.rabi, o.gamma, o.omega, o.eta};
+    k_obs<T><<<nblk, 256, 0, st>>>(psi, ph, oa, dens, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_obs_finalize(const double* partials, int nblk, double* out, hipStream_t st) {
+    k_obs_finalize<<<1, 256, 0, st>>>(partials, nblk, out);
+    return hipGetLastError();
+}
+
+#define GP_INST(T)                                                                                             \
+    template hipError_t launch_x<T>(const XLaunch<T>&, hipStream_t);                                           \
+    template hipError_t launch_y<T>(const YLaunch<T>&, hipStream_t);                                           \
+    template int y_blocks<T>(const YLaunch<T>&);                                                               \
+    template hipError_t launch_local<T>(cx<T>*, const Phys&, bool, hipStream_t);                               \
+    template hipError_t launch_scale<T>(cx<T>*, size_t, const double*, hipStream_t);                           \
+    template hipError_t launch_norm_partials<T>(const cx<T>*, size_t, double*, int, hipStream_t);              \
+    template hipError_t launch_obs<T>(const cx<T>*, const Phys&, const ObsLaunch&, T*, double*, int, hipStream_t);
+GP_INST(double)
+GP_INST(float)
+
+}  // namespace gp

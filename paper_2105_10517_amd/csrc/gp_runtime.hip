@@ -1,0 +1,666 @@
+// Host runtime behind the C ABI of include/gp_spin1.h: parameter validation,
+// Thomas pivot tables per line, stability checks, the launch plan and the
+// step sequencing on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gp_kernels.hpp"
+#include "gp_spin1.h"
+
+using zd = std::complex<double>;
+
+namespace {
+
+struct DirTable {
+    int K = 0, lines = 0;
+    zd b{1.0, 0.0};
+    double decay = 0.0;
+    bool dominant = true;
+    void* d_piv = nullptr;
+    void* d_ae = nullptr;
+};
+
+struct ModeState {
+    DirTable x, y;
+    bool stable = false;
+    std::string why;
+    bool window = false;
+    int h = 0, L = 0;
+    int ypart_blocks = 0;
+    gp_spin1_plan plan{};
+};
+
+}  // namespace
+
+struct gp_spin1 {
+    gp_spin1_params p{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    ModeState mode[2];  // [0] real time, [1] imaginary time
+    int xK = 4, xG = 64, xR = 1;
+    double* d_scale = nullptr;
+    int* d_flag = nullptr;
+    double* d_part = nullptr;
+    size_t n_part = 0;
+    double* d_obs = nullptr;
+    int obs_blocks = 0;
+    void* d_work = nullptr;  // a second wave function: the x sweep writes it, the y sweep reads it
+    // optional per-kernel timing: pairs of events around launches of kind k
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_open;
+    size_t ev_next = 0;
+    int64_t t_launches[4] = {0, 0, 0, 0};
+    double t_ms[4] = {0, 0, 0, 0};
+    std::string err;
+};
+
+namespace {
+
+constexpr double kNu[3] = {1.0, 0.0, -1.0};  // eigenvalue order of the basis changes (+1, 0, -1)
+
+int fail(gp_spin1* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+int hip_fail(gp_spin1* h, hipError_t e, const char* where) {
+    return fail(h, GP_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// Tridiagonal coefficients of (I + alpha h1) for h1 = -1/2 d^2 + c d on step s:
+// sub a = alpha (-1/(2 s^2) - c/(2 s)), diag b = 1 + alpha/s^2, super e = alpha (-1/(2 s^2) + c/(2 s)).
+void coeffs(zd alpha, double s, zd c, zd& a, zd& b, zd& e) {
+    a = alpha * (-0.5 / (s * s) - c / (2.0 * s));
+    b = 1.0 + alpha / (s * s);
+    e = alpha * (-0.5 / (s * s) + c / (2.0 * s));
+}
+
+// Converged pivot: the root of w^2 - b w + a e = 0 of larger modulus (the
+// attracting fixed point of w -> b - a e / w).
+zd pivot_limit(zd a, zd b, zd e) {
+    const zd d = std::sqrt(b * b - 4.0 * a * e);
+    const zd w1 = 0.5 * (b + d), w2 = 0.5 * (b - d);
+    return std::abs(w1) >= std::abs(w2) ? w1 : w2;
+}
+
+template <typename T>
+gp::cx<T> to_dev(zd z) {
+    return gp::mk<T>((T)z.real(), (T)z.imag());
+}
+
+// Pivot table of one direction, computed on the host in FP64: lines =
+// nother * 3 (line index = other * 3 + eigenvalue index), line length n.
+struct HostDir {
+    int K = 1, lines = 0;
+    zd b{1.0, 0.0};
+    double decay = 0.0;
+    bool dominant = true;
+    std::vector<zd> A, E, W;
+};
+
+// Round a complex coefficient to the storage precision T and back.
+template <typename T>
+zd round_to(zd z) {
+    return zd((double)(T)z.real(), (double)(T)z.imag());
+}
+
+template <typename T, typename F>
+void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
+    const int lines = nother * 3;
+    d.lines = lines;
+    d.A.assign(lines, zd());
+    d.E.assign(lines, zd());
+    d.W.assign(lines, zd());
+    // the finite-precision recurrence settles a few ulp from the exact fixed point
+    const double tol = 32.0 * 1.1102230246251565e-16;
+    int K = 1;
+    d.dominant = true;
+    d.decay = 0.0;
+    for (int l = 0; l < lines; ++l) {
+        zd a, e;
+        coeffs(alpha, step, coef(l), a, d.b, e);
+        // the kernels see the coefficients in precision T; the pivots are those
+        // of the rounded matrix
+        a = round_to<T>(a); e = round_to<T>(e); d.b = round_to<T>(d.b);
+        d.A[l] = a; d.E[l] = e;
+        if (std::abs(d.b) < (std::abs(a) + std::abs(e)) * (1.0 - 1e-12)) d.dominant = false;
+        const zd wl = pivot_limit(a, d.b, e);
+        d.W[l] = wl;
+        zd w = d.b;
+        int k = 0;
+        while (k < n - 1 && std::abs(w - wl) > tol * std::abs(wl)) {
+            w = d.b - a * e / w;
+            ++k;
+        }
+        if (k + 1 > K) K = k + 1;
+        d.decay = std::max(d.decay, std::max(std::abs(a / wl), std::abs(e / wl)));
+    }
+    d.K = std::min(K, n);
+}
+
+template <typename T>
+void set_piv(gp::Piv<T>& pv, zd a, zd e, zd w) {
+    const zd m = 1.0 / w;
+    pv.m = to_dev<T>(m);
+    pv.mlo = to_dev<T>(m - round_to<T>(m));
+    pv.am = to_dev<T>(a * m);
+    pv.cp = to_dev<T>(e * m);
+}
+
+template <typename T>
+int upload_dir(gp_spin1* h, const HostDir& hd, DirTable& d) {
+    const int lines = hd.lines, K = hd.K;
+    d.lines = lines; d.K = K; d.b = hd.b; d.decay = hd.decay; d.dominant = hd.dominant;
+    std::vector<gp::Piv<T>> piv((size_t)lines * (K + 1));
+    std::vector<gp::cx<T>> ae((size_t)lines * 2);
+    for (int l = 0; l < lines; ++l) {
+        zd w = hd.b;
+        for (int k = 0; k < K; ++k) {
+            if (k > 0) w = hd.b - hd.A[l] * hd.E[l] / w;
+            set_piv<T>(piv[(size_t)l * (K + 1) + k], hd.A[l], hd.E[l], w);
+        }
+        set_piv<T>(piv[(size_t)l * (K + 1) + K], hd.A[l], hd.E[l], hd.W[l]);
+        ae[2 * (size_t)l] = to_dev<T>(hd.A[l]);
+        ae[2 * (size_t)l + 1] = to_dev<T>(hd.E[l]);
+    }
+    hipError_t e1 = hipMalloc(&d.d_piv, piv.size() * sizeof(gp::Piv<T>));
+    if (e1 != hipSuccess) return fail(h, GP_ENOMEM, "pivot table allocation failed");
+    hipError_t e2 = hipMalloc(&d.d_ae, ae.size() * sizeof(gp::cx<T>));
+    if (e2 != hipSuccess) return fail(h, GP_ENOMEM, "coefficient table allocation failed");
+    hipError_t e3 = hipMemcpy(d.d_piv, piv.data(), piv.size() * sizeof(gp::Piv<T>), hipMemcpyHostToDevice);
+    if (e3 != hipSuccess) return hip_fail(h, e3, "pivot table upload");
+    hipError_t e4 = hipMemcpy(d.d_ae, ae.data(), ae.size() * sizeof(gp::cx<T>), hipMemcpyHostToDevice);
+    if (e4 != hipSuccess) return hip_fail(h, e4, "coefficient table upload");
+    return GP_OK;
+}
+
+template <typename T>
+gp::LineSet<T> lineset(const DirTable& d) {
+    gp::LineSet<T> ls;
+    ls.piv = (const gp::Piv<T>*)d.d_piv;
+    ls.ae = (const gp::cx<T>*)d.d_ae;
+    ls.b = to_dev<T>(d.b);
+    ls.K = d.K;
+    return ls;
+}
+
+gp::Phys phys(const gp_spin1_params& p) {
+    gp::Phys ph;
+    ph.nx = p.nx; ph.ny = p.ny;
+    ph.dx = p.dx; ph.dy = p.dy; ph.x0 = p.x0; ph.y0 = p.y0; ph.dt = p.dt;
+    ph.c0 = p.c0; ph.c2 = p.c2; ph.rabi = p.rabi;
+    return ph;
+}
+
+// Line tables, stability checks and the y plan of one propagation mode,
+// all on the host.
+struct HostMode {
+    HostDir x, y;
+    bool stable = true;
+    std::string why;
+    bool window = false;
+    int h = 0, L = 0;
+};
+
+template <typename T>
+void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
+    const zd alpha = imag ? zd(0.5 * p.dt, 0.0) : zd(0.0, 0.5 * p.dt);
+    host_dir<T>(hm.x, p.nx, p.ny, alpha, p.dx, [&](int l) {
+        const double y = p.y0 + (l / 3) * p.dy;
+        return zd(0.0, -(p.omega * y - p.gamma * kNu[l % 3]));  // c = -i (Omega y - gamma nu)
+    });
+    host_dir<T>(hm.y, p.ny, p.nx, alpha, p.dy, [&](int l) {
+        const double x = p.x0 + (l / 3) * p.dx;
+        return zd(0.0, p.omega * x - p.eta * p.gamma * kNu[l % 3]);  // c = i (Omega x - eta gamma mu)
+    });
+    hm.stable = true;
+    hm.why.clear();
+    if (!hm.x.dominant || !hm.y.dominant) {
+        hm.stable = false;
+        hm.why = "line systems are not diagonally dominant (dt too large for dx, dy and the rotation/SO terms)";
+    }
+    if (imag) {
+        const double Lmax = std::max(std::max(std::fabs(p.x0), std::fabs(p.x0 + (p.nx - 1) * p.dx)),
+                                     std::max(std::fabs(p.y0), std::fabs(p.y0 + (p.ny - 1) * p.dy)));
+        const double cm = std::fabs(p.omega) * Lmax + std::fabs(p.gamma);
+        if (0.25 * p.dt * cm * cm >= 1.0) {
+            hm.stable = false;
+            hm.why = "imaginary-time Cayley bound (dt/4)(|Omega| L_max + |gamma|)^2 < 1 fails";
+        }
+    }
+    // y plan: windows of W rows overlapping by h rows on each side, where the
+    // truncated carries decay by decay^h below the rounding level of T.
+    constexpr int W = gp::YCfg<T>::S * gp::YCfg<T>::KY;
+    const double tolw = sizeof(T) == 8 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -32);
+    int hh;
+    if (hm.y.decay <= 0.0) hh = 1;
+    else if (hm.y.decay >= 1.0) hh = 1 << 20;
+    else hh = (int)std::ceil(std::log(tolw) / std::log(hm.y.decay)) + 1;
+    hm.window = false;
+    hm.h = 0;
+    hm.L = 0;
+    if (p.y_solver != GP_YSOLVER_THOMAS) {
+        if (p.ny <= W) {
+            hm.window = true; hm.h = 0; hm.L = W;
+        } else if (2 * hh <= W / 2) {
+            hm.window = true; hm.h = hh; hm.L = W - 2 * hh;
+        }
+    }
+}
+
+int x_points_per_thread(int nx) {
+    if (nx <= 128) return 2;
+    if (nx <= 1024) return 4;
+    if (nx <= 4096) return 8;
+    return 16;
+}
+
+template <typename T>
+void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out) {
+    std::memset(out, 0, sizeof *out);
+    const int K = x_points_per_thread(p.nx);
+    const int G = ((p.nx + K - 1) / K + 63) / 64 * 64;
+    out->x_points_per_thread = K;
+    out->x_threads_per_row = G;
+    out->x_rows_per_block = std::max(1, std::min(8, 256 / G));
+    out->y_solver = hm.window ? GP_YSOLVER_WINDOW : GP_YSOLVER_THOMAS;
+    out->y_halo = hm.h;
+    out->y_rows_out = hm.L;
+    out->y_tile_cols = gp::YCfg<T>::TW;
+    out->y_segments = gp::YCfg<T>::S;
+    out->y_rows_per_thread = gp::YCfg<T>::KY;
+    out->pivots_x = hm.x.K;
+    out->pivots_y = hm.y.K;
+    out->decay_x = hm.x.decay;
+    out->decay_y = hm.y.decay;
+    out->stable = hm.stable ? 1 : 0;
+}
+
+template <typename T>
+int build_mode(gp_spin1* h, ModeState& ms, bool imag) {
+    const gp_spin1_params& p = h->p;
+    HostMode hm;
+    host_mode<T>(p, imag, hm);
+    int rc = upload_dir<T>(h, hm.x, ms.x);
+    if (rc) return rc;
+    rc = upload_dir<T>(h, hm.y, ms.y);
+    if (rc) return rc;
+    ms.stable = hm.stable;
+    ms.why = hm.why;
+    ms.window = hm.window;
+    ms.h = hm.h;
+    ms.L = hm.L;
+    fill_plan<T>(p, hm, &ms.plan);
+    if (ms.window) {
+        const int ncs = (p.nx + gp::YCfg<T>::TW - 1) / gp::YCfg<T>::TW;
+        ms.ypart_blocks = ncs * ((p.ny + ms.L - 1) / ms.L);
+    } else {
+        ms.ypart_blocks = (p.nx + 255) / 256;
+    }
+    return GP_OK;
+}
+
+void free_dir(DirTable& d) {
+    if (d.d_piv) (void)hipFree(d.d_piv);
+    if (d.d_ae) (void)hipFree(d.d_ae);
+    d.d_piv = d.d_ae = nullptr;
+}
+
+void destroy_all(gp_spin1* h) {
+    for (auto& m : h->mode) { free_dir(m.x); free_dir(m.y); }
+    if (h->d_scale) (void)hipFree(h->d_scale);
+    if (h->d_flag) (void)hipFree(h->d_flag);
+    if (h->d_part) (void)hipFree(h->d_part);
+    if (h->d_obs) (void)hipFree(h->d_obs);
+    if (h->d_work) (void)hipFree(h->d_work);
+    for (hipEvent_t e : h->ev_pool) (void)hipEventDestroy(e);
+    delete h;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+int validate(const gp_spin1_params* p, std::string& why) {
+    if (!p) { why = "params is NULL"; return GP_EINVAL; }
+    if (p->nx < 3 || p->ny < 3) { why = "nx and ny must be >= 3"; return GP_EINVAL; }
+    if (!(p->dx > 0) || !(p->dy > 0) || !finite(p->dx) || !finite(p->dy)) { why = "dx, dy must be finite and > 0"; return GP_EINVAL; }
+    if (!(p->dt > 0) || !finite(p->dt)) { why = "dt must be finite and > 0"; return GP_EINVAL; }
+    if (!finite(p->c0) || !finite(p->c2) || !finite(p->gamma) || !finite(p->rabi) || !finite(p->omega)) {
+        why = "c0, c2, gamma, rabi, omega must be finite";
+        return GP_EINVAL;
+    }
+    if ((!std::isnan(p->x0) && !finite(p->x0)) || (!std::isnan(p->y0) && !finite(p->y0))) {
+        why = "x0, y0 must be finite (or NaN for the default)";
+        return GP_EINVAL;
+    }
+    if (p->eta != 1 && p->eta != -1) { why = "eta must be +1 (Rashba) or -1 (Dresselhaus)"; return GP_EINVAL; }
+    if (p->precision != GP_FP64 && p->precision != GP_FP32) { why = "precision must be GP_FP64 or GP_FP32"; return GP_EINVAL; }
+    if (p->y_solver < GP_YSOLVER_AUTO || p->y_solver > GP_YSOLVER_THOMAS) { why = "unknown y_solver"; return GP_EINVAL; }
+    const int nmax = 8192;
+    if (p->nx > nmax) { why = "nx above the largest row this build holds on chip"; return GP_EUNSUPPORTED; }
+    if ((double)p->nx * (double)p->ny * 3.0 > 4.0e9) { why = "grid too large"; return GP_EUNSUPPORTED; }
+    return GP_OK;
+}
+
+template <typename T>
+int create_t(gp_spin1* h) {
+    const gp_spin1_params& p = h->p;
+    // x plan: K consecutive points per thread, rows of G = 64 * nw threads
+    const int K = x_points_per_thread(p.nx);
+    const int G = ((p.nx + K - 1) / K + 63) / 64 * 64;
+    h->xK = K;
+    h->xG = G;
+    h->xR = std::max(1, std::min(8, 256 / G));
+    for (int m = 0; m < 2; ++m) {
+        int rc = build_mode<T>(h, h->mode[m], m == 1);
+        if (rc) return rc;
+    }
+    size_t need = 1;
+    for (auto& m : h->mode) need = std::max(need, (size_t)m.ypart_blocks);
+    const size_t npts = (size_t)p.nx * p.ny;
+    h->obs_blocks = (int)std::min<size_t>(1024, (npts + 255) / 256);
+    need = std::max(need, (size_t)h->obs_blocks * gp::kObsCount);
+    need = std::max(need, (size_t)1024);
+    h->n_part = need;
+    if (hipMalloc(&h->d_part, need * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&h->d_scale, sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&h->d_flag, sizeof(int)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&h->d_obs, gp::kObsCount * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&h->d_work, (size_t)3 * p.nx * p.ny * sizeof(gp::cx<T>)) != hipSuccess)
+        return fail(h, GP_ENOMEM, "work buffer allocation failed");
+    const double one = 1.0;
+    const int zero = 0;
+    hipError_t e;
+    if ((e = hipMemcpy(h->d_scale, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
+    if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
+    return GP_OK;
+}
+
+template <typename T>
+gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool local) {
+    gp::XLaunch<T> a;
+    a.src = (const gp::cx<T>*)src;
+    a.dst = (gp::cx<T>*)dst;
+    a.ph = phys(h->p);
+    a.ls = lineset<T>(h->mode[imag].x);
+    a.scale = h->d_scale;
+    a.K = h->xK; a.G = h->xG; a.R = h->xR;
+    a.imag = imag; a.local = local;
+    return a;
+}
+
+template <typename T>
+gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool norm) {
+    const ModeState& ms = h->mode[imag];
+    gp::YLaunch<T> a;
+    a.src = (const gp::cx<T>*)src;
+    a.dst = (gp::cx<T>*)dst;
+    a.ph = phys(h->p);
+    a.ls = lineset<T>(ms.y);
+    a.partials = h->d_part;
+    a.L = ms.L; a.h = ms.h;
+    a.window = ms.window; a.imag = imag; a.norm = norm;
+    return a;
+}
+
+// Timing: fold finished event pairs into the per-kind sums.
+hipError_t timing_drain(gp_spin1* h) {
+    if (h->ev_open.empty()) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return e;
+    for (auto& o : h->ev_open) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, o.second.first, o.second.second);
+        if (e != hipSuccess) return e;
+        h->t_ms[o.first] += ms;
+        h->t_launches[o.first] += 1;
+    }
+    h->ev_open.clear();
+    h->ev_next = 0;
+    return hipSuccess;
+}
+
+// Launch f() bracketed by an event pair of kind k when timing is on.
+template <typename F>
+hipError_t timed(gp_spin1* h, int k, F f) {
+    if (!h->timing) return f();
+    if (h->ev_next + 2 > 4096) {
+        hipError_t e = timing_drain(h);
+        if (e != hipSuccess) return e;
+    }
+    while (h->ev_pool.size() < h->ev_next + 2) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+        h->ev_pool.push_back(ev);
+    }
+    hipEvent_t a = h->ev_pool[h->ev_next], b = h->ev_pool[h->ev_next + 1];
+    h->ev_next += 2;
+    hipError_t e = hipEventRecord(a, h->stream);
+    if (e != hipSuccess) return e;
+    e = f();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, h->stream);
+    if (e != hipSuccess) return e;
+    h->ev_open.push_back({k, {a, b}});
+    return hipSuccess;
+}
+
+template <typename T>
+int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
+    const ModeState& ms = h->mode[imag];
+    if (!ms.stable) return fail(h, GP_EUNSTABLE, ms.why);
+    if (n == 0) return GP_OK;
+    hipStream_t st = h->stream;
+    const gp::XLaunch<T> xa = xlaunch<T>(h, psi, h->d_work, imag, true);
+    const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, psi, imag, imag);
+    const double dxdy = h->p.dx * h->p.dy;
+    hipError_t e;
+    if (imag && (e = gp::launch_set_scale(h->d_scale, 1.0, st)) != hipSuccess) return hip_fail(h, e, "set_scale");
+    for (int64_t s = 0; s < n; ++s) {
+        if ((e = timed(h, 0, [&] { return gp::launch_x<T>(xa, st); })) != hipSuccess) return hip_fail(h, e, "x sweep launch");
+        if ((e = timed(h, 1, [&] { return gp::launch_y<T>(ya, st); })) != hipSuccess) return hip_fail(h, e, "y sweep launch");
+        if (imag && (e = timed(h, 2, [&] {
+                         return gp::launch_norm_finalize(h->d_part, ms.ypart_blocks, dxdy, h->d_scale, h->d_flag, st);
+                     })) != hipSuccess)
+            return hip_fail(h, e, "norm launch");
+    }
+    if (imag) {
+        const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
+        if ((e = timed(h, 3, [&] { return gp::launch_scale<T>((gp::cx<T>*)psi, n3, h->d_scale, st); })) != hipSuccess)
+            return hip_fail(h, e, "scale launch");
+    }
+    return GP_OK;
+}
+
+template <typename T>
+int substep_t(gp_spin1* h, void* psi, int which, bool imag) {
+    hipStream_t st = h->stream;
+    hipError_t e = hipSuccess;
+    const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
+    switch (which) {
+        case 0: e = gp::launch_local<T>((gp::cx<T>*)psi, phys(h->p), imag, st); break;
+        case 1:
+        case 2: {
+            // out of place into the work buffer, then back
+            if (which == 1) e = gp::launch_x<T>(xlaunch<T>(h, psi, h->d_work, imag, false), st);
+            else e = gp::launch_y<T>(ylaunch<T>(h, psi, h->d_work, imag, false), st);
+            if (e != hipSuccess) break;
+            e = hipMemcpyAsync(psi, h->d_work, n3 * sizeof(gp::cx<T>), hipMemcpyDeviceToDevice, st);
+            break;
+        }
+        case 3: {
+            const int nblk = (int)std::min<size_t>(1024, (n3 + 255) / 256);
+            if ((e = gp::launch_norm_partials<T>((const gp::cx<T>*)psi, n3, h->d_part, nblk, st)) != hipSuccess) break;
+            if ((e = gp::launch_norm_finalize(h->d_part, nblk, h->p.dx * h->p.dy, h->d_scale, h->d_flag, st)) != hipSuccess) break;
+            e = gp::launch_scale<T>((gp::cx<T>*)psi, n3, h->d_scale, st);
+            break;
+        }
+        default: return fail(h, GP_EINVAL, "substep: which must be 0..3");
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "substep launch");
+    return GP_OK;
+}
+
+template <typename T>
+int obs_t(gp_spin1* h, const void* psi, gp_spin1_obs* out, void* dens) {
+    hipStream_t st = h->stream;
+    gp::ObsLaunch o{h->p.c0, h->p.c2, h->p.rabi, h->p.gamma, h->p.omega, h->p.eta};
+    hipError_t e;
+    if ((e = gp::launch_obs<T>((const gp::cx<T>*)psi, phys(h->p), o, (T*)dens, h->d_part, h->obs_blocks, st)) != hipSuccess)
+        return hip_fail(h, e, "observables launch");
+    if ((e = gp::launch_obs_finalize(h->d_part, h->obs_blocks, h->d_obs, st)) != hipSuccess)
+        return hip_fail(h, e, "observables finalize launch");
+    double q[gp::kObsCount];
+    if ((e = hipMemcpyAsync(q, h->d_obs, sizeof q, hipMemcpyDeviceToHost, st)) != hipSuccess) return hip_fail(h, e, "observables copy");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(h, e, "observables sync");
+    const double w = h->p.dx * h->p.dy;
+    for (double& v : q) v *= w;
+    out->norm[0] = q[0]; out->norm[1] = q[1]; out->norm[2] = q[2];
+    out->norm_total = q[0] + q[1] + q[2];
+    out->magnetization = q[0] - q[2];
+    out->e_kin = q[3]; out->e_trap = q[4]; out->e_int = q[5]; out->e_rot = q[6];
+    out->e_so = q[7]; out->e_rabi = q[8]; out->lz = q[9];
+    out->energy = q[3] + q[4] + q[5] + q[6] + q[7] + q[8];
+    for (int m = 0; m < 3; ++m) out->mu[m] = q[10 + m] / q[m];
+    out->mu_total = (q[10] + q[11] + q[12]) / out->norm_total;
+    for (double v : q)
+        if (!std::isfinite(v)) return fail(h, GP_ENONFINITE, "non-finite value in the observables");
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out) {
+    if (!out) return GP_EINVAL;
+    std::string why;
+    int rc = validate(p, why);
+    if (rc) return rc;
+    gp_spin1* h = new (std::nothrow) gp_spin1();
+    if (!h) return GP_ENOMEM;
+    h->p = *p;
+    if (std::isnan(h->p.x0)) h->p.x0 = -0.5 * h->p.nx * h->p.dx;
+    if (std::isnan(h->p.y0)) h->p.y0 = -0.5 * h->p.ny * h->p.dy;
+    h->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&h->device) != hipSuccess) { destroy_all(h); return GP_EHIP; }
+    rc = h->p.precision == GP_FP64 ? create_t<double>(h) : create_t<float>(h);
+    if (rc) { destroy_all(h); return rc; }
+    *out = h;
+    return GP_OK;
+}
+
+int gp_spin1_destroy(gp_spin1_t* h) {
+    if (!h) return GP_EINVAL;
+    destroy_all(h);
+    return GP_OK;
+}
+
+int gp_spin1_step_imag(gp_spin1_t* h, void* psi, int64_t nsteps) {
+    if (!h) return GP_EINVAL;
+    if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
+    return h->p.precision == GP_FP64 ? steps_t<double>(h, psi, nsteps, true) : steps_t<float>(h, psi, nsteps, true);
+}
+
+int gp_spin1_step_real(gp_spin1_t* h, void* psi, int64_t nsteps) {
+    if (!h) return GP_EINVAL;
+    if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
+    return h->p.precision == GP_FP64 ? steps_t<double>(h, psi, nsteps, false) : steps_t<float>(h, psi, nsteps, false);
+}
+
+int gp_spin1_substep(gp_spin1_t* h, void* psi, int32_t which, int32_t imag) {
+    if (!h) return GP_EINVAL;
+    if (!psi) return fail(h, GP_EINVAL, "psi is NULL");
+    return h->p.precision == GP_FP64 ? substep_t<double>(h, psi, which, imag != 0)
+                                     : substep_t<float>(h, psi, which, imag != 0);
+}
+
+int gp_spin1_observables(gp_spin1_t* h, const void* psi, gp_spin1_obs* out, void* dens) {
+    if (!h) return GP_EINVAL;
+    if (!psi || !out) return fail(h, GP_EINVAL, "psi or out is NULL");
+    return h->p.precision == GP_FP64 ? obs_t<double>(h, psi, out, dens) : obs_t<float>(h, psi, out, dens);
+}
+
+int gp_spin1_sync(gp_spin1_t* h) {
+    if (!h) return GP_EINVAL;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "sync");
+    int flag = 0;
+    if ((e = hipMemcpy(&flag, h->d_flag, sizeof flag, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(h, e, "flag read");
+    if (flag) {
+        const int zero = 0;
+        if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "flag clear");
+        return fail(h, GP_ENONFINITE, "an imaginary-time norm was not finite");
+    }
+    return GP_OK;
+}
+
+int gp_spin1_get_plan(const gp_spin1_t* h, int32_t imag, gp_spin1_plan* out) {
+    if (!h || !out) return GP_EINVAL;
+    *out = h->mode[imag ? 1 : 0].plan;
+    return GP_OK;
+}
+
+int gp_spin1_plan_query(const gp_spin1_params* p, int32_t imag, gp_spin1_plan* out) {
+    if (!out) return GP_EINVAL;
+    std::string why;
+    int rc = validate(p, why);
+    if (rc) return rc;
+    gp_spin1_params q = *p;
+    if (std::isnan(q.x0)) q.x0 = -0.5 * q.nx * q.dx;
+    if (std::isnan(q.y0)) q.y0 = -0.5 * q.ny * q.dy;
+    HostMode hm;
+    if (q.precision == GP_FP64) {
+        host_mode<double>(q, imag != 0, hm);
+        fill_plan<double>(q, hm, out);
+    } else {
+        host_mode<float>(q, imag != 0, hm);
+        fill_plan<float>(q, hm, out);
+    }
+    return GP_OK;
+}
+
+int gp_spin1_timing_enable(gp_spin1_t* h, int32_t enable) {
+    if (!h) return GP_EINVAL;
+    hipError_t e = timing_drain(h);
+    if (e != hipSuccess) return hip_fail(h, e, "timing");
+    h->timing = enable != 0;
+    for (int k = 0; k < 4; ++k) { h->t_launches[k] = 0; h->t_ms[k] = 0.0; }
+    return GP_OK;
+}
+
+int gp_spin1_timing_read(gp_spin1_t* h, gp_spin1_timing* out) {
+    if (!h || !out) return GP_EINVAL;
+    hipError_t e = timing_drain(h);
+    if (e != hipSuccess) return hip_fail(h, e, "timing");
+    for (int k = 0; k < 4; ++k) { out->launches[k] = h->t_launches[k]; out->ms[k] = h->t_ms[k]; }
+    return GP_OK;
+}
+
+const char* gp_spin1_strerror(int status) {
+    switch (status) {
+        case GP_OK: return "success";
+        case GP_EINVAL: return "invalid argument";
+        case GP_EUNSTABLE: return "parameters fail the stability checks for this propagation";
+        case GP_ENOMEM: return "device allocation failed";
+        case GP_EHIP: return "HIP runtime error";
+        case GP_ENONFINITE: return "non-finite value";
+        case GP_EUNSUPPORTED: return "unsupported size or option";
+        default: return "unknown status";
+    }
+}
+
+const char* gp_spin1_last_error(const gp_spin1_t* h) {
+    if (!h) return "";
+    return h->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry point
+the header declares, validates parameters and computes its plan on the host."""
+import math
+import os
+import re
+
+import pytest
+
+from paper_2105_10517_amd import binding, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    src = open(os.path.join(ROOT, "include", "gp_spin1.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(gp_spin1_\w+)\s*\(", src, re.M)))
+
+
+def test_header_matches_binding_exports():
+    assert declared() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.load()
+    for name in declared():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_covers_every_status():
+    lib = binding.load()
+    seen = set()
+    for st in range(0, -7, -1):
+        msg = lib.gp_spin1_strerror(st).decode()
+        assert msg and msg != "unknown status"
+        seen.add(msg)
+    assert len(seen) == 7
+
+
+BASE = inputs.params(64, 48, 0.1, dt=1e-3, c0=10.0, c2=-1.0, gamma=0.5, omega=0.3)
+
+
+@pytest.mark.parametrize("change,status", [
+    ({"nx": 2}, binding.GP_EINVAL), ({"ny": 1}, binding.GP_EINVAL),
+    ({"dx": 0.0}, binding.GP_EINVAL), ({"dy": -0.1}, binding.GP_EINVAL),
+    ({"dt": 0.0}, binding.GP_EINVAL), ({"dt": math.inf}, binding.GP_EINVAL),
+    ({"c0": math.nan}, binding.GP_EINVAL), ({"eta": 0}, binding.GP_EINVAL),
+    ({"omega": math.inf}, binding.GP_EINVAL), ({"x0": math.inf}, binding.GP_EINVAL),
+    ({"nx": 9000}, binding.GP_EUNSUPPORTED),
+])
+def test_validation(change, status):
+    p = dict(BASE, **change)
+    with pytest.raises(binding.GPError) as ei:
+        binding.plan_query(p, True)
+    assert ei.value.status == status
+
+
+def test_plan_of_the_workloads():
+    c1 = binding.plan_query(inputs.config_c1(), True)
+    assert c1["stable"] == 1 and c1["y_solver"] == binding.GP_YSOLVER_WINDOW and c1["y_halo"] == 0
+    c2 = binding.plan_query(inputs.config_c2(), False)
+    assert c2["stable"] == 1 and c2["y_solver"] == binding.GP_YSOLVER_WINDOW
+    # the window halo makes decay^h fall below 2^-60
+    assert c2["decay_y"] ** c2["y_halo"] < 2.0 ** -60
+    assert c2["y_rows_out"] == c2["y_segments"] * c2["y_rows_per_thread"] - 2 * c2["y_halo"]
+    for prec in ("fp64", "fp32"):
+        c3 = binding.plan_query(inputs.config_c3(4096), True, prec)
+        assert c3["stable"] == 1 and c3["y_solver"] == binding.GP_YSOLVER_WINDOW
+        assert c3["x_points_per_thread"] * c3["x_threads_per_row"] >= 4096
+    th = binding.plan_query(inputs.config_c2(), False, y_solver="thomas")
+    assert th["y_solver"] == binding.GP_YSOLVER_THOMAS
+
+
+def test_decay_matches_closed_form():
+    # imaginary time without rotation or SO: (I + a h) has b = 1 + beta, a = e = -beta/2
+    # (beta = dt/(2 dx^2)); the converged Thomas multiplier is the small root of
+    # beta/2 r^2 - (1 + beta) r + beta/2 = 0
+    dx, dt = 0.1, 1e-3
+    p = inputs.params(64, 64, dx, dt=dt)
+    pl = binding.plan_query(p, True)
+    beta = dt / (2 * dx * dx)
+    r = ((1 + beta) - math.sqrt((1 + beta) ** 2 - beta * beta)) / beta
+    assert abs(pl["decay_x"] - r) < 1e-14 and abs(pl["decay_y"] - r) < 1e-14
+
+
+def test_stability_checks():
+    # imaginary-time Cayley bound (dt/4)(|Omega| L + |gamma|)^2 < 1
+    p = inputs.params(64, 64, 0.1, dt=0.5, omega=0.9, gamma=1.0)
+    assert binding.plan_query(p, True)["stable"] == 0
+    # real time with a huge dt and strong rotation loses diagonal dominance
+    q = inputs.params(64, 64, 0.1, dt=5.0, omega=5.0)
+    assert binding.plan_query(q, False)["stable"] == 0
+    assert binding.plan_query(inputs.config_c2(), False)["stable"] == 1

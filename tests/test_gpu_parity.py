@@ -1,0 +1,271 @@
+"""Parity of the gfx950 HIP path (called through the C ABI) with the FP64 CPU
+oracle, element by element on the same seeded inputs.
+
+Tolerances: FP64 substeps 1e-13 relative L2 (rounding only); FP64 full runs
+1e-10 relative L2 on psi after up to 1000 steps; FP32 bulk: density 1e-5
+relative to the peak density, chemical potential 1e-6 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10517_amd import binding, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy().astype(np.complex128)
+
+
+def gpu_run(p, psi0, nsteps, imag, precision="fp64", y_solver="auto"):
+    s = binding.Solver(p, precision, y_solver)
+    t = dev(psi0, s.dtype)
+    (s.step_imag if imag else s.step_real)(t, nsteps)
+    s.sync()
+    out = host(t)
+    obs = s.observables(t)
+    s.close()
+    return out, obs
+
+
+def all_couplings(nx, ny, dx, dy=None, dt=0.01, eta=1, **kw):
+    base = dict(c0=35.0, c2=-3.0, gamma=0.6, eta=eta, rabi=0.25, omega=0.45)
+    base.update(kw)
+    return inputs.params(nx, ny, dx, dy=dy, dt=dt, **base)
+
+
+# ---------------------------------------------------------------------------
+# Substeps on random input
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("imag", [True, False])
+def test_local_substep(imag):
+    p = all_couplings(53, 37, 0.21, dt=0.02)
+    psi = inputs.random_state(53, 37, seed=21, scale=0.6)
+    s = binding.Solver(p)
+    t = dev(psi)
+    s.substep(t, binding.SUB_LOCAL, imag)
+    got = host(t)
+    want = oracle.pointwise(p, psi, imag)
+    assert rel(got, want) < 1e-13
+
+
+@pytest.mark.parametrize("imag", [True, False])
+@pytest.mark.parametrize("nx", [3, 53, 128, 130, 700, 1024, 1500, 4096, 5000])
+def test_x_sweep(imag, nx):
+    ny = 5
+    p = all_couplings(nx, ny, 24.0 / nx + 0.001, dy=0.2, dt=0.004, eta=-1 if nx % 2 else 1)
+    psi = inputs.random_state(nx, ny, seed=nx)
+    s = binding.Solver(p)
+    t = dev(psi)
+    s.substep(t, binding.SUB_X, imag)
+    got = host(t)
+    want = oracle.sweep_x(p, psi, imag)
+    assert rel(got, want) < 1e-13, s.plan(imag)
+
+
+@pytest.mark.parametrize("imag", [True, False])
+@pytest.mark.parametrize("solver", ["window", "thomas"])
+@pytest.mark.parametrize("ny", [3, 100, 128, 129, 600, 1000])
+def test_y_sweep(imag, solver, ny):
+    nx = 19 if ny % 2 else 40
+    p = all_couplings(nx, ny, 0.2, dy=24.0 / ny + 0.001, dt=5e-4, eta=1 if ny % 3 else -1)
+    psi = inputs.random_state(nx, ny, seed=ny + 7)
+    s = binding.Solver(p, y_solver=solver)
+    plan = s.plan(imag)
+    t = dev(psi)
+    s.substep(t, binding.SUB_Y, imag)
+    got = host(t)
+    want = oracle.sweep_y(p, psi, imag)
+    assert rel(got, want) < 1e-13, plan
+    if solver == "window":
+        assert plan["y_solver"] == binding.GP_YSOLVER_WINDOW
+        if ny > plan["y_segments"] * plan["y_rows_per_thread"]:
+            assert plan["y_halo"] > 0  # the truncated-window path is exercised
+    else:
+        assert plan["y_solver"] == binding.GP_YSOLVER_THOMAS
+
+
+def test_normalize_substep():
+    p = all_couplings(33, 29, 0.3)
+    psi = inputs.random_state(33, 29, seed=5)
+    s = binding.Solver(p)
+    t = dev(psi)
+    s.substep(t, binding.SUB_NORMALIZE, True)
+    assert rel(host(t), oracle.normalize(p, psi)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# Whole steps
+# ---------------------------------------------------------------------------
+def test_c1_imaginary_time_200_steps():
+    # 128 x 128, dx = 0.1, dt = 5e-4, c0 = 50, c2 = -1, Rashba gamma = 0.5, Omega = 0.5
+    p = inputs.config_c1()
+    psi0 = inputs.gaussian(128, 128, 0.1, 0.1, seed=1, phase_noise=0.1)
+    got, obs = gpu_run(p, psi0, 200, True)
+    want = oracle.step(p, psi0, 200, True)
+    assert rel(got, want) < 1e-10
+    o = oracle.observables(p, want)
+    for k in ("energy", "mu_total", "e_kin", "e_trap", "e_int", "e_rot", "e_so", "lz", "magnetization"):
+        assert abs(obs[k] - o[k]) <= 1e-10 * max(1.0, abs(o[k])), k
+    assert abs(obs["norm_total"] - 1.0) < 1e-13
+
+
+@pytest.mark.parametrize("imag", [True, False])
+def test_1000_steps(imag):
+    # spec bar: relative L2 <= 1e-10 on psi after 1000 FP64 steps
+    if imag:
+        p = inputs.config_c1()
+        psi0 = inputs.gaussian(128, 128, 0.1, 0.1, seed=1, phase_noise=0.1)
+    else:
+        # the real-time workload's couplings on a 128^2 grid of the same box
+        p = inputs.params(128, 128, 0.2, dt=4e-4, c0=200.0, c2=5.0, gamma=1.0, eta=-1, rabi=0.2, omega=0.9)
+        psi0 = inputs.add_noise(inputs.gaussian(128, 128, 0.2, 0.2, seed=2), 0.2, 0.2, 1e-3, seed=3)
+    got, obs = gpu_run(p, psi0, 1000, imag)
+    want = oracle.step(p, psi0, 1000, imag)
+    assert rel(got, want) < 1e-10
+    if not imag:
+        assert abs(obs["norm_total"] - 1.0) < 1e-12  # unitary real-time step
+
+
+@pytest.mark.parametrize("imag", [True, False])
+def test_ragged_rectangular_grid(imag):
+    p = all_couplings(97, 61, 0.17, dy=0.23, dt=0.005, eta=-1)
+    p["x0"], p["y0"] = -7.3, -6.1
+    psi0 = inputs.gaussian(97, 61, 0.17, 0.23, x0=p["x0"], y0=p["y0"], seed=4, center=(0.3, -0.2))
+    got, _ = gpu_run(p, psi0, 100, imag)
+    want = oracle.step(p, psi0, 100, imag)
+    assert rel(got, want) < 1e-11
+
+
+@pytest.mark.parametrize("shape", [(3, 3), (3, 200), (200, 3), (5, 131)])
+def test_degenerate_small_grids(shape):
+    nx, ny = shape
+    p = all_couplings(nx, ny, 0.4, dt=0.003)
+    psi0 = inputs.random_state(nx, ny, seed=nx * ny, scale=0.3)
+    for imag in (True, False):
+        got, _ = gpu_run(p, psi0, 20, imag)
+        want = oracle.step(p, psi0, 20, imag)
+        assert rel(got, want) < 1e-11
+
+
+def test_window_and_thomas_agree_on_tall_grid():
+    p = all_couplings(48, 1100, 0.25, dy=0.02, dt=2e-4)
+    psi0 = inputs.gaussian(48, 1100, 0.25, 0.02, seed=8)
+    a, _ = gpu_run(p, psi0, 30, True, y_solver="window")
+    b, _ = gpu_run(p, psi0, 30, True, y_solver="thomas")
+    assert rel(a, b) < 1e-13
+    want = oracle.step(p, psi0, 30, True)
+    assert rel(a, want) < 1e-12
+
+
+def test_observables_match_oracle():
+    p = all_couplings(64, 56, 0.3, eta=-1)
+    psi = inputs.gaussian(64, 56, 0.3, 0.3, seed=9, phase_noise=0.5, windings=(1, 0, -1))
+    s = binding.Solver(p)
+    t = dev(psi)
+    dens = torch.empty((3, 56, 64), dtype=torch.float64, device=DEV)
+    obs = s.observables(t, dens)
+    o = oracle.observables(p, psi)
+    for k in ("norm_total", "magnetization", "energy", "e_kin", "e_trap", "e_int", "e_rot", "e_so",
+              "e_rabi", "lz", "mu_total"):
+        assert abs(obs[k] - o[k]) <= 1e-12 * max(1.0, abs(o[k])), k
+    for m in range(3):
+        assert abs(obs["mu"][m] - o["mu"][m]) <= 1e-12 * max(1.0, abs(o["mu"][m]))
+        assert abs(obs["norm"][m] - o["norm"][m]) <= 1e-13
+    assert np.abs(dens.cpu().numpy() - np.abs(psi) ** 2).max() < 1e-15
+
+
+# ---------------------------------------------------------------------------
+# FP32 bulk with FP64 reductions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("imag", [True, False])
+def test_fp32_bulk(imag):
+    if imag:
+        p = inputs.config_c1()
+        psi0 = inputs.gaussian(128, 128, 0.1, 0.1, seed=1, phase_noise=0.1)
+        n = 200
+    else:
+        p = inputs.params(128, 128, 0.2, dt=4e-4, c0=200.0, c2=5.0, gamma=1.0, eta=-1, rabi=0.2, omega=0.9)
+        psi0 = inputs.add_noise(inputs.gaussian(128, 128, 0.2, 0.2, seed=2), 0.2, 0.2, 1e-3, seed=3)
+        n = 1000
+    got, obs = gpu_run(p, psi0, n, imag, precision="fp32")
+    want = oracle.step(p, psi0, n, imag)
+    o = oracle.observables(p, want)
+    rho_g, rho_w = np.abs(got) ** 2, np.abs(want) ** 2
+    dens_err = float(np.abs(rho_g - rho_w).max() / rho_w.max())
+    mu_err = abs(obs["mu_total"] - o["mu_total"]) / abs(o["mu_total"])
+    print(f"fp32 {'imag' if imag else 'real'}: density err {dens_err:.2e}, mu err {mu_err:.2e}")
+    assert dens_err < 1e-5
+    assert mu_err < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# Full workload sizes, in the launch configuration the benchmark times
+# ---------------------------------------------------------------------------
+def test_c2_full_size_steps():
+    p = inputs.config_c2()
+    psi0 = inputs.add_noise(inputs.gaussian(512, 512, 0.05, 0.05, seed=2), 0.05, 0.05, 1e-3, seed=3)
+    got, obs = gpu_run(p, psi0, 2, False)
+    want = oracle.step(p, psi0, 2, False)
+    assert rel(got, want) < 1e-13
+    # many steps: the unitary real-time step keeps the norm
+    s = binding.Solver(p)
+    t = dev(psi0)
+    s.step_real(t, 2000)
+    assert abs(s.observables(t)["norm_total"] - 1.0) < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c3_2048_one_step(precision):
+    p = inputs.config_c3(2048)
+    psi0 = inputs.gaussian(2048, 2048, 0.02, 0.02, seed=4, full_phase=True)
+    got, obs = gpu_run(p, psi0, 1, True, precision=precision)
+    want = oracle.step(p, psi0, 1, True)
+    tol = 1e-13 if precision == "fp64" else 2e-6
+    assert rel(got, want) < tol
+
+
+# ---------------------------------------------------------------------------
+# Error paths (forced from the host; every kernel still exits normally)
+# ---------------------------------------------------------------------------
+def test_unstable_parameters_are_refused():
+    p = inputs.params(64, 64, 0.1, dt=0.5, omega=0.9, gamma=1.0)
+    s = binding.Solver(p)
+    t = dev(inputs.gaussian(64, 64, 0.1, 0.1, seed=1))
+    with pytest.raises(binding.GPError) as ei:
+        s.step_imag(t, 1)
+    assert ei.value.status == binding.GP_EUNSTABLE
+
+
+def test_nonfinite_is_reported():
+    p = all_couplings(40, 40, 0.3)
+    psi = inputs.gaussian(40, 40, 0.3, 0.3, seed=1)
+    psi[1, 20, 20] = complex(math.nan, 0.0)
+    s = binding.Solver(p)
+    t = dev(psi)
+    s.step_imag(t, 2)
+    with pytest.raises(binding.GPError) as ei:
+        s.sync()
+    assert ei.value.status == binding.GP_ENONFINITE
+    with pytest.raises(binding.GPError) as ei:
+        s.observables(t)
+    assert ei.value.status == binding.GP_ENONFINITE
+    s.sync()  # the flag was cleared
