@@ -160,8 +160,9 @@ int gp_spin1_plan_query(const gp_spin1_params* p, int32_t imag, gp_spin1_plan* o
  * every kernel launch with HIP events on the handle's stream; gp_spin1_timing_read
  * waits for the stream and returns, per kernel kind, the number of launches
  * and their summed duration in milliseconds since the last enable (which
- * resets the counters).  Kinds: 0 x sweep (with the fused local substep),
- * 1 y sweep, 2 norm finalize, 3 final renormalisation. */
+ * resets the counters).  Kinds: 0 x sweep (with the fused local substep and
+ * the pending renormalisation), 1 y sweep (with the fused norm reduction),
+ * 2 unused, 3 final renormalisation at the end of an imaginary-time call. */
 typedef struct {
     int64_t launches[4];
     double ms[4];

@@ -18,34 +18,33 @@
 namespace gp {
 
 // ---------------------------------------------------------------------------
-// Partitioned Thomas on one line held as K consecutive values per thread.
-// Works in place on u[]; n is the line length, i0 the first index of this
-// thread's block.  Every thread of the block must call it (barriers).
+// Crank-Nicolson line solve in increment form.  With A = I + alpha h the
+// tridiagonal matrix (sub a, diagonal b, super e), the new values are
+// u' = A^{-1} (2I - A) u = u + delta with A delta = -2 (A - I) u: the
+// increment is small (of order alpha/dx^2 relative to u), so the rounding of
+// the elimination is small relative to u and u + delta is rounded once.  (In
+// FP32 the direct form drifts in norm by a few 1e-8 per sweep.)
+//
+// Partitioned Thomas on one row held as K consecutive values per thread; works
+// in place on u[], uses the neighbour values left/right of the thread's block.
+// Every thread of the block must call it (barriers).
 // ---------------------------------------------------------------------------
 template <typename T, int K>
-__device__ inline void row_line_solve(cx<T> (&u)[K], const LineSet<T>& ls, int line, int i0, int n, int lane,
-                                      int w, int nw, cx<T>* shA, cx<T>* shB) {
+__device__ inline void row_line_solve(cx<T> (&u)[K], cx<T> left, cx<T> right, const LineSet<T>& ls, int line,
+                                      int i0, int n, int lane, int w, int nw, cx<T>* shA, cx<T>* shB) {
     using C = cx<T>;
-    const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], b = ls.b;
+    const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], bm1 = ls.bm1;
     const Piv<T> lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
-    // neighbours of the block ends (ghost zeros beyond the row)
-    C left = shfl_up_c(u[K - 1], 1), right = shfl_down_c(u[0], 1);
-    if (lane == 63) shA[w] = u[K - 1];
-    if (lane == 0) shB[w] = u[0];
-    __syncthreads();
-    if (lane == 0) left = (w > 0) ? shA[w - 1] : zero_c<C>();
-    if (lane == 63) right = (w + 1 < nw) ? shB[w + 1] : zero_c<C>();
-    __syncthreads();
     C r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const C um = (k == 0) ? left : u[k - 1];
         const C up = (k == K - 1) ? right : u[k + 1];
-        // r = 2u - (a u_{k-1} + b u_k + e u_{k+1})
-        C t = cmul(b, u[k]);
+        // r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
+        C t = cmul(bm1, u[k]);
         t = cfma(um, a, t);
         t = cfma(up, e, t);
-        r[k] = (i0 + k < n) ? csub(cscale(u[k], (T)2), t) : zero_c<C>();
+        r[k] = (i0 + k < n) ? cscale(t, (T)-2) : zero_c<C>();
     }
     // forward elimination over the block from a zero carry
     C E = zero_c<C>(), P = one_c<C>();
@@ -60,7 +59,7 @@ __device__ inline void row_line_solve(cx<T> (&u)[K], const LineSet<T>& ls, int l
             E = zero_c<C>();
             P = zero_c<C>();
         }
-        u[k] = E;
+        r[k] = E;
     }
     const C din = row_scan_fwd(P, E, lane, w, nw, shA, shB);
     {
@@ -71,7 +70,7 @@ __device__ inline void row_line_solve(cx<T> (&u)[K], const LineSet<T>& ls, int l
             if (i < n) {
                 const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
                 Q = cmul(mk<T>(-pv.am.x, -pv.am.y), Q);
-                u[k] = cfma(din, Q, u[k]);
+                r[k] = cfma(din, Q, r[k]);
             }
         }
     }
@@ -82,13 +81,13 @@ __device__ inline void row_line_solve(cx<T> (&u)[K], const LineSet<T>& ls, int l
         const int i = i0 + k;
         if (i < n) {
             const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
-            G = csub(u[k], cmul(pv.cp, G));
+            G = csub(r[k], cmul(pv.cp, G));
             R = cmul(mk<T>(-pv.cp.x, -pv.cp.y), R);
         } else {
             G = zero_c<C>();
             R = zero_c<C>();
         }
-        u[k] = G;
+        r[k] = G;
     }
     const C xin = row_scan_bwd(R, G, lane, w, nw, shA, shB);
     {
@@ -99,7 +98,7 @@ __device__ inline void row_line_solve(cx<T> (&u)[K], const LineSet<T>& ls, int l
             if (i < n) {
                 const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
                 Sx = cmul(mk<T>(-pv.cp.x, -pv.cp.y), Sx);
-                u[k] = cfma(xin, Sx, u[k]);
+                u[k] = cadd(u[k], cfma(xin, Sx, r[k]));
             }
         }
     }
@@ -109,8 +108,9 @@ template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
 __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
                                                LineSet<T> ls, const double* __restrict__ scale, int G, int R) {
     using C = cx<T>;
-    __shared__ C shA[16 * 16];
-    __shared__ C shB[16 * 16];
+    __shared__ C shA[16 * 8];
+    __shared__ C shB[16 * 8];
+    __shared__ C shN[2 * 3 * 16];
     const int tid = threadIdx.x;
     const int r = tid / G, t = tid - r * G;
     const int lane = t & 63, w = t >> 6, nw = G >> 6;
@@ -153,10 +153,27 @@ __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    // neighbours of the block ends for all three components (ghost zeros beyond the row)
+    C left[3], right[3];
+    const int nrow = r * nw;  // first wave of this row in the block
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        left[q] = shfl_up_c(v[q][K - 1], 1);
+        right[q] = shfl_down_c(v[q][0], 1);
+        if (lane == 63) shN[(nrow + w) * 3 + q] = v[q][K - 1];
+        if (lane == 0) shN[48 + (nrow + w) * 3 + q] = v[q][0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (lane == 0) left[q] = (w > 0) ? shN[(nrow + w - 1) * 3 + q] : zero_c<C>();
+        if (lane == 63) right[q] = (w + 1 < nw) ? shN[48 + (nrow + w + 1) * 3 + q] : zero_c<C>();
+    }
     const int jl = row_ok ? j : 0;
 #pragma unroll
     for (int q = 0; q < 3; ++q)
-        row_line_solve<T, K>(v[q], ls, jl * 3 + q, i0, nx, lane, w, nw, shA + 16 * r, shB + 16 * r);
+        row_line_solve<T, K>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, lane, w, nw, shA + 8 * r,
+                             shB + 8 * r);
 #pragma unroll
     for (int k = 0; k < K; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
     if (row_ok && i0 + K <= nx) {
@@ -190,19 +207,52 @@ __device__ inline double block_sum(double v, double* sh) {
     return s;
 }
 
+// Norm reduction finished by the last block to arrive: every block stores its
+// partial sum, then takes a ticket; the block that draws the last ticket sums
+// the partials in block order (deterministic), writes scale = 1/sqrt(dx dy sum)
+// and re-arms the ticket counter for the next launch.
+__device__ inline void finish_norm(double part, double* sh, NormOut no) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        no.partials[blockIdx.x] = part;
+        __threadfence();
+        const unsigned int tk = atomicAdd(no.ticket, 1u);
+        last = (tk == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double acc = 0;
+    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) acc += no.partials[k];
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        const double nn = tot * no.dxdy;
+        if (nn > 0.0 && isfinite(nn)) {
+            *no.scale = 1.0 / sqrt(nn);
+        } else {
+            *no.scale = 1.0;
+            *no.flag = 1;
+        }
+        *no.ticket = 0u;
+    }
+}
+
 // ---------------------------------------------------------------------------
-// y sweep, windowed partitioned Thomas over column tiles.
+// y sweep, windowed partitioned Thomas over column tiles (increment form).
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, int KY, int TW, int S, bool NORM>
 __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
-                                                   LineSet<T> ls, int L, int h, int ncs,
-                                                   double* __restrict__ partials) {
+                                                   LineSet<T> ls, int L, int h, int ncs, NormOut no) {
     using C = cx<T>;
-    __shared__ C shP[TW * S];
-    __shared__ C shE[TW * S];
+    constexpr int SPW = 64 / TW, NWV = S / SPW;
+    __shared__ C shP[NWV * TW];
+    __shared__ C shE[NWV * TW];
+    __shared__ C shU[3 * NWV * TW];
+    __shared__ C shD[3 * NWV * TW];
     __shared__ double shr[16];
     const int tid = threadIdx.x;
     const int c = tid % TW, s = tid / TW;
+    const int sw = s % SPW, wv = s / SPW;
     const int cs = blockIdx.x % ncs, rt = blockIdx.x / ncs;
     const int i = cs * TW + c;
     const bool col_ok = i < ph.nx;
@@ -221,30 +271,39 @@ __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ sr
     }
 #pragma unroll
     for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    // rows just above and below this thread's segment, for all three components
+    // (zeros outside the window)
+    C up[3], dn[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        up[q] = shfl_up_c(v[q][KY - 1], TW);
+        dn[q] = shfl_down_c(v[q][0], TW);
+        if (sw == SPW - 1) shU[(wv * 3 + q) * TW + c] = v[q][KY - 1];
+        if (sw == 0) shD[(wv * 3 + q) * TW + c] = v[q][0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (sw == 0) up[q] = (wv > 0) ? shU[((wv - 1) * 3 + q) * TW + c] : zero_c<C>();
+        if (sw == SPW - 1) dn[q] = (wv + 1 < NWV) ? shD[((wv + 1) * 3 + q) * TW + c] : zero_c<C>();
+    }
     const int il = col_ok ? i : 0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
         C (&u)[KY] = v[q];
         const int line = il * 3 + q;
-        const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], b = ls.b;
+        const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], bm1 = ls.bm1;
         const Piv<T> lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
-        // segment-end neighbours through shared memory (zeros outside the window)
-        shP[tid] = u[KY - 1];
-        shE[tid] = u[0];
-        __syncthreads();
-        const C up = (s > 0) ? shP[tid - TW] : zero_c<C>();
-        const C dn = (s + 1 < S) ? shE[tid + TW] : zero_c<C>();
-        __syncthreads();
         C r[KY];
 #pragma unroll
         for (int k = 0; k < KY; ++k) {
             const int g = g0 + k;
-            const C um = (k == 0) ? up : u[k - 1];
-            const C uq = (k == KY - 1) ? dn : u[k + 1];
-            C t = cmul(b, u[k]);
+            const C um = (k == 0) ? up[q] : u[k - 1];
+            const C uq = (k == KY - 1) ? dn[q] : u[k + 1];
+            C t = cmul(bm1, u[k]);
             t = cfma(um, a, t);
             t = cfma(uq, e, t);
-            r[k] = (g >= 0 && g < ny) ? csub(cscale(u[k], (T)2), t) : zero_c<C>();
+            r[k] = (g >= 0 && g < ny) ? cscale(t, (T)-2) : zero_c<C>();
         }
         C E = zero_c<C>(), P = one_c<C>();
 #pragma unroll
@@ -258,7 +317,7 @@ __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ sr
                 E = zero_c<C>();
                 P = zero_c<C>();
             }
-            u[k] = E;
+            r[k] = E;
         }
         const C din = seg_scan<C, TW, S, false>(P, E, c, s, shP, shE);
         {
@@ -269,7 +328,7 @@ __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ sr
                 if (g >= 0 && g < ny) {
                     const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
                     Q = cmul(mk<T>(-pv.am.x, -pv.am.y), Q);
-                    u[k] = cfma(din, Q, u[k]);
+                    r[k] = cfma(din, Q, r[k]);
                 }
             }
         }
@@ -279,13 +338,13 @@ __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ sr
             const int g = g0 + k;
             if (g >= 0 && g < ny) {
                 const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
-                G = csub(u[k], cmul(pv.cp, G));
+                G = csub(r[k], cmul(pv.cp, G));
                 R = cmul(mk<T>(-pv.cp.x, -pv.cp.y), R);
             } else {
                 G = zero_c<C>();
                 R = zero_c<C>();
             }
-            u[k] = G;
+            r[k] = G;
         }
         const C xin = seg_scan<C, TW, S, true>(R, G, c, s, shP, shE);
         {
@@ -296,7 +355,7 @@ __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ sr
                 if (g >= 0 && g < ny) {
                     const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
                     Sx = cmul(mk<T>(-pv.cp.x, -pv.cp.y), Sx);
-                    u[k] = cfma(xin, Sx, u[k]);
+                    u[k] = cadd(u[k], cfma(xin, Sx, r[k]));
                 }
             }
         }
@@ -316,18 +375,16 @@ __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ sr
             }
         }
     }
-    if (NORM) {
-        const double tot = block_sum(acc, shr);
-        if (tid == 0) partials[blockIdx.x] = tot;
-    }
+    if (NORM) finish_norm(block_sum(acc, shr), shr, no);
 }
 
 // ---------------------------------------------------------------------------
-// y sweep, exact per-thread Thomas down whole columns.
+// y sweep, exact per-thread Thomas down whole columns (increment form): the
+// forward eliminations go to dst, the back substitution re-reads src.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, bool NORM>
 __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
-                                                 LineSet<T> ls, double* __restrict__ partials) {
+                                                 LineSet<T> ls, NormOut no) {
     using C = cx<T>;
     __shared__ double shr[16];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -344,7 +401,7 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
             lim[q] = ls.piv[(size_t)(i * 3 + q) * (ls.K + 1) + ls.K];
         }
         auto load_sx = [&](int g, C (&o)[3]) {
-            if (g < ny) {
+            if (g >= 0 && g < ny) {
 #pragma unroll
                 for (int m = 0; m < 3; ++m) o[m] = src[m * plane + (size_t)g * nx + i];
                 to_sx<C, T>(o[0], o[1], o[2]);
@@ -360,10 +417,10 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
             load_sx(g + 1, nxt);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                C t = cmul(ls.b, cur[q]);
+                C t = cmul(ls.bm1, cur[q]);
                 t = cfma(prev[q], a[q], t);
                 t = cfma(nxt[q], e[q], t);
-                const C rr = csub(cscale(cur[q], (T)2), t);
+                const C rr = cscale(t, (T)-2);
                 const Piv<T> pv = (g < ls.K) ? piv_at(ls, i * 3 + q, g) : lim[q];
                 d[q] = csub(mul_m(pv, rr), cmul(pv.am, carry[q]));
                 carry[q] = d[q];
@@ -375,14 +432,15 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
         }
         C x[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
         for (int g = ny - 1; g >= 0; --g) {
-            C o[3];
+            C o[3], uu[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) o[m] = dst[m * plane + (size_t)g * nx + i];
+            load_sx(g, uu);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 const Piv<T> pv = (g < ls.K) ? piv_at(ls, i * 3 + q, g) : lim[q];
                 x[q] = csub(o[q], cmul(pv.cp, x[q]));
-                o[q] = x[q];
+                o[q] = cadd(uu[q], x[q]);
             }
             from_sx<C, T>(o[0], o[1], o[2]);
 #pragma unroll
@@ -392,10 +450,7 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
             }
         }
     }
-    if (NORM) {
-        const double tot = block_sum(acc, shr);
-        if (threadIdx.x == 0) partials[blockIdx.x] = tot;
-    }
+    if (NORM) finish_norm(block_sum(acc, shr), shr, no);
 }
 
 // ---------------------------------------------------------------------------
@@ -593,7 +648,7 @@ static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st) {
     const int ncs = (a.ph.nx + TW - 1) / TW;
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
     k_y_window<T, IMAG, KY, TW, S, NORM><<<dim3(ncs * nrt), dim3(TW * S), 0, st>>>(a.src, a.dst, a.ph, a.ls, a.L, a.h,
-                                                                                  ncs, a.partials);
+                                                                                  ncs, a.no);
     return hipGetLastError();
 }
 
@@ -614,11 +669,11 @@ hipError_t launch_y(const YLaunch<T>& a, hipStream_t st) {
     }
     const dim3 grid((a.ph.nx + 255) / 256), block(256);
     if (a.imag) {
-        if (a.norm) k_y_thomas<T, true, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
-        else k_y_thomas<T, true, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
+        if (a.norm) k_y_thomas<T, true, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
+        else k_y_thomas<T, true, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
     } else {
-        if (a.norm) k_y_thomas<T, false, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
-        else k_y_thomas<T, false, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.partials);
+        if (a.norm) k_y_thomas<T, false, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
+        else k_y_thomas<T, false, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
     }
     return hipGetLastError();
 }

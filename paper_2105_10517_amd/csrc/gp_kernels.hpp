@@ -8,13 +8,25 @@ namespace gp {
 constexpr int kObsCount = 13;
 
 // Tile geometry of the windowed y sweep per precision: TW columns (a
-// contiguous 256 B run of each row) x S segments of KY rows per thread.
+// contiguous run of each row) x S segments of KY rows per thread; a window
+// spans S * KY = 128 rows.
 template <typename T> struct YCfg;
-template <> struct YCfg<double> { static constexpr int KY = 8, TW = 16, S = 16; };
+template <> struct YCfg<double> { static constexpr int KY = 4, TW = 16, S = 32; };
 template <> struct YCfg<float> { static constexpr int KY = 8, TW = 32, S = 16; };
 
 // Both sweeps run out of place (src -> dst): the y windows overlap, so a
 // window's halo rows must not be rewritten by its neighbour while it reads.
+// Where the y sweep leaves the imaginary-time norm: per-block partial sums,
+// a ticket counter (zero between launches), the resulting scale factor and the
+// non-finite flag.
+struct NormOut {
+    double* partials;
+    unsigned int* ticket;
+    double* scale;
+    int* flag;
+    double dxdy;
+};
+
 template <typename T> struct XLaunch {
     const cx<T>* src;
     cx<T>* dst;
@@ -30,7 +42,7 @@ template <typename T> struct YLaunch {
     cx<T>* dst;
     Phys ph;
     LineSet<T> ls;
-    double* partials;
+    NormOut no;
     int L, h;
     bool window, imag, norm;
 };

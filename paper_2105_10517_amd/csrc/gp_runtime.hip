@@ -21,6 +21,7 @@ namespace {
 struct DirTable {
     int K = 0, lines = 0;
     zd b{1.0, 0.0};
+    zd bm1{0.0, 0.0};
     double decay = 0.0;
     bool dominant = true;
     void* d_piv = nullptr;
@@ -47,6 +48,7 @@ struct gp_spin1 {
     int xK = 4, xG = 64, xR = 1;
     double* d_scale = nullptr;
     int* d_flag = nullptr;
+    unsigned int* d_ticket = nullptr;  // zero between launches (the last block re-arms it)
     double* d_part = nullptr;
     size_t n_part = 0;
     double* d_obs = nullptr;
@@ -100,7 +102,8 @@ gp::cx<T> to_dev(zd z) {
 // nother * 3 (line index = other * 3 + eigenvalue index), line length n.
 struct HostDir {
     int K = 1, lines = 0;
-    zd b{1.0, 0.0};
+    zd b{1.0, 0.0};    // 1 + bm1, the diagonal whose pivots the table holds
+    zd bm1{0.0, 0.0};  // b - 1 as the kernels see it (rounded to T)
     double decay = 0.0;
     bool dominant = true;
     std::vector<zd> A, E, W;
@@ -125,11 +128,13 @@ void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
     d.dominant = true;
     d.decay = 0.0;
     for (int l = 0; l < lines; ++l) {
-        zd a, e;
-        coeffs(alpha, step, coef(l), a, d.b, e);
-        // the kernels see the coefficients in precision T; the pivots are those
-        // of the rounded matrix
-        a = round_to<T>(a); e = round_to<T>(e); d.b = round_to<T>(d.b);
+        zd a, e, b;
+        coeffs(alpha, step, coef(l), a, b, e);
+        // the kernels see a, e and b - 1 in precision T; the pivots are those of
+        // the matrix with exactly these rounded entries
+        a = round_to<T>(a); e = round_to<T>(e);
+        d.bm1 = round_to<T>(alpha / (step * step));
+        d.b = 1.0 + d.bm1;
         d.A[l] = a; d.E[l] = e;
         if (std::abs(d.b) < (std::abs(a) + std::abs(e)) * (1.0 - 1e-12)) d.dominant = false;
         const zd wl = pivot_limit(a, d.b, e);
@@ -158,7 +163,7 @@ void set_piv(gp::Piv<T>& pv, zd a, zd e, zd w) {
 template <typename T>
 int upload_dir(gp_spin1* h, const HostDir& hd, DirTable& d) {
     const int lines = hd.lines, K = hd.K;
-    d.lines = lines; d.K = K; d.b = hd.b; d.decay = hd.decay; d.dominant = hd.dominant;
+    d.lines = lines; d.K = K; d.b = hd.b; d.bm1 = hd.bm1; d.decay = hd.decay; d.dominant = hd.dominant;
     std::vector<gp::Piv<T>> piv((size_t)lines * (K + 1));
     std::vector<gp::cx<T>> ae((size_t)lines * 2);
     for (int l = 0; l < lines; ++l) {
@@ -187,7 +192,7 @@ gp::LineSet<T> lineset(const DirTable& d) {
     gp::LineSet<T> ls;
     ls.piv = (const gp::Piv<T>*)d.d_piv;
     ls.ae = (const gp::cx<T>*)d.d_ae;
-    ls.b = to_dev<T>(d.b);
+    ls.bm1 = to_dev<T>(d.bm1);
     ls.K = d.K;
     return ls;
 }
@@ -318,6 +323,7 @@ void destroy_all(gp_spin1* h) {
     for (auto& m : h->mode) { free_dir(m.x); free_dir(m.y); }
     if (h->d_scale) (void)hipFree(h->d_scale);
     if (h->d_flag) (void)hipFree(h->d_flag);
+    if (h->d_ticket) (void)hipFree(h->d_ticket);
     if (h->d_part) (void)hipFree(h->d_part);
     if (h->d_obs) (void)hipFree(h->d_obs);
     if (h->d_work) (void)hipFree(h->d_work);
@@ -372,6 +378,7 @@ int create_t(gp_spin1* h) {
     if (hipMalloc(&h->d_part, need * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_scale, sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_flag, sizeof(int)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&h->d_ticket, sizeof(unsigned int)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_obs, gp::kObsCount * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_work, (size_t)3 * p.nx * p.ny * sizeof(gp::cx<T>)) != hipSuccess)
         return fail(h, GP_ENOMEM, "work buffer allocation failed");
@@ -380,6 +387,7 @@ int create_t(gp_spin1* h) {
     hipError_t e;
     if ((e = hipMemcpy(h->d_scale, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
+    if ((e = hipMemcpy(h->d_ticket, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     return GP_OK;
 }
 
@@ -404,7 +412,11 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.dst = (gp::cx<T>*)dst;
     a.ph = phys(h->p);
     a.ls = lineset<T>(ms.y);
-    a.partials = h->d_part;
+    a.no.partials = h->d_part;
+    a.no.ticket = h->d_ticket;
+    a.no.scale = h->d_scale;
+    a.no.flag = h->d_flag;
+    a.no.dxdy = h->p.dx * h->p.dy;
     a.L = ms.L; a.h = ms.h;
     a.window = ms.window; a.imag = imag; a.norm = norm;
     return a;
@@ -461,16 +473,12 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     hipStream_t st = h->stream;
     const gp::XLaunch<T> xa = xlaunch<T>(h, psi, h->d_work, imag, true);
     const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, psi, imag, imag);
-    const double dxdy = h->p.dx * h->p.dy;
     hipError_t e;
     if (imag && (e = gp::launch_set_scale(h->d_scale, 1.0, st)) != hipSuccess) return hip_fail(h, e, "set_scale");
     for (int64_t s = 0; s < n; ++s) {
         if ((e = timed(h, 0, [&] { return gp::launch_x<T>(xa, st); })) != hipSuccess) return hip_fail(h, e, "x sweep launch");
+        // the y sweep also finishes the norm and the scale (last block to arrive)
         if ((e = timed(h, 1, [&] { return gp::launch_y<T>(ya, st); })) != hipSuccess) return hip_fail(h, e, "y sweep launch");
-        if (imag && (e = timed(h, 2, [&] {
-                         return gp::launch_norm_finalize(h->d_part, ms.ypart_blocks, dxdy, h->d_scale, h->d_flag, st);
-                     })) != hipSuccess)
-            return hip_fail(h, e, "norm launch");
     }
     if (imag) {
         const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;

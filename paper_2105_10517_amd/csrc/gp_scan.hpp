@@ -6,7 +6,8 @@
 // transfer maps are composed across threads by a scan, and each thread adds
 // the carry that enters its block times the running product of its
 // multipliers.  The scans below return the exclusive prefix, i.e. the carry
-// that enters each thread's block.
+// that enters each thread's block.  Composition order: (f o g)(z) = f(g(z)),
+// with g the map nearer the start of the scan direction.
 #pragma once
 
 #include "gp_device.hpp"
@@ -54,29 +55,33 @@ __device__ inline C row_scan_bwd(C P, C E, int lane, int w, int nw, C* shP, C* s
     return ex;
 }
 
-// Exclusive scan across the S segments of a column tile, thread (c, s) at
-// index c + TW s; Kogge-Stone through shared memory (shP/shE: S*TW entries).
+// Exclusive scan across the S segments of a column tile.  Thread (c, s) sits
+// at index c + TW s, so one wave holds SPW = 64/TW consecutive segments of the
+// same TW columns: the scan runs by shuffles across lanes TW apart inside a
+// wave, and through shared memory (shP/shE: (S/SPW) * TW entries) across waves.
 // REV = false: carry from segments 0..s-1; REV = true: from s+1..S-1.
 template <typename C, int TW, int S, bool REV>
 __device__ inline C seg_scan(C P, C E, int c, int s, C* shP, C* shE) {
-    const int idx = c + TW * s;
+    constexpr int SPW = 64 / TW, NWV = S / SPW;
+    const int sw = s % SPW, w = s / SPW;
 #pragma unroll
-    for (int off = 1; off < S; off <<= 1) {
-        shP[idx] = P; shE[idx] = E;
-        __syncthreads();
-        const int o = REV ? s + off : s - off;
-        if (REV ? (o < S) : (o >= 0)) {
-            const C Po = shP[c + TW * o], Eo = shE[c + TW * o];
-            E = cfma(Eo, P, E);
-            P = cmul(P, Po);
-        }
-        __syncthreads();
+    for (int off = 1; off < SPW; off <<= 1) {
+        const C Po = REV ? shfl_down_c(P, off * TW) : shfl_up_c(P, off * TW);
+        const C Eo = REV ? shfl_down_c(E, off * TW) : shfl_up_c(E, off * TW);
+        if (REV ? (sw + off < SPW) : (sw >= off)) { E = cfma(Eo, P, E); P = cmul(P, Po); }
     }
-    // inclusive value -> exclusive: take the neighbour's inclusive map applied to 0
-    shE[idx] = E;
+    // wave totals: the inclusive map of the last segment of each wave in scan order
+    if (REV ? (sw == 0) : (sw == SPW - 1)) { shP[w * TW + c] = P; shE[w * TW + c] = E; }
     __syncthreads();
-    const int o = REV ? s + 1 : s - 1;
-    C ex = (REV ? (o < S) : (o >= 0)) ? shE[c + TW * o] : zero_c<C>();
+    C din = zero_c<C>();
+    if (!REV) {
+        for (int v = 0; v < w; ++v) din = cfma(din, shP[v * TW + c], shE[v * TW + c]);
+    } else {
+        for (int v = NWV - 1; v > w; --v) din = cfma(din, shP[v * TW + c], shE[v * TW + c]);
+    }
+    const C incl = cfma(din, P, E);
+    C ex = REV ? shfl_down_c(incl, TW) : shfl_up_c(incl, TW);
+    if (REV ? (sw == SPW - 1) : (sw == 0)) ex = din;
     __syncthreads();
     return ex;
 }
