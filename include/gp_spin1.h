@@ -80,6 +80,10 @@ typedef struct {
     double omega;      /* rotation frequency Omega (in units of the trap frequency)            */
     int32_t precision; /* gp_precision                                                         */
     int32_t y_solver;  /* gp_ysolver                                                           */
+    int32_t x_points;  /* points per thread of the x sweep: 0 = chosen by the library, else 1, 2, 4, 8 or 16 */
+    int32_t y_tile;    /* tile shape of the windowed y sweep: 0 = chosen by the library, else 1..4            */
+    int32_t autotune;  /* != 0: time the candidate x and y launch shapes at creation and keep the fastest
+                          (only for the fields left at 0); the choice depends on the grid shape only        */
 } gp_spin1_params;
 
 /* Observables of one wave function (all FP64, rectangle-rule quadrature
@@ -106,7 +110,10 @@ typedef struct {
     int32_t y_solver;            /* GP_YSOLVER_WINDOW or GP_YSOLVER_THOMAS                        */
     int32_t y_halo;              /* rows of overlap on each side of a y window                   */
     int32_t y_rows_out;          /* rows written per y window                                    */
-    int32_t y_tile_cols, y_segments, y_rows_per_thread;
+    int32_t y_tile;              /* 1..4, the tile shape below                                     */
+    int32_t y_tile_cols;         /* columns per y block (4 per wave)                              */
+    int32_t y_segments;          /* segments per column and window (16: one DPP row of lanes)     */
+    int32_t y_rows_per_thread;   /* a window spans y_segments * y_rows_per_thread rows            */
     int32_t pivots_x, pivots_y;  /* tabulated Thomas pivots per line before the constant limit  */
     double decay_x, decay_y;     /* largest |a m| or |c'| of the converged pivots per direction  */
     int32_t stable;              /* 1 if the mode passed the stability checks                    */

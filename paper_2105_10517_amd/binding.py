@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("c0", ctypes.c_double), ("c2", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("eta", ctypes.c_int32), ("rabi", ctypes.c_double), ("omega", ctypes.c_double),
-                ("precision", ctypes.c_int32), ("y_solver", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("y_solver", ctypes.c_int32),
+                ("x_points", ctypes.c_int32), ("y_tile", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -65,7 +66,7 @@ class Plan(ctypes.Structure):
     _fields_ = [("x_points_per_thread", ctypes.c_int32), ("x_threads_per_row", ctypes.c_int32),
                 ("x_rows_per_block", ctypes.c_int32), ("y_solver", ctypes.c_int32),
                 ("y_halo", ctypes.c_int32), ("y_rows_out", ctypes.c_int32),
-                ("y_tile_cols", ctypes.c_int32), ("y_segments", ctypes.c_int32),
+                ("y_tile", ctypes.c_int32), ("y_tile_cols", ctypes.c_int32), ("y_segments", ctypes.c_int32),
                 ("y_rows_per_thread", ctypes.c_int32), ("pivots_x", ctypes.c_int32),
                 ("pivots_y", ctypes.c_int32), ("decay_x", ctypes.c_double), ("decay_y", ctypes.c_double),
                 ("stable", ctypes.c_int32)]
@@ -108,7 +109,8 @@ def load():
     return lib
 
 
-def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto") -> Params:
+def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0, y_tile: int = 0,
+                autotune: bool = False) -> Params:
     """Params from a plain mapping (keys nx, ny, dx, dy, x0, y0, dt, c0, c2,
     gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2)."""
     prec = {"fp64": GP_FP64, "fp32": GP_FP32}[precision]
@@ -116,7 +118,8 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto") -> Par
     return Params(int(p["nx"]), int(p["ny"]), float(p["dx"]), float(p.get("dy", p["dx"])),
                   float(p.get("x0", math.nan)), float(p.get("y0", math.nan)), float(p["dt"]),
                   float(p.get("c0", 0.0)), float(p.get("c2", 0.0)), float(p.get("gamma", 0.0)),
-                  int(p.get("eta", 1)), float(p.get("rabi", 0.0)), float(p.get("omega", 0.0)), prec, ys)
+                  int(p.get("eta", 1)), float(p.get("rabi", 0.0)), float(p.get("omega", 0.0)), prec, ys,
+                  int(x_points), int(y_tile), int(bool(autotune)))
 
 
 def _obs_dict(o: Obs) -> dict:
@@ -125,12 +128,13 @@ def _obs_dict(o: Obs) -> dict:
             "e_so": o.e_so, "e_rabi": o.e_rabi, "lz": o.lz, "mu": list(o.mu), "mu_total": o.mu_total}
 
 
-def plan_query(p: dict, imag: bool, precision: str = "fp64", y_solver: str = "auto") -> dict:
+def plan_query(p: dict, imag: bool, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0,
+               y_tile: int = 0) -> dict:
     """Host-only plan (no GPU needed): pivot table lengths, decay factors,
     y solver and stability flag for these parameters."""
     lib = load()
     pl = Plan()
-    pp = make_params(p, precision, y_solver)
+    pp = make_params(p, precision, y_solver, x_points, y_tile)
     rc = lib.gp_spin1_plan_query(ctypes.byref(pp), int(bool(imag)), ctypes.byref(pl))
     if rc != GP_OK:
         raise GPError(rc, "gp_spin1_plan_query: " + lib.gp_spin1_strerror(rc).decode())
@@ -140,7 +144,8 @@ def plan_query(p: dict, imag: bool, precision: str = "fp64", y_solver: str = "au
 class Solver:
     """One condensate on one stream: a handle of the C ABI."""
 
-    def __init__(self, p: dict, precision: str = "fp64", y_solver: str = "auto", stream=None):
+    def __init__(self, p: dict, precision: str = "fp64", y_solver: str = "auto", stream=None, x_points: int = 0,
+                 y_tile: int = 0, autotune: bool = False):
         import torch
         self._lib = load()
         self.precision = precision
@@ -152,7 +157,7 @@ class Solver:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._h = ctypes.c_void_p()
-        pp = make_params(p, precision, y_solver)
+        pp = make_params(p, precision, y_solver, x_points, y_tile, autotune)
         rc = self._lib.gp_spin1_create(ctypes.byref(pp), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
         if rc != GP_OK:
             raise GPError(rc, "gp_spin1_create: " + self._lib.gp_spin1_strerror(rc).decode())

@@ -56,19 +56,12 @@ template <typename C> __device__ inline C shfl_down_c(C v, int d) { C z; z.x = s
 // Thomas pivots of one line, tabulated on the host.  For the tridiagonal
 // system  a u_{k-1} + b u_k + e u_{k+1} = r_k  with w_0 = b,
 // w_k = b - a e / w_{k-1}:  m = 1/w_k, am = a m, cp = e m.  Entries past the
-// table length repeat the converged limit.  In FP32 the coefficients are
-// rounded first and the pivots derived from the rounded values, and m carries
-// a second term mlo (m = m + mlo to ~2^-48), so that the elimination inverts
-// the very matrix whose rounded coefficients form the right-hand side; in
-// FP64 mlo is zero and unused.
+// table length repeat the converged limit.  The coefficients are rounded to
+// the kernels' precision first and the pivots derived from the rounded
+// values, so that the elimination inverts the very matrix whose rounded
+// coefficients form the right-hand side.
 // ---------------------------------------------------------------------------
-template <typename T> struct Piv { cx<T> m, mlo, am, cp; };
-
-// m r with the compensated multiplier in FP32.
-template <typename T> __device__ inline cx<T> mul_m(const Piv<T>& pv, cx<T> r) {
-    if (sizeof(T) == 4) return cfma(r, pv.mlo, cmul(pv.m, r));
-    return cmul(pv.m, r);
-}
+template <typename T> struct Piv { cx<T> m, am, cp; };
 
 template <typename T> struct LineSet {
     const Piv<T>* piv;   // [lines][K + 1]

@@ -25,79 +25,137 @@ namespace gp {
 // the elimination is small relative to u and u + delta is rounded once.  (In
 // FP32 the direct form drifts in norm by a few 1e-8 per sweep.)
 //
-// Partitioned Thomas on one row held as K consecutive values per thread; works
-// in place on u[], uses the neighbour values left/right of the thread's block.
-// Every thread of the block must call it (barriers).
+// Partitioned Thomas on one line held as K consecutive values per thread
+// (indices i0 .. i0+K-1 of a line of length n; indices outside [0, n) are
+// padding), in place on u[]; left/right are the line values just outside the
+// thread's block.  FS and BS are the forward and backward exclusive scans of
+// the block transfer maps across the threads sharing the line; every thread
+// must reach them (they contain barriers).
+//
+// Blocks entirely inside the line and past the tabulated transient of the
+// pivots take a fast path with the converged pivots held in registers.
 // ---------------------------------------------------------------------------
-template <typename T, int K>
-__device__ inline void row_line_solve(cx<T> (&u)[K], cx<T> left, cx<T> right, const LineSet<T>& ls, int line,
-                                      int i0, int n, int lane, int w, int nw, cx<T>* shA, cx<T>* shB) {
+template <typename T, bool IMAG> __device__ inline cx<T> mul_bm1(cx<T> bm1, cx<T> u) {
+    // b - 1 = alpha / dx^2: real in imaginary time, imaginary in real time
+    return IMAG ? cscale(u, bm1.x) : cscale(ctimes_i(u), bm1.y);
+}
+template <typename C> __device__ inline C cneg(C a) { C z; z.x = -a.x; z.y = -a.y; return z; }
+template <typename C, int K> __device__ inline C cpow_k(C a) {
+    C r = one_c<C>(), b = a;
+#pragma unroll
+    for (int k = K; k > 0; k >>= 1) {
+        if (k & 1) r = cmul(r, b);
+        b = cmul(b, b);
+    }
+    return r;
+}
+
+template <typename T, int K, bool IMAG, typename FS, typename BS>
+__device__ inline void block_solve(cx<T> (&u)[K], cx<T> left, cx<T> right, const LineSet<T>& ls, int line, int i0,
+                                   int n, FS fscan, BS bscan) {
     using C = cx<T>;
-    const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], bm1 = ls.bm1;
+    const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1];
     const Piv<T> lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
+    const bool fast = i0 >= ls.K && i0 + K <= n;
+    // right-hand side of the increment system: r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
     C r[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const C um = (k == 0) ? left : u[k - 1];
         const C up = (k == K - 1) ? right : u[k + 1];
-        // r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
-        C t = cmul(bm1, u[k]);
+        C t = mul_bm1<T, IMAG>(ls.bm1, u[k]);
         t = cfma(um, a, t);
         t = cfma(up, e, t);
-        r[k] = (i0 + k < n) ? cscale(t, (T)-2) : zero_c<C>();
+        r[k] = cscale(t, (T)-2);
     }
-    // forward elimination over the block from a zero carry
-    C E = zero_c<C>(), P = one_c<C>();
+    const C nam = cneg(lim.am), ncp = cneg(lim.cp);
+    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1}
+    C E = zero_c<C>(), P;
+    if (fast) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int i = i0 + k;
-        if (i < n) {
-            const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
-            E = csub(mul_m(pv, r[k]), cmul(pv.am, E));
-            P = cmul(mk<T>(-pv.am.x, -pv.am.y), P);
-        } else {
-            E = zero_c<C>();
-            P = zero_c<C>();
+        for (int k = 0; k < K; ++k) {
+            E = cfma(E, nam, cmul(lim.m, r[k]));
+            r[k] = E;
         }
-        r[k] = E;
+        P = cpow_k<C, K>(nam);
+    } else {
+        P = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                E = cfma(E, cneg(pv.am), cmul(pv.m, r[k]));
+                P = cmul(cneg(pv.am), P);
+            } else {
+                E = zero_c<C>();
+                P = zero_c<C>();
+            }
+            r[k] = E;
+        }
     }
-    const C din = row_scan_fwd(P, E, lane, w, nw, shA, shB);
-    {
+    const C din = fscan(P, E);
+    // add the carry that enters the block, times the running product of -am
+    if (fast) {
+        C Q = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            Q = cmul(Q, nam);
+            r[k] = cfma(din, Q, r[k]);
+        }
+    } else {
         C Q = one_c<C>();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = i0 + k;
-            if (i < n) {
+            if (i >= 0 && i < n) {
                 const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
-                Q = cmul(mk<T>(-pv.am.x, -pv.am.y), Q);
+                Q = cmul(Q, cneg(pv.am));
                 r[k] = cfma(din, Q, r[k]);
             }
         }
     }
-    // back substitution over the block from a zero carry
-    C G = zero_c<C>(), R = one_c<C>();
+    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1}
+    C G = zero_c<C>(), R;
+    if (fast) {
 #pragma unroll
-    for (int k = K - 1; k >= 0; --k) {
-        const int i = i0 + k;
-        if (i < n) {
-            const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
-            G = csub(r[k], cmul(pv.cp, G));
-            R = cmul(mk<T>(-pv.cp.x, -pv.cp.y), R);
-        } else {
-            G = zero_c<C>();
-            R = zero_c<C>();
+        for (int k = K - 1; k >= 0; --k) {
+            G = cfma(G, ncp, r[k]);
+            r[k] = G;
         }
-        r[k] = G;
+        R = cpow_k<C, K>(ncp);
+    } else {
+        R = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                G = cfma(G, cneg(pv.cp), r[k]);
+                R = cmul(cneg(pv.cp), R);
+            } else {
+                G = zero_c<C>();
+                R = zero_c<C>();
+            }
+            r[k] = G;
+        }
     }
-    const C xin = row_scan_bwd(R, G, lane, w, nw, shA, shB);
-    {
+    const C xin = bscan(R, G);
+    if (fast) {
+        C Sx = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            Sx = cmul(Sx, ncp);
+            u[k] = cadd(u[k], cfma(xin, Sx, r[k]));
+        }
+    } else {
         C Sx = one_c<C>();
 #pragma unroll
         for (int k = K - 1; k >= 0; --k) {
             const int i = i0 + k;
-            if (i < n) {
+            if (i >= 0 && i < n) {
                 const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
-                Sx = cmul(mk<T>(-pv.cp.x, -pv.cp.y), Sx);
+                Sx = cmul(Sx, cneg(pv.cp));
                 u[k] = cadd(u[k], cfma(xin, Sx, r[k]));
             }
         }
@@ -170,10 +228,12 @@ __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx
         if (lane == 63) right[q] = (w + 1 < nw) ? shN[48 + (nrow + w + 1) * 3 + q] : zero_c<C>();
     }
     const int jl = row_ok ? j : 0;
+    C* sa = shA + 8 * r;
+    C* sb = shB + 8 * r;
+    auto fs = [&](C P, C E) { return row_scan<true>(P, E, lane, w, nw, sa, sb); };
+    auto bs = [&](C P, C E) { return row_scan<false>(P, E, lane, w, nw, sa, sb); };
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
-        row_line_solve<T, K>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, lane, w, nw, shA + 8 * r,
-                             shB + 8 * r);
+    for (int q = 0; q < 3; ++q) block_solve<T, K, IMAG>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, fs, bs);
 #pragma unroll
     for (int k = 0; k < K; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
     if (row_ok && i0 + K <= nx) {
@@ -239,27 +299,28 @@ __device__ inline void finish_norm(double part, double* sh, NormOut no) {
 
 // ---------------------------------------------------------------------------
 // y sweep, windowed partitioned Thomas over column tiles (increment form).
+// Each wave holds 4 columns; each DPP row of 16 lanes holds the 16 segments of
+// one column; each lane KY consecutive rows of its segment, so a window spans
+// 16 KY rows.  The segment scans and the exchange of segment-end neighbours
+// are DPP moves inside a row: no shared memory and no barrier (except for the
+// norm reduction at the end).  Consecutive windows overlap by h rows on each
+// side and write only their L = 16 KY - 2 h middle rows.
 // ---------------------------------------------------------------------------
-template <typename T, bool IMAG, int KY, int TW, int S, bool NORM>
-__global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
-                                                   LineSet<T> ls, int L, int h, int ncs, NormOut no) {
+template <typename T, bool IMAG, int KY, int NW, bool NORM>
+__global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                      Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no) {
     using C = cx<T>;
-    constexpr int SPW = 64 / TW, NWV = S / SPW;
-    __shared__ C shP[NWV * TW];
-    __shared__ C shE[NWV * TW];
-    __shared__ C shU[3 * NWV * TW];
-    __shared__ C shD[3 * NWV * TW];
+    constexpr int CPB = 4 * NW;  // columns per block
     __shared__ double shr[16];
-    const int tid = threadIdx.x;
-    const int c = tid % TW, s = tid / TW;
-    const int sw = s % SPW, wv = s / SPW;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane & 15, cw = lane >> 4;
     const int cs = blockIdx.x % ncs, rt = blockIdx.x / ncs;
-    const int i = cs * TW + c;
+    const int i = cs * CPB + wv * 4 + cw;
     const bool col_ok = i < ph.nx;
     const int nx = ph.nx, ny = ph.ny;
     const size_t plane = (size_t)nx * ny;
     const int j0 = rt * L;
-    const int g0 = j0 - h + s * KY;  // first row of this thread
+    const int g0 = j0 - h + seg * KY;  // first row of this lane
     C v[3][KY];
 #pragma unroll
     for (int k = 0; k < KY; ++k) {
@@ -271,95 +332,18 @@ __global__ __launch_bounds__(TW* S) void k_y_window(const cx<T>* __restrict__ sr
     }
 #pragma unroll
     for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
-    // rows just above and below this thread's segment, for all three components
-    // (zeros outside the window)
+    // rows just above and below this lane's segment (zeros outside the window)
     C up[3], dn[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
-        up[q] = shfl_up_c(v[q][KY - 1], TW);
-        dn[q] = shfl_down_c(v[q][0], TW);
-        if (sw == SPW - 1) shU[(wv * 3 + q) * TW + c] = v[q][KY - 1];
-        if (sw == 0) shD[(wv * 3 + q) * TW + c] = v[q][0];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        if (sw == 0) up[q] = (wv > 0) ? shU[((wv - 1) * 3 + q) * TW + c] : zero_c<C>();
-        if (sw == SPW - 1) dn[q] = (wv + 1 < NWV) ? shD[((wv + 1) * 3 + q) * TW + c] : zero_c<C>();
+        up[q] = dpp_c<0x111>(zero_c<C>(), v[q][KY - 1]);  // row_shr:1
+        dn[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
     }
     const int il = col_ok ? i : 0;
+    auto fs = [&](C P, C E) { return seg16_scan<true>(P, E); };
+    auto bs = [&](C P, C E) { return seg16_scan<false>(P, E); };
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        C (&u)[KY] = v[q];
-        const int line = il * 3 + q;
-        const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1], bm1 = ls.bm1;
-        const Piv<T> lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
-        C r[KY];
-#pragma unroll
-        for (int k = 0; k < KY; ++k) {
-            const int g = g0 + k;
-            const C um = (k == 0) ? up[q] : u[k - 1];
-            const C uq = (k == KY - 1) ? dn[q] : u[k + 1];
-            C t = cmul(bm1, u[k]);
-            t = cfma(um, a, t);
-            t = cfma(uq, e, t);
-            r[k] = (g >= 0 && g < ny) ? cscale(t, (T)-2) : zero_c<C>();
-        }
-        C E = zero_c<C>(), P = one_c<C>();
-#pragma unroll
-        for (int k = 0; k < KY; ++k) {
-            const int g = g0 + k;
-            if (g >= 0 && g < ny) {
-                const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
-                E = csub(mul_m(pv, r[k]), cmul(pv.am, E));
-                P = cmul(mk<T>(-pv.am.x, -pv.am.y), P);
-            } else {
-                E = zero_c<C>();
-                P = zero_c<C>();
-            }
-            r[k] = E;
-        }
-        const C din = seg_scan<C, TW, S, false>(P, E, c, s, shP, shE);
-        {
-            C Q = one_c<C>();
-#pragma unroll
-            for (int k = 0; k < KY; ++k) {
-                const int g = g0 + k;
-                if (g >= 0 && g < ny) {
-                    const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
-                    Q = cmul(mk<T>(-pv.am.x, -pv.am.y), Q);
-                    r[k] = cfma(din, Q, r[k]);
-                }
-            }
-        }
-        C G = zero_c<C>(), R = one_c<C>();
-#pragma unroll
-        for (int k = KY - 1; k >= 0; --k) {
-            const int g = g0 + k;
-            if (g >= 0 && g < ny) {
-                const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
-                G = csub(r[k], cmul(pv.cp, G));
-                R = cmul(mk<T>(-pv.cp.x, -pv.cp.y), R);
-            } else {
-                G = zero_c<C>();
-                R = zero_c<C>();
-            }
-            r[k] = G;
-        }
-        const C xin = seg_scan<C, TW, S, true>(R, G, c, s, shP, shE);
-        {
-            C Sx = one_c<C>();
-#pragma unroll
-            for (int k = KY - 1; k >= 0; --k) {
-                const int g = g0 + k;
-                if (g >= 0 && g < ny) {
-                    const Piv<T> pv = (g < ls.K) ? piv_at(ls, line, g) : lim;
-                    Sx = cmul(mk<T>(-pv.cp.x, -pv.cp.y), Sx);
-                    u[k] = cadd(u[k], cfma(xin, Sx, r[k]));
-                }
-            }
-        }
-    }
+    for (int q = 0; q < 3; ++q) block_solve<T, KY, IMAG>(v[q], up[q], dn[q], ls, il * 3 + q, g0, ny, fs, bs);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     double acc = 0;
@@ -417,12 +401,12 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
             load_sx(g + 1, nxt);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
-                C t = cmul(ls.bm1, cur[q]);
+                C t = mul_bm1<T, IMAG>(ls.bm1, cur[q]);
                 t = cfma(prev[q], a[q], t);
                 t = cfma(nxt[q], e[q], t);
                 const C rr = cscale(t, (T)-2);
                 const Piv<T> pv = (g < ls.K) ? piv_at(ls, i * 3 + q, g) : lim[q];
-                d[q] = csub(mul_m(pv, rr), cmul(pv.am, carry[q]));
+                d[q] = cfma(carry[q], cneg(pv.am), cmul(pv.m, rr));
                 carry[q] = d[q];
                 prev[q] = cur[q];
                 cur[q] = nxt[q];
@@ -620,13 +604,13 @@ static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph
                              const double* scale, int G, int R, hipStream_t st) {
     const int nblk = (ph.ny + R - 1) / R;
     const dim3 grid(nblk), block(G * R);
-    if (G * R > 512) return hipErrorInvalidValue;
+    if (G * R > xk_bound(K) || G % 64 || G / 64 > 16 || R > 8) return hipErrorInvalidValue;
     switch (K) {
-        case 1: k_x_scan<T, IMAG, 1, LOCAL, SCALE, 256><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 2: k_x_scan<T, IMAG, 2, LOCAL, SCALE, 256><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 4: k_x_scan<T, IMAG, 4, LOCAL, SCALE, 256><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 8: k_x_scan<T, IMAG, 8, LOCAL, SCALE, 512><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 16: k_x_scan<T, IMAG, 16, LOCAL, SCALE, 512><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 1: k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 2: k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 4: k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 8: k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 16: k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -642,20 +626,32 @@ hipError_t launch_x(const XLaunch<T>& a, hipStream_t st) {
     return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
 }
 
+template <typename T, bool IMAG, bool NORM, int TI>
+static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st) {
+    constexpr YTile yt = ytile<T>(TI);
+    const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
+    const int nrt = (a.ph.ny + a.L - 1) / a.L;
+    k_y_window<T, IMAG, yt.KY, yt.NW, NORM><<<dim3(ncs * nrt), dim3(64 * yt.NW), 0, st>>>(a.src, a.dst, a.ph, a.ls,
+                                                                                        a.L, a.h, ncs, a.no);
+    return hipGetLastError();
+}
+
 template <typename T, bool IMAG, bool NORM>
 static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st) {
-    constexpr int KY = YCfg<T>::KY, TW = YCfg<T>::TW, S = YCfg<T>::S;
-    const int ncs = (a.ph.nx + TW - 1) / TW;
-    const int nrt = (a.ph.ny + a.L - 1) / a.L;
-    k_y_window<T, IMAG, KY, TW, S, NORM><<<dim3(ncs * nrt), dim3(TW * S), 0, st>>>(a.src, a.dst, a.ph, a.ls, a.L, a.h,
-                                                                                  ncs, a.no);
-    return hipGetLastError();
+    switch (a.tile) {
+        case 0: return launch_yw_t<T, IMAG, NORM, 0>(a, st);
+        case 1: return launch_yw_t<T, IMAG, NORM, 1>(a, st);
+        case 2: return launch_yw_t<T, IMAG, NORM, 2>(a, st);
+        case 3: return launch_yw_t<T, IMAG, NORM, 3>(a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T>
 int y_blocks(const YLaunch<T>& a) {
     if (a.window) {
-        const int ncs = (a.ph.nx + YCfg<T>::TW - 1) / YCfg<T>::TW;
+        const YTile yt = ytile<T>(a.tile);
+        const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
         return ncs * ((a.ph.ny + a.L - 1) / a.L);
     }
     return (a.ph.nx + 255) / 256;

@@ -7,12 +7,23 @@ namespace gp {
 
 constexpr int kObsCount = 13;
 
-// Tile geometry of the windowed y sweep per precision: TW columns (a
-// contiguous run of each row) x S segments of KY rows per thread; a window
-// spans S * KY = 128 rows.
-template <typename T> struct YCfg;
-template <> struct YCfg<double> { static constexpr int KY = 4, TW = 16, S = 32; };
-template <> struct YCfg<float> { static constexpr int KY = 8, TW = 32, S = 16; };
+// Tile shapes of the windowed y sweep: KY rows per lane, NW waves (4 columns
+// each) per block.  A window spans 16 * KY rows (16 segments per column).
+constexpr int kNumYTiles = 4;
+struct YTile { int KY, NW; };
+template <typename T> __host__ __device__ constexpr YTile ytile(int t);
+template <> __host__ __device__ constexpr YTile ytile<double>(int t) {
+    return t == 0 ? YTile{8, 2} : t == 1 ? YTile{8, 4} : t == 2 ? YTile{4, 4} : YTile{4, 8};
+}
+template <> __host__ __device__ constexpr YTile ytile<float>(int t) {
+    return t == 0 ? YTile{8, 4} : t == 1 ? YTile{16, 2} : t == 2 ? YTile{16, 4} : YTile{8, 8};
+}
+__host__ __device__ constexpr int ywindow(YTile t) { return 16 * t.KY; }
+
+// x sweep: K consecutive points per thread; the launch bound of each K.
+constexpr int kNumXK = 5;
+__host__ __device__ constexpr int xk_value(int idx) { return 1 << idx; }  // 1, 2, 4, 8, 16
+__host__ __device__ constexpr int xk_bound(int K) { return K == 1 ? 1024 : 512; }
 
 // Both sweeps run out of place (src -> dst): the y windows overlap, so a
 // window's halo rows must not be rewritten by its neighbour while it reads.
@@ -43,7 +54,7 @@ template <typename T> struct YLaunch {
     Phys ph;
     LineSet<T> ls;
     NormOut no;
-    int L, h;
+    int L, h, tile;
     bool window, imag, norm;
 };
 

@@ -33,8 +33,10 @@ struct ModeState {
     bool stable = false;
     std::string why;
     bool window = false;
-    int h = 0, L = 0;
-    int ypart_blocks = 0;
+    int hh = 0;        // halo the truncation bound asks for
+    int h = 0, L = 0;  // halo and rows written per window for the chosen tile
+    int xK = 2, xG = 64, xR = 1;  // x sweep: points per thread, threads per row, rows per block
+    int ytile = 0;                // windowed y sweep tile shape (0-based)
     gp_spin1_plan plan{};
 };
 
@@ -45,7 +47,6 @@ struct gp_spin1 {
     hipStream_t stream = nullptr;
     int device = 0;
     ModeState mode[2];  // [0] real time, [1] imaginary time
-    int xK = 4, xG = 64, xR = 1;
     double* d_scale = nullptr;
     int* d_flag = nullptr;
     unsigned int* d_ticket = nullptr;  // zero between launches (the last block re-arms it)
@@ -155,7 +156,6 @@ template <typename T>
 void set_piv(gp::Piv<T>& pv, zd a, zd e, zd w) {
     const zd m = 1.0 / w;
     pv.m = to_dev<T>(m);
-    pv.mlo = to_dev<T>(m - round_to<T>(m));
     pv.am = to_dev<T>(a * m);
     pv.cp = to_dev<T>(e * m);
 }
@@ -205,15 +205,46 @@ gp::Phys phys(const gp_spin1_params& p) {
     return ph;
 }
 
-// Line tables, stability checks and the y plan of one propagation mode,
+// x launch shape for K points per thread: G threads per row (a multiple of
+// 64), R rows per block; false if this K cannot hold a row of nx points.
+bool x_shape(int nx, int K, int& G, int& R) {
+    G = ((nx + K - 1) / K + 63) / 64 * 64;
+    if (G > gp::xk_bound(K) || G > 1024) return false;
+    R = std::max(1, std::min(8, 256 / G));
+    while (G * R > gp::xk_bound(K)) --R;
+    return true;
+}
+
+// Default x shape before any tuning: the fewest points per thread (at least
+// two) that keep a row within 512 threads.
+int x_default_k(int nx) {
+    for (int idx = 1; idx < gp::kNumXK; ++idx) {
+        const int K = gp::xk_value(idx);
+        int G, R;
+        if (x_shape(nx, K, G, R) && G <= 512) return K;
+    }
+    return 16;
+}
+
+// Line tables, stability checks and the launch plan of one propagation mode,
 // all on the host.
 struct HostMode {
     HostDir x, y;
     bool stable = true;
     std::string why;
     bool window = false;
-    int h = 0, L = 0;
+    int hh = 0, h = 0, L = 0;
+    int xK = 2, xG = 64, xR = 1, ytile = 0;
 };
+
+// Window of a y tile shape: the whole column fits one window (no halo), or
+// windows of W rows overlap by the halo hh on each side and write W - 2 hh
+// rows (accepted while the halo is at most a quarter of the window).
+bool tile_window(int ny, int hh, int W, int& h, int& L) {
+    if (ny <= W) { h = 0; L = W; return true; }
+    if (2 * hh <= W / 2) { h = hh; L = W - 2 * hh; return true; }
+    return false;
+}
 
 template <typename T>
 void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
@@ -241,47 +272,44 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
             hm.why = "imaginary-time Cayley bound (dt/4)(|Omega| L_max + |gamma|)^2 < 1 fails";
         }
     }
-    // y plan: windows of W rows overlapping by h rows on each side, where the
-    // truncated carries decay by decay^h below the rounding level of T.
-    constexpr int W = gp::YCfg<T>::S * gp::YCfg<T>::KY;
+    // y plan: windows overlapping by h rows on each side, where the truncated
+    // carries decay by decay^h below the rounding level of T.
     const double tolw = sizeof(T) == 8 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -32);
-    int hh;
-    if (hm.y.decay <= 0.0) hh = 1;
-    else if (hm.y.decay >= 1.0) hh = 1 << 20;
-    else hh = (int)std::ceil(std::log(tolw) / std::log(hm.y.decay)) + 1;
+    if (hm.y.decay <= 0.0) hm.hh = 1;
+    else if (hm.y.decay >= 1.0) hm.hh = 1 << 20;
+    else hm.hh = (int)std::ceil(std::log(tolw) / std::log(hm.y.decay)) + 1;
     hm.window = false;
     hm.h = 0;
     hm.L = 0;
+    hm.ytile = 0;
     if (p.y_solver != GP_YSOLVER_THOMAS) {
-        if (p.ny <= W) {
-            hm.window = true; hm.h = 0; hm.L = W;
-        } else if (2 * hh <= W / 2) {
-            hm.window = true; hm.h = hh; hm.L = W - 2 * hh;
+        if (p.y_tile > 0) {
+            hm.ytile = p.y_tile - 1;
+            hm.window = tile_window(p.ny, hm.hh, gp::ywindow(gp::ytile<T>(hm.ytile)), hm.h, hm.L);
+        } else {
+            for (int t = 0; t < gp::kNumYTiles && !hm.window; ++t)
+                if (tile_window(p.ny, hm.hh, gp::ywindow(gp::ytile<T>(t)), hm.h, hm.L)) { hm.window = true; hm.ytile = t; }
         }
     }
-}
-
-int x_points_per_thread(int nx) {
-    if (nx <= 128) return 2;
-    if (nx <= 1024) return 4;
-    if (nx <= 4096) return 8;
-    return 16;
+    // launch shapes requested in p, else the defaults (autotuning may replace them)
+    hm.xK = p.x_points > 0 ? p.x_points : x_default_k(p.nx);
+    x_shape(p.nx, hm.xK, hm.xG, hm.xR);
 }
 
 template <typename T>
 void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out) {
     std::memset(out, 0, sizeof *out);
-    const int K = x_points_per_thread(p.nx);
-    const int G = ((p.nx + K - 1) / K + 63) / 64 * 64;
-    out->x_points_per_thread = K;
-    out->x_threads_per_row = G;
-    out->x_rows_per_block = std::max(1, std::min(8, 256 / G));
+    out->x_points_per_thread = hm.xK;
+    out->x_threads_per_row = hm.xG;
+    out->x_rows_per_block = hm.xR;
     out->y_solver = hm.window ? GP_YSOLVER_WINDOW : GP_YSOLVER_THOMAS;
     out->y_halo = hm.h;
     out->y_rows_out = hm.L;
-    out->y_tile_cols = gp::YCfg<T>::TW;
-    out->y_segments = gp::YCfg<T>::S;
-    out->y_rows_per_thread = gp::YCfg<T>::KY;
+    const gp::YTile yt = gp::ytile<T>(hm.ytile);
+    out->y_tile = hm.ytile + 1;
+    out->y_tile_cols = 4 * yt.NW;
+    out->y_segments = 16;
+    out->y_rows_per_thread = yt.KY;
     out->pivots_x = hm.x.K;
     out->pivots_y = hm.y.K;
     out->decay_x = hm.x.decay;
@@ -301,16 +329,27 @@ int build_mode(gp_spin1* h, ModeState& ms, bool imag) {
     ms.stable = hm.stable;
     ms.why = hm.why;
     ms.window = hm.window;
+    ms.hh = hm.hh;
     ms.h = hm.h;
     ms.L = hm.L;
+    ms.xK = hm.xK; ms.xG = hm.xG; ms.xR = hm.xR;
+    ms.ytile = hm.ytile;
     fill_plan<T>(p, hm, &ms.plan);
-    if (ms.window) {
-        const int ncs = (p.nx + gp::YCfg<T>::TW - 1) / gp::YCfg<T>::TW;
-        ms.ypart_blocks = ncs * ((p.ny + ms.L - 1) / ms.L);
-    } else {
-        ms.ypart_blocks = (p.nx + 255) / 256;
-    }
     return GP_OK;
+}
+
+// Blocks of the y sweep for the largest grid of any tile shape (partials).
+template <typename T>
+size_t max_y_blocks(const gp_spin1_params& p, const ModeState& ms) {
+    if (!ms.window) return (size_t)(p.nx + 255) / 256;
+    size_t best = 1;
+    for (int t = 0; t < gp::kNumYTiles; ++t) {
+        const gp::YTile yt = gp::ytile<T>(t);
+        int h, L;
+        if (!tile_window(p.ny, ms.hh, gp::ywindow(yt), h, L)) continue;
+        best = std::max(best, (size_t)((p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((p.ny + L - 1) / L));
+    }
+    return best;
 }
 
 void free_dir(DirTable& d) {
@@ -355,21 +394,112 @@ int validate(const gp_spin1_params* p, std::string& why) {
     return GP_OK;
 }
 
+template <typename T> gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool local);
+template <typename T> gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool norm);
+
+// Mean duration in ms of `reps` launches of f() after two warm-up launches.
+template <typename F>
+int time_launches(gp_spin1* h, F f, int reps, float& ms) {
+    hipEvent_t a, b;
+    hipError_t e;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(h, e, "autotune");
+    if ((e = hipEventCreate(&b)) != hipSuccess) { (void)hipEventDestroy(a); return hip_fail(h, e, "autotune"); }
+    int rc = GP_OK;
+    for (int w = 0; w < 2 && rc == GP_OK; ++w)
+        if ((e = f()) != hipSuccess) rc = hip_fail(h, e, "autotune launch");
+    if (rc == GP_OK && (e = hipEventRecord(a, h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    for (int r = 0; r < reps && rc == GP_OK; ++r)
+        if ((e = f()) != hipSuccess) rc = hip_fail(h, e, "autotune launch");
+    if (rc == GP_OK && (e = hipEventRecord(b, h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    if (rc == GP_OK && (e = hipEventSynchronize(b)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    if (rc == GP_OK && (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    ms /= reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return rc;
+}
+
+// Time every admissible x points-per-thread and y tile shape on a scratch
+// wave function of this grid, per propagation mode, and keep the fastest
+// (fields fixed in the parameters are left as given).
+template <typename T>
+int autotune_t(gp_spin1* h) {
+    const gp_spin1_params& p = h->p;
+    const size_t bytes = (size_t)3 * p.nx * p.ny * sizeof(gp::cx<T>);
+    void* tmp = nullptr;
+    hipError_t e = hipMalloc(&tmp, bytes);
+    if (e != hipSuccess) return fail(h, GP_ENOMEM, "autotune buffer allocation failed");
+    int rc = GP_OK;
+    if ((e = hipMemsetAsync(tmp, 0, bytes, h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    const int reps = 5;
+    for (int m = 0; m < 2 && rc == GP_OK; ++m) {
+        ModeState& ms = h->mode[m];
+        const bool imag = m == 1;
+        if (p.x_points == 0) {
+            float best = 1e30f;
+            int bestK = ms.xK;
+            for (int idx = 0; idx < gp::kNumXK && rc == GP_OK; ++idx) {
+                const int K = gp::xk_value(idx);
+                int G, R;
+                if (!x_shape(p.nx, K, G, R)) continue;
+                ms.xK = K; ms.xG = G; ms.xR = R;
+                const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
+                float t = 0.f;
+                rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, t);
+                if (rc == GP_OK && t < best) { best = t; bestK = K; }
+            }
+            ms.xK = bestK;
+            x_shape(p.nx, bestK, ms.xG, ms.xR);
+        }
+        if (p.y_tile == 0 && ms.window) {
+            float best = 1e30f;
+            int bestT = ms.ytile;
+            for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
+                if (!tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(t)), ms.h, ms.L)) continue;
+                ms.ytile = t;
+                const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag);
+                float tt = 0.f;
+                rc = time_launches(h, [&] { return gp::launch_y<T>(ya, h->stream); }, reps, tt);
+                if (rc == GP_OK && tt < best) { best = tt; bestT = t; }
+            }
+            ms.ytile = bestT;
+            tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(bestT)), ms.h, ms.L);
+        }
+        ms.plan.x_points_per_thread = ms.xK;
+        ms.plan.x_threads_per_row = ms.xG;
+        ms.plan.x_rows_per_block = ms.xR;
+        const gp::YTile yt = gp::ytile<T>(ms.ytile);
+        ms.plan.y_tile = ms.ytile + 1;
+        ms.plan.y_tile_cols = 4 * yt.NW;
+        ms.plan.y_segments = 16;
+        ms.plan.y_rows_per_thread = yt.KY;
+        ms.plan.y_halo = ms.h;
+        ms.plan.y_rows_out = ms.L;
+    }
+    const double one = 1.0;
+    const int zero = 0;
+    if (rc == GP_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    if (rc == GP_OK && (e = hipMemcpy(h->d_scale, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    if (rc == GP_OK && (e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    (void)hipFree(tmp);
+    return rc;
+}
+
 template <typename T>
 int create_t(gp_spin1* h) {
     const gp_spin1_params& p = h->p;
-    // x plan: K consecutive points per thread, rows of G = 64 * nw threads
-    const int K = x_points_per_thread(p.nx);
-    const int G = ((p.nx + K - 1) / K + 63) / 64 * 64;
-    h->xK = K;
-    h->xG = G;
-    h->xR = std::max(1, std::min(8, 256 / G));
+    if (p.x_points > 0) {
+        int G, R;
+        if ((p.x_points & (p.x_points - 1)) || p.x_points > 16 || !x_shape(p.nx, p.x_points, G, R))
+            return fail(h, GP_EUNSUPPORTED, "x_points must be 1, 2, 4, 8 or 16 and hold a row in one block");
+    }
+    if (p.y_tile < 0 || p.y_tile > gp::kNumYTiles) return fail(h, GP_EINVAL, "y_tile must be 0..4");
     for (int m = 0; m < 2; ++m) {
         int rc = build_mode<T>(h, h->mode[m], m == 1);
         if (rc) return rc;
     }
     size_t need = 1;
-    for (auto& m : h->mode) need = std::max(need, (size_t)m.ypart_blocks);
+    for (auto& m : h->mode) need = std::max(need, max_y_blocks<T>(p, m));
     const size_t npts = (size_t)p.nx * p.ny;
     h->obs_blocks = (int)std::min<size_t>(1024, (npts + 255) / 256);
     need = std::max(need, (size_t)h->obs_blocks * gp::kObsCount);
@@ -388,6 +518,10 @@ int create_t(gp_spin1* h) {
     if ((e = hipMemcpy(h->d_scale, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     if ((e = hipMemcpy(h->d_ticket, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
+    if (p.autotune) {
+        int rc = autotune_t<T>(h);
+        if (rc) return rc;
+    }
     return GP_OK;
 }
 
@@ -399,7 +533,8 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.ph = phys(h->p);
     a.ls = lineset<T>(h->mode[imag].x);
     a.scale = h->d_scale;
-    a.K = h->xK; a.G = h->xG; a.R = h->xR;
+    const ModeState& ms = h->mode[imag];
+    a.K = ms.xK; a.G = ms.xG; a.R = ms.xR;
     a.imag = imag; a.local = local;
     return a;
 }
@@ -417,7 +552,7 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.no.scale = h->d_scale;
     a.no.flag = h->d_flag;
     a.no.dxdy = h->p.dx * h->p.dy;
-    a.L = ms.L; a.h = ms.h;
+    a.L = ms.L; a.h = ms.h; a.tile = ms.ytile;
     a.window = ms.window; a.imag = imag; a.norm = norm;
     return a;
 }

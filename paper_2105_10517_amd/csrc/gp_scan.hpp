@@ -6,84 +6,125 @@
 // transfer maps are composed across threads by a scan, and each thread adds
 // the carry that enters its block times the running product of its
 // multipliers.  The scans below return the exclusive prefix, i.e. the carry
-// that enters each thread's block.  Composition order: (f o g)(z) = f(g(z)),
-// with g the map nearer the start of the scan direction.
+// that enters each thread's block.
+//
+// Inside a wave the scans use DPP lane moves (row_shr / row_shl within rows of
+// 16 lanes, readlane across the four rows, wave_shr / wave_shl for the final
+// shift); across the waves of a row they go through shared memory.
 #pragma once
 
 #include "gp_device.hpp"
 
 namespace gp {
 
-// Forward exclusive scan over the G = 64 * nw threads of one row (thread t =
-// 64 w + lane).  shP/shE: >= nw entries of shared memory private to the row.
-// Every thread of the block must call it (it contains barriers).
-template <typename C>
-__device__ inline C row_scan_fwd(C P, C E, int lane, int w, int nw, C* shP, C* shE) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const C Pp = shfl_up_c(P, off), Ep = shfl_up_c(E, off);
-        if (lane >= off) { E = cfma(Ep, P, E); P = cmul(P, Pp); }
-    }
-    if (lane == 63) { shP[w] = P; shE[w] = E; }
-    __syncthreads();
-    C din = zero_c<C>();
-    for (int v = 0; v < w; ++v) din = cfma(din, shP[v], shE[v]);
-    const C incl = cfma(din, P, E);
-    C ex = shfl_up_c(incl, 1);
-    if (lane == 0) ex = din;
-    __syncthreads();
-    return ex;
+template <typename C> struct Aff { C P, E; };
+
+// (f o g)(z) = f(g(z)): g applies first.
+template <typename C> __device__ inline Aff<C> compose(const Aff<C>& f, const Aff<C>& g) {
+    return Aff<C>{cmul(f.P, g.P), cfma(g.E, f.P, f.E)};
+}
+template <typename C> __device__ inline Aff<C> aff_id() { return Aff<C>{one_c<C>(), zero_c<C>()}; }
+
+// --- DPP lane moves (lanes without a source lane keep `old`) ----------------
+template <int CTRL, int RM> __device__ inline int dpp_i(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, RM, 0xF, false);
+}
+template <int CTRL, int RM> __device__ inline float dpp_r(float old, float v) {
+    return __int_as_float(dpp_i<CTRL, RM>(__float_as_int(old), __float_as_int(v)));
+}
+template <int CTRL, int RM> __device__ inline double dpp_r(double old, double v) {
+    const long long o = __double_as_longlong(old), x = __double_as_longlong(v);
+    const int lo = dpp_i<CTRL, RM>((int)o, (int)x);
+    const int hi = dpp_i<CTRL, RM>((int)(o >> 32), (int)(x >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int CTRL, int RM = 0xF, typename C> __device__ inline C dpp_c(C old, C v) {
+    C z; z.x = dpp_r<CTRL, RM>(old.x, v.x); z.y = dpp_r<CTRL, RM>(old.y, v.y); return z;
+}
+template <int CTRL, typename C> __device__ inline Aff<C> dpp_aff(const Aff<C>& a) {
+    const Aff<C> id = aff_id<C>();
+    return Aff<C>{dpp_c<CTRL>(id.P, a.P), dpp_c<CTRL>(id.E, a.E)};
 }
 
-// Backward exclusive scan: the carry entering thread t from the right is
-// (g_{t+1} o g_{t+2} o ... o g_{G-1})(0).
-template <typename C>
-__device__ inline C row_scan_bwd(C P, C E, int lane, int w, int nw, C* shP, C* shE) {
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const C Pn = shfl_down_c(P, off), En = shfl_down_c(E, off);
-        if (lane + off < 64) { E = cfma(En, P, E); P = cmul(P, Pn); }
-    }
-    if (lane == 0) { shP[w] = P; shE[w] = E; }
-    __syncthreads();
-    C din = zero_c<C>();
-    for (int v = nw - 1; v > w; --v) din = cfma(din, shP[v], shE[v]);
-    const C incl = cfma(din, P, E);
-    C ex = shfl_down_c(incl, 1);
-    if (lane == 63) ex = din;
-    __syncthreads();
-    return ex;
+__device__ inline float readlane_r(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+__device__ inline double readlane_r(double v, int l) {
+    const long long x = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename C> __device__ inline C readlane_c(C v, int l) {
+    C z; z.x = readlane_r(v.x, l); z.y = readlane_r(v.y, l); return z;
+}
+template <typename C> __device__ inline Aff<C> readlane_aff(const Aff<C>& a, int l) {
+    return Aff<C>{readlane_c(a.P, l), readlane_c(a.E, l)};
 }
 
-// Exclusive scan across the S segments of a column tile.  Thread (c, s) sits
-// at index c + TW s, so one wave holds SPW = 64/TW consecutive segments of the
-// same TW columns: the scan runs by shuffles across lanes TW apart inside a
-// wave, and through shared memory (shP/shE: (S/SPW) * TW entries) across waves.
-// REV = false: carry from segments 0..s-1; REV = true: from s+1..S-1.
-template <typename C, int TW, int S, bool REV>
-__device__ inline C seg_scan(C P, C E, int c, int s, C* shP, C* shE) {
-    constexpr int SPW = 64 / TW, NWV = S / SPW;
-    const int sw = s % SPW, w = s / SPW;
-#pragma unroll
-    for (int off = 1; off < SPW; off <<= 1) {
-        const C Po = REV ? shfl_down_c(P, off * TW) : shfl_up_c(P, off * TW);
-        const C Eo = REV ? shfl_down_c(E, off * TW) : shfl_up_c(E, off * TW);
-        if (REV ? (sw + off < SPW) : (sw >= off)) { E = cfma(Eo, P, E); P = cmul(P, Po); }
-    }
-    // wave totals: the inclusive map of the last segment of each wave in scan order
-    if (REV ? (sw == 0) : (sw == SPW - 1)) { shP[w * TW + c] = P; shE[w * TW + c] = E; }
-    __syncthreads();
-    C din = zero_c<C>();
-    if (!REV) {
-        for (int v = 0; v < w; ++v) din = cfma(din, shP[v * TW + c], shE[v * TW + c]);
+// Inclusive scans within each row of 16 lanes.  FWD: lane l holds
+// f_l o f_{l-1} o ... o f_{row start}; backward: f_l o f_{l+1} o ... o f_{row end}.
+template <bool FWD, typename C> __device__ inline Aff<C> row16_incl(Aff<C> a) {
+    if (FWD) {
+        a = compose(a, dpp_aff<0x111>(a));  // row_shr:1
+        a = compose(a, dpp_aff<0x112>(a));  // row_shr:2
+        a = compose(a, dpp_aff<0x114>(a));  // row_shr:4
+        a = compose(a, dpp_aff<0x118>(a));  // row_shr:8
     } else {
-        for (int v = NWV - 1; v > w; --v) din = cfma(din, shP[v * TW + c], shE[v * TW + c]);
+        a = compose(a, dpp_aff<0x101>(a));  // row_shl:1
+        a = compose(a, dpp_aff<0x102>(a));  // row_shl:2
+        a = compose(a, dpp_aff<0x104>(a));  // row_shl:4
+        a = compose(a, dpp_aff<0x108>(a));  // row_shl:8
     }
-    const C incl = cfma(din, P, E);
-    C ex = REV ? shfl_down_c(incl, TW) : shfl_up_c(incl, TW);
-    if (REV ? (sw == SPW - 1) : (sw == 0)) ex = din;
-    __syncthreads();
-    return ex;
+    return a;
+}
+
+// Inclusive scan over the 64 lanes of a wave (lane order forward or backward).
+template <bool FWD, typename C> __device__ inline Aff<C> wave_incl(Aff<C> a, int lane) {
+    a = row16_incl<FWD>(a);
+    const int row = lane >> 4;
+    Aff<C> pre = aff_id<C>();
+    if (FWD) {
+        // prefix of the rows below: S_1 = T_0, S_2 = T_1 o T_0, S_3 = T_2 o T_1 o T_0
+        const Aff<C> t0 = readlane_aff(a, 15), t1 = readlane_aff(a, 31), t2 = readlane_aff(a, 47);
+        const Aff<C> s2 = compose(t1, t0), s3 = compose(t2, s2);
+        if (row == 1) pre = t0;
+        if (row == 2) pre = s2;
+        if (row == 3) pre = s3;
+    } else {
+        const Aff<C> t1 = readlane_aff(a, 16), t2 = readlane_aff(a, 32), t3 = readlane_aff(a, 48);
+        const Aff<C> s1 = compose(t2, t3), s0 = compose(t1, s1);
+        if (row == 0) pre = s0;
+        if (row == 1) pre = s1;
+        if (row == 2) pre = t3;
+    }
+    return compose(a, pre);
+}
+
+// Exclusive scan over the G = 64 * nw threads of one row (thread t = 64 w +
+// lane): the value of the composite of the maps before this thread (FWD) or
+// after it (backward), applied to a zero carry.  shP/shE: >= nw entries of
+// shared memory private to the row.  Every thread of the block must call it.
+template <bool FWD, typename C>
+__device__ inline C row_scan(C P, C E, int lane, int w, int nw, C* shP, C* shE) {
+    const Aff<C> a = wave_incl<FWD>(Aff<C>{P, E}, lane);
+    C din = zero_c<C>();
+    if (nw > 1) {
+        if (lane == (FWD ? 63 : 0)) { shP[w] = a.P; shE[w] = a.E; }
+        __syncthreads();
+        if (FWD) {
+            for (int v = 0; v < w; ++v) din = cfma(din, shP[v], shE[v]);
+        } else {
+            for (int v = nw - 1; v > w; --v) din = cfma(din, shP[v], shE[v]);
+        }
+        __syncthreads();
+    }
+    const C val = cfma(din, a.P, a.E);  // this thread's inclusive map applied to the carry into the wave
+    return FWD ? dpp_c<0x138>(din, val) : dpp_c<0x130>(din, val);  // wave_shr:1 / wave_shl:1
+}
+
+// Exclusive scan across the 16 lanes of a DPP row (segments of one column in
+// the y sweep): no shared memory, no barrier.
+template <bool FWD, typename C> __device__ inline C seg16_scan(C P, C E) {
+    const Aff<C> a = row16_incl<FWD>(Aff<C>{P, E});
+    return FWD ? dpp_c<0x111>(zero_c<C>(), a.E) : dpp_c<0x101>(zero_c<C>(), a.E);
 }
 
 }  // namespace gp
