@@ -138,7 +138,7 @@ def main():
     npts = p["nx"] * p["ny"]
     results = {}
     for prec in ("fp64", "fp32"):
-        s = binding.Solver(p, prec)
+        s = binding.Solver(p, prec, autotune=True)
         t = torch.from_numpy(psi0).to("cuda").to(s.dtype)
         s.step_real(t, args.warmup)
         ms = time_steps(s, t, args.steps, False, torch)
@@ -163,7 +163,7 @@ def main():
         psi3 = inputs.gaussian(4096, 4096, q["dx"], q["dy"], seed=4, full_phase=True)
         n3 = 4096 * 4096
         for prec in ("fp64", "fp32"):
-            s = binding.Solver(q, prec)
+            s = binding.Solver(q, prec, autotune=True)
             t = torch.from_numpy(psi3).to("cuda").to(s.dtype)
             s.step_imag(t, 5)
             ms = time_steps(s, t, args.c3_steps, True, torch)

@@ -164,12 +164,14 @@ int gp_spin1_get_plan(const gp_spin1_t* h, int32_t imag, gp_spin1_plan* out);
 int gp_spin1_plan_query(const gp_spin1_params* p, int32_t imag, gp_spin1_plan* out);
 
 /* Per-kernel timing (diagnostics).  While enabled, the step calls bracket
- * every kernel launch with HIP events on the handle's stream; gp_spin1_timing_read
+ * every kernel launch with a HIP event pair on the handle's stream; gp_spin1_timing_read
  * waits for the stream and returns, per kernel kind, the number of launches
  * and their summed duration in milliseconds since the last enable (which
  * resets the counters).  Kinds: 0 x sweep (with the fused local substep and
- * the pending renormalisation), 1 y sweep (with the fused norm reduction),
- * 2 unused, 3 final renormalisation at the end of an imaginary-time call. */
+ * the pending renormalisation), 1 y sweep (with the fused norm partial sums),
+ * 2 imaginary-time norm total (one block, after each y sweep), 3 final
+ * renormalisation at the end of an imaginary-time call.  The events are
+ * stamped by the kernel dispatches themselves (kernel durations only). */
 typedef struct {
     int64_t launches[4];
     double ms[4];

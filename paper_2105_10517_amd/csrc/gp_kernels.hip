@@ -12,6 +12,8 @@
 //   k_y_thomas   exact per-thread Thomas down whole columns (one thread per
 //                column, forward eliminations stored in place).
 //   k_local, k_scale, k_set_scale, k_norm_finalize, k_obs, k_obs_finalize.
+#include <hip/hip_ext.h>
+
 #include "gp_kernels.hpp"
 #include "gp_scan.hpp"
 
@@ -162,12 +164,160 @@ __device__ inline void block_solve(cx<T> (&u)[K], cx<T> left, cx<T> right, const
     }
 }
 
+template <typename T, int K, bool IMAG, typename FS, typename BS>
+__device__ inline void block_solve3(cx<T> (&u)[3][K], const cx<T> (&left)[3], const cx<T> (&right)[3],
+                                    const LineSet<T>& ls, int line0, int i0, int n, FS fscan, BS bscan) {
+    using C = cx<T>;
+    C a[3], e[3], nam[3], ncp[3], lm[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        a[q] = ls.ae[2 * (line0 + q)];
+        e[q] = ls.ae[2 * (line0 + q) + 1];
+        const Piv<T> lim = ls.piv[(size_t)(line0 + q) * (ls.K + 1) + ls.K];
+        lm[q] = lim.m;
+        nam[q] = cneg(lim.am);
+        ncp[q] = cneg(lim.cp);
+    }
+    const bool fast = i0 >= ls.K && i0 + K <= n;
+    // right-hand side of the increment system: r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
+    C r[3][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const C um = (k == 0) ? left[q] : u[q][k - 1];
+            const C up = (k == K - 1) ? right[q] : u[q][k + 1];
+            C t = mul_bm1<T, IMAG>(ls.bm1, u[q][k]);
+            t = cfma(um, a[q], t);
+            t = cfma(up, e[q], t);
+            r[q][k] = cscale(t, (T)-2);
+        }
+    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1}
+    C E[3], P[3], din[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) E[q] = zero_c<C>();
+    if (fast) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                E[q] = cfma(E[q], nam[q], cmul(lm[q], r[q][k]));
+                r[q][k] = E[q];
+            }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[q] = cpow_k<C, K>(nam[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[q] = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            const bool in = i >= 0 && i < n;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (in) {
+                    const Piv<T> pv = piv_at(ls, line0 + q, i);
+                    E[q] = cfma(E[q], cneg(pv.am), cmul(pv.m, r[q][k]));
+                    P[q] = cmul(cneg(pv.am), P[q]);
+                } else {
+                    E[q] = zero_c<C>();
+                    P[q] = zero_c<C>();
+                }
+                r[q][k] = E[q];
+            }
+        }
+    }
+    fscan(P, E, din);
+    // add the carry that enters the block, times the running product of -am
+    if (fast) {
+        C Q[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                Q[q] = cmul(Q[q], nam[q]);
+                r[q][k] = cfma(din[q], Q[q], r[q][k]);
+            }
+    } else {
+        C Q[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    Q[q] = cmul(Q[q], cneg(piv_at(ls, line0 + q, i).am));
+                    r[q][k] = cfma(din[q], Q[q], r[q][k]);
+                }
+            }
+        }
+    }
+    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1}
+    C G[3], R[3], xin[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) G[q] = zero_c<C>();
+    if (fast) {
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                G[q] = cfma(G[q], ncp[q], r[q][k]);
+                r[q][k] = G[q];
+            }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) R[q] = cpow_k<C, K>(ncp[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) R[q] = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            const bool in = i >= 0 && i < n;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (in) {
+                    const C nc = cneg(piv_at(ls, line0 + q, i).cp);
+                    G[q] = cfma(G[q], nc, r[q][k]);
+                    R[q] = cmul(nc, R[q]);
+                } else {
+                    G[q] = zero_c<C>();
+                    R[q] = zero_c<C>();
+                }
+                r[q][k] = G[q];
+            }
+        }
+    }
+    bscan(R, G, xin);
+    if (fast) {
+        C Sx[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                Sx[q] = cmul(Sx[q], ncp[q]);
+                u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
+            }
+    } else {
+        C Sx[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    Sx[q] = cmul(Sx[q], cneg(piv_at(ls, line0 + q, i).cp));
+                    u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
+                }
+            }
+        }
+    }
+}
+
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
 __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
                                                LineSet<T> ls, const double* __restrict__ scale, int G, int R) {
     using C = cx<T>;
-    __shared__ C shA[16 * 8];
-    __shared__ C shB[16 * 8];
+    __shared__ C shS[6 * 16];
     __shared__ C shN[2 * 3 * 16];
     const int tid = threadIdx.x;
     const int r = tid / G, t = tid - r * G;
@@ -228,12 +378,19 @@ __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx
         if (lane == 63) right[q] = (w + 1 < nw) ? shN[48 + (nrow + w + 1) * 3 + q] : zero_c<C>();
     }
     const int jl = row_ok ? j : 0;
-    C* sa = shA + 8 * r;
-    C* sb = shB + 8 * r;
-    auto fs = [&](C P, C E) { return row_scan<true>(P, E, lane, w, nw, sa, sb); };
-    auto bs = [&](C P, C E) { return row_scan<false>(P, E, lane, w, nw, sa, sb); };
+    C* ss = shS + 6 * nrow;
+    if constexpr (sizeof(T) * K <= 32) {
+        // the three lines' chains interleaved (fits the register file for small blocks)
+        auto fs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) { row_scan3<true>(P, E, o, lane, w, nw, ss); };
+        auto bs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) { row_scan3<false>(P, E, o, lane, w, nw, ss); };
+        block_solve3<T, K, IMAG>(v, left, right, ls, jl * 3, i0, nx, fs, bs);
+    } else {
+        // one line after the other
+        auto fs = [&](C P, C E) { return row_scan<true>(P, E, lane, w, nw, ss, ss + nw); };
+        auto bs = [&](C P, C E) { return row_scan<false>(P, E, lane, w, nw, ss, ss + nw); };
 #pragma unroll
-    for (int q = 0; q < 3; ++q) block_solve<T, K, IMAG>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, fs, bs);
+        for (int q = 0; q < 3; ++q) block_solve<T, K, IMAG>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, fs, bs);
+    }
 #pragma unroll
     for (int k = 0; k < K; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
     if (row_ok && i0 + K <= nx) {
@@ -267,34 +424,11 @@ __device__ inline double block_sum(double v, double* sh) {
     return s;
 }
 
-// Norm reduction finished by the last block to arrive: every block stores its
-// partial sum, then takes a ticket; the block that draws the last ticket sums
-// the partials in block order (deterministic), writes scale = 1/sqrt(dx dy sum)
-// and re-arms the ticket counter for the next launch.
-__device__ inline void finish_norm(double part, double* sh, NormOut no) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        no.partials[blockIdx.x] = part;
-        __threadfence();
-        const unsigned int tk = atomicAdd(no.ticket, 1u);
-        last = (tk == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double acc = 0;
-    for (int k = threadIdx.x; k < (int)gridDim.x; k += blockDim.x) acc += no.partials[k];
-    const double tot = block_sum(acc, sh);
-    if (threadIdx.x == 0) {
-        const double nn = tot * no.dxdy;
-        if (nn > 0.0 && isfinite(nn)) {
-            *no.scale = 1.0 / sqrt(nn);
-        } else {
-            *no.scale = 1.0;
-            *no.flag = 1;
-        }
-        *no.ticket = 0u;
-    }
+// Per-block partial sum of the imaginary-time norm, in block order; a one-block
+// kernel launched next on the same stream forms the total (a device-wide
+// release fence per block would write back the L2 of its XCD every time).
+__device__ inline void store_norm_partial(double part, NormOut no) {
+    if (threadIdx.x == 0) no.partials[blockIdx.x] = part;
 }
 
 // ---------------------------------------------------------------------------
@@ -340,10 +474,9 @@ __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ 
         dn[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
     }
     const int il = col_ok ? i : 0;
-    auto fs = [&](C P, C E) { return seg16_scan<true>(P, E); };
-    auto bs = [&](C P, C E) { return seg16_scan<false>(P, E); };
-#pragma unroll
-    for (int q = 0; q < 3; ++q) block_solve<T, KY, IMAG>(v[q], up[q], dn[q], ls, il * 3 + q, g0, ny, fs, bs);
+    auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan3<true>(P, E, o); };
+    auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan3<false>(P, E, o); };
+    block_solve3<T, KY, IMAG>(v, up, dn, ls, il * 3, g0, ny, fs, bs);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     double acc = 0;
@@ -359,7 +492,7 @@ __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ 
             }
         }
     }
-    if (NORM) finish_norm(block_sum(acc, shr), shr, no);
+    if (NORM) store_norm_partial(block_sum(acc, shr), no);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,7 +567,7 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
             }
         }
     }
-    if (NORM) finish_norm(block_sum(acc, shr), shr, no);
+    if (NORM) store_norm_partial(block_sum(acc, shr), no);
 }
 
 // ---------------------------------------------------------------------------
@@ -599,50 +732,52 @@ __global__ __launch_bounds__(256) void k_obs_finalize(const double* __restrict__
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+
 template <typename T, bool IMAG, bool LOCAL, bool SCALE>
 static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph, const LineSet<T>& ls,
-                             const double* scale, int G, int R, hipStream_t st) {
+                             const double* scale, int G, int R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nblk = (ph.ny + R - 1) / R;
     const dim3 grid(nblk), block(G * R);
     if (G * R > xk_bound(K) || G % 64 || G / 64 > 16 || R > 8) return hipErrorInvalidValue;
+
     switch (K) {
-        case 1: k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 2: k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 4: k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 8: k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
-        case 16: k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)><<<grid, block, 0, st>>>(src, dst, ph, ls, scale, G, R); break;
+        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_x(const XLaunch<T>& a, hipStream_t st) {
+hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (a.imag) {
-        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
-        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
+        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
     }
-    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
-    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st);
+    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
 }
 
 template <typename T, bool IMAG, bool NORM, int TI>
-static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st) {
+static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     constexpr YTile yt = ytile<T>(TI);
     const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
-    k_y_window<T, IMAG, yt.KY, yt.NW, NORM><<<dim3(ncs * nrt), dim3(64 * yt.NW), 0, st>>>(a.src, a.dst, a.ph, a.ls,
-                                                                                        a.L, a.h, ncs, a.no);
+    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, NORM>, dim3(ncs * nrt), dim3(64 * yt.NW), 0, st, e0, e1, 0,
+                          a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no);
     return hipGetLastError();
 }
 
 template <typename T, bool IMAG, bool NORM>
-static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st) {
+static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     switch (a.tile) {
-        case 0: return launch_yw_t<T, IMAG, NORM, 0>(a, st);
-        case 1: return launch_yw_t<T, IMAG, NORM, 1>(a, st);
-        case 2: return launch_yw_t<T, IMAG, NORM, 2>(a, st);
-        case 3: return launch_yw_t<T, IMAG, NORM, 3>(a, st);
+        case 0: return launch_yw_t<T, IMAG, NORM, 0>(a, st, e0, e1);
+        case 1: return launch_yw_t<T, IMAG, NORM, 1>(a, st, e0, e1);
+        case 2: return launch_yw_t<T, IMAG, NORM, 2>(a, st, e0, e1);
+        case 3: return launch_yw_t<T, IMAG, NORM, 3>(a, st, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -658,18 +793,18 @@ int y_blocks(const YLaunch<T>& a) {
 }
 
 template <typename T>
-hipError_t launch_y(const YLaunch<T>& a, hipStream_t st) {
+hipError_t launch_y(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (a.window) {
-        if (a.imag) return a.norm ? launch_yw<T, true, true>(a, st) : launch_yw<T, true, false>(a, st);
-        return a.norm ? launch_yw<T, false, true>(a, st) : launch_yw<T, false, false>(a, st);
+        if (a.imag) return a.norm ? launch_yw<T, true, true>(a, st, e0, e1) : launch_yw<T, true, false>(a, st, e0, e1);
+        return a.norm ? launch_yw<T, false, true>(a, st, e0, e1) : launch_yw<T, false, false>(a, st, e0, e1);
     }
     const dim3 grid((a.ph.nx + 255) / 256), block(256);
     if (a.imag) {
-        if (a.norm) k_y_thomas<T, true, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
-        else k_y_thomas<T, true, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
+        if (a.norm) hipExtLaunchKernelGGL(k_y_thomas<T, true, true>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+        else hipExtLaunchKernelGGL(k_y_thomas<T, true, false>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
     } else {
-        if (a.norm) k_y_thomas<T, false, true><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
-        else k_y_thomas<T, false, false><<<grid, block, 0, st>>>(a.src, a.dst, a.ph, a.ls, a.no);
+        if (a.norm) hipExtLaunchKernelGGL(k_y_thomas<T, false, true>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+        else hipExtLaunchKernelGGL(k_y_thomas<T, false, false>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
     }
     return hipGetLastError();
 }
@@ -684,9 +819,9 @@ hipError_t launch_local(cx<T>* psi, const Phys& ph, bool imag, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_scale(cx<T>* psi, size_t n, const double* scale, hipStream_t st) {
+hipError_t launch_scale(cx<T>* psi, size_t n, const double* scale, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const int nblk = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
-    k_scale<T><<<nblk, 256, 0, st>>>(psi, n, scale);
+    hipExtLaunchKernelGGL(k_scale<T>, dim3(nblk), dim3(256), 0, st, e0, e1, 0, psi, n, scale);
     return hipGetLastError();
 }
 
@@ -701,8 +836,9 @@ hipError_t launch_set_scale(double* scale, double v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, double* scale, int* flag, hipStream_t st) {
-    k_norm_finalize<<<1, 256, 0, st>>>(partials, n, dxdy, scale, flag);
+hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, double* scale, int* flag, hipStream_t st,
+                                hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, e0, e1, 0, partials, n, dxdy, scale, flag);
     return hipGetLastError();
 }
 
@@ -720,11 +856,11 @@ hipError_t launch_obs_finalize(const double* partials, int nblk, double* out, hi
 }
 
 #define GP_INST(T)                                                                                             \
-    template hipError_t launch_x<T>(const XLaunch<T>&, hipStream_t);                                           \
-    template hipError_t launch_y<T>(const YLaunch<T>&, hipStream_t);                                           \
+    template hipError_t launch_x<T>(const XLaunch<T>&, hipStream_t, hipEvent_t, hipEvent_t);                   \
+    template hipError_t launch_y<T>(const YLaunch<T>&, hipStream_t, hipEvent_t, hipEvent_t);                   \
     template int y_blocks<T>(const YLaunch<T>&);                                                               \
     template hipError_t launch_local<T>(cx<T>*, const Phys&, bool, hipStream_t);                               \
-    template hipError_t launch_scale<T>(cx<T>*, size_t, const double*, hipStream_t);                           \
+    template hipError_t launch_scale<T>(cx<T>*, size_t, const double*, hipStream_t, hipEvent_t, hipEvent_t);   \
     template hipError_t launch_norm_partials<T>(const cx<T>*, size_t, double*, int, hipStream_t);              \
     template hipError_t launch_obs<T>(const cx<T>*, const Phys&, const ObsLaunch&, T*, double*, int, hipStream_t);
 GP_INST(double)

@@ -27,15 +27,11 @@ __host__ __device__ constexpr int xk_bound(int K) { return K == 1 ? 1024 : 512; 
 
 // Both sweeps run out of place (src -> dst): the y windows overlap, so a
 // window's halo rows must not be rewritten by its neighbour while it reads.
-// Where the y sweep leaves the imaginary-time norm: per-block partial sums,
-// a ticket counter (zero between launches), the resulting scale factor and the
-// non-finite flag.
+// Where the y sweep leaves the imaginary-time norm: one partial sum per block
+// (summed by launch_norm_finalize into the scale factor and the non-finite
+// flag).
 struct NormOut {
     double* partials;
-    unsigned int* ticket;
-    double* scale;
-    int* flag;
-    double dxdy;
 };
 
 template <typename T> struct XLaunch {
@@ -63,15 +59,22 @@ struct ObsLaunch {
     int eta;
 };
 
-template <typename T> hipError_t launch_x(const XLaunch<T>& a, hipStream_t st);
-template <typename T> hipError_t launch_y(const YLaunch<T>& a, hipStream_t st);
+// The sweep, scale and norm launchers take an optional event pair that the
+// dispatch itself stamps at kernel start and end (per-kernel timing).
+template <typename T>
+hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+template <typename T>
+hipError_t launch_y(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T> int y_blocks(const YLaunch<T>& a);
 template <typename T> hipError_t launch_local(cx<T>* psi, const Phys& ph, bool imag, hipStream_t st);
-template <typename T> hipError_t launch_scale(cx<T>* psi, size_t n, const double* scale, hipStream_t st);
+template <typename T>
+hipError_t launch_scale(cx<T>* psi, size_t n, const double* scale, hipStream_t st, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_norm_partials(const cx<T>* psi, size_t n, double* partials, int nblk, hipStream_t st);
 hipError_t launch_set_scale(double* scale, double v, hipStream_t st);
-hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, double* scale, int* flag, hipStream_t st);
+hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, double* scale, int* flag, hipStream_t st,
+                                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_obs(const cx<T>* psi, const Phys& ph, const ObsLaunch& o, T* dens, double* partials, int nblk,
                       hipStream_t st);

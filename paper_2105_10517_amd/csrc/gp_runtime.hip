@@ -49,7 +49,6 @@ struct gp_spin1 {
     ModeState mode[2];  // [0] real time, [1] imaginary time
     double* d_scale = nullptr;
     int* d_flag = nullptr;
-    unsigned int* d_ticket = nullptr;  // zero between launches (the last block re-arms it)
     double* d_part = nullptr;
     size_t n_part = 0;
     double* d_obs = nullptr;
@@ -362,7 +361,6 @@ void destroy_all(gp_spin1* h) {
     for (auto& m : h->mode) { free_dir(m.x); free_dir(m.y); }
     if (h->d_scale) (void)hipFree(h->d_scale);
     if (h->d_flag) (void)hipFree(h->d_flag);
-    if (h->d_ticket) (void)hipFree(h->d_ticket);
     if (h->d_part) (void)hipFree(h->d_part);
     if (h->d_obs) (void)hipFree(h->d_obs);
     if (h->d_work) (void)hipFree(h->d_work);
@@ -508,7 +506,6 @@ int create_t(gp_spin1* h) {
     if (hipMalloc(&h->d_part, need * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_scale, sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_flag, sizeof(int)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
-    if (hipMalloc(&h->d_ticket, sizeof(unsigned int)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_obs, gp::kObsCount * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_work, (size_t)3 * p.nx * p.ny * sizeof(gp::cx<T>)) != hipSuccess)
         return fail(h, GP_ENOMEM, "work buffer allocation failed");
@@ -517,7 +514,6 @@ int create_t(gp_spin1* h) {
     hipError_t e;
     if ((e = hipMemcpy(h->d_scale, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
-    if ((e = hipMemcpy(h->d_ticket, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     if (p.autotune) {
         int rc = autotune_t<T>(h);
         if (rc) return rc;
@@ -548,10 +544,6 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.ph = phys(h->p);
     a.ls = lineset<T>(ms.y);
     a.no.partials = h->d_part;
-    a.no.ticket = h->d_ticket;
-    a.no.scale = h->d_scale;
-    a.no.flag = h->d_flag;
-    a.no.dxdy = h->p.dx * h->p.dy;
     a.L = ms.L; a.h = ms.h; a.tile = ms.ytile;
     a.window = ms.window; a.imag = imag; a.norm = norm;
     return a;
@@ -574,10 +566,11 @@ hipError_t timing_drain(gp_spin1* h) {
     return hipSuccess;
 }
 
-// Launch f() bracketed by an event pair of kind k when timing is on.
+// Launch f(start, stop) with an event pair of kind k that the dispatch stamps
+// at kernel start and end when timing is on (null events otherwise).
 template <typename F>
 hipError_t timed(gp_spin1* h, int k, F f) {
-    if (!h->timing) return f();
+    if (!h->timing) return f(nullptr, nullptr);
     if (h->ev_next + 2 > 4096) {
         hipError_t e = timing_drain(h);
         if (e != hipSuccess) return e;
@@ -590,11 +583,7 @@ hipError_t timed(gp_spin1* h, int k, F f) {
     }
     hipEvent_t a = h->ev_pool[h->ev_next], b = h->ev_pool[h->ev_next + 1];
     h->ev_next += 2;
-    hipError_t e = hipEventRecord(a, h->stream);
-    if (e != hipSuccess) return e;
-    e = f();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, h->stream);
+    hipError_t e = f(a, b);
     if (e != hipSuccess) return e;
     h->ev_open.push_back({k, {a, b}});
     return hipSuccess;
@@ -608,16 +597,20 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     hipStream_t st = h->stream;
     const gp::XLaunch<T> xa = xlaunch<T>(h, psi, h->d_work, imag, true);
     const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, psi, imag, imag);
+    const int nyb = gp::y_blocks<T>(ya);
+    const double dxdy = h->p.dx * h->p.dy;
     hipError_t e;
     if (imag && (e = gp::launch_set_scale(h->d_scale, 1.0, st)) != hipSuccess) return hip_fail(h, e, "set_scale");
     for (int64_t s = 0; s < n; ++s) {
-        if ((e = timed(h, 0, [&] { return gp::launch_x<T>(xa, st); })) != hipSuccess) return hip_fail(h, e, "x sweep launch");
-        // the y sweep also finishes the norm and the scale (last block to arrive)
-        if ((e = timed(h, 1, [&] { return gp::launch_y<T>(ya, st); })) != hipSuccess) return hip_fail(h, e, "y sweep launch");
+        if ((e = timed(h, 0, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_x<T>(xa, st, a, b); })) != hipSuccess) return hip_fail(h, e, "x sweep launch");
+        // the y sweep leaves per-block norm partials; one block sums them into the scale
+        if ((e = timed(h, 1, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_y<T>(ya, st, a, b); })) != hipSuccess) return hip_fail(h, e, "y sweep launch");
+        if (imag && (e = timed(h, 2, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_norm_finalize(h->d_part, nyb, dxdy, h->d_scale, h->d_flag, st, a, b); })) != hipSuccess)
+            return hip_fail(h, e, "norm launch");
     }
     if (imag) {
         const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
-        if ((e = timed(h, 3, [&] { return gp::launch_scale<T>((gp::cx<T>*)psi, n3, h->d_scale, st); })) != hipSuccess)
+        if ((e = timed(h, 3, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_scale<T>((gp::cx<T>*)psi, n3, h->d_scale, st, a, b); })) != hipSuccess)
             return hip_fail(h, e, "scale launch");
     }
     return GP_OK;

@@ -120,11 +120,93 @@ __device__ inline C row_scan(C P, C E, int lane, int w, int nw, C* shP, C* shE) 
     return FWD ? dpp_c<0x138>(din, val) : dpp_c<0x130>(din, val);  // wave_shr:1 / wave_shl:1
 }
 
-// Exclusive scan across the 16 lanes of a DPP row (segments of one column in
-// the y sweep): no shared memory, no barrier.
-template <bool FWD, typename C> __device__ inline C seg16_scan(C P, C E) {
-    const Aff<C> a = row16_incl<FWD>(Aff<C>{P, E});
-    return FWD ? dpp_c<0x111>(zero_c<C>(), a.E) : dpp_c<0x101>(zero_c<C>(), a.E);
+// Exclusive scans of the three eigencomponent lines at once (the three chains
+// are independent, so their lane moves and compositions interleave).
+template <bool FWD, typename C> __device__ inline void row16_incl3(Aff<C> (&a)[3]) {
+#define GP_STAGE(CTRL)                                                        \
+    {                                                                         \
+        Aff<C> s[3];                                                          \
+        _Pragma("unroll") for (int q = 0; q < 3; ++q) s[q] = dpp_aff<CTRL>(a[q]); \
+        _Pragma("unroll") for (int q = 0; q < 3; ++q) a[q] = compose(a[q], s[q]); \
+    }
+    if (FWD) {
+        GP_STAGE(0x111) GP_STAGE(0x112) GP_STAGE(0x114) GP_STAGE(0x118)  // row_shr:1,2,4,8
+    } else {
+        GP_STAGE(0x101) GP_STAGE(0x102) GP_STAGE(0x104) GP_STAGE(0x108)  // row_shl:1,2,4,8
+    }
+#undef GP_STAGE
+}
+
+// Inclusive scan over the 64 lanes of a wave, three maps at once.
+template <bool FWD, typename C> __device__ inline void wave_incl3(Aff<C> (&a)[3], int lane) {
+    row16_incl3<FWD>(a);
+    const int row = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        Aff<C> pre = aff_id<C>();
+        if (FWD) {
+            // prefix of the rows below: S_1 = T_0, S_2 = T_1 o T_0, S_3 = T_2 o T_1 o T_0
+            const Aff<C> t0 = readlane_aff(a[q], 15), t1 = readlane_aff(a[q], 31), t2 = readlane_aff(a[q], 47);
+            const Aff<C> s2 = compose(t1, t0), s3 = compose(t2, s2);
+            if (row == 1) pre = t0;
+            if (row == 2) pre = s2;
+            if (row == 3) pre = s3;
+        } else {
+            const Aff<C> t1 = readlane_aff(a[q], 16), t2 = readlane_aff(a[q], 32), t3 = readlane_aff(a[q], 48);
+            const Aff<C> s1 = compose(t2, t3), s0 = compose(t1, s1);
+            if (row == 0) pre = s0;
+            if (row == 1) pre = s1;
+            if (row == 2) pre = t3;
+        }
+        a[q] = compose(a[q], pre);
+    }
+}
+
+// Exclusive scan over the G = 64 * nw threads of one row (thread t = 64 w +
+// lane) for the three lines: out[q] is the composite of the maps before this
+// thread (FWD) or after it (backward) applied to a zero carry.  sh: >= 6 nw
+// entries of shared memory private to the row.  Every thread of the block
+// must call it.
+template <bool FWD, typename C>
+__device__ inline void row_scan3(const C (&P)[3], const C (&E)[3], C (&out)[3], int lane, int w, int nw, C* sh) {
+    Aff<C> a[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a[q] = Aff<C>{P[q], E[q]};
+    wave_incl3<FWD>(a, lane);
+    C din[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
+    if (nw > 1) {
+        if (lane == (FWD ? 63 : 0)) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) { sh[(2 * q) * nw + w] = a[q].P; sh[(2 * q + 1) * nw + w] = a[q].E; }
+        }
+        __syncthreads();
+        if (FWD) {
+            for (int v = 0; v < w; ++v)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) din[q] = cfma(din[q], sh[(2 * q) * nw + v], sh[(2 * q + 1) * nw + v]);
+        } else {
+            for (int v = nw - 1; v > w; --v)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) din[q] = cfma(din[q], sh[(2 * q) * nw + v], sh[(2 * q + 1) * nw + v]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const C val = cfma(din[q], a[q].P, a[q].E);  // inclusive map applied to the carry into the wave
+        out[q] = FWD ? dpp_c<0x138>(din[q], val) : dpp_c<0x130>(din[q], val);  // wave_shr:1 / wave_shl:1
+    }
+}
+
+// Exclusive scans across the 16 lanes of a DPP row (segments of one column in
+// the y sweep) for the three lines: no shared memory, no barrier.
+template <bool FWD, typename C> __device__ inline void seg16_scan3(const C (&P)[3], const C (&E)[3], C (&out)[3]) {
+    Aff<C> a[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a[q] = Aff<C>{P[q], E[q]};
+    row16_incl3<FWD>(a);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) out[q] = FWD ? dpp_c<0x111>(zero_c<C>(), a[q].E) : dpp_c<0x101>(zero_c<C>(), a[q].E);
 }
 
 }  // namespace gp
