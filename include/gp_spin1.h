@@ -182,6 +182,58 @@ int gp_spin1_timing_read(gp_spin1_t* h, gp_spin1_timing* out);
 const char* gp_spin1_strerror(int status);
 const char* gp_spin1_last_error(const gp_spin1_t* h); /* per-handle message of the last failure */
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent condensates.  The paper's workflows run many
+ * separate SSCN solutions (parameter scans of Omega, couplings and SO type,
+ * imaginary- then real-time runs, Sec. "Numerical results" of the
+ * Supplementary Material); a batch advances such condensates together, each
+ * with its own grid, spacings, time step, couplings and propagation mode, in
+ * one kernel launch per sweep over the rows and column tiles of all of them.
+ * Each condensate follows exactly the step of gp_spin1_step_imag /
+ * gp_spin1_step_real; results equal those of a single handle created with
+ * the batch's x_points and y_tile (gp_spin1_batch_info) bit for bit.
+ *
+ * gp_spin1_batch_create: p is an array of n parameter sets (n >= 1), one per
+ *   slot; an entry with nx == 0 leaves its slot empty.  Every entry carries
+ *   the same precision.  Each slot owns the tables and scratch of a single
+ *   handle (allocated here, freed by set_slot / destroy).  Work runs on
+ *   hip_stream.  GP_EINVAL / GP_EUNSUPPORTED as gp_spin1_create.
+ * gp_spin1_batch_set_slot: replaces the condensate of one slot (admission of a
+ *   new request); p == NULL or p->nx == 0 empties it.  Waits for the stream
+ *   when it frees the old slot's tables.
+ * gp_spin1_batch_step: psi_dev[s] is the device wave function of slot s in
+ *   the layout above (complex128 / complex64 by the batch precision);
+ *   nsteps[s] >= 0 steps in mode[s] (0 imaginary time, renormalised every
+ *   step; 1 real time); active (nullable) masks slots out.  Slots whose
+ *   windowed y sweep does not fit the batch tile run on their own, on the
+ *   same stream.  Asynchronous like gp_spin1_step_*; psi_dev arrays may be
+ *   reused as soon as the call returns.  Calls that overlap on one batch are
+ *   not allowed (a batch is not thread-safe).
+ * gp_spin1_batch_sync: waits for the stream; GP_ENONFINITE names the slot
+ *   whose imaginary-time norm was not finite.
+ * gp_spin1_batch_observables: gp_spin1_observables for one slot.
+ * gp_spin1_batch_info_read: the launch shape of the last batch_step call. */
+typedef struct gp_spin1_batch gp_spin1_batch_t;
+typedef struct {                 /* [0] imaginary-time launches, [1] real-time launches (0 if none) */
+    int32_t x_points[2]; /* points per thread of the batched x sweep */
+    int32_t x_block[2];  /* threads per block of the batched x sweep */
+    int32_t y_tile[2];   /* 1-based y tile of the batched y sweep */
+    int32_t grouped;     /* condensates that ran in the batched launches */
+    int32_t individual;  /* condensates that ran on their own plan */
+    int32_t phases;      /* groups of steps with a fixed set of condensates */
+    int64_t launches;    /* batched sweep and norm launches */
+} gp_spin1_batch_info;
+int gp_spin1_batch_create(const gp_spin1_params* p, int32_t n, void* hip_stream, gp_spin1_batch_t** out);
+int gp_spin1_batch_set_slot(gp_spin1_batch_t* b, int32_t slot, const gp_spin1_params* p);
+int gp_spin1_batch_step(gp_spin1_batch_t* b, void* const* psi_dev, const int64_t* nsteps, const int32_t* mode,
+                        const uint8_t* active);
+int gp_spin1_batch_sync(gp_spin1_batch_t* b);
+int gp_spin1_batch_observables(gp_spin1_batch_t* b, int32_t slot, const void* psi_dev, gp_spin1_obs* out_host,
+                               void* dens_dev);
+int gp_spin1_batch_info_read(const gp_spin1_batch_t* b, gp_spin1_batch_info* out);
+int gp_spin1_batch_destroy(gp_spin1_batch_t* b);
+const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b);
+
 #ifdef __cplusplus
 }
 #endif

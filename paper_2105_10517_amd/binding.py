@@ -24,7 +24,10 @@ SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
 EXPORTS = ("gp_spin1_create", "gp_spin1_destroy", "gp_spin1_step_imag", "gp_spin1_step_real",
            "gp_spin1_substep", "gp_spin1_observables", "gp_spin1_sync", "gp_spin1_get_plan",
            "gp_spin1_plan_query", "gp_spin1_timing_enable", "gp_spin1_timing_read",
-           "gp_spin1_strerror", "gp_spin1_last_error")
+           "gp_spin1_strerror", "gp_spin1_last_error",
+           "gp_spin1_batch_create", "gp_spin1_batch_set_slot", "gp_spin1_batch_step", "gp_spin1_batch_sync",
+           "gp_spin1_batch_observables", "gp_spin1_batch_info_read", "gp_spin1_batch_destroy",
+           "gp_spin1_batch_last_error")
 
 
 class LibraryNotBuilt(RuntimeError):
@@ -72,6 +75,12 @@ class Plan(ctypes.Structure):
                 ("stable", ctypes.c_int32)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("x_points", ctypes.c_int32 * 2), ("x_block", ctypes.c_int32 * 2), ("y_tile", ctypes.c_int32 * 2),
+                ("grouped", ctypes.c_int32), ("individual", ctypes.c_int32), ("phases", ctypes.c_int32),
+                ("launches", ctypes.c_int64)]
+
+
 _lib = None
 
 
@@ -97,6 +106,16 @@ def load():
         "gp_spin1_timing_enable": [vp, i32],
         "gp_spin1_timing_read": [vp, ctypes.POINTER(Timing)],
     }
+    sig.update({
+        "gp_spin1_batch_create": [ctypes.POINTER(Params), i32, vp, ctypes.POINTER(vp)],
+        "gp_spin1_batch_set_slot": [vp, i32, ctypes.POINTER(Params)],
+        "gp_spin1_batch_step": [vp, ctypes.POINTER(vp), ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                ctypes.POINTER(ctypes.c_uint8)],
+        "gp_spin1_batch_sync": [vp],
+        "gp_spin1_batch_observables": [vp, i32, vp, ctypes.POINTER(Obs), vp],
+        "gp_spin1_batch_info_read": [vp, ctypes.POINTER(BatchInfo)],
+        "gp_spin1_batch_destroy": [vp],
+    })
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
@@ -105,6 +124,8 @@ def load():
     lib.gp_spin1_strerror.restype = ctypes.c_char_p
     lib.gp_spin1_last_error.argtypes = [vp]
     lib.gp_spin1_last_error.restype = ctypes.c_char_p
+    lib.gp_spin1_batch_last_error.argtypes = [vp]
+    lib.gp_spin1_batch_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -211,6 +232,108 @@ class Solver:
     def close(self):
         if self._h:
             self._lib.gp_spin1_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+MODES = {"imag": 0, "real": 1, 0: 0, 1: 1}
+
+
+class Batch:
+    """Independent condensates advanced together (one launch per sweep over
+    all of them).  ``params`` holds one parameter mapping per slot, or None
+    for an empty slot; every slot has the batch precision."""
+
+    def __init__(self, params, precision: str = "fp64", stream=None):
+        import torch
+        self._lib = load()
+        self.precision = precision
+        self.n = len(params)
+        self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.params = [dict(p) if p is not None else None for p in params]
+        arr = (Params * self.n)(*[self._mk(p) for p in params])
+        self._h = ctypes.c_void_p()
+        rc = self._lib.gp_spin1_batch_create(arr, self.n, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
+        if rc != GP_OK:
+            raise GPError(rc, "gp_spin1_batch_create: " + self._lib.gp_spin1_strerror(rc).decode())
+
+    def _mk(self, p):
+        if p is None:
+            q = Params()
+            q.precision = {"fp64": GP_FP64, "fp32": GP_FP32}[self.precision]
+            return q
+        return make_params(p, self.precision)
+
+    def _check(self, rc, what):
+        if rc != GP_OK:
+            msg = self._lib.gp_spin1_batch_last_error(self._h).decode()
+            raise GPError(rc, f"{what}: {self._lib.gp_spin1_strerror(rc).decode()}: {msg}")
+
+    def set_slot(self, slot: int, p):
+        q = self._mk(p)
+        self._check(self._lib.gp_spin1_batch_set_slot(self._h, int(slot), ctypes.byref(q)), "batch_set_slot")
+        self.params[slot] = dict(p) if p is not None else None
+
+    def _psi(self, slot, psi):
+        p = self.params[slot]
+        if p is None:
+            return psi.data_ptr()  # the library reports the empty slot
+        shape = (3, int(p["ny"]), int(p["nx"]))
+        if psi.dtype != self.dtype or tuple(psi.shape) != shape or not psi.is_contiguous() or not psi.is_cuda:
+            raise ValueError(f"slot {slot}: psi must be a contiguous CUDA {self.dtype} tensor of shape {shape}")
+        return psi.data_ptr()
+
+    def step(self, psis, nsteps, modes, active=None):
+        """psis[s]: tensor or None (slot skipped); nsteps[s] >= 0; modes[s] in
+        {'imag', 'real', 0, 1}; active: optional sequence of booleans."""
+        n = self.n
+        ptrs = (ctypes.c_void_p * n)()
+        ns = (ctypes.c_int64 * n)()
+        md = (ctypes.c_int32 * n)()
+        ac = (ctypes.c_uint8 * n)()
+        for s in range(n):
+            on = psis[s] is not None and (active is None or bool(active[s])) and int(nsteps[s]) > 0
+            ac[s] = 1 if on else 0
+            ns[s] = int(nsteps[s]) if on else 0
+            md[s] = MODES[modes[s]] if on else 0
+            ptrs[s] = self._psi(s, psis[s]) if on else None
+        self._check(self._lib.gp_spin1_batch_step(self._h, ptrs, ns, md, ac), "batch_step")
+
+    def sync(self):
+        self._check(self._lib.gp_spin1_batch_sync(self._h), "batch_sync")
+
+    def observables(self, slot: int, psi) -> dict:
+        o = Obs()
+        self._check(self._lib.gp_spin1_batch_observables(self._h, int(slot), ctypes.c_void_p(self._psi(slot, psi)),
+                                                         ctypes.byref(o), None), "batch_observables")
+        return _obs_dict(o)
+
+    def info(self) -> dict:
+        b = BatchInfo()
+        self._check(self._lib.gp_spin1_batch_info_read(self._h, ctypes.byref(b)), "batch_info_read")
+        out = {}
+        for k, _ in BatchInfo._fields_:
+            v = getattr(b, k)
+            out[k] = list(v) if k in ("x_points", "x_block", "y_tile") else v
+        return out
+
+    def close(self):
+        if self._h:
+            self._lib.gp_spin1_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

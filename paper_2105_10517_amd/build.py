@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgp_spin1.so")
-SOURCES = ["gp_kernels.hip", "gp_runtime.hip"]
+SOURCES = ["gp_xsweep.hip", "gp_ysweep.hip", "gp_misc.hip", "gp_runtime.hip"]
 ARCH = os.environ.get("GP_OFFLOAD_ARCH", "gfx950")
 
 

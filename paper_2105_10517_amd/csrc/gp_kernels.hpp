@@ -54,6 +54,45 @@ template <typename T> struct YLaunch {
     bool window, imag, norm;
 };
 
+// Batched launches: one descriptor per condensate and one map entry per block,
+// (condensate << kMapShift) | (block index within that condensate).
+constexpr unsigned kMapShift = 20;
+constexpr unsigned kMapMask = (1u << kMapShift) - 1;
+constexpr int kMaxBatchSlots = 1 << (32 - kMapShift);
+constexpr int kScaleChunk = 4096;  // values per block of the batched scale kernel
+
+template <typename T> struct XSlot {
+    const cx<T>* src;
+    cx<T>* dst;
+    Phys ph;
+    LineSet<T> ls;
+    const double* scale;
+    int G, R;
+};
+
+template <typename T> struct YSlot {
+    const cx<T>* src;
+    cx<T>* dst;
+    Phys ph;
+    LineSet<T> ls;
+    double* partials;
+    int L, h, ncs;
+};
+
+struct NSlot {
+    const double* partials;
+    int n;
+    double dxdy;
+    double* scale;
+    int* flag;
+};
+
+template <typename T> struct SSlot {
+    cx<T>* psi;
+    size_t n;
+    const double* scale;
+};
+
 struct ObsLaunch {
     double c0, c2, rabi, gamma, omega;
     int eta;
@@ -79,5 +118,19 @@ template <typename T>
 hipError_t launch_obs(const cx<T>* psi, const Phys& ph, const ObsLaunch& o, T* dens, double* partials, int nblk,
                       hipStream_t st);
 hipError_t launch_obs_finalize(const double* partials, int nblk, double* out, hipStream_t st);
+
+// Batched forms: the x sweep (local substep fused; imaginary time also applies
+// each condensate's pending scale) and the windowed y sweep (imaginary time
+// stores norm partials) over the map's blocks; per-condensate norm totals,
+// scale resets and final scaling.
+template <typename T>
+hipError_t launch_x_batch(const XSlot<T>* slots, const unsigned* map, int nblk, int K, int block, bool imag,
+                          hipStream_t st);
+template <typename T>
+hipError_t launch_y_batch(const YSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st);
+hipError_t launch_set_scale_batch(const NSlot* slots, int n, double v, hipStream_t st);
+hipError_t launch_norm_finalize_batch(const NSlot* slots, int n, hipStream_t st);
+template <typename T>
+hipError_t launch_scale_batch(const SSlot<T>* slots, const unsigned* map, int nblk, hipStream_t st);
 
 }  // namespace gp

@@ -672,11 +672,9 @@ int obs_t(gp_spin1* h, const void* psi, gp_spin1_obs* out, void* dens) {
     return GP_OK;
 }
 
-}  // namespace
 
-extern "C" {
-
-int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out) {
+// A handle from validated parameters (also the slots of a batch).
+int make_handle(const gp_spin1_params* p, hipStream_t st, gp_spin1** out) {
     if (!out) return GP_EINVAL;
     std::string why;
     int rc = validate(p, why);
@@ -686,12 +684,268 @@ int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out
     h->p = *p;
     if (std::isnan(h->p.x0)) h->p.x0 = -0.5 * h->p.nx * h->p.dx;
     if (std::isnan(h->p.y0)) h->p.y0 = -0.5 * h->p.ny * h->p.dy;
-    h->stream = (hipStream_t)hip_stream;
+    h->stream = st;
     if (hipGetDevice(&h->device) != hipSuccess) { destroy_all(h); return GP_EHIP; }
     rc = h->p.precision == GP_FP64 ? create_t<double>(h) : create_t<float>(h);
     if (rc) { destroy_all(h); return rc; }
     *out = h;
     return GP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batches: independent condensates (own grid, couplings, time step and mode)
+// advanced together.  Every sweep is one launch over the rows / column tiles
+// of all condensates that share the batch's launch shape; a condensate whose
+// y windows do not fit the batch tile runs on its own handle (same stream).
+// ---------------------------------------------------------------------------
+struct gp_spin1_batch {
+    int n = 0;
+    int precision = GP_FP64;
+    hipStream_t stream = nullptr;
+    std::vector<gp_spin1*> slot;  // nullptr: empty slot
+    void* h_stage = nullptr;      // pinned host staging of descriptors and block maps
+    size_t h_cap = 0;
+    void* d_stage = nullptr;
+    size_t d_cap = 0;
+    hipEvent_t staged = nullptr;  // recorded after the last upload from h_stage
+    bool staged_pending = false;
+    gp_spin1_batch_info info{};
+    std::string err;
+};
+
+namespace {
+
+int bfail(gp_spin1_batch* b, int code, const std::string& msg) {
+    b->err = msg;
+    return code;
+}
+int bhip(gp_spin1_batch* b, hipError_t e, const std::string& where) {
+    b->err = where + ": " + hipGetErrorString(e);
+    return GP_EHIP;
+}
+
+void batch_free(gp_spin1_batch* b) {
+    for (gp_spin1* h : b->slot)
+        if (h) destroy_all(h);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->d_stage) (void)hipFree(b->d_stage);
+    if (b->staged) (void)hipEventDestroy(b->staged);
+    delete b;
+}
+
+// Append a POD array to the staging image at a 256-byte boundary; returns its offset.
+template <typename V>
+size_t stage_put(std::vector<unsigned char>& img, const std::vector<V>& v) {
+    size_t off = (img.size() + 255) / 256 * 256;
+    img.resize(off + v.size() * sizeof(V));
+    if (!v.empty()) std::memcpy(img.data() + off, v.data(), v.size() * sizeof(V));
+    return off;
+}
+
+// The launch shape shared by a group: x points per thread and block size
+// from the widest row, the y tile that the most condensates can window.
+struct BatchShape {
+    int K = 2, block = 64, tile = 0;
+};
+
+template <typename T>
+BatchShape batch_shape(const std::vector<gp_spin1*>& hs, bool imag) {
+    BatchShape bs;
+    int nxmax = 3;
+    for (gp_spin1* h : hs) nxmax = std::max(nxmax, h->p.nx);
+    bs.K = x_default_k(nxmax);
+    int G, R;
+    x_shape(nxmax, bs.K, G, R);
+    bs.block = G;
+    int best = -1;
+    for (int t = 0; t < gp::kNumYTiles; ++t) {
+        int cnt = 0;
+        for (gp_spin1* h : hs) {
+            const ModeState& ms = h->mode[imag];
+            int hh, L;
+            if (ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(t)), hh, L)) ++cnt;
+        }
+        if (cnt > best) { best = cnt; bs.tile = t; }
+    }
+    return bs;
+}
+
+template <typename T>
+int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, const int32_t* mode,
+                 const uint8_t* active) {
+    using C = gp::cx<T>;
+    hipStream_t st = b->stream;
+    std::vector<int> act;
+    for (int s = 0; s < b->n; ++s) {
+        if (active && !active[s]) continue;
+        if (nsteps[s] < 0) return bfail(b, GP_EINVAL, "slot " + std::to_string(s) + ": nsteps < 0");
+        if (nsteps[s] == 0) continue;
+        if (!b->slot[s]) return bfail(b, GP_EINVAL, "slot " + std::to_string(s) + " is empty");
+        if (!psi[s]) return bfail(b, GP_EINVAL, "slot " + std::to_string(s) + ": psi is NULL");
+        if (mode[s] != 0 && mode[s] != 1) return bfail(b, GP_EINVAL, "slot " + std::to_string(s) + ": mode must be 0 or 1");
+        const ModeState& ms = b->slot[s]->mode[mode[s] == 0];
+        if (!ms.stable) return bfail(b, GP_EUNSTABLE, "slot " + std::to_string(s) + ": " + ms.why);
+        act.push_back(s);
+    }
+    b->info = gp_spin1_batch_info{};
+    if (act.empty()) return GP_OK;
+    // launch shape per mode (index 1 = imaginary time) and the grouped / individual split
+    BatchShape shape[2];
+    std::vector<int> grouped[2];
+    for (int im = 0; im < 2; ++im) {
+        std::vector<gp_spin1*> hs;
+        for (int s : act)
+            if ((mode[s] == 0) == (im == 1)) hs.push_back(b->slot[s]);
+        if (hs.empty()) continue;
+        shape[im] = batch_shape<T>(hs, im == 1);
+    }
+    int64_t maxn = 0;
+    for (int s : act) {
+        const bool im = mode[s] == 0;
+        gp_spin1* h = b->slot[s];
+        const ModeState& ms = h->mode[im];
+        int hh, L, G, R;
+        const bool ok = ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
+                        x_shape(h->p.nx, shape[im].K, G, R) && G <= shape[im].block;
+        if (ok) {
+            grouped[im].push_back(s);
+            maxn = std::max(maxn, nsteps[s]);
+        } else {
+            // on its own handle, with its own plan
+            int rc = steps_t<T>(h, psi[s], nsteps[s], im);
+            if (rc) return bfail(b, rc, "slot " + std::to_string(s) + ": " + h->err);
+            b->info.individual += 1;
+        }
+    }
+    b->info.grouped = (int)(grouped[0].size() + grouped[1].size());
+    for (int md = 0; md < 2; ++md) {
+        const int im = md == 0 ? 1 : 0;  // info index is the ABI mode (0 imaginary)
+        if (grouped[im].empty()) continue;
+        b->info.x_points[md] = shape[im].K;
+        b->info.x_block[md] = shape[im].block;
+        b->info.y_tile[md] = shape[im].tile + 1;
+    }
+    // phases: the grouped condensates still running share each launch
+    int64_t done = 0;
+    while (done < maxn) {
+        int64_t next = maxn;
+        for (int im = 0; im < 2; ++im)
+            for (int s : grouped[im])
+                if (nsteps[s] > done) next = std::min(next, nsteps[s]);
+        const int64_t c = next - done;
+        // descriptors and block maps of this phase
+        std::vector<unsigned char> img;
+        struct GroupTables {
+            size_t xs = 0, ys = 0, ns = 0, ss = 0, xm = 0, ym = 0, sm = 0;
+            int nslot = 0, xblk = 0, yblk = 0, sblk = 0;
+        } tb[2];
+        for (int im = 0; im < 2; ++im) {
+            std::vector<gp::XSlot<T>> xs;
+            std::vector<gp::YSlot<T>> ys;
+            std::vector<gp::NSlot> ns;
+            std::vector<gp::SSlot<T>> ss;
+            std::vector<unsigned> xm, ym, sm;
+            const gp::YTile yt = gp::ytile<T>(shape[im].tile);
+            for (int s : grouped[im]) {
+                if (nsteps[s] <= done) continue;
+                gp_spin1* h = b->slot[s];
+                const ModeState& ms = h->mode[im];
+                const unsigned id = (unsigned)xs.size();
+                int G, R, hh, L;
+                x_shape(h->p.nx, shape[im].K, G, R);
+                R = std::max(1, std::min(8, shape[im].block / G));
+                tile_window(h->p.ny, ms.hh, gp::ywindow(yt), hh, L);
+                const int ncs = (h->p.nx + 4 * yt.NW - 1) / (4 * yt.NW);
+                const int nyb = ncs * ((h->p.ny + L - 1) / L);
+                const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
+                const int nsb = (int)((n3 + gp::kScaleChunk - 1) / gp::kScaleChunk);
+                xs.push_back(gp::XSlot<T>{(const C*)psi[s], (C*)h->d_work, phys(h->p), lineset<T>(ms.x), h->d_scale, G, R});
+                ys.push_back(gp::YSlot<T>{(const C*)h->d_work, (C*)psi[s], phys(h->p), lineset<T>(ms.y), h->d_part, L, hh, ncs});
+                ns.push_back(gp::NSlot{h->d_part, nyb, h->p.dx * h->p.dy, h->d_scale, h->d_flag});
+                ss.push_back(gp::SSlot<T>{(C*)psi[s], n3, h->d_scale});
+                for (int k = 0; k < (h->p.ny + R - 1) / R; ++k) xm.push_back((id << gp::kMapShift) | (unsigned)k);
+                for (int k = 0; k < nyb; ++k) ym.push_back((id << gp::kMapShift) | (unsigned)k);
+                for (int k = 0; k < nsb; ++k) sm.push_back((id << gp::kMapShift) | (unsigned)k);
+            }
+            tb[im].nslot = (int)xs.size();
+            if (!tb[im].nslot) continue;
+            if (tb[im].nslot > gp::kMaxBatchSlots) return bfail(b, GP_EUNSUPPORTED, "too many condensates in one launch");
+            tb[im].xblk = (int)xm.size();
+            tb[im].yblk = (int)ym.size();
+            tb[im].sblk = (int)sm.size();
+            tb[im].xs = stage_put(img, xs);
+            tb[im].ys = stage_put(img, ys);
+            tb[im].ns = stage_put(img, ns);
+            tb[im].ss = stage_put(img, ss);
+            tb[im].xm = stage_put(img, xm);
+            tb[im].ym = stage_put(img, ym);
+            tb[im].sm = stage_put(img, sm);
+        }
+        // upload through pinned staging (wait until the previous upload has left it)
+        hipError_t e;
+        if (b->staged_pending) {
+            if ((e = hipEventSynchronize(b->staged)) != hipSuccess) return bhip(b, e, "batch staging");
+            b->staged_pending = false;
+        }
+        if (img.size() > b->h_cap) {
+            if (b->h_stage) (void)hipHostFree(b->h_stage);
+            b->h_stage = nullptr;
+            b->h_cap = 0;
+            if ((e = hipHostMalloc(&b->h_stage, img.size())) != hipSuccess) return bhip(b, e, "batch staging");
+            b->h_cap = img.size();
+        }
+        if (img.size() > b->d_cap) {
+            // the stream may still read the old tables
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return bhip(b, e, "batch staging");
+            if (b->d_stage) (void)hipFree(b->d_stage);
+            b->d_stage = nullptr;
+            b->d_cap = 0;
+            if ((e = hipMalloc(&b->d_stage, img.size())) != hipSuccess) return bfail(b, GP_ENOMEM, "batch tables");
+            b->d_cap = img.size();
+        }
+        std::memcpy(b->h_stage, img.data(), img.size());
+        if ((e = hipMemcpyAsync(b->d_stage, b->h_stage, img.size(), hipMemcpyHostToDevice, st)) != hipSuccess)
+            return bhip(b, e, "batch upload");
+        if ((e = hipEventRecord(b->staged, st)) != hipSuccess) return bhip(b, e, "batch upload");
+        b->staged_pending = true;
+        auto at = [&](size_t off) { return (void*)((unsigned char*)b->d_stage + off); };
+        // imaginary-time scales start at one
+        if (tb[1].nslot &&
+            (e = gp::launch_set_scale_batch((const gp::NSlot*)at(tb[1].ns), tb[1].nslot, 1.0, st)) != hipSuccess)
+            return bhip(b, e, "batch set_scale");
+        for (int64_t k = 0; k < c; ++k) {
+            for (int im = 1; im >= 0; --im) {
+                if (!tb[im].nslot) continue;
+                const GroupTables& g = tb[im];
+                if ((e = gp::launch_x_batch<T>((const gp::XSlot<T>*)at(g.xs), (const unsigned*)at(g.xm), g.xblk,
+                                               shape[im].K, shape[im].block, im == 1, st)) != hipSuccess)
+                    return bhip(b, e, "batch x sweep");
+                if ((e = gp::launch_y_batch<T>((const gp::YSlot<T>*)at(g.ys), (const unsigned*)at(g.ym), g.yblk,
+                                               shape[im].tile, im == 1, st)) != hipSuccess)
+                    return bhip(b, e, "batch y sweep");
+                if (im == 1 && (e = gp::launch_norm_finalize_batch((const gp::NSlot*)at(g.ns), g.nslot, st)) != hipSuccess)
+                    return bhip(b, e, "batch norm");
+                b->info.launches += im == 1 ? 3 : 2;
+            }
+        }
+        if (tb[1].nslot &&
+            (e = gp::launch_scale_batch<T>((const gp::SSlot<T>*)at(tb[1].ss), (const unsigned*)at(tb[1].sm), tb[1].sblk,
+                                           st)) != hipSuccess)
+            return bhip(b, e, "batch scale");
+        b->info.phases += 1;
+        done = next;
+    }
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out) {
+    return make_handle(p, (hipStream_t)hip_stream, out);
 }
 
 int gp_spin1_destroy(gp_spin1_t* h) {
@@ -797,6 +1051,95 @@ const char* gp_spin1_strerror(int status) {
 const char* gp_spin1_last_error(const gp_spin1_t* h) {
     if (!h) return "";
     return h->err.c_str();
+}
+
+
+int gp_spin1_batch_create(const gp_spin1_params* p, int32_t n, void* hip_stream, gp_spin1_batch_t** out) {
+    if (!out || !p || n < 1 || n > 65536) return GP_EINVAL;
+    for (int s = 1; s < n; ++s)
+        if (p[s].precision != p[0].precision) return GP_EINVAL;
+    if (p[0].precision != GP_FP64 && p[0].precision != GP_FP32) return GP_EINVAL;
+    gp_spin1_batch* b = new (std::nothrow) gp_spin1_batch();
+    if (!b) return GP_ENOMEM;
+    b->n = n;
+    b->precision = p[0].precision;
+    b->stream = (hipStream_t)hip_stream;
+    b->slot.assign(n, nullptr);
+    if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) { batch_free(b); return GP_EHIP; }
+    for (int s = 0; s < n; ++s) {
+        if (p[s].nx == 0) continue;  // empty slot
+        int rc = make_handle(&p[s], b->stream, &b->slot[s]);
+        if (rc) { batch_free(b); return rc; }
+    }
+    *out = b;
+    return GP_OK;
+}
+
+int gp_spin1_batch_set_slot(gp_spin1_batch_t* b, int32_t slot, const gp_spin1_params* p) {
+    if (!b) return GP_EINVAL;
+    if (slot < 0 || slot >= b->n) return bfail(b, GP_EINVAL, "slot out of range");
+    if (p && p->nx != 0 && p->precision != b->precision) return bfail(b, GP_EINVAL, "precision differs from the batch");
+    gp_spin1* h = nullptr;
+    if (p && p->nx != 0) {
+        int rc = make_handle(p, b->stream, &h);
+        if (rc) return bfail(b, rc, "slot " + std::to_string(slot) + ": invalid or unsupported parameters");
+    }
+    if (b->slot[slot]) {
+        // the stream may still use the old slot's tables
+        hipError_t e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) {
+            if (h) destroy_all(h);
+            return bhip(b, e, "set_slot");
+        }
+        destroy_all(b->slot[slot]);
+    }
+    b->slot[slot] = h;
+    return GP_OK;
+}
+
+int gp_spin1_batch_step(gp_spin1_batch_t* b, void* const* psi_dev, const int64_t* nsteps, const int32_t* mode,
+                        const uint8_t* active) {
+    if (!b) return GP_EINVAL;
+    if (!psi_dev || !nsteps || !mode) return bfail(b, GP_EINVAL, "psi_dev, nsteps and mode are required");
+    return b->precision == GP_FP64 ? batch_step_t<double>(b, psi_dev, nsteps, mode, active)
+                                   : batch_step_t<float>(b, psi_dev, nsteps, mode, active);
+}
+
+int gp_spin1_batch_sync(gp_spin1_batch_t* b) {
+    if (!b) return GP_EINVAL;
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(b, e, "sync");
+    for (int s = 0; s < b->n; ++s) {
+        if (!b->slot[s]) continue;
+        int rc = gp_spin1_sync(b->slot[s]);
+        if (rc) return bfail(b, rc, "slot " + std::to_string(s) + ": " + b->slot[s]->err);
+    }
+    return GP_OK;
+}
+
+int gp_spin1_batch_observables(gp_spin1_batch_t* b, int32_t slot, const void* psi, gp_spin1_obs* out, void* dens) {
+    if (!b) return GP_EINVAL;
+    if (slot < 0 || slot >= b->n || !b->slot[slot]) return bfail(b, GP_EINVAL, "slot out of range or empty");
+    int rc = gp_spin1_observables(b->slot[slot], psi, out, dens);
+    if (rc) return bfail(b, rc, "slot " + std::to_string(slot) + ": " + b->slot[slot]->err);
+    return GP_OK;
+}
+
+int gp_spin1_batch_info_read(const gp_spin1_batch_t* b, gp_spin1_batch_info* out) {
+    if (!b || !out) return GP_EINVAL;
+    *out = b->info;
+    return GP_OK;
+}
+
+int gp_spin1_batch_destroy(gp_spin1_batch_t* b) {
+    if (!b) return GP_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    return GP_OK;
+}
+
+const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b) {
+    return b ? b->err.c_str() : "null batch";
 }
 
 }  // extern "C"

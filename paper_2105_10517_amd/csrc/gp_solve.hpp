@@ -1,0 +1,327 @@
+// Line solves and block reductions shared by the sweep kernels.
+#pragma once
+
+#include "gp_kernels.hpp"
+#include "gp_scan.hpp"
+
+namespace gp {
+
+// ---------------------------------------------------------------------------
+// Crank-Nicolson line solve in increment form.  With A = I + alpha h the
+// tridiagonal matrix (sub a, diagonal b, super e), the new values are
+// u' = A^{-1} (2I - A) u = u + delta with A delta = -2 (A - I) u: the
+// increment is small (of order alpha/dx^2 relative to u), so the rounding of
+// the elimination is small relative to u and u + delta is rounded once.  (In
+// FP32 the direct form drifts in norm by a few 1e-8 per sweep.)
+//
+// Partitioned Thomas on one line held as K consecutive values per thread
+// (indices i0 .. i0+K-1 of a line of length n; indices outside [0, n) are
+// padding), in place on u[]; left/right are the line values just outside the
+// thread's block.  FS and BS are the forward and backward exclusive scans of
+// the block transfer maps across the threads sharing the line; every thread
+// must reach them (they contain barriers).
+//
+// Blocks entirely inside the line and past the tabulated transient of the
+// pivots take a fast path with the converged pivots held in registers.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG> __device__ inline cx<T> mul_bm1(cx<T> bm1, cx<T> u) {
+    // b - 1 = alpha / dx^2: real in imaginary time, imaginary in real time
+    return IMAG ? cscale(u, bm1.x) : cscale(ctimes_i(u), bm1.y);
+}
+template <typename C> __device__ inline C cneg(C a) { C z; z.x = -a.x; z.y = -a.y; return z; }
+template <typename C, int K> __device__ inline C cpow_k(C a) {
+    C r = one_c<C>(), b = a;
+#pragma unroll
+    for (int k = K; k > 0; k >>= 1) {
+        if (k & 1) r = cmul(r, b);
+        b = cmul(b, b);
+    }
+    return r;
+}
+
+template <typename T, int K, bool IMAG, typename FS, typename BS>
+__device__ inline void block_solve(cx<T> (&u)[K], cx<T> left, cx<T> right, const LineSet<T>& ls, int line, int i0,
+                                   int n, FS fscan, BS bscan) {
+    using C = cx<T>;
+    const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1];
+    const Piv<T> lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
+    const bool fast = i0 >= ls.K && i0 + K <= n;
+    // right-hand side of the increment system: r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
+    C r[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const C um = (k == 0) ? left : u[k - 1];
+        const C up = (k == K - 1) ? right : u[k + 1];
+        C t = mul_bm1<T, IMAG>(ls.bm1, u[k]);
+        t = cfma(um, a, t);
+        t = cfma(up, e, t);
+        r[k] = cscale(t, (T)-2);
+    }
+    const C nam = cneg(lim.am), ncp = cneg(lim.cp);
+    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1}
+    C E = zero_c<C>(), P;
+    if (fast) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            E = cfma(E, nam, cmul(lim.m, r[k]));
+            r[k] = E;
+        }
+        P = cpow_k<C, K>(nam);
+    } else {
+        P = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                E = cfma(E, cneg(pv.am), cmul(pv.m, r[k]));
+                P = cmul(cneg(pv.am), P);
+            } else {
+                E = zero_c<C>();
+                P = zero_c<C>();
+            }
+            r[k] = E;
+        }
+    }
+    const C din = fscan(P, E);
+    // add the carry that enters the block, times the running product of -am
+    if (fast) {
+        C Q = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            Q = cmul(Q, nam);
+            r[k] = cfma(din, Q, r[k]);
+        }
+    } else {
+        C Q = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                Q = cmul(Q, cneg(pv.am));
+                r[k] = cfma(din, Q, r[k]);
+            }
+        }
+    }
+    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1}
+    C G = zero_c<C>(), R;
+    if (fast) {
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            G = cfma(G, ncp, r[k]);
+            r[k] = G;
+        }
+        R = cpow_k<C, K>(ncp);
+    } else {
+        R = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                G = cfma(G, cneg(pv.cp), r[k]);
+                R = cmul(cneg(pv.cp), R);
+            } else {
+                G = zero_c<C>();
+                R = zero_c<C>();
+            }
+            r[k] = G;
+        }
+    }
+    const C xin = bscan(R, G);
+    if (fast) {
+        C Sx = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            Sx = cmul(Sx, ncp);
+            u[k] = cadd(u[k], cfma(xin, Sx, r[k]));
+        }
+    } else {
+        C Sx = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+                const Piv<T> pv = (i < ls.K) ? piv_at(ls, line, i) : lim;
+                Sx = cmul(Sx, cneg(pv.cp));
+                u[k] = cadd(u[k], cfma(xin, Sx, r[k]));
+            }
+        }
+    }
+}
+
+template <typename T, int K, bool IMAG, typename FS, typename BS>
+__device__ inline void block_solve3(cx<T> (&u)[3][K], const cx<T> (&left)[3], const cx<T> (&right)[3],
+                                    const LineSet<T>& ls, int line0, int i0, int n, FS fscan, BS bscan) {
+    using C = cx<T>;
+    C a[3], e[3], nam[3], ncp[3], lm[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        a[q] = ls.ae[2 * (line0 + q)];
+        e[q] = ls.ae[2 * (line0 + q) + 1];
+        const Piv<T> lim = ls.piv[(size_t)(line0 + q) * (ls.K + 1) + ls.K];
+        lm[q] = lim.m;
+        nam[q] = cneg(lim.am);
+        ncp[q] = cneg(lim.cp);
+    }
+    const bool fast = i0 >= ls.K && i0 + K <= n;
+    // right-hand side of the increment system: r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
+    C r[3][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const C um = (k == 0) ? left[q] : u[q][k - 1];
+            const C up = (k == K - 1) ? right[q] : u[q][k + 1];
+            C t = mul_bm1<T, IMAG>(ls.bm1, u[q][k]);
+            t = cfma(um, a[q], t);
+            t = cfma(up, e[q], t);
+            r[q][k] = cscale(t, (T)-2);
+        }
+    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1}
+    C E[3], P[3], din[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) E[q] = zero_c<C>();
+    if (fast) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                E[q] = cfma(E[q], nam[q], cmul(lm[q], r[q][k]));
+                r[q][k] = E[q];
+            }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[q] = cpow_k<C, K>(nam[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) P[q] = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            const bool in = i >= 0 && i < n;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (in) {
+                    const Piv<T> pv = piv_at(ls, line0 + q, i);
+                    E[q] = cfma(E[q], cneg(pv.am), cmul(pv.m, r[q][k]));
+                    P[q] = cmul(cneg(pv.am), P[q]);
+                } else {
+                    E[q] = zero_c<C>();
+                    P[q] = zero_c<C>();
+                }
+                r[q][k] = E[q];
+            }
+        }
+    }
+    fscan(P, E, din);
+    // add the carry that enters the block, times the running product of -am
+    if (fast) {
+        C Q[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                Q[q] = cmul(Q[q], nam[q]);
+                r[q][k] = cfma(din[q], Q[q], r[q][k]);
+            }
+    } else {
+        C Q[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    Q[q] = cmul(Q[q], cneg(piv_at(ls, line0 + q, i).am));
+                    r[q][k] = cfma(din[q], Q[q], r[q][k]);
+                }
+            }
+        }
+    }
+    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1}
+    C G[3], R[3], xin[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) G[q] = zero_c<C>();
+    if (fast) {
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                G[q] = cfma(G[q], ncp[q], r[q][k]);
+                r[q][k] = G[q];
+            }
+#pragma unroll
+        for (int q = 0; q < 3; ++q) R[q] = cpow_k<C, K>(ncp[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) R[q] = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            const bool in = i >= 0 && i < n;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (in) {
+                    const C nc = cneg(piv_at(ls, line0 + q, i).cp);
+                    G[q] = cfma(G[q], nc, r[q][k]);
+                    R[q] = cmul(nc, R[q]);
+                } else {
+                    G[q] = zero_c<C>();
+                    R[q] = zero_c<C>();
+                }
+                r[q][k] = G[q];
+            }
+        }
+    }
+    bscan(R, G, xin);
+    if (fast) {
+        C Sx[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                Sx[q] = cmul(Sx[q], ncp[q]);
+                u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
+            }
+    } else {
+        C Sx[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            const int i = i0 + k;
+            if (i >= 0 && i < n) {
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    Sx[q] = cmul(Sx[q], cneg(piv_at(ls, line0 + q, i).cp));
+                    u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Block reduction of one double (all threads call; result valid in thread 0).
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < nw; ++k) s += sh[k];
+    __syncthreads();
+    return s;
+}
+
+// Per-block partial sum of the imaginary-time norm, in block order; a one-block
+// kernel launched next on the same stream forms the total (a device-wide
+// release fence per block would write back the L2 of its XCD every time).
+__device__ inline void store_norm_partial(double part, NormOut no, int blk) {
+    if (threadIdx.x == 0) no.partials[blk] = part;
+}
+
+}  // namespace gp

@@ -1,0 +1,181 @@
+// x sweep of the SSCN step on gfx950: the local substep (and a pending
+// imaginary-time renormalisation) fused into the x Crank-Nicolson sweep.  One
+// row per thread group, K consecutive points per thread in registers, exact
+// partitioned Thomas (local recurrences + wave/LDS scans of the block
+// carries).  k_x_scan serves one condensate; k_x_batch one launch over the
+// rows of many condensates (a block map names each block's condensate).
+#include <hip/hip_ext.h>
+
+#include "gp_solve.hpp"
+
+namespace gp {
+
+// One block of the x sweep: rows blk R .. blk R + R - 1 of one condensate, G
+// threads per row (threads past G R idle through the barriers).
+template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE>
+__device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
+                              const LineSet<T>& ls, const double* __restrict__ scale, int G, int R, int blk) {
+    using C = cx<T>;
+    __shared__ C shS[6 * 16];
+    __shared__ C shN[2 * 3 * 16];
+    const int tid = threadIdx.x;
+    const int r = tid / G, t = tid - r * G;
+    const int lane = t & 63, w = t >> 6, nw = G >> 6;
+    const int j = blk * R + r;
+    const bool row_ok = r < R && j < ph.ny;
+    const int nx = ph.nx;
+    const size_t plane = (size_t)ph.nx * ph.ny;
+    const int i0 = t * K;
+    const size_t rowoff = (size_t)(row_ok ? j : 0) * nx;
+    const C* rowp = src + rowoff;
+    C* rowq = dst + rowoff;
+    C v[3][K];
+    if (row_ok && i0 + K <= nx) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[m][k] = rowp[m * plane + i0 + k];
+    } else {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                v[m][k] = (row_ok && i0 + k < nx) ? rowp[m * plane + i0 + k] : zero_c<C>();
+    }
+    if (SCALE) {
+        const T s = (T)(*scale);
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[m][k] = cscale(v[m][k], s);
+    }
+    if (LOCAL) {
+        const T y = (T)(ph.y0 + (row_ok ? j : 0) * ph.dy);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T x = (T)(ph.x0 + (i0 + k) * ph.dx);
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], (T)0.5 * (x * x + y * y), (T)ph.dt, (T)ph.c0,
+                                   (T)ph.c2, (T)ph.rabi);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    // neighbours of the block ends for all three components (ghost zeros beyond the row)
+    C left[3], right[3];
+    const int nrow = r * nw;  // first wave of this row in the block
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        left[q] = shfl_up_c(v[q][K - 1], 1);
+        right[q] = shfl_down_c(v[q][0], 1);
+        if (lane == 63) shN[(nrow + w) * 3 + q] = v[q][K - 1];
+        if (lane == 0) shN[48 + (nrow + w) * 3 + q] = v[q][0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (lane == 0) left[q] = (w > 0) ? shN[(nrow + w - 1) * 3 + q] : zero_c<C>();
+        if (lane == 63) right[q] = (w + 1 < nw) ? shN[48 + (nrow + w + 1) * 3 + q] : zero_c<C>();
+    }
+    const int jl = row_ok ? j : 0;
+    C* ss = shS + 6 * nrow;
+    if constexpr (sizeof(T) * K <= 32) {
+        // the three lines' chains interleaved (fits the register file for small blocks)
+        auto fs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) { row_scan3<true>(P, E, o, lane, w, nw, ss); };
+        auto bs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) { row_scan3<false>(P, E, o, lane, w, nw, ss); };
+        block_solve3<T, K, IMAG>(v, left, right, ls, jl * 3, i0, nx, fs, bs);
+    } else {
+        // one line after the other
+        auto fs = [&](C P, C E) { return row_scan<true>(P, E, lane, w, nw, ss, ss + nw); };
+        auto bs = [&](C P, C E) { return row_scan<false>(P, E, lane, w, nw, ss, ss + nw); };
+#pragma unroll
+        for (int q = 0; q < 3; ++q) block_solve<T, K, IMAG>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, fs, bs);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    if (row_ok && i0 + K <= nx) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k) rowq[m * plane + i0 + k] = v[m][k];
+    } else if (row_ok) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (i0 + k < nx) rowq[m * plane + i0 + k] = v[m][k];
+    }
+}
+
+template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
+__global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
+                                               LineSet<T> ls, const double* __restrict__ scale, int G, int R) {
+    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, ph, ls, scale, G, R, (int)blockIdx.x);
+}
+
+template <typename T, bool IMAG, int K, int LB>
+__global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
+    const unsigned e = map[blockIdx.x];
+    const XSlot<T>& s = slots[e >> kMapShift];
+    x_rows<T, IMAG, K, true, IMAG>(s.src, s.dst, s.ph, s.ls, s.scale, s.G, s.R, (int)(e & kMapMask));
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, bool LOCAL, bool SCALE>
+static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph, const LineSet<T>& ls,
+                             const double* scale, int G, int R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const int nblk = (ph.ny + R - 1) / R;
+    const dim3 grid(nblk), block(G * R);
+    if (G * R > xk_bound(K) || G % 64 || G / 64 > 16 || R > 8) return hipErrorInvalidValue;
+
+    switch (K) {
+        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (a.imag) {
+        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+    }
+    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+}
+
+template <typename T, bool IMAG>
+static hipError_t launch_x_batch_t(const XSlot<T>* slots, const unsigned* map, int nblk, int K, int block,
+                                   hipStream_t st) {
+    if (block > xk_bound(K) || block % 64 || block > 1024 || nblk <= 0) return hipErrorInvalidValue;
+    const dim3 grid(nblk), blk(block);
+    switch (K) {
+        case 1: hipExtLaunchKernelGGL(k_x_batch<T, IMAG, 1, xk_bound(1)>, grid, blk, 0, st, nullptr, nullptr, 0, slots, map); break;
+        case 2: hipExtLaunchKernelGGL(k_x_batch<T, IMAG, 2, xk_bound(2)>, grid, blk, 0, st, nullptr, nullptr, 0, slots, map); break;
+        case 4: hipExtLaunchKernelGGL(k_x_batch<T, IMAG, 4, xk_bound(4)>, grid, blk, 0, st, nullptr, nullptr, 0, slots, map); break;
+        case 8: hipExtLaunchKernelGGL(k_x_batch<T, IMAG, 8, xk_bound(8)>, grid, blk, 0, st, nullptr, nullptr, 0, slots, map); break;
+        case 16: hipExtLaunchKernelGGL(k_x_batch<T, IMAG, 16, xk_bound(16)>, grid, blk, 0, st, nullptr, nullptr, 0, slots, map); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_x_batch(const XSlot<T>* slots, const unsigned* map, int nblk, int K, int block, bool imag,
+                          hipStream_t st) {
+    return imag ? launch_x_batch_t<T, true>(slots, map, nblk, K, block, st)
+                : launch_x_batch_t<T, false>(slots, map, nblk, K, block, st);
+}
+
+template hipError_t launch_x<double>(const XLaunch<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_x<float>(const XLaunch<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_x_batch<double>(const XSlot<double>*, const unsigned*, int, int, int, bool, hipStream_t);
+template hipError_t launch_x_batch<float>(const XSlot<float>*, const unsigned*, int, int, int, bool, hipStream_t);
+
+}  // namespace gp

@@ -1,0 +1,252 @@
+// y sweep of the SSCN step on gfx950.
+//
+//   k_y_window   column tiles: 4 NW columns x 16 segments of KY rows; exact
+//                partitioned Thomas inside the tile, windows overlapping by h
+//                rows so that the truncated carries at the window ends decay
+//                below the rounding level before the rows that are written.
+//                Norm partials fused into the store.  k_y_batch: the same
+//                over the tiles of many condensates in one launch.
+//   k_y_thomas   exact per-thread Thomas down whole columns (one thread per
+//                column, forward eliminations stored in place).
+#include <hip/hip_ext.h>
+
+#include "gp_solve.hpp"
+
+namespace gp {
+
+// ---------------------------------------------------------------------------
+// y sweep, windowed partitioned Thomas over column tiles (increment form).
+// Each wave holds 4 columns; each DPP row of 16 lanes holds the 16 segments of
+// one column; each lane KY consecutive rows of its segment, so a window spans
+// 16 KY rows.  The segment scans and the exchange of segment-end neighbours
+// are DPP moves inside a row: no shared memory and no barrier (except for the
+// norm reduction at the end).  Consecutive windows overlap by h rows on each
+// side and write only their L = 16 KY - 2 h middle rows.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, int KY, int NW, bool NORM>
+__device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
+                                const LineSet<T>& ls, int L, int h, int ncs, NormOut no, int blk) {
+    using C = cx<T>;
+    constexpr int CPB = 4 * NW;  // columns per block
+    __shared__ double shr[16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane & 15, cw = lane >> 4;
+    const int cs = blk % ncs, rt = blk / ncs;
+    const int i = cs * CPB + wv * 4 + cw;
+    const bool col_ok = i < ph.nx;
+    const int nx = ph.nx, ny = ph.ny;
+    const size_t plane = (size_t)nx * ny;
+    const int j0 = rt * L;
+    const int g0 = j0 - h + seg * KY;  // first row of this lane
+    C v[3][KY];
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        const bool ok = col_ok && g >= 0 && g < ny;
+        const size_t o = (size_t)(ok ? g : 0) * nx + (col_ok ? i : 0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? src[m * plane + o] : zero_c<C>();
+    }
+#pragma unroll
+    for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    // rows just above and below this lane's segment (zeros outside the window)
+    C up[3], dn[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        up[q] = dpp_c<0x111>(zero_c<C>(), v[q][KY - 1]);  // row_shr:1
+        dn[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
+    }
+    const int il = col_ok ? i : 0;
+    auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan3<true>(P, E, o); };
+    auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan3<false>(P, E, o); };
+    block_solve3<T, KY, IMAG>(v, up, dn, ls, il * 3, g0, ny, fs, bs);
+#pragma unroll
+    for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    double acc = 0;
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        if (col_ok && g >= j0 && g < j0 + L && g < ny) {
+            const size_t o = (size_t)g * nx + i;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                dst[m * plane + o] = v[m][k];
+                if (NORM) acc += (double)cnorm2(v[m][k]);
+            }
+        }
+    }
+    if (NORM) store_norm_partial(block_sum(acc, shr), no, blk);
+}
+
+template <typename T, bool IMAG, int KY, int NW, bool NORM>
+__global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                      Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no) {
+    y_window<T, IMAG, KY, NW, NORM>(src, dst, ph, ls, L, h, ncs, no, (int)blockIdx.x);
+}
+
+template <typename T, bool IMAG, int KY, int NW>
+__global__ __launch_bounds__(64 * NW) void k_y_batch(const YSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
+    const unsigned e = map[blockIdx.x];
+    const YSlot<T>& s = slots[e >> kMapShift];
+    y_window<T, IMAG, KY, NW, IMAG>(s.src, s.dst, s.ph, s.ls, s.L, s.h, s.ncs, NormOut{s.partials}, (int)(e & kMapMask));
+}
+
+// ---------------------------------------------------------------------------
+// y sweep, exact per-thread Thomas down whole columns (increment form): the
+// forward eliminations go to dst, the back substitution re-reads src.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, bool NORM>
+__global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
+                                                 LineSet<T> ls, NormOut no) {
+    using C = cx<T>;
+    __shared__ double shr[16];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nx = ph.nx, ny = ph.ny;
+    const size_t plane = (size_t)nx * ny;
+    double acc = 0;
+    if (i < nx) {
+        C a[3], e[3];
+        Piv<T> lim[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            a[q] = ls.ae[2 * (i * 3 + q)];
+            e[q] = ls.ae[2 * (i * 3 + q) + 1];
+            lim[q] = ls.piv[(size_t)(i * 3 + q) * (ls.K + 1) + ls.K];
+        }
+        auto load_sx = [&](int g, C (&o)[3]) {
+            if (g >= 0 && g < ny) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) o[m] = src[m * plane + (size_t)g * nx + i];
+                to_sx<C, T>(o[0], o[1], o[2]);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) o[m] = zero_c<C>();
+            }
+        };
+        C prev[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()}, cur[3], nxt[3], d[3];
+        load_sx(0, cur);
+        C carry[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
+        for (int g = 0; g < ny; ++g) {
+            load_sx(g + 1, nxt);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                C t = mul_bm1<T, IMAG>(ls.bm1, cur[q]);
+                t = cfma(prev[q], a[q], t);
+                t = cfma(nxt[q], e[q], t);
+                const C rr = cscale(t, (T)-2);
+                const Piv<T> pv = (g < ls.K) ? piv_at(ls, i * 3 + q, g) : lim[q];
+                d[q] = cfma(carry[q], cneg(pv.am), cmul(pv.m, rr));
+                carry[q] = d[q];
+                prev[q] = cur[q];
+                cur[q] = nxt[q];
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) dst[m * plane + (size_t)g * nx + i] = d[m];
+        }
+        C x[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
+        for (int g = ny - 1; g >= 0; --g) {
+            C o[3], uu[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) o[m] = dst[m * plane + (size_t)g * nx + i];
+            load_sx(g, uu);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const Piv<T> pv = (g < ls.K) ? piv_at(ls, i * 3 + q, g) : lim[q];
+                x[q] = csub(o[q], cmul(pv.cp, x[q]));
+                o[q] = cadd(uu[q], x[q]);
+            }
+            from_sx<C, T>(o[0], o[1], o[2]);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                dst[m * plane + (size_t)g * nx + i] = o[m];
+                if (NORM) acc += (double)cnorm2(o[m]);
+            }
+        }
+    }
+    if (NORM) store_norm_partial(block_sum(acc, shr), no, (int)blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, bool NORM, int TI>
+static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    constexpr YTile yt = ytile<T>(TI);
+    const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
+    const int nrt = (a.ph.ny + a.L - 1) / a.L;
+    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, NORM>, dim3(ncs * nrt), dim3(64 * yt.NW), 0, st, e0, e1, 0,
+                          a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no);
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG, bool NORM>
+static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    switch (a.tile) {
+        case 0: return launch_yw_t<T, IMAG, NORM, 0>(a, st, e0, e1);
+        case 1: return launch_yw_t<T, IMAG, NORM, 1>(a, st, e0, e1);
+        case 2: return launch_yw_t<T, IMAG, NORM, 2>(a, st, e0, e1);
+        case 3: return launch_yw_t<T, IMAG, NORM, 3>(a, st, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+int y_blocks(const YLaunch<T>& a) {
+    if (a.window) {
+        const YTile yt = ytile<T>(a.tile);
+        const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
+        return ncs * ((a.ph.ny + a.L - 1) / a.L);
+    }
+    return (a.ph.nx + 255) / 256;
+}
+
+template <typename T>
+hipError_t launch_y(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (a.window) {
+        if (a.imag) return a.norm ? launch_yw<T, true, true>(a, st, e0, e1) : launch_yw<T, true, false>(a, st, e0, e1);
+        return a.norm ? launch_yw<T, false, true>(a, st, e0, e1) : launch_yw<T, false, false>(a, st, e0, e1);
+    }
+    const dim3 grid((a.ph.nx + 255) / 256), block(256);
+    if (a.imag) {
+        if (a.norm) hipExtLaunchKernelGGL(k_y_thomas<T, true, true>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+        else hipExtLaunchKernelGGL(k_y_thomas<T, true, false>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+    } else {
+        if (a.norm) hipExtLaunchKernelGGL(k_y_thomas<T, false, true>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+        else hipExtLaunchKernelGGL(k_y_thomas<T, false, false>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG, int TI>
+static hipError_t launch_y_batch_t(const YSlot<T>* slots, const unsigned* map, int nblk, hipStream_t st) {
+    constexpr YTile yt = ytile<T>(TI);
+    hipExtLaunchKernelGGL(k_y_batch<T, IMAG, yt.KY, yt.NW>, dim3(nblk), dim3(64 * yt.NW), 0, st, nullptr, nullptr, 0,
+                          slots, map);
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG>
+static hipError_t launch_y_batch_i(const YSlot<T>* slots, const unsigned* map, int nblk, int tile, hipStream_t st) {
+    if (nblk <= 0) return hipErrorInvalidValue;
+    switch (tile) {
+        case 0: return launch_y_batch_t<T, IMAG, 0>(slots, map, nblk, st);
+        case 1: return launch_y_batch_t<T, IMAG, 1>(slots, map, nblk, st);
+        case 2: return launch_y_batch_t<T, IMAG, 2>(slots, map, nblk, st);
+        case 3: return launch_y_batch_t<T, IMAG, 3>(slots, map, nblk, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_y_batch(const YSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st) {
+    return imag ? launch_y_batch_i<T, true>(slots, map, nblk, tile, st) : launch_y_batch_i<T, false>(slots, map, nblk, tile, st);
+}
+
+template hipError_t launch_y<double>(const YLaunch<double>&, hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_y<float>(const YLaunch<float>&, hipStream_t, hipEvent_t, hipEvent_t);
+template int y_blocks<double>(const YLaunch<double>&);
+template int y_blocks<float>(const YLaunch<float>&);
+template hipError_t launch_y_batch<double>(const YSlot<double>*, const unsigned*, int, int, bool, hipStream_t);
+template hipError_t launch_y_batch<float>(const YSlot<float>*, const unsigned*, int, int, bool, hipStream_t);
+
+}  // namespace gp

@@ -90,3 +90,20 @@ def test_stability_checks():
     q = inputs.params(64, 64, 0.1, dt=5.0, omega=5.0)
     assert binding.plan_query(q, False)["stable"] == 0
     assert binding.plan_query(inputs.config_c2(), False)["stable"] == 1
+
+
+def test_batch_create_validates_before_touching_the_device():
+    import ctypes
+    lib = binding.load()
+    out = ctypes.c_void_p()
+    # no parameter array, or no output pointer
+    assert lib.gp_spin1_batch_create(None, 2, None, ctypes.byref(out)) == binding.GP_EINVAL
+    arr = (binding.Params * 2)(binding.make_params(BASE, "fp64"), binding.make_params(BASE, "fp32"))
+    # slots of different precision
+    assert lib.gp_spin1_batch_create(arr, 2, None, ctypes.byref(out)) == binding.GP_EINVAL
+    # empty batch
+    assert lib.gp_spin1_batch_create(arr, 0, None, ctypes.byref(out)) == binding.GP_EINVAL
+    # null handles
+    assert lib.gp_spin1_batch_step(None, None, None, None, None) == binding.GP_EINVAL
+    assert lib.gp_spin1_batch_destroy(None) == binding.GP_EINVAL
+    assert lib.gp_spin1_batch_last_error(None).decode() == "null batch"

@@ -1,0 +1,183 @@
+"""Batched launches over many condensates (C ABI gp_spin1_batch_*).
+
+A condensate advanced inside a batch must give the wave function of the same
+condensate advanced alone on a handle with the batch's launch shape: the same
+blocking, scans and reduction order, so the two agree to rounding (the
+batched and single kernels are separate instantiations of one source, and
+the compiler may contract a product and a sum into an FMA in one and not the
+other, a last-bit difference).  Tolerance: relative L2 1e-12 (FP64) and 2e-6
+(FP32) after up to 30 steps.  Against the oracle: the FP64 parity bar.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10517_amd import binding, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).to(DEV)
+
+
+def mixed_slots():
+    """Different grids (ragged, rectangular), couplings, SO types and time steps."""
+    ps = [
+        inputs.params(64, 64, 0.25, dt=0.1 * 0.25 ** 2, c0=40.0, c2=-2.0, gamma=0.5, eta=1, rabi=0.1, omega=0.4),
+        inputs.params(96, 160, 0.15, dy=0.12, dt=0.004, c0=120.0, c2=4.0, gamma=0.9, eta=-1, rabi=0.3, omega=0.7),
+        inputs.params(200, 130, 0.1, dt=0.002, c0=300.0, c2=-8.0, gamma=0.3, eta=1, rabi=0.0, omega=0.9),
+        inputs.params(37, 45, 0.3, dt=0.01, c0=10.0, c2=1.0, gamma=0.0, eta=1, rabi=0.5, omega=0.0),
+        inputs.params(256, 256, 0.1, dt=0.001, c0=500.0, c2=15.0, gamma=1.0, eta=-1, rabi=0.2, omega=0.95),
+    ]
+    return ps
+
+
+def initial(p, seed):
+    return inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], x0=p["x0"], y0=p["y0"], seed=seed)
+
+
+def same(got, want, precision):
+    tol = 1e-12 if precision == "fp64" else 2e-6
+    err = float(torch.linalg.vector_norm((got - want).flatten()) / torch.linalg.vector_norm(want.flatten()))
+    return err <= tol, err
+
+
+def alone(p, psi0, n, mode, precision, info, dtype):
+    """The same condensate on a single handle with the batch's launch shape."""
+    md = 0 if mode == "imag" else 1
+    s = binding.Solver(p, precision, x_points=info["x_points"][md], y_tile=info["y_tile"][md])
+    t = dev(psi0, dtype)
+    (s.step_imag if mode == "imag" else s.step_real)(t, n)
+    s.sync()
+    out = t.cpu()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_equals_single_handles(precision):
+    ps = mixed_slots()
+    modes = ["imag", "real", "imag", "real", "imag"]
+    nsteps = [30, 12, 7, 30, 19]  # several phases
+    b = binding.Batch(ps, precision)
+    psi0 = [initial(p, 10 + k) for k, p in enumerate(ps)]
+    ts = [dev(a, b.dtype) for a in psi0]
+    b.step(ts, nsteps, modes)
+    b.sync()
+    info = b.info()
+    assert info["grouped"] == len(ps) and info["individual"] == 0
+    assert info["phases"] == len(set(nsteps))
+    for k, p in enumerate(ps):
+        want = alone(p, psi0[k], nsteps[k], modes[k], precision, info, b.dtype)
+        got = ts[k].cpu()
+        ok, err = same(got, want, precision)
+        assert ok, f"slot {k}: relative L2 {err:.3e}"
+    b.close()
+
+
+def test_batch_matches_oracle():
+    ps = mixed_slots()[:4]
+    modes = ["imag", "real", "real", "imag"]
+    nsteps = [25, 25, 10, 40]
+    b = binding.Batch(ps, "fp64")
+    psi0 = [initial(p, 20 + k) for k, p in enumerate(ps)]
+    ts = [dev(a, torch.complex128) for a in psi0]
+    b.step(ts, nsteps, modes)
+    b.sync()
+    for k, p in enumerate(ps):
+        want = oracle.step(p, psi0[k], nsteps[k], modes[k] == "imag")
+        got = ts[k].cpu().numpy()
+        err = float(np.linalg.norm(got - want) / np.linalg.norm(want))
+        assert err < 1e-11, (k, err)
+    b.close()
+
+
+def test_empty_and_inactive_slots_are_untouched():
+    ps = mixed_slots()[:3]
+    b = binding.Batch([ps[0], None, ps[2]], "fp64")
+    psi0 = [initial(p, 30 + k) for k, p in enumerate(ps)]
+    t0, t2 = dev(psi0[0], torch.complex128), dev(psi0[2], torch.complex128)
+    before2 = t2.clone()
+    b.step([t0, None, t2], [5, 0, 5], ["imag", "imag", "real"], active=[True, False, False])
+    b.sync()
+    assert torch.equal(t2, before2)
+    assert not torch.equal(t0.cpu(), torch.from_numpy(psi0[0]))
+    with pytest.raises(binding.GPError):
+        b.step([t0, t0, t2], [1, 1, 1], ["imag", "imag", "imag"])  # slot 1 is empty
+    b.close()
+
+
+def test_set_slot_admits_a_new_condensate():
+    ps = mixed_slots()
+    b = binding.Batch([ps[0], ps[1]], "fp64")
+    b.set_slot(1, ps[4])
+    psi = [initial(ps[0], 40), initial(ps[4], 41)]
+    ts = [dev(a, torch.complex128) for a in psi]
+    b.step(ts, [8, 8], ["imag", "real"])
+    b.sync()
+    info = b.info()
+    want = alone(ps[4], psi[1], 8, "real", "fp64", info, torch.complex128)
+    assert same(ts[1].cpu(), want, "fp64")[0]
+    b.set_slot(0, None)
+    with pytest.raises(binding.GPError):
+        b.step(ts, [1, 1], ["imag", "real"])
+    b.close()
+
+
+def test_slot_outside_the_batch_tile_runs_alone():
+    # a tall grid with slow decay in y (large dt / dy^2) needs a bigger window
+    # than the tile chosen for the rest; it runs on its own plan
+    small = inputs.params(48, 48, 0.3, dt=0.009, c0=20.0, c2=-1.0, gamma=0.4, eta=1, rabi=0.1, omega=0.3)
+    tall = inputs.params(40, 700, 0.2, dy=0.05, dt=0.02, c0=20.0, c2=-1.0, gamma=0.4, eta=1, rabi=0.1, omega=0.3)
+    if binding.plan_query(tall, True)["y_solver"] == binding.GP_YSOLVER_WINDOW:
+        pytest.skip("the tall grid windows with every tile here")
+    b = binding.Batch([small, tall], "fp64")
+    psi = [initial(small, 50), initial(tall, 51)]
+    ts = [dev(a, torch.complex128) for a in psi]
+    b.step(ts, [6, 6], ["imag", "imag"])
+    b.sync()
+    info = b.info()
+    assert info["individual"] == 1 and info["grouped"] == 1
+    s = binding.Solver(tall, "fp64")
+    t = dev(psi[1], torch.complex128)
+    s.step_imag(t, 6)
+    s.sync()
+    assert torch.equal(ts[1].cpu(), t.cpu())  # the same kernels and plan: bit for bit
+    s.close()
+    b.close()
+
+
+def test_batch_nonfinite_names_the_slot():
+    ps = mixed_slots()[:2]
+    b = binding.Batch(ps, "fp64")
+    bad = initial(ps[1], 60)
+    bad[0, 10, 10] = complex(math.nan, 0.0)
+    ts = [dev(initial(ps[0], 61), torch.complex128), dev(bad, torch.complex128)]
+    b.step(ts, [3, 3], ["imag", "imag"])
+    with pytest.raises(binding.GPError) as ei:
+        b.sync()
+    assert ei.value.status == binding.GP_ENONFINITE and "slot 1" in str(ei.value)
+    b.close()
+
+
+def test_batch_scan_workload_sample():
+    """The 32 k x 32 k parameter-scan grids (k = 4..16), FP32 bulk, against
+    single handles with the batch shape (a sample of the scan, few steps)."""
+    ps = inputs.batch_scan(24, seed=5)
+    b = binding.Batch(ps, "fp32")
+    psi0 = [initial(p, 1000 + k) for k, p in enumerate(ps)]
+    ts = [dev(a, torch.complex64) for a in psi0]
+    b.step(ts, [20] * len(ps), ["imag"] * len(ps))
+    b.sync()
+    info = b.info()
+    assert info["grouped"] + info["individual"] == len(ps)
+    for k in (0, 7, 23):
+        want = alone(ps[k], psi0[k], 20, "imag", "fp32", info, torch.complex64)
+        assert same(ts[k].cpu(), want, "fp32")[0]
+    b.close()
