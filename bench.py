@@ -112,6 +112,77 @@ def cpu_baseline(p, psi0, seconds):
                       f"{dt:.1f} s)"}
 
 
+def batch_c4(torch, binding, inputs, nsteps):
+    """256 condensates of the parameter scan (FP32 bulk, imaginary time) in
+    batched launches, against the same solves one at a time in FP64."""
+    ps = inputs.batch_scan(256, seed=5)
+    psi0 = [inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], x0=p["x0"], y0=p["y0"], seed=1000 + k)
+            for k, p in enumerate(ps)]
+    pts = sum(p["nx"] * p["ny"] for p in ps) * nsteps
+    b = binding.Batch(ps, "fp32")
+    ts = [torch.from_numpy(a).to(torch.complex64).to("cuda") for a in psi0]
+    b.step(ts, [5] * len(ps), ["imag"] * len(ps))  # warm-up
+    b.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    b.step(ts, [nsteps] * len(ps), ["imag"] * len(ps))
+    e1.record()
+    b.sync()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    info = b.info()
+    b.close()
+    del ts
+    # the same solves one at a time, FP64
+    t64 = [torch.from_numpy(a).to("cuda") for a in psi0]
+    solvers = [binding.Solver(p, "fp64") for p in ps]
+    for s_, t in zip(solvers, t64):
+        s_.step_imag(t, 5)
+    torch.cuda.synchronize()
+    e0.record()
+    for s_, t in zip(solvers, t64):
+        s_.step_imag(t, nsteps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1)
+    for s_ in solvers:
+        s_.close()
+    del t64
+    torch.cuda.empty_cache()
+    out = {"workload": f"256 condensates, N = 32 k (k ~ U{{4..16}}), {nsteps} imaginary-time steps each",
+           "value_fp32_batched": pts / (ms_b / 1e3), "value_fp64_one_at_a_time": pts / (ms_s / 1e3),
+           "ms_batched": ms_b, "ms_one_at_a_time": ms_s, "unit": UNIT, "grouped": info["grouped"],
+           "individual": info["individual"], "x_points": info["x_points"][0], "y_tile": info["y_tile"][0]}
+    log(f"[bench] C4 batch: FP32 batched {out['value_fp32_batched']:.3e} pt-steps/s vs FP64 one at a time "
+        f"{out['value_fp64_one_at_a_time']:.3e} ({ms_b:.1f} ms vs {ms_s:.1f} ms)")
+    return out
+
+
+def serving_c5(torch, binding, inputs, n, rate):
+    """The serving trace (Poisson arrivals, N in {128..1024}, 500-5000 steps,
+    imaginary or real time, FP32) replayed in real time."""
+    trace = inputs.serving_trace(n, rate, seed=6)
+    reqs = []
+    for r in trace:
+        p = r["params"]
+        a = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], x0=p["x0"], y0=p["y0"], seed=r["seed"])
+        reqs.append(dict(r, psi=torch.from_numpy(a).to(torch.complex64).to("cuda")))
+    torch.cuda.synchronize()
+    res, st = binding.serve(reqs, "fp32", max_slots=256, hbm_budget_bytes=200e9, chunk_steps=250, time_scale=1.0)
+    out = {"workload": f"{n} requests, Poisson {rate:g}/s, N in {{128,256,512,1024}} (p .4/.3/.2/.1), "
+                       f"500-5000 steps, imaginary or real time, FP32, 200 GB budget",
+           "p50_latency_s": st["p50_latency"], "p99_latency_s": st["p99_latency"],
+           "mean_latency_s": st["mean_latency"], "served_rate": st["served_rate"],
+           "offered_rate": st["offered_rate"], "wall_s": st["wall_s"], "rounds": st["rounds"],
+           "mean_in_flight": st["mean_active"], "max_in_flight": st["max_active"], "unit_rate": UNIT}
+    log(f"[bench] C5 serving: p50 {st['p50_latency']:.3f} s, p99 {st['p99_latency']:.3f} s, served "
+        f"{st['served_rate']:.3e} vs offered {st['offered_rate']:.3e} pt-steps/s, {st['mean_active']:.1f} in flight")
+    del reqs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +191,10 @@ def main():
     ap.add_argument("--c3-steps", type=int, default=100, help="timed steps of the 4096^2 grid (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample length (0 = skip)")
     ap.add_argument("--timing-steps", type=int, default=500, help="steps of the per-kernel timing pass")
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="imaginary-time steps of the 256-condensate batch (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=25.0, help="arrival rate of the serving trace (1/s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (each condensate runs on "
@@ -181,6 +256,9 @@ def main():
             torch.cuda.empty_cache()
         del psi3
 
+    c4 = batch_c4(torch, binding, inputs, args.batch_steps) if args.batch_steps > 0 else None
+    c5 = serving_c5(torch, binding, inputs, args.serve_requests, args.serve_rate) if args.serve_requests > 0 else None
+
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(p, psi0, args.cpu_seconds)
@@ -206,7 +284,12 @@ def main():
                         "step_roofline_frac": round(v["step_frac"], 4)} for k, v in c3.items()},
         "plan": {"x_points_per_thread": r["plan"]["x_points_per_thread"], "y_solver": r["plan"]["y_solver"],
                  "y_halo": r["plan"]["y_halo"]},
+        "batch_c4": c4,
+        "serving_c5": c5,
     }
+    if c5 is not None:
+        line["p50_latency_s"] = c5["p50_latency_s"]
+        line["p99_latency_s"] = c5["p99_latency_s"]
     print(json.dumps(line), flush=True)
 
 

@@ -234,6 +234,54 @@ int gp_spin1_batch_info_read(const gp_spin1_batch_t* b, gp_spin1_batch_info* out
 int gp_spin1_batch_destroy(gp_spin1_batch_t* b);
 const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b);
 
+/* ---------------------------------------------------------------------------
+ * Serving loop.  Replays a trace of independent solve requests against the
+ * clock on one batch: requests are admitted in arrival order while a slot is
+ * free and the device-memory budget allows (an admitted condensate is charged
+ * 2 * 3 nx ny s bytes for its wave function and work copy, 432 (nx + ny) s
+ * for its line tables and 64 KiB of scratch, s = 16 or 8); each round advances every admitted
+ * condensate together by the steps left to the nearest completion (at most
+ * chunk_steps), so requests join and leave between rounds.  A request's
+ * latency runs from its arrival to the end of the round that completes it.
+ *
+ * req[n]: sorted by arrival (seconds after the start of the trace, scaled by
+ *   time_scale; 0 replays every request as arriving at once); p as for
+ *   gp_spin1_create, the same precision for all; nsteps >= 1 steps in mode
+ *   (0 imaginary time, 1 real time) advance psi_dev (caller-owned device
+ *   memory in the usual layout) in place.
+ * out[n]: admission and completion times (seconds after the start).
+ * stats: wall time, pt-steps served, served and offered pt-steps per second,
+ *   latency percentiles (p50, p99; linear interpolation), rounds and mean /
+ *   maximum condensates in flight.
+ * Blocks until every request is done.  Allocates the slot tables as requests
+ * are admitted and frees them as they complete.  GP_EINVAL for unsorted or
+ * malformed requests or a request larger than the budget; errors of the
+ * batch calls otherwise (message on stderr). */
+typedef struct {
+    double arrival;        /* seconds after the start of the trace */
+    gp_spin1_params p;
+    int64_t nsteps;
+    int32_t mode;          /* 0 imaginary time, 1 real time */
+    void* psi_dev;
+} gp_spin1_request;
+typedef struct {
+    int32_t max_slots;        /* condensates in flight at most (1 .. 4096) */
+    double hbm_budget_bytes;  /* device bytes the admitted condensates may hold */
+    int64_t chunk_steps;      /* steps per round at most (0: to the nearest completion) */
+    double time_scale;        /* factor on the arrival times (1 = real time) */
+} gp_spin1_serve_config;
+typedef struct {
+    double start, finish;     /* seconds after the start of the trace */
+} gp_spin1_request_result;
+typedef struct {
+    double wall_s, pt_steps, served_rate, offered_rate;
+    double p50_latency, p99_latency, mean_latency, max_latency;
+    int32_t completed, max_active, rounds;
+    double mean_active;
+} gp_spin1_serve_stats;
+int gp_spin1_serve(const gp_spin1_request* req, int32_t n, const gp_spin1_serve_config* cfg, void* hip_stream,
+                   gp_spin1_request_result* out, gp_spin1_serve_stats* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ EXPORTS = ("gp_spin1_create", "gp_spin1_destroy", "gp_spin1_step_imag", "gp_spin
            "gp_spin1_strerror", "gp_spin1_last_error",
            "gp_spin1_batch_create", "gp_spin1_batch_set_slot", "gp_spin1_batch_step", "gp_spin1_batch_sync",
            "gp_spin1_batch_observables", "gp_spin1_batch_info_read", "gp_spin1_batch_destroy",
-           "gp_spin1_batch_last_error")
+           "gp_spin1_batch_last_error", "gp_spin1_serve")
 
 
 class LibraryNotBuilt(RuntimeError):
@@ -81,6 +81,28 @@ class BatchInfo(ctypes.Structure):
                 ("launches", ctypes.c_int64)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("arrival", ctypes.c_double), ("p", Params), ("nsteps", ctypes.c_int64), ("mode", ctypes.c_int32),
+                ("psi_dev", ctypes.c_void_p)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_double),
+                ("chunk_steps", ctypes.c_int64), ("time_scale", ctypes.c_double)]
+
+
+class RequestResult(ctypes.Structure):
+    _fields_ = [("start", ctypes.c_double), ("finish", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("wall_s", ctypes.c_double), ("pt_steps", ctypes.c_double), ("served_rate", ctypes.c_double),
+                ("offered_rate", ctypes.c_double), ("p50_latency", ctypes.c_double),
+                ("p99_latency", ctypes.c_double), ("mean_latency", ctypes.c_double),
+                ("max_latency", ctypes.c_double), ("completed", ctypes.c_int32), ("max_active", ctypes.c_int32),
+                ("rounds", ctypes.c_int32), ("mean_active", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -116,6 +138,8 @@ def load():
         "gp_spin1_batch_info_read": [vp, ctypes.POINTER(BatchInfo)],
         "gp_spin1_batch_destroy": [vp],
     })
+    sig["gp_spin1_serve"] = [ctypes.POINTER(Request), i32, ctypes.POINTER(ServeConfig), vp,
+                             ctypes.POINTER(RequestResult), ctypes.POINTER(ServeStats)]
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
@@ -347,3 +371,33 @@ class Batch:
 
     def __exit__(self, *a):
         self.close()
+
+
+def serve(requests, precision: str = "fp32", max_slots: int = 64, hbm_budget_bytes: float = 200e9,
+          chunk_steps: int = 250, time_scale: float = 1.0, stream=None):
+    """Replay a request trace through the library's serving loop.  Each
+    request is a mapping with keys arrival (s), params (mapping), nsteps,
+    mode ('imag' / 'real') and psi (device tensor, advanced in place).
+    Returns (per-request [(start, finish)], stats dict)."""
+    import torch
+    lib = load()
+    n = len(requests)
+    arr = (Request * n)()
+    dtype = torch.complex128 if precision == "fp64" else torch.complex64
+    for k, r in enumerate(requests):
+        p = r["params"]
+        t = r["psi"]
+        if t.dtype != dtype or tuple(t.shape) != (3, int(p["ny"]), int(p["nx"])) or not t.is_contiguous() \
+                or not t.is_cuda:
+            raise ValueError(f"request {k}: psi must be a contiguous CUDA {dtype} tensor of shape (3, ny, nx)")
+        arr[k] = Request(float(r["arrival"]), make_params(p, precision), int(r["nsteps"]), MODES[r["mode"]],
+                         ctypes.c_void_p(t.data_ptr()))
+    cfg = ServeConfig(int(max_slots), float(hbm_budget_bytes), int(chunk_steps), float(time_scale))
+    out = (RequestResult * n)()
+    st = ServeStats()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    rc = lib.gp_spin1_serve(arr, n, ctypes.byref(cfg), ctypes.c_void_p(stream.cuda_stream), out, ctypes.byref(st))
+    if rc != GP_OK:
+        raise GPError(rc, "gp_spin1_serve: " + lib.gp_spin1_strerror(rc).decode())
+    return [(o.start, o.finish) for o in out], {k: getattr(st, k) for k, _ in ServeStats._fields_}

@@ -3,12 +3,16 @@
 // step sequencing on the caller's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <climits>
 #include <cmath>
 #include <complex>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gp_kernels.hpp"
@@ -940,6 +944,156 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
     return GP_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// Serving: a trace of requests (arrival time, parameters, steps, mode, a
+// device wave function each) replayed against the clock.  Requests are
+// admitted in arrival order into the slots of one batch while a slot is free
+// and the device-memory budget allows; every round advances all admitted
+// condensates together by the steps left to the nearest completion (at most
+// chunk_steps), so requests join and leave between rounds (continuous
+// batching).  Latency runs from arrival to the end of the round that
+// completes the request.
+// ---------------------------------------------------------------------------
+// Device bytes a condensate holds while admitted: its wave function, the
+// work copy and the per-line tables (pivots + coefficients, both directions).
+size_t request_bytes(const gp_spin1_params& p) {
+    const size_t s = p.precision == GP_FP64 ? 16 : 8;
+    const size_t state = (size_t)3 * p.nx * p.ny * s;
+    const size_t tables = (size_t)2 * 3 * ((size_t)p.nx + p.ny) * 72 * s;  // generous bound
+    return 2 * state + tables + (1u << 16);
+}
+
+double seconds_since(const std::chrono::steady_clock::time_point& t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& cfg, hipStream_t st,
+              gp_spin1_request_result* out, gp_spin1_serve_stats* stats, std::string& err) {
+    const int prec = req[0].p.precision;
+    for (int k = 0; k < n; ++k) {
+        if (req[k].p.precision != prec) { err = "requests differ in precision"; return GP_EINVAL; }
+        if (req[k].nsteps < 1 || (req[k].mode != 0 && req[k].mode != 1) || !req[k].psi_dev) {
+            err = "request " + std::to_string(k) + ": nsteps < 1, bad mode or NULL psi";
+            return GP_EINVAL;
+        }
+        if (k && req[k].arrival < req[k - 1].arrival) { err = "requests must be sorted by arrival"; return GP_EINVAL; }
+        if ((double)request_bytes(req[k].p) > cfg.hbm_budget_bytes) {
+            err = "request " + std::to_string(k) + " alone exceeds the memory budget";
+            return GP_EINVAL;
+        }
+    }
+    const int ns = cfg.max_slots;
+    std::vector<gp_spin1_params> empty(ns);
+    for (auto& e : empty) { std::memset(&e, 0, sizeof e); e.precision = prec; }
+    gp_spin1_batch* b = nullptr;
+    int rc = gp_spin1_batch_create(empty.data(), ns, (void*)st, &b);
+    if (rc) { err = "batch create failed"; return rc; }
+    std::vector<int> who(ns, -1);
+    std::vector<int64_t> left(ns, 0);
+    std::vector<void*> psi(ns, nullptr);
+    std::vector<int64_t> nst(ns, 0);
+    std::vector<int32_t> md(ns, 0);
+    std::vector<uint8_t> on(ns, 0);
+    std::vector<double> lat;
+    lat.reserve(n);
+    double in_use = 0.0, active_sum = 0.0, pts = 0.0;
+    int next = 0, done = 0, active = 0, max_active = 0, rounds = 0;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto arrival = [&](int k) { return req[k].arrival * cfg.time_scale; };
+    while (done < n) {
+        double now = seconds_since(t0);
+        // admission, first come first served
+        for (int sl = 0; sl < ns && next < n; ++sl) {
+            if (who[sl] >= 0) continue;
+            if (arrival(next) > now) break;
+            const double need = (double)request_bytes(req[next].p);
+            if (in_use + need > cfg.hbm_budget_bytes) break;
+            rc = gp_spin1_batch_set_slot(b, sl, &req[next].p);
+            if (rc) { err = "request " + std::to_string(next) + ": " + b->err; break; }
+            who[sl] = next;
+            left[sl] = req[next].nsteps;
+            psi[sl] = req[next].psi_dev;
+            md[sl] = req[next].mode;
+            out[next].start = now;
+            in_use += need;
+            ++active;
+            ++next;
+        }
+        if (rc) break;
+        if (active == 0) {
+            // idle until the next arrival
+            if (next < n) {
+                const double wait = arrival(next) - seconds_since(t0);
+                if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
+            }
+            continue;
+        }
+        max_active = std::max(max_active, active);
+        int64_t c = cfg.chunk_steps > 0 ? cfg.chunk_steps : INT64_MAX;
+        for (int sl = 0; sl < ns; ++sl)
+            if (who[sl] >= 0) c = std::min(c, left[sl]);
+        for (int sl = 0; sl < ns; ++sl) {
+            on[sl] = who[sl] >= 0;
+            nst[sl] = on[sl] ? c : 0;
+        }
+        rc = gp_spin1_batch_step(b, psi.data(), nst.data(), md.data(), on.data());
+        if (rc) { err = b->err; break; }
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { err = std::string("serve: ") + hipGetErrorString(e); rc = GP_EHIP; break; }
+        now = seconds_since(t0);
+        ++rounds;
+        active_sum += active;
+        for (int sl = 0; sl < ns; ++sl) {
+            if (who[sl] < 0) continue;
+            const int k = who[sl];
+            pts += (double)c * req[k].p.nx * req[k].p.ny;
+            left[sl] -= c;
+            if (left[sl] > 0) continue;
+            out[k].finish = now;
+            lat.push_back(now - arrival(k));
+            in_use -= (double)request_bytes(req[k].p);
+            who[sl] = -1;
+            --active;
+            ++done;
+            rc = gp_spin1_batch_set_slot(b, sl, nullptr);
+            if (rc) { err = b->err; break; }
+        }
+        if (rc) break;
+    }
+    if (rc == GP_OK) rc = gp_spin1_batch_sync(b);
+    const double wall = seconds_since(t0);
+    (void)gp_spin1_batch_destroy(b);
+    if (rc) return rc;
+    std::sort(lat.begin(), lat.end());
+    auto pct = [&](double q) {
+        if (lat.empty()) return 0.0;
+        const double pos = q * (lat.size() - 1);
+        const size_t i = (size_t)pos;
+        const double f = pos - i;
+        return i + 1 < lat.size() ? lat[i] * (1 - f) + lat[i + 1] * f : lat[i];
+    };
+    double offered = 0.0;
+    for (int k = 0; k < n; ++k) offered += (double)req[k].nsteps * req[k].p.nx * req[k].p.ny;
+    const double span = n > 1 ? arrival(n - 1) - arrival(0) : 0.0;
+    std::memset(stats, 0, sizeof *stats);
+    stats->wall_s = wall;
+    stats->pt_steps = pts;
+    stats->served_rate = wall > 0 ? pts / wall : 0.0;
+    stats->offered_rate = span > 0 ? offered / span : 0.0;
+    stats->p50_latency = pct(0.50);
+    stats->p99_latency = pct(0.99);
+    double sum = 0.0;
+    for (double v : lat) sum += v;
+    stats->mean_latency = lat.empty() ? 0.0 : sum / lat.size();
+    stats->max_latency = lat.empty() ? 0.0 : lat.back();
+    stats->completed = done;
+    stats->max_active = max_active;
+    stats->rounds = rounds;
+    stats->mean_active = rounds ? active_sum / rounds : 0.0;
+    return GP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1140,6 +1294,20 @@ int gp_spin1_batch_destroy(gp_spin1_batch_t* b) {
 
 const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b) {
     return b ? b->err.c_str() : "null batch";
+}
+
+
+int gp_spin1_serve(const gp_spin1_request* req, int32_t n, const gp_spin1_serve_config* cfg, void* hip_stream,
+                   gp_spin1_request_result* out, gp_spin1_serve_stats* stats) {
+    if (!req || n < 1 || !cfg || !out || !stats) return GP_EINVAL;
+    if (cfg->max_slots < 1 || cfg->max_slots > gp::kMaxBatchSlots || !(cfg->hbm_budget_bytes > 0) ||
+        !(cfg->time_scale >= 0) || cfg->chunk_steps < 0)
+        return GP_EINVAL;
+    for (int k = 0; k < n; ++k) out[k].start = out[k].finish = -1.0;
+    std::string err;
+    const int rc = serve_run(req, n, *cfg, (hipStream_t)hip_stream, out, stats, err);
+    if (rc) std::fprintf(stderr, "gp_spin1_serve: %s\n", err.c_str());
+    return rc;
 }
 
 }  // extern "C"

@@ -104,3 +104,27 @@ def batch_scan(n_condensates: int = 256, seed: int = 5) -> list:
                           eta=1 if rng.random() < 0.5 else -1, rabi=float(rng.uniform(0, 0.5)),
                           omega=float(rng.uniform(0, 0.95))))
     return out
+
+
+def serving_trace(n_requests: int = 2000, rate: float = 200.0, seed: int = 6) -> list:
+    """Poisson arrivals of rate ``rate`` per second; N in {128, 256, 512, 1024}
+    with probability {0.4, 0.3, 0.2, 0.1} on the box [-12.8, 12.8) (dx = 25.6/N);
+    couplings drawn as in ``batch_scan``; steps ~ U{500..5000}; imaginary or
+    real time with probability 1/2, dt = 0.1 dx^2 (imaginary) or 0.025 dx^2
+    (real).  Returns dicts with arrival, params, nsteps, mode, seed (the
+    initial-state seed 10^6 + k)."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n_requests):
+        t += float(rng.exponential(1.0 / rate))
+        n = int(rng.choice([128, 256, 512, 1024], p=[0.4, 0.3, 0.2, 0.1]))
+        dx = 25.6 / n
+        imag = bool(rng.random() < 0.5)
+        p = params(n, n, dx, dt=(0.1 if imag else 0.025) * dx * dx, c0=float(rng.uniform(10, 500)),
+                   c2=float(rng.uniform(-20, 20)), gamma=float(rng.uniform(0, 1)),
+                   eta=1 if rng.random() < 0.5 else -1, rabi=float(rng.uniform(0, 0.5)),
+                   omega=float(rng.uniform(0, 0.95)))
+        out.append({"arrival": t, "params": p, "nsteps": int(rng.integers(500, 5001)),
+                    "mode": "imag" if imag else "real", "seed": 10 ** 6 + k})
+    return out

@@ -1,0 +1,109 @@
+"""Serving loop (gp_spin1_serve): requests admitted into one batch as they
+arrive and as memory allows, advanced together, retired as they finish.
+
+Every served wave function must equal the same request solved on its own
+handle (to rounding: rounds may group the request with different neighbours,
+so the batch launch shape can change between rounds), and the schedule must
+respect arrival order, the slot limit and the memory budget."""
+import numpy as np
+import pytest
+
+from paper_2105_10517_amd import binding, inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def small_trace(n, seed=7, rate=50.0, sizes=(32, 48, 64, 96)):
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        N = int(rng.choice(list(sizes)))
+        dx = 12.8 / N
+        imag = bool(rng.random() < 0.5)
+        p = inputs.params(N, N, dx, dt=(0.1 if imag else 0.025) * dx * dx, c0=float(rng.uniform(10, 200)),
+                          c2=float(rng.uniform(-10, 10)), gamma=float(rng.uniform(0, 1)),
+                          eta=1 if rng.random() < 0.5 else -1, rabi=float(rng.uniform(0, 0.5)),
+                          omega=float(rng.uniform(0, 0.9)))
+        out.append({"arrival": t, "params": p, "nsteps": int(rng.integers(5, 41)),
+                    "mode": "imag" if imag else "real", "seed": 10 ** 6 + k})
+    return out
+
+
+def with_states(trace, dtype):
+    out = []
+    for r in trace:
+        p = r["params"]
+        psi = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], x0=p["x0"], y0=p["y0"], seed=r["seed"])
+        out.append(dict(r, psi=torch.from_numpy(psi).to(dtype).to(DEV), psi0=psi))
+    return out
+
+
+def solo(r, precision, dtype):
+    s = binding.Solver(r["params"], precision)
+    t = torch.from_numpy(r["psi0"]).to(dtype).to(DEV)
+    (s.step_imag if r["mode"] == "imag" else s.step_real)(t, r["nsteps"])
+    s.sync()
+    out = t.cpu()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_served_states_equal_solo_runs(precision):
+    dtype = torch.complex128 if precision == "fp64" else torch.complex64
+    reqs = with_states(small_trace(12), dtype)
+    res, st = binding.serve(reqs, precision, max_slots=4, hbm_budget_bytes=1e9, chunk_steps=7, time_scale=0.0)
+    assert st["completed"] == len(reqs)
+    assert 1 <= st["max_active"] <= 4
+    assert st["rounds"] >= 1 and st["p99_latency"] >= st["p50_latency"] > 0
+    for k, r in enumerate(reqs):
+        start, finish = res[k]
+        assert 0 <= start < finish
+        want = solo(r, precision, dtype)
+        got = r["psi"].cpu()
+        err = float(torch.linalg.vector_norm((got - want).flatten()) / torch.linalg.vector_norm(want.flatten()))
+        assert err < (1e-12 if precision == "fp64" else 2e-6), (k, err)
+    # first come, first served
+    starts = [s for s, _ in res]
+    assert starts == sorted(starts)
+
+
+def charge(p, s=8):
+    """Device bytes the serving loop charges an admitted condensate."""
+    return 2 * 3 * p["nx"] * p["ny"] * s + 432 * (p["nx"] + p["ny"]) * s + 65536
+
+
+def test_memory_budget_limits_admission():
+    reqs = with_states(small_trace(5, seed=8, sizes=(64,)), torch.complex64)
+    sizes = sorted(charge(r["params"]) for r in reqs)
+    # room for the largest condensate, never for two at once
+    res, st = binding.serve(reqs, "fp32", max_slots=8, hbm_budget_bytes=sizes[0] + sizes[1] - 1, chunk_steps=0,
+                            time_scale=0.0)
+    assert sizes[-1] <= sizes[0] + sizes[1] - 1
+    assert st["completed"] == 5 and st["max_active"] == 1
+    for k in range(1, 5):
+        assert res[k][0] >= res[k - 1][1] - 1e-9  # admitted after the previous one finished
+
+
+def test_real_time_replay():
+    trace = small_trace(6, seed=9, rate=40.0)
+    reqs = with_states(trace, torch.complex64)
+    res, st = binding.serve(reqs, "fp32", max_slots=8, hbm_budget_bytes=1e9, chunk_steps=5, time_scale=1.0)
+    assert st["completed"] == 6
+    for k, r in enumerate(reqs):
+        assert res[k][0] >= r["arrival"] - 1e-3
+        assert res[k][1] > res[k][0]
+    assert st["offered_rate"] > 0 and st["served_rate"] > 0
+
+
+def test_unsorted_trace_is_refused():
+    reqs = with_states(small_trace(3, seed=10), torch.complex64)
+    reqs[0], reqs[2] = reqs[2], reqs[0]
+    with pytest.raises(binding.GPError) as ei:
+        binding.serve(reqs, "fp32", max_slots=2, time_scale=0.0)
+    assert ei.value.status == binding.GP_EINVAL
