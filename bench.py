@@ -56,6 +56,23 @@ def kernel_roofline(timing, npts, prec):
             "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in rows.items()}}
 
 
+def traffic_for(roof, prec, imag, plan, workload):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when there is none for these kernel sources."""
+    from paper_2105_10517_amd import profile_summary
+    t = profile_summary.read_traffic(os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.md"))
+    T = "double" if prec == "fp64" else "float"
+    im = "true" if imag else "false"
+    if roof["kernel"] == "x_sweep":
+        prefix = f"gp::k_x_scan<{T}, {im}, {plan['x_points_per_thread']}, "
+    else:
+        prefix = f"gp::k_y_window<{T}, {im}, {plan['y_rows_per_thread']}, {plan['y_tile_cols'] // 4}, "
+    for k, v in t.items():
+        if k.startswith(prefix):
+            return v
+    return None
+
+
 def time_steps(solver, t, nsteps, imag, torch):
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -220,6 +237,7 @@ def main():
         norm = s.observables(t)["norm_total"]
         tim = kernel_timing(s, t, args.timing_steps, False)
         roof = kernel_roofline(tim, npts, prec)
+        roof["traffic"] = traffic_for(roof, prec, False, s.plan(False), "c2_512")
         val = npts * args.steps / (ms / 1e3)
         step_bytes = 12 * bytes_per_complex(prec) * npts
         results[prec] = {"value": val, "ms_per_step": ms / args.steps, "roofline": roof,
@@ -244,6 +262,7 @@ def main():
             ms = time_steps(s, t, args.c3_steps, True, torch)
             tim = kernel_timing(s, t, max(10, args.c3_steps // 5), True)
             roof = kernel_roofline(tim, n3, prec)
+            roof["traffic"] = traffic_for(roof, prec, True, s.plan(True), "c3_4096")
             val = n3 * args.c3_steps / (ms / 1e3)
             step_bytes = 12 * bytes_per_complex(prec) * n3
             c3[prec] = {"value": val, "ms_per_step": ms / args.c3_steps, "roofline": roof,

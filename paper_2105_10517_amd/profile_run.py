@@ -25,6 +25,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"))
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--copy-mib", type=int, default=0, help="run a plain copy of this many MiB instead")
+    ap.add_argument("--autotune", action="store_true", help="tune the launch shapes first (as bench.py does)")
     args = ap.parse_args()
 
     import torch
@@ -45,7 +46,7 @@ def main():
         p, imag = inputs.config_c3(int(args.workload.split("_")[1])), True
     else:
         raise SystemExit(f"unknown workload {args.workload}")
-    s = binding.Solver(p, args.precision)
+    s = binding.Solver(p, args.precision, autotune=args.autotune)
     psi = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], seed=4, full_phase=imag)
     t = torch.from_numpy(psi).to("cuda").to(s.dtype)
     (s.step_imag if imag else s.step_real)(t, args.steps)

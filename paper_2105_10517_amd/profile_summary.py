@@ -1,0 +1,140 @@
+"""Text summaries of rocprofv3 output for ``profiles/``.
+
+    python3 paper_2105_10517_amd/profile_summary.py stats RUN_DIR --command "..." --out profiles/NAME.md
+    python3 paper_2105_10517_amd/profile_summary.py traffic --fetch DIR --write DIR --copy-fetch DIR \
+        --copy-write DIR --copy-mib 512 --command "..." --out profiles/NAME.md
+
+``stats`` condenses ``*_kernel_stats.csv`` of a ``--kernel-trace --stats``
+run (calls, mean / min / max duration per kernel).  ``traffic`` turns
+``FETCH_SIZE`` and ``WRITE_SIZE`` passes (KiB per dispatch) into bytes per
+launch of every SSCN kernel, scaled by what the same counters read for a
+plain device copy of known size, and records a hash of the kernel sources so
+that a reader (``bench.py``) can tell whether the numbers still describe the
+kernels it runs.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the device and launch sources of the library."""
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".hip", ".hpp")) and f != "gp_runtime.hip":
+            h.update(f.encode())
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    n = re.sub(r"\(.*", "", name)
+    n = re.sub(r"^void ", "", n)
+    return n
+
+
+def find(d: str, suffix: str) -> str:
+    hits = glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def counters(d: str, counter: str) -> dict:
+    """Mean value per dispatch of one counter, per kernel."""
+    acc = {}
+    for row in csv.DictReader(open(find(d, "counter_collection.csv"))):
+        if row["Counter_Name"] != counter:
+            continue
+        acc.setdefault(short(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def cmd_stats(a):
+    rows = list(csv.DictReader(open(find(a.run_dir, "kernel_stats.csv"))))
+    lines = [f"# Kernel durations: {a.title}", "", "Command:", "", "```", a.command, "```", "",
+             f"Kernel sources: `{kernel_source_hash()}`", "",
+             "| kernel | calls | mean us | min us | max us | share |", "|---|---:|---:|---:|---:|---:|"]
+    for r in rows:
+        lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}% |")
+    open(a.out, "w").write("\n".join(lines) + "\n")
+
+
+def cmd_traffic(a):
+    copy_bytes = a.copy_mib * (1 << 20)
+    cf = counters(a.copy_fetch, "FETCH_SIZE")
+    cw = counters(a.copy_write, "WRITE_SIZE")
+    ck = max(cf, key=cf.get)  # the copy kernel reads the most
+    f_scale = copy_bytes / (cf[ck] * 1024.0)
+    w_scale = copy_bytes / (cw[max(cw, key=cw.get)] * 1024.0)
+    fetch = counters(a.fetch, "FETCH_SIZE")
+    write = counters(a.write, "WRITE_SIZE")
+    s = 16 if a.precision == "fp64" else 8
+    algo = 3 * s * a.points  # read or write of one sweep kernel, bytes per launch
+    lines = [f"# HBM traffic per launch: {a.title}", "", "Commands (one counter per pass):", "", "```",
+             a.command, "```", "",
+             f"Kernel sources: `{kernel_source_hash()}`", "",
+             f"Calibration: a plain copy of {a.copy_mib} MiB reads FETCH_SIZE = {cf[ck]:.0f} KiB and "
+             f"WRITE_SIZE = {cw[max(cw, key=cw.get)]:.0f} KiB per dispatch: fetch factor {f_scale:.3f}, "
+             f"write factor {w_scale:.3f}.", "",
+             f"Algorithmic bytes per sweep launch: read {algo} B + write {algo} B "
+             f"(3 complex values of {s} B per point, {a.points} points).", "",
+             "| kernel | fetch B | write B | traffic B | fetch / algo | write / algo |",
+             "|---|---:|---:|---:|---:|---:|"]
+    for k in sorted(set(fetch) & set(write)):
+        if "k_x_" not in k and "k_y_" not in k:
+            continue
+        fb = fetch[k] * 1024.0 * f_scale
+        wb = write[k] * 1024.0 * w_scale
+        lines.append(f"| `{k}` | {fb:.4g} | {wb:.4g} | {fb + wb:.4g} | {fb / algo:.3f} | {wb / algo:.3f} |")
+    open(a.out, "w").write("\n".join(lines) + "\n")
+
+
+def read_traffic(path: str) -> dict:
+    """Kernel -> traffic bytes per launch from a summary written by ``traffic``,
+    or {} when the kernel sources have changed since."""
+    if not os.path.exists(path):
+        return {}
+    txt = open(path).read()
+    m = re.search(r"Kernel sources: `([0-9a-f]+)`", txt)
+    if not m or m.group(1) != kernel_source_hash():
+        return {}
+    out = {}
+    for line in txt.splitlines():
+        mm = re.match(r"\| `([^`]+)` \| ([0-9.e+]+) \| ([0-9.e+]+) \| ([0-9.e+]+) \|", line)
+        if mm:
+            out[mm.group(1)] = float(mm.group(4))
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("run_dir")
+    s.add_argument("--command", required=True)
+    s.add_argument("--title", default="")
+    s.add_argument("--out", required=True)
+    t = sub.add_parser("traffic")
+    for k in ("fetch", "write", "copy_fetch", "copy_write"):
+        t.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
+    t.add_argument("--copy-mib", type=int, required=True)
+    t.add_argument("--points", type=int, required=True, help="grid points nx ny of the workload")
+    t.add_argument("--precision", choices=("fp64", "fp32"), required=True)
+    t.add_argument("--command", required=True)
+    t.add_argument("--title", default="")
+    t.add_argument("--out", required=True)
+    a = ap.parse_args()
+    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    main()
