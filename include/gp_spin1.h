@@ -68,6 +68,14 @@ typedef enum {
     GP_YSOLVER_THOMAS = 2  /* exact per-thread Thomas down whole columns (one thread per column) */
 } gp_ysolver;
 
+/* Order of the substeps within one step. */
+typedef enum {
+    GP_SPLIT_LIE = 0,    /* local substep (dt), x sweep, y sweep: the order the paper's scheme name implies */
+    GP_SPLIT_STRANG = 1  /* local substep (dt/2), x sweep, y sweep, local substep (dt/2): symmetric in the
+                            local / linear split (second order in dt where the sweeps commute, i.e.
+                            Omega = gamma = 0, and the frozen local exponential is exact) */
+} gp_split;
+
 typedef struct {
     int32_t nx, ny;    /* grid points, each >= 3; nx <= 8192 (one row is held on chip)        */
     double dx, dy;     /* grid steps, > 0 (lengths in l0)                                      */
@@ -84,6 +92,15 @@ typedef struct {
     int32_t y_tile;    /* tile shape of the windowed y sweep: 0 = chosen by the library, else 1..4            */
     int32_t autotune;  /* != 0: time the candidate x and y launch shapes at creation and keep the fastest
                           (only for the fields left at 0); the choice depends on the grid shape only        */
+    double trap_gx, trap_gy; /* trap V = (gx^2 x^2 + gy^2 y^2)/2 (Eq. (S.3) with the harmonic trap, optionally
+                                anisotropic); 0 selects 1, the paper's isotropic trap                        */
+    int32_t split;           /* gp_split                                                                   */
+    int32_t fix_magnetization; /* imaginary time: != 0 renormalises to total norm 1 AND magnetisation
+                                  N_{+1} - N_{-1} = magnetization (the two conditions stated after Eq. (S.5)),
+                                  with the third condition s_{+1} s_{-1} = s_0^2 on the component scale
+                                  factors of the normalised gradient flow (Bao and Lim, SIAM J. Sci.
+                                  Comput. 30, 2008); needs gamma = rabi = 0 and |magnetization| < 1     */
+    double magnetization;
 } gp_spin1_params;
 
 /* Observables of one wave function (all FP64, rectangle-rule quadrature

@@ -7,7 +7,9 @@ arithmetic, this module only marshals numpy arrays through ctypes.
 
 Parameters are passed as a plain mapping with the keys
 ``nx, ny, dx, dy, x0, y0, dt, c0, c2, gamma, eta, rabi, omega`` (explicit grid
-origins: x_i = x0 + i dx, y_j = y0 + j dy).  Wave functions are complex128
+origins: x_i = x0 + i dx, y_j = y0 + j dy) and the optional keys ``gx, gy``
+(trap frequencies, default 1), ``split`` (0 Lie, 1 Strang), ``fix_m`` and
+``magnetization`` (imaginary-time projection to a fixed magnetisation).  Wave functions are complex128
 arrays of shape (3, ny, nx), components ordered m = +1, 0, -1.
 
 Every function cites the passage of arXiv:2105.10517 it follows; the C file
@@ -23,6 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIBPATH = os.path.join(_HERE, "liboracle.so")
 
 PARAM_KEYS = ("nx", "ny", "dx", "dy", "x0", "y0", "dt", "c0", "c2", "gamma", "eta", "rabi", "omega")
+OPTIONAL_KEYS = {"gx": 1.0, "gy": 1.0, "split": 0, "fix_m": 0, "magnetization": 0.0}
 
 
 class _Params(ctypes.Structure):
@@ -30,7 +33,9 @@ class _Params(ctypes.Structure):
                 ("dx", ctypes.c_double), ("dy", ctypes.c_double),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("dt", ctypes.c_double),
                 ("c0", ctypes.c_double), ("c2", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("eta", ctypes.c_int32), ("rabi", ctypes.c_double), ("omega", ctypes.c_double)]
+                ("eta", ctypes.c_int32), ("rabi", ctypes.c_double), ("omega", ctypes.c_double),
+                ("gx", ctypes.c_double), ("gy", ctypes.c_double), ("split", ctypes.c_int32),
+                ("fix_m", ctypes.c_int32), ("magnetization", ctypes.c_double)]
 
 
 class _Obs(ctypes.Structure):
@@ -79,7 +84,9 @@ def _params(p) -> _Params:
         raise KeyError(f"oracle parameters missing {missing}")
     return _Params(int(p["nx"]), int(p["ny"]), float(p["dx"]), float(p["dy"]), float(p["x0"]),
                    float(p["y0"]), float(p["dt"]), float(p["c0"]), float(p["c2"]), float(p["gamma"]),
-                   int(p["eta"]), float(p["rabi"]), float(p["omega"]))
+                   int(p["eta"]), float(p["rabi"]), float(p["omega"]),
+                   float(p.get("gx", 1.0)), float(p.get("gy", 1.0)), int(p.get("split", 0)),
+                   int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)))
 
 
 def _checked(p, psi):

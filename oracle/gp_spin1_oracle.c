@@ -25,6 +25,8 @@
  *   - 3-point second difference, central first difference, psi = 0 on the
  *     ghost points just outside the grid.
  *   - V = (x^2 + y^2)/2 (isotropic harmonic trap, lengths in l0).  [Eq. S.3]
+ *     Optionally anisotropic, V = (gx^2 x^2 + gy^2 y^2)/2 (the paper calls
+ *     V "the confining trap" without fixing its shape).
  *   - The local substep applies the exact exponential of the 3x3 Hermitian
  *     matrix H_loc = (V + c0 rho) I + c2 F.Sigma + R Sigma_x, frozen at the
  *     substep input; H_loc psi reproduces every non-derivative term of
@@ -34,6 +36,13 @@
  *   - Real time: CN with alpha = i dt/2, local factor exp(-i dt H_loc).
  *   - Rectangle-rule quadrature; kinetic energy from forward differences over
  *     the ghost-padded range (equal to <psi| -D2/2 |psi>).
+ *   - Optional Strang order: half local substep, x sweep, y sweep, half local
+ *     substep (second order in dt for the same substeps).
+ *   - Optional fixed magnetisation in imaginary time (gamma = R = 0): after
+ *     each step the components are rescaled so that the total norm is 1 and
+ *     N_{+1} - N_{-1} = m (normalisation and magnetisation conditions stated
+ *     with Eq. (S.5)), with the third condition s_{+1} s_{-1} = s_0^2 of the
+ *     normalised gradient flow of Bao and Lim (SIAM J. Sci. Comput. 30, 2008).
  *
  * Layout of every wave function: psi[(m * ny + j) * nx + i], m = 0 (+1),
  * 1 (0), 2 (-1); x_i = x0 + i dx, y_j = y0 + j dy.
@@ -57,6 +66,10 @@ typedef struct {
     double c0, c2, gamma;
     int32_t eta; /* +1 Rashba, -1 Dresselhaus */
     double rabi, omega;
+    double gx, gy;        /* trap V = (gx^2 x^2 + gy^2 y^2)/2; 1, 1 is the paper's isotropic trap */
+    int32_t split;        /* 0 Lie: local, x, y; 1 Strang: local(dt/2), x, y, local(dt/2) */
+    int32_t fix_m;        /* imaginary time: project to norm 1 and magnetisation `magnetization` */
+    double magnetization;
 } orc_params;
 
 typedef struct {
@@ -192,6 +205,11 @@ static void m3_expm(const cplx A[9], cplx E[9]) {
  * which reproduces the bracketed c2 terms, the {} spin-mixing terms and the
  * Rabi terms of Eqs. (S.1)-(S.2), with the trap and c0 rho of H in Eq. (S.3).
  * ------------------------------------------------------------------------- */
+/* Trap potential V(x, y) (Eq. S.3, harmonic, optionally anisotropic). */
+static double orc_trap(const orc_params *p, double x, double y) {
+    return 0.5 * (p->gx * p->gx * x * x + p->gy * p->gy * y * y);
+}
+
 void orc_local_matrix(const orc_params *p, const cplx v[3], double x, double y, cplx H[9]) {
     cplx Sx[9], Sy[9], Sz[9], w[3];
     spin_x(Sx); spin_y(Sy); spin_z(Sz);
@@ -202,7 +220,7 @@ void orc_local_matrix(const orc_params *p, const cplx v[3], double x, double y, 
         m3_vec(S[a], v, w);
         F[a] = creal(conj(v[0]) * w[0] + conj(v[1]) * w[1] + conj(v[2]) * w[2]);
     }
-    const double V = 0.5 * (x * x + y * y);
+    const double V = orc_trap(p, x, y);
     m3_eye(H);
     for (int k = 0; k < 9; ++k)
         H[k] = H[k] * (V + p->c0 * rho) + p->c2 * (F[0] * Sx[k] + F[1] * Sy[k] + F[2] * Sz[k]) + p->rabi * Sx[k];
@@ -384,19 +402,58 @@ double orc_norm(const orc_params *p, const cplx *psi) {
     return s * p->dx * p->dy;
 }
 
-void orc_normalize(const orc_params *p, cplx *psi) {
-    const double f = 1.0 / sqrt(orc_norm(p, psi));
-    const size_t n = (size_t)3 * p->nx * p->ny;
-    for (size_t k = 0; k < n; ++k) psi[k] *= f;
+/* Norm of one component, N_m = dx dy sum |psi_m|^2. */
+static double orc_component_norm(const orc_params *p, const cplx *psi, int m) {
+    double s = 0.0;
+    for (int j = 0; j < p->ny; ++j) {
+        double r = 0.0;
+        for (int i = 0; i < p->nx; ++i) {
+            const cplx v = psi[IDX(p, m, j, i)];
+            r += creal(v) * creal(v) + cimag(v) * cimag(v);
+        }
+        s += r;
+    }
+    return s * p->dx * p->dy;
 }
 
-/* One SSCN step = local substep, x sweep, y sweep, then (imaginary time)
- * renormalisation to unit norm. */
+/* Imaginary-time normalisation.  Total norm: psi <- psi / sqrt(N).  Fixed
+ * magnetisation m: psi_j <- s_j psi_j with
+ *   s_{+1}^2 N_{+1} + s_0^2 N_0 + s_{-1}^2 N_{-1} = 1,
+ *   s_{+1}^2 N_{+1} - s_{-1}^2 N_{-1} = m,
+ *   s_{+1} s_{-1} = s_0^2.
+ * The first two give s_{+-1}^2 = (1 +- m - u N_0) / (2 N_{+-1}) with
+ * u = s_0^2; the third then reads
+ *   (N_0^2 - 4 N_{+1} N_{-1}) u^2 - 2 N_0 u + (1 - m^2) = 0,
+ * whose root that stays finite as N_0^2 -> 4 N_{+1} N_{-1} is
+ *   u = (1 - m^2) / (N_0 + sqrt(m^2 N_0^2 + 4 (1 - m^2) N_{+1} N_{-1})). */
+void orc_normalize(const orc_params *p, cplx *psi) {
+    double f[3];
+    if (p->fix_m) {
+        const double n1 = orc_component_norm(p, psi, 0), n0 = orc_component_norm(p, psi, 1),
+                     nm = orc_component_norm(p, psi, 2), m = p->magnetization;
+        const double u = (1.0 - m * m) / (n0 + sqrt(m * m * n0 * n0 + 4.0 * (1.0 - m * m) * n1 * nm));
+        f[1] = sqrt(u);
+        f[0] = sqrt((1.0 + m - u * n0) / (2.0 * n1));
+        f[2] = sqrt((1.0 - m - u * n0) / (2.0 * nm));
+    } else {
+        f[0] = f[1] = f[2] = 1.0 / sqrt(orc_norm(p, psi));
+    }
+    const size_t plane = (size_t)p->nx * p->ny;
+    for (int c = 0; c < 3; ++c)
+        for (size_t k = 0; k < plane; ++k) psi[c * plane + k] *= f[c];
+}
+
+/* One SSCN step.  Lie: local substep, x sweep, y sweep; Strang: half local
+ * substep, x sweep, y sweep, half local substep; then (imaginary time) the
+ * normalisation. */
 void orc_step(const orc_params *p, cplx *psi, int64_t nsteps, int imag) {
+    orc_params half = *p;
+    half.dt = 0.5 * p->dt;
     for (int64_t s = 0; s < nsteps; ++s) {
-        orc_pointwise(p, psi, imag);
+        orc_pointwise(p->split ? &half : p, psi, imag);
         orc_sweep_x(p, psi, imag);
         orc_sweep_y(p, psi, imag);
+        if (p->split) orc_pointwise(&half, psi, imag);
         if (imag) orc_normalize(p, psi);
     }
 }
@@ -429,7 +486,7 @@ void orc_apply_h(const orc_params *p, const cplx *psi, cplx *out) {
             }
             const double rp = creal(v[0] * conj(v[0])), r0 = creal(v[1] * conj(v[1])), rm = creal(v[2] * conj(v[2]));
             const double rho = rp + r0 + rm;
-            const double V = 0.5 * (x * x + y * y);
+            const double V = orc_trap(p, x, y);
             cplx Hv[3];
             for (int m = 0; m < 3; ++m) {
                 const cplx Lz = -I * (x * ddy[m] - y * ddx[m]);
@@ -488,7 +545,7 @@ void orc_observables(const orc_params *p, const cplx *psi, orc_obs *o) {
             }
             const double rp = creal(v[0] * conj(v[0])), r0 = creal(v[1] * conj(v[1])), rm = creal(v[2] * conj(v[2]));
             const double rho = rp + r0 + rm;
-            const double V = 0.5 * (x * x + y * y);
+            const double V = orc_trap(p, x, y);
             q[Q_N0] += rp; q[Q_N1] += r0; q[Q_N2] += rm;
             q[Q_TRAP] += V * rho;
             /* 1/2 { c0 rho^2 + c2 [ ... ] } of Eq. (S.6) */

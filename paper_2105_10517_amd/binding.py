@@ -47,7 +47,9 @@ class Params(ctypes.Structure):
                 ("c0", ctypes.c_double), ("c2", ctypes.c_double), ("gamma", ctypes.c_double),
                 ("eta", ctypes.c_int32), ("rabi", ctypes.c_double), ("omega", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("y_solver", ctypes.c_int32),
-                ("x_points", ctypes.c_int32), ("y_tile", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("x_points", ctypes.c_int32), ("y_tile", ctypes.c_int32), ("autotune", ctypes.c_int32),
+                ("trap_gx", ctypes.c_double), ("trap_gy", ctypes.c_double), ("split", ctypes.c_int32),
+                ("fix_magnetization", ctypes.c_int32), ("magnetization", ctypes.c_double)]
 
 
 class Obs(ctypes.Structure):
@@ -157,14 +159,16 @@ def load():
 def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0, y_tile: int = 0,
                 autotune: bool = False) -> Params:
     """Params from a plain mapping (keys nx, ny, dx, dy, x0, y0, dt, c0, c2,
-    gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2)."""
+    gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2;
+    optional gx, gy (trap), split (0 Lie, 1 Strang), fix_m and magnetization)."""
     prec = {"fp64": GP_FP64, "fp32": GP_FP32}[precision]
     ys = {"auto": GP_YSOLVER_AUTO, "window": GP_YSOLVER_WINDOW, "thomas": GP_YSOLVER_THOMAS}[y_solver]
     return Params(int(p["nx"]), int(p["ny"]), float(p["dx"]), float(p.get("dy", p["dx"])),
                   float(p.get("x0", math.nan)), float(p.get("y0", math.nan)), float(p["dt"]),
                   float(p.get("c0", 0.0)), float(p.get("c2", 0.0)), float(p.get("gamma", 0.0)),
                   int(p.get("eta", 1)), float(p.get("rabi", 0.0)), float(p.get("omega", 0.0)), prec, ys,
-                  int(x_points), int(y_tile), int(bool(autotune)))
+                  int(x_points), int(y_tile), int(bool(autotune)), float(p.get("gx", 1.0)), float(p.get("gy", 1.0)),
+                  int(p.get("split", 0)), int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)))
 
 
 def _obs_dict(o: Obs) -> dict:

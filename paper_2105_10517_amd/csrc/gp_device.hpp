@@ -81,7 +81,13 @@ struct Phys {
     int nx, ny;
     double dx, dy, x0, y0, dt;
     double c0, c2, rabi;
+    double dtl;       // time step of each local substep: dt (Lie) or dt/2 (Strang, two per step)
+    double gx2, gy2;  // trap V = (gx^2 x^2 + gy^2 y^2)/2
 };
+
+template <typename T> __device__ inline T trap_v(const Phys& ph, T x, T y) {
+    return (T)0.5 * ((T)ph.gx2 * x * x + (T)ph.gy2 * y * y);
+}
 
 // ---------------------------------------------------------------------------
 // Local substep, closed form.  With B = c2 F + R e_x, b = |B| and M = B.Sigma

@@ -27,11 +27,18 @@ __host__ __device__ constexpr int xk_bound(int K) { return K == 1 ? 1024 : 512; 
 
 // Both sweeps run out of place (src -> dst): the y windows overlap, so a
 // window's halo rows must not be rewritten by its neighbour while it reads.
-// Where the y sweep leaves the imaginary-time norm: one partial sum per block
-// (summed by launch_norm_finalize into the scale factor and the non-finite
-// flag).
+// Where the y sweep leaves the imaginary-time norm: three partial sums per
+// block, one per component (partials[3 blk + m]); launch_norm_finalize turns
+// them into the three scale factors of the next step and the non-finite flag.
 struct NormOut {
     double* partials;
+};
+
+// How the norm totals become scale factors: the total norm to one, or (fixed
+// magnetisation) the component norms to total one and N_{+1} - N_{-1} = mag.
+struct NormRule {
+    int fix_m;
+    double mag;
 };
 
 template <typename T> struct XLaunch {
@@ -52,6 +59,7 @@ template <typename T> struct YLaunch {
     NormOut no;
     int L, h, tile;
     bool window, imag, norm;
+    bool outl;  // second half local substep on the way out (Strang)
 };
 
 // Batched launches: one descriptor per condensate and one map entry per block,
@@ -85,11 +93,12 @@ struct NSlot {
     double dxdy;
     double* scale;
     int* flag;
+    NormRule rule;
 };
 
 template <typename T> struct SSlot {
     cx<T>* psi;
-    size_t n;
+    size_t plane;
     const double* scale;
 };
 
@@ -106,14 +115,16 @@ template <typename T>
 hipError_t launch_y(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T> int y_blocks(const YLaunch<T>& a);
 template <typename T> hipError_t launch_local(cx<T>* psi, const Phys& ph, bool imag, hipStream_t st);
+// psi[m][plane] *= scale[m] (three factors, one per component)
 template <typename T>
-hipError_t launch_scale(cx<T>* psi, size_t n, const double* scale, hipStream_t st, hipEvent_t e0 = nullptr,
+hipError_t launch_scale(cx<T>* psi, size_t plane, const double* scale, hipStream_t st, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
 template <typename T>
-hipError_t launch_norm_partials(const cx<T>* psi, size_t n, double* partials, int nblk, hipStream_t st);
+hipError_t launch_norm_partials(const cx<T>* psi, size_t plane, double* partials, int nblk, hipStream_t st);
 hipError_t launch_set_scale(double* scale, double v, hipStream_t st);
-hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, double* scale, int* flag, hipStream_t st,
-                                hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// n blocks' worth of partials (3 n values) -> scale[3], flag
+hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, NormRule rule, double* scale, int* flag,
+                                hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
 hipError_t launch_obs(const cx<T>* psi, const Phys& ph, const ObsLaunch& o, T* dens, double* partials, int nblk,
                       hipStream_t st);

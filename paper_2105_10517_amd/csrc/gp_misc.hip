@@ -16,48 +16,54 @@ __global__ __launch_bounds__(256) void k_local(cx<T>* __restrict__ psi, Phys ph)
         const int i = (int)(idx % ph.nx), j = (int)(idx / ph.nx);
         const T x = (T)(ph.x0 + i * ph.dx), y = (T)(ph.y0 + j * ph.dy);
         cx<T> p = psi[idx], z = psi[plane + idx], m = psi[2 * plane + idx];
-        local_substep<T, IMAG>(p, z, m, (T)0.5 * (x * x + y * y), (T)ph.dt, (T)ph.c0, (T)ph.c2, (T)ph.rabi);
+        local_substep<T, IMAG>(p, z, m, trap_v<T>(ph, x, y), (T)ph.dt, (T)ph.c0, (T)ph.c2, (T)ph.rabi);
         psi[idx] = p; psi[plane + idx] = z; psi[2 * plane + idx] = m;
     }
 }
 
+// psi[m][.] *= scale[m]
 template <typename T>
-__global__ __launch_bounds__(256) void k_scale(cx<T>* __restrict__ psi, size_t n, const double* __restrict__ scale) {
-    const T s = (T)(*scale);
+__global__ __launch_bounds__(256) void k_scale(cx<T>* __restrict__ psi, size_t plane, const double* __restrict__ scale) {
+    const T s[3] = {(T)scale[0], (T)scale[1], (T)scale[2]};
+    const size_t n = 3 * plane;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x)
-        psi[idx] = cscale(psi[idx], s);
+        psi[idx] = cscale(psi[idx], s[idx / plane]);
 }
 
+// Per-block partial component norms (partials[3 b + m]).
 template <typename T>
-__global__ __launch_bounds__(256) void k_norm_partials(const cx<T>* __restrict__ psi, size_t n, double* __restrict__ partials) {
-    __shared__ double shr[16];
-    double acc = 0;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x)
-        acc += (double)cnorm2(psi[idx]);
-    const double tot = block_sum(acc, shr);
-    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+__global__ __launch_bounds__(256) void k_norm_partials(const cx<T>* __restrict__ psi, size_t plane, double* __restrict__ partials) {
+    __shared__ double shr[48];
+    double acc[3] = {0, 0, 0};
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane; idx += (size_t)gridDim.x * blockDim.x)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) acc[m] += (double)cnorm2(psi[m * plane + idx]);
+    store_norm_partials(acc, shr, NormOut{partials}, (int)blockIdx.x);
 }
 
 __global__ void k_set_scale(double* scale, double v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *scale = v;
+    if (blockIdx.x == 0 && threadIdx.x < 3) scale[threadIdx.x] = v;
 }
 
-// Sum the per-block partial norms in a fixed order; scale = 1/sqrt(dx dy sum).
-__global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict__ partials, int n, double dxdy,
-                                                      double* __restrict__ scale, int* __restrict__ flag) {
-    __shared__ double shr[16];
-    double acc = 0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) acc += partials[k];
-    const double tot = block_sum(acc, shr);
+// Sum the per-block partial component norms in a fixed order and turn them
+// into the three scale factors (flag on a non-finite or non-positive result).
+__device__ inline void finalize_norms(const double* __restrict__ partials, int n, double dxdy, NormRule rule,
+                                      double* __restrict__ scale, int* __restrict__ flag, double* shr) {
+    double acc[3] = {0, 0, 0};
+    for (int k = threadIdx.x; k < n; k += blockDim.x)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) acc[m] += partials[3 * k + m];
+    block_sum3(acc, shr);
     if (threadIdx.x == 0) {
-        const double nn = tot * dxdy;
-        if (nn > 0.0 && isfinite(nn)) {
-            *scale = 1.0 / sqrt(nn);
-        } else {
-            *scale = 1.0;
-            *flag = 1;
-        }
+        const double N[3] = {acc[0] * dxdy, acc[1] * dxdy, acc[2] * dxdy};
+        if (!norm_scales(N, rule, scale)) *flag = 1;
     }
+}
+
+__global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict__ partials, int n, double dxdy,
+                                                      NormRule rule, double* __restrict__ scale, int* __restrict__ flag) {
+    __shared__ double shr[48];
+    finalize_norms(partials, n, dxdy, rule, scale, flag, shr);
 }
 
 // ---------------------------------------------------------------------------
@@ -107,7 +113,7 @@ __global__ __launch_bounds__(256) void k_obs(const cx<T>* __restrict__ psi, Phys
         }
         const double rp = cnorm2(v[0]), r0 = cnorm2(v[1]), rm = cnorm2(v[2]);
         const double rho = rp + r0 + rm;
-        const double V = 0.5 * (x * x + y * y);
+        const double V = 0.5 * (ph.gx2 * x * x + ph.gy2 * y * y);
         acc[0] += rp; acc[1] += r0; acc[2] += rm;
         acc[4] += V * rho;
         // spin density
@@ -170,25 +176,14 @@ __global__ __launch_bounds__(256) void k_obs_finalize(const double* __restrict__
 // ---------------------------------------------------------------------------
 __global__ void k_set_scale_batch(const NSlot* __restrict__ slots, int n, double v) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < n) *slots[s].scale = v;
+    if (s < 3 * n) slots[s / 3].scale[s % 3] = v;
 }
 
-// One block per condensate: the total of its norm partials, as k_norm_finalize.
+// One block per condensate: its norm totals and scale factors, as k_norm_finalize.
 __global__ __launch_bounds__(256) void k_norm_finalize_batch(const NSlot* __restrict__ slots) {
-    __shared__ double shr[16];
+    __shared__ double shr[48];
     const NSlot& s = slots[blockIdx.x];
-    double acc = 0;
-    for (int k = threadIdx.x; k < s.n; k += blockDim.x) acc += s.partials[k];
-    const double tot = block_sum(acc, shr);
-    if (threadIdx.x == 0) {
-        const double nn = tot * s.dxdy;
-        if (nn > 0.0 && isfinite(nn)) {
-            *s.scale = 1.0 / sqrt(nn);
-        } else {
-            *s.scale = 1.0;
-            *s.flag = 1;
-        }
-    }
+    finalize_norms(s.partials, s.n, s.dxdy, s.rule, s.scale, s.flag, shr);
 }
 
 // Block b scales chunk (map & mask) of kScaleChunk values of condensate (map >> shift).
@@ -197,10 +192,11 @@ __global__ __launch_bounds__(256) void k_scale_batch(const SSlot<T>* __restrict_
     const unsigned e = map[blockIdx.x];
     const SSlot<T>& s = slots[e >> kMapShift];
     const size_t base = (size_t)(e & kMapMask) * kScaleChunk;
-    const T f = (T)(*s.scale);
+    const size_t n = 3 * s.plane;
+    const T f[3] = {(T)s.scale[0], (T)s.scale[1], (T)s.scale[2]};
     for (int k = threadIdx.x; k < kScaleChunk; k += blockDim.x) {
         const size_t i = base + k;
-        if (i < s.n) s.psi[i] = cscale(s.psi[i], f);
+        if (i < n) s.psi[i] = cscale(s.psi[i], f[i / s.plane]);
     }
 }
 
@@ -217,15 +213,16 @@ hipError_t launch_local(cx<T>* psi, const Phys& ph, bool imag, hipStream_t st) {
 }
 
 template <typename T>
-hipError_t launch_scale(cx<T>* psi, size_t n, const double* scale, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+hipError_t launch_scale(cx<T>* psi, size_t plane, const double* scale, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const size_t n = 3 * plane;
     const int nblk = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
-    hipExtLaunchKernelGGL(k_scale<T>, dim3(nblk), dim3(256), 0, st, e0, e1, 0, psi, n, scale);
+    hipExtLaunchKernelGGL(k_scale<T>, dim3(nblk), dim3(256), 0, st, e0, e1, 0, psi, plane, scale);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_norm_partials(const cx<T>* psi, size_t n, double* partials, int nblk, hipStream_t st) {
-    k_norm_partials<T><<<nblk, 256, 0, st>>>(psi, n, partials);
+hipError_t launch_norm_partials(const cx<T>* psi, size_t plane, double* partials, int nblk, hipStream_t st) {
+    k_norm_partials<T><<<nblk, 256, 0, st>>>(psi, plane, partials);
     return hipGetLastError();
 }
 
@@ -234,9 +231,9 @@ hipError_t launch_set_scale(double* scale, double v, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, double* scale, int* flag, hipStream_t st,
-                                hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, e0, e1, 0, partials, n, dxdy, scale, flag);
+hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, NormRule rule, double* scale, int* flag,
+                                hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    hipExtLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, e0, e1, 0, partials, n, dxdy, rule, scale, flag);
     return hipGetLastError();
 }
 
@@ -255,7 +252,7 @@ hipError_t launch_obs_finalize(const double* partials, int nblk, double* out, hi
 
 hipError_t launch_set_scale_batch(const NSlot* slots, int n, double v, hipStream_t st) {
     if (n <= 0) return hipErrorInvalidValue;
-    k_set_scale_batch<<<(n + 255) / 256, 256, 0, st>>>(slots, n, v);
+    k_set_scale_batch<<<(3 * n + 255) / 256, 256, 0, st>>>(slots, n, v);
     return hipGetLastError();
 }
 

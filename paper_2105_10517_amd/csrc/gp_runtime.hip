@@ -205,7 +205,15 @@ gp::Phys phys(const gp_spin1_params& p) {
     ph.nx = p.nx; ph.ny = p.ny;
     ph.dx = p.dx; ph.dy = p.dy; ph.x0 = p.x0; ph.y0 = p.y0; ph.dt = p.dt;
     ph.c0 = p.c0; ph.c2 = p.c2; ph.rabi = p.rabi;
+    ph.dtl = p.split == GP_SPLIT_STRANG ? 0.5 * p.dt : p.dt;
+    const double gx = p.trap_gx == 0.0 ? 1.0 : p.trap_gx, gy = p.trap_gy == 0.0 ? 1.0 : p.trap_gy;
+    ph.gx2 = gx * gx;
+    ph.gy2 = gy * gy;
     return ph;
+}
+
+gp::NormRule norm_rule(const gp_spin1_params& p) {
+    return gp::NormRule{p.fix_magnetization, p.magnetization};
 }
 
 // x launch shape for K points per thread: G threads per row (a multiple of
@@ -393,6 +401,19 @@ int validate(const gp_spin1_params* p, std::string& why) {
     const int nmax = 8192;
     if (p->nx > nmax) { why = "nx above the largest row this build holds on chip"; return GP_EUNSUPPORTED; }
     if ((double)p->nx * (double)p->ny * 3.0 > 4.0e9) { why = "grid too large"; return GP_EUNSUPPORTED; }
+    if (!finite(p->trap_gx) || !finite(p->trap_gy) || p->trap_gx < 0 || p->trap_gy < 0) {
+        why = "trap_gx, trap_gy must be finite and >= 0 (0 selects 1)";
+        return GP_EINVAL;
+    }
+    if (p->split != GP_SPLIT_LIE && p->split != GP_SPLIT_STRANG) { why = "split must be GP_SPLIT_LIE or GP_SPLIT_STRANG"; return GP_EINVAL; }
+    if (p->fix_magnetization != 0 && p->fix_magnetization != 1) { why = "fix_magnetization must be 0 or 1"; return GP_EINVAL; }
+    if (p->fix_magnetization) {
+        if (!(std::fabs(p->magnetization) < 1.0)) { why = "fixed magnetisation must lie in (-1, 1)"; return GP_EINVAL; }
+        if (p->gamma != 0.0 || p->rabi != 0.0) {
+            why = "fixed magnetisation needs gamma = 0 and rabi = 0 (otherwise the flow does not conserve it)";
+            return GP_EINVAL;
+        }
+    }
     return GP_OK;
 }
 
@@ -481,7 +502,8 @@ int autotune_t(gp_spin1* h) {
     const double one = 1.0;
     const int zero = 0;
     if (rc == GP_OK && (e = hipStreamSynchronize(h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
-    if (rc == GP_OK && (e = hipMemcpy(h->d_scale, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) rc = hip_fail(h, e, "autotune");
+    const double ones[3] = {one, one, one};
+    if (rc == GP_OK && (e = hipMemcpy(h->d_scale, ones, sizeof ones, hipMemcpyHostToDevice)) != hipSuccess) rc = hip_fail(h, e, "autotune");
     if (rc == GP_OK && (e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) rc = hip_fail(h, e, "autotune");
     (void)hipFree(tmp);
     return rc;
@@ -504,11 +526,12 @@ int create_t(gp_spin1* h) {
     for (auto& m : h->mode) need = std::max(need, max_y_blocks<T>(p, m));
     const size_t npts = (size_t)p.nx * p.ny;
     h->obs_blocks = (int)std::min<size_t>(1024, (npts + 255) / 256);
+    need *= 3;  // three component partials per y block
     need = std::max(need, (size_t)h->obs_blocks * gp::kObsCount);
     need = std::max(need, (size_t)1024);
     h->n_part = need;
     if (hipMalloc(&h->d_part, need * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
-    if (hipMalloc(&h->d_scale, sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
+    if (hipMalloc(&h->d_scale, 3 * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_flag, sizeof(int)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_obs, gp::kObsCount * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_work, (size_t)3 * p.nx * p.ny * sizeof(gp::cx<T>)) != hipSuccess)
@@ -516,7 +539,8 @@ int create_t(gp_spin1* h) {
     const double one = 1.0;
     const int zero = 0;
     hipError_t e;
-    if ((e = hipMemcpy(h->d_scale, &one, sizeof one, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
+    const double ones[3] = {one, one, one};
+    if ((e = hipMemcpy(h->d_scale, ones, sizeof ones, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "init");
     if (p.autotune) {
         int rc = autotune_t<T>(h);
@@ -550,6 +574,7 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.no.partials = h->d_part;
     a.L = ms.L; a.h = ms.h; a.tile = ms.ytile;
     a.window = ms.window; a.imag = imag; a.norm = norm;
+    a.outl = false;
     return a;
 }
 
@@ -600,21 +625,23 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     if (n == 0) return GP_OK;
     hipStream_t st = h->stream;
     const gp::XLaunch<T> xa = xlaunch<T>(h, psi, h->d_work, imag, true);
-    const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, psi, imag, imag);
+    gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, psi, imag, imag);
+    ya.outl = h->p.split == GP_SPLIT_STRANG;
     const int nyb = gp::y_blocks<T>(ya);
     const double dxdy = h->p.dx * h->p.dy;
+    const gp::NormRule rule = norm_rule(h->p);
     hipError_t e;
     if (imag && (e = gp::launch_set_scale(h->d_scale, 1.0, st)) != hipSuccess) return hip_fail(h, e, "set_scale");
     for (int64_t s = 0; s < n; ++s) {
         if ((e = timed(h, 0, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_x<T>(xa, st, a, b); })) != hipSuccess) return hip_fail(h, e, "x sweep launch");
         // the y sweep leaves per-block norm partials; one block sums them into the scale
         if ((e = timed(h, 1, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_y<T>(ya, st, a, b); })) != hipSuccess) return hip_fail(h, e, "y sweep launch");
-        if (imag && (e = timed(h, 2, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_norm_finalize(h->d_part, nyb, dxdy, h->d_scale, h->d_flag, st, a, b); })) != hipSuccess)
+        if (imag && (e = timed(h, 2, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_norm_finalize(h->d_part, nyb, dxdy, rule, h->d_scale, h->d_flag, st, a, b); })) != hipSuccess)
             return hip_fail(h, e, "norm launch");
     }
     if (imag) {
-        const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
-        if ((e = timed(h, 3, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_scale<T>((gp::cx<T>*)psi, n3, h->d_scale, st, a, b); })) != hipSuccess)
+        const size_t plane = (size_t)h->p.nx * h->p.ny;
+        if ((e = timed(h, 3, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_scale<T>((gp::cx<T>*)psi, plane, h->d_scale, st, a, b); })) != hipSuccess)
             return hip_fail(h, e, "scale launch");
     }
     return GP_OK;
@@ -638,9 +665,12 @@ int substep_t(gp_spin1* h, void* psi, int which, bool imag) {
         }
         case 3: {
             const int nblk = (int)std::min<size_t>(1024, (n3 + 255) / 256);
-            if ((e = gp::launch_norm_partials<T>((const gp::cx<T>*)psi, n3, h->d_part, nblk, st)) != hipSuccess) break;
-            if ((e = gp::launch_norm_finalize(h->d_part, nblk, h->p.dx * h->p.dy, h->d_scale, h->d_flag, st)) != hipSuccess) break;
-            e = gp::launch_scale<T>((gp::cx<T>*)psi, n3, h->d_scale, st);
+            const size_t plane = n3 / 3;
+            if ((e = gp::launch_norm_partials<T>((const gp::cx<T>*)psi, plane, h->d_part, nblk, st)) != hipSuccess) break;
+            if ((e = gp::launch_norm_finalize(h->d_part, nblk, h->p.dx * h->p.dy, norm_rule(h->p), h->d_scale, h->d_flag,
+                                              st)) != hipSuccess)
+                break;
+            e = gp::launch_scale<T>((gp::cx<T>*)psi, plane, h->d_scale, st);
             break;
         }
         default: return fail(h, GP_EINVAL, "substep: which must be 0..3");
@@ -811,7 +841,8 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
         gp_spin1* h = b->slot[s];
         const ModeState& ms = h->mode[im];
         int hh, L, G, R;
-        const bool ok = ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
+        // Strang slots need the y sweep's output substep, which the batched kernel does not carry
+        const bool ok = h->p.split == GP_SPLIT_LIE && ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
                         x_shape(h->p.nx, shape[im].K, G, R) && G <= shape[im].block;
         if (ok) {
             grouped[im].push_back(s);
@@ -867,8 +898,8 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
                 const int nsb = (int)((n3 + gp::kScaleChunk - 1) / gp::kScaleChunk);
                 xs.push_back(gp::XSlot<T>{(const C*)psi[s], (C*)h->d_work, phys(h->p), lineset<T>(ms.x), h->d_scale, G, R});
                 ys.push_back(gp::YSlot<T>{(const C*)h->d_work, (C*)psi[s], phys(h->p), lineset<T>(ms.y), h->d_part, L, hh, ncs});
-                ns.push_back(gp::NSlot{h->d_part, nyb, h->p.dx * h->p.dy, h->d_scale, h->d_flag});
-                ss.push_back(gp::SSlot<T>{(C*)psi[s], n3, h->d_scale});
+                ns.push_back(gp::NSlot{h->d_part, nyb, h->p.dx * h->p.dy, h->d_scale, h->d_flag, norm_rule(h->p)});
+                ss.push_back(gp::SSlot<T>{(C*)psi[s], n3 / 3, h->d_scale});
                 for (int k = 0; k < (h->p.ny + R - 1) / R; ++k) xm.push_back((id << gp::kMapShift) | (unsigned)k);
                 for (int k = 0; k < nyb; ++k) ym.push_back((id << gp::kMapShift) | (unsigned)k);
                 for (int k = 0; k < nsb; ++k) sm.push_back((id << gp::kMapShift) | (unsigned)k);

@@ -317,11 +317,64 @@ __device__ inline double block_sum(double v, double* sh) {
     return s;
 }
 
-// Per-block partial sum of the imaginary-time norm, in block order; a one-block
-// kernel launched next on the same stream forms the total (a device-wide
-// release fence per block would write back the L2 of its XCD every time).
-__device__ inline void store_norm_partial(double part, NormOut no, int blk) {
-    if (threadIdx.x == 0) no.partials[blk] = part;
+// Block reduction of three doubles at once (all threads call; results valid
+// in thread 0).
+__device__ inline void block_sum3(double (&v)[3], double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m] += __shfl_down(v[m], off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sh[m * 16 + w] = v[m];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            double s = 0;
+            for (int k = 0; k < nw; ++k) s += sh[m * 16 + k];
+            v[m] = s;
+        }
+    __syncthreads();
+}
+
+// Per-block partial sums of the imaginary-time component norms, in block
+// order; a one-block kernel launched next on the same stream forms the totals
+// (a device-wide release fence per block would write back the L2 of its XCD
+// every time).
+__device__ inline void store_norm_partials(double (&acc)[3], double* sh, NormOut no, int blk) {
+    block_sum3(acc, sh);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) no.partials[3 * blk + m] = acc[m];
+}
+
+// Scale factors of the three components from their norms N[m] (dx dy sum
+// |psi_m|^2).  Total norm one: s_m = 1 / sqrt(N_{+1} + N_0 + N_{-1}).  Fixed
+// magnetisation mag: the s_m that give total norm one, N_{+1} - N_{-1} = mag
+// and s_{+1} s_{-1} = s_0^2 (normalised gradient flow of Bao and Lim):
+// with u = s_0^2 the conditions give u = (1 - mag^2) / (N_0 + sqrt(mag^2 N_0^2
+// + 4 (1 - mag^2) N_{+1} N_{-1})) and s_{+-1}^2 = (1 +- mag - u N_0) / (2 N_{+-1}).
+// Returns false (and unit factors) when a factor is not a positive finite number.
+__device__ inline bool norm_scales(const double (&N)[3], NormRule r, double* s) {
+    double f0, f1, f2;
+    if (r.fix_m) {
+        const double m = r.mag, q = 1.0 - m * m;
+        const double u = q / (N[1] + sqrt(m * m * N[1] * N[1] + 4.0 * q * N[0] * N[2]));
+        f1 = sqrt(u);
+        f0 = sqrt((1.0 + m - u * N[1]) / (2.0 * N[0]));
+        f2 = sqrt((1.0 - m - u * N[1]) / (2.0 * N[2]));
+    } else {
+        const double t = N[0] + N[1] + N[2];
+        f0 = f1 = f2 = 1.0 / sqrt(t);
+    }
+    const bool ok = isfinite(f0) && isfinite(f1) && isfinite(f2) && f0 > 0.0 && f1 > 0.0 && f2 > 0.0;
+    s[0] = ok ? f0 : 1.0;
+    s[1] = ok ? f1 : 1.0;
+    s[2] = ok ? f2 : 1.0;
+    return ok;
 }
 
 }  // namespace gp

@@ -43,18 +43,19 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
                 v[m][k] = (row_ok && i0 + k < nx) ? rowp[m * plane + i0 + k] : zero_c<C>();
     }
     if (SCALE) {
-        const T s = (T)(*scale);
 #pragma unroll
-        for (int m = 0; m < 3; ++m)
+        for (int m = 0; m < 3; ++m) {
+            const T s = (T)scale[m];
 #pragma unroll
             for (int k = 0; k < K; ++k) v[m][k] = cscale(v[m][k], s);
+        }
     }
     if (LOCAL) {
         const T y = (T)(ph.y0 + (row_ok ? j : 0) * ph.dy);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const T x = (T)(ph.x0 + (i0 + k) * ph.dx);
-            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], (T)0.5 * (x * x + y * y), (T)ph.dt, (T)ph.c0,
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], trap_v<T>(ph, x, y), (T)ph.dtl, (T)ph.c0,
                                    (T)ph.c2, (T)ph.rabi);
         }
     }

@@ -23,12 +23,12 @@ namespace gp {
 // norm reduction at the end).  Consecutive windows overlap by h rows on each
 // side and write only their L = 16 KY - 2 h middle rows.
 // ---------------------------------------------------------------------------
-template <typename T, bool IMAG, int KY, int NW, bool NORM>
+template <typename T, bool IMAG, int KY, int NW, bool NORM, bool OUTL>
 __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
                                 const LineSet<T>& ls, int L, int h, int ncs, NormOut no, int blk) {
     using C = cx<T>;
     constexpr int CPB = 4 * NW;  // columns per block
-    __shared__ double shr[16];
+    __shared__ double shr[48];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane & 15, cw = lane >> 4;
     const int cs = blk % ncs, rt = blk / ncs;
@@ -62,7 +62,17 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     block_solve3<T, KY, IMAG>(v, up, dn, ls, il * 3, g0, ny, fs, bs);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
-    double acc = 0;
+    if (OUTL) {
+        // Strang: the second half local substep, on the way out
+        const T x = (T)(ph.x0 + il * ph.dx);
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            const T y = (T)(ph.y0 + (g0 + k) * ph.dy);
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], trap_v<T>(ph, x, y), (T)ph.dtl, (T)ph.c0, (T)ph.c2,
+                                   (T)ph.rabi);
+        }
+    }
+    double acc[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k < KY; ++k) {
         const int g = g0 + k;
@@ -71,39 +81,40 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 dst[m * plane + o] = v[m][k];
-                if (NORM) acc += (double)cnorm2(v[m][k]);
+                if (NORM) acc[m] += (double)cnorm2(v[m][k]);
             }
         }
     }
-    if (NORM) store_norm_partial(block_sum(acc, shr), no, blk);
+    if (NORM) store_norm_partials(acc, shr, no, blk);
 }
 
-template <typename T, bool IMAG, int KY, int NW, bool NORM>
+template <typename T, bool IMAG, int KY, int NW, bool NORM, bool OUTL>
 __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                       Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no) {
-    y_window<T, IMAG, KY, NW, NORM>(src, dst, ph, ls, L, h, ncs, no, (int)blockIdx.x);
+    y_window<T, IMAG, KY, NW, NORM, OUTL>(src, dst, ph, ls, L, h, ncs, no, (int)blockIdx.x);
 }
 
 template <typename T, bool IMAG, int KY, int NW>
 __global__ __launch_bounds__(64 * NW) void k_y_batch(const YSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
     const YSlot<T>& s = slots[e >> kMapShift];
-    y_window<T, IMAG, KY, NW, IMAG>(s.src, s.dst, s.ph, s.ls, s.L, s.h, s.ncs, NormOut{s.partials}, (int)(e & kMapMask));
+    y_window<T, IMAG, KY, NW, IMAG, false>(s.src, s.dst, s.ph, s.ls, s.L, s.h, s.ncs, NormOut{s.partials},
+                                           (int)(e & kMapMask));
 }
 
 // ---------------------------------------------------------------------------
 // y sweep, exact per-thread Thomas down whole columns (increment form): the
 // forward eliminations go to dst, the back substitution re-reads src.
 // ---------------------------------------------------------------------------
-template <typename T, bool IMAG, bool NORM>
+template <typename T, bool IMAG, bool NORM, bool OUTL>
 __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
                                                  LineSet<T> ls, NormOut no) {
     using C = cx<T>;
-    __shared__ double shr[16];
+    __shared__ double shr[48];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nx = ph.nx, ny = ph.ny;
     const size_t plane = (size_t)nx * ny;
-    double acc = 0;
+    double acc[3] = {0, 0, 0};
     if (i < nx) {
         C a[3], e[3];
         Piv<T> lim[3];
@@ -156,36 +167,41 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
                 o[q] = cadd(uu[q], x[q]);
             }
             from_sx<C, T>(o[0], o[1], o[2]);
+            if (OUTL) {
+                const T x = (T)(ph.x0 + i * ph.dx), y = (T)(ph.y0 + g * ph.dy);
+                local_substep<T, IMAG>(o[0], o[1], o[2], trap_v<T>(ph, x, y), (T)ph.dtl, (T)ph.c0, (T)ph.c2,
+                                       (T)ph.rabi);
+            }
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
                 dst[m * plane + (size_t)g * nx + i] = o[m];
-                if (NORM) acc += (double)cnorm2(o[m]);
+                if (NORM) acc[m] += (double)cnorm2(o[m]);
             }
         }
     }
-    if (NORM) store_norm_partial(block_sum(acc, shr), no, (int)blockIdx.x);
+    if (NORM) store_norm_partials(acc, shr, no, (int)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-template <typename T, bool IMAG, bool NORM, int TI>
+template <typename T, bool IMAG, bool NORM, bool OUTL, int TI>
 static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     constexpr YTile yt = ytile<T>(TI);
     const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
-    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, NORM>, dim3(ncs * nrt), dim3(64 * yt.NW), 0, st, e0, e1, 0,
-                          a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no);
+    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, NORM, OUTL>, dim3(ncs * nrt), dim3(64 * yt.NW), 0, st, e0,
+                          e1, 0, a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no);
     return hipGetLastError();
 }
 
-template <typename T, bool IMAG, bool NORM>
+template <typename T, bool IMAG, bool NORM, bool OUTL>
 static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     switch (a.tile) {
-        case 0: return launch_yw_t<T, IMAG, NORM, 0>(a, st, e0, e1);
-        case 1: return launch_yw_t<T, IMAG, NORM, 1>(a, st, e0, e1);
-        case 2: return launch_yw_t<T, IMAG, NORM, 2>(a, st, e0, e1);
-        case 3: return launch_yw_t<T, IMAG, NORM, 3>(a, st, e0, e1);
+        case 0: return launch_yw_t<T, IMAG, NORM, OUTL, 0>(a, st, e0, e1);
+        case 1: return launch_yw_t<T, IMAG, NORM, OUTL, 1>(a, st, e0, e1);
+        case 2: return launch_yw_t<T, IMAG, NORM, OUTL, 2>(a, st, e0, e1);
+        case 3: return launch_yw_t<T, IMAG, NORM, OUTL, 3>(a, st, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -200,21 +216,27 @@ int y_blocks(const YLaunch<T>& a) {
     return (a.ph.nx + 255) / 256;
 }
 
+template <typename T, bool IMAG, bool NORM, bool OUTL>
+static hipError_t launch_yt(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    const dim3 grid((a.ph.nx + 255) / 256), block(256);
+    hipExtLaunchKernelGGL(k_y_thomas<T, IMAG, NORM, OUTL>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+    return hipGetLastError();
+}
+
+// (imag, norm, outl): the steps use (1, 1, *) and (0, 0, *); the substep calls (*, 0, 0).
+template <typename T, bool IMAG, bool NORM, bool OUTL>
+static hipError_t launch_y_v(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    return a.window ? launch_yw<T, IMAG, NORM, OUTL>(a, st, e0, e1) : launch_yt<T, IMAG, NORM, OUTL>(a, st, e0, e1);
+}
+
 template <typename T>
 hipError_t launch_y(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    if (a.window) {
-        if (a.imag) return a.norm ? launch_yw<T, true, true>(a, st, e0, e1) : launch_yw<T, true, false>(a, st, e0, e1);
-        return a.norm ? launch_yw<T, false, true>(a, st, e0, e1) : launch_yw<T, false, false>(a, st, e0, e1);
+    if (a.outl) {
+        if (a.norm != a.imag) return hipErrorInvalidValue;
+        return a.imag ? launch_y_v<T, true, true, true>(a, st, e0, e1) : launch_y_v<T, false, false, true>(a, st, e0, e1);
     }
-    const dim3 grid((a.ph.nx + 255) / 256), block(256);
-    if (a.imag) {
-        if (a.norm) hipExtLaunchKernelGGL(k_y_thomas<T, true, true>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
-        else hipExtLaunchKernelGGL(k_y_thomas<T, true, false>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
-    } else {
-        if (a.norm) hipExtLaunchKernelGGL(k_y_thomas<T, false, true>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
-        else hipExtLaunchKernelGGL(k_y_thomas<T, false, false>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
-    }
-    return hipGetLastError();
+    if (a.imag) return a.norm ? launch_y_v<T, true, true, false>(a, st, e0, e1) : launch_y_v<T, true, false, false>(a, st, e0, e1);
+    return a.norm ? launch_y_v<T, false, true, false>(a, st, e0, e1) : launch_y_v<T, false, false, false>(a, st, e0, e1);
 }
 
 template <typename T, bool IMAG, int TI>

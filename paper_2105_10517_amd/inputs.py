@@ -62,13 +62,17 @@ def random_state(nx: int, ny: int, seed: int, scale: float = 1.0) -> np.ndarray:
 
 def params(nx: int, ny: int, dx: float, dy: float | None = None, dt: float = 5e-4, c0: float = 0.0,
            c2: float = 0.0, gamma: float = 0.0, eta: int = 1, rabi: float = 0.0, omega: float = 0.0,
-           x0: float | None = None, y0: float | None = None) -> dict:
-    """Plain parameter mapping understood by both the oracle and the library binding."""
+           x0: float | None = None, y0: float | None = None, gx: float = 1.0, gy: float = 1.0, split: int = 0,
+           fix_m: int = 0, magnetization: float = 0.0) -> dict:
+    """Plain parameter mapping understood by both the oracle and the library binding
+    (gx, gy: trap frequencies; split: 0 Lie, 1 Strang; fix_m, magnetization:
+    imaginary-time projection to a fixed magnetisation)."""
     dy = dx if dy is None else dy
     return {"nx": int(nx), "ny": int(ny), "dx": float(dx), "dy": float(dy),
             "x0": float(-nx * dx / 2.0 if x0 is None else x0), "y0": float(-ny * dy / 2.0 if y0 is None else y0),
             "dt": float(dt), "c0": float(c0), "c2": float(c2), "gamma": float(gamma), "eta": int(eta),
-            "rabi": float(rabi), "omega": float(omega)}
+            "rabi": float(rabi), "omega": float(omega), "gx": float(gx), "gy": float(gy), "split": int(split),
+            "fix_m": int(fix_m), "magnetization": float(magnetization)}
 
 
 # The five workloads, as concrete seeded inputs.

@@ -107,3 +107,30 @@ def test_batch_create_validates_before_touching_the_device():
     assert lib.gp_spin1_batch_step(None, None, None, None, None) == binding.GP_EINVAL
     assert lib.gp_spin1_batch_destroy(None) == binding.GP_EINVAL
     assert lib.gp_spin1_batch_last_error(None).decode() == "null batch"
+
+
+@pytest.mark.parametrize("change", [
+    {"fix_m": 1, "magnetization": 0.2},                       # gamma != 0 in BASE
+    {"fix_m": 1, "magnetization": 1.0, "gamma": 0.0},         # |m| must be < 1
+    {"split": 2}, {"gx": -1.0}, {"gy": math.inf},
+])
+def test_validation_of_the_next_row_options(change):
+    p = dict(BASE, **change)
+    with pytest.raises(binding.GPError) as ei:
+        binding.plan_query(p, True)
+    assert ei.value.status == binding.GP_EINVAL
+
+
+def test_unit_helper_reproduces_the_printed_couplings():
+    # Eq. (S.4) with the paper's 87Rb / 23Na inputs (l0 / sqrt(kappa) = 4 micrometres)
+    import json
+    from paper_2105_10517_amd import units
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "couplings_rb87_na23.json")))
+    for c in g["cases"]:
+        for kappa in (1.0, 20.0):
+            l0 = g["l0_over_sqrt_kappa_m"] * math.sqrt(kappa)
+            c0, c2 = units.couplings(c["N"], c["a0_bohr"], c["a2_bohr"], l0, kappa)
+            assert round(c0, c["c0_digits"]) == c["c0_printed"]
+            assert round(c2, c["c2_digits"]) == c["c2_printed"]
+    # oscillator length of 87Rb in a 2 pi x 20 Hz trap: about 2.4 micrometres
+    assert abs(units.oscillator_length(86.909 * 1.66053906660e-27, 2 * math.pi * 20.0) - 2.41e-6) < 0.02e-6

@@ -453,3 +453,92 @@ def test_ferromagnetic_so_vortices_are_the_lowest_seeded_type(eta):
         if w == tuple(case["windings"]):
             assert winding(psi, p, 1.0) == w and winding(psi, p, 2.0) == w
     assert energies[tuple(case["windings"])] < energies[mirror] - 1e-3
+
+
+# ---------------------------------------------------------------------------
+# Next rows: Strang order, fixed magnetisation, anisotropic trap
+# ---------------------------------------------------------------------------
+def one_d_ground(n, dx, x0, g):
+    """Lowest eigenvalue of -1/2 D_xx + g^2 x^2 / 2 on the 1-D grid (Dirichlet ghosts)."""
+    x = x0 + dx * np.arange(n)
+    H = np.diag(1.0 / dx ** 2 + 0.5 * g * g * x ** 2) + np.diag(np.full(n - 1, -0.5 / dx ** 2), 1) \
+        + np.diag(np.full(n - 1, -0.5 / dx ** 2), -1)
+    return float(np.linalg.eigvalsh(H)[0])
+
+
+def test_strang_is_second_order_and_lie_first_order():
+    # real time, Omega = gamma = R = 0: the two sweeps commute and the frozen local exponential is the
+    # exact local flow (rho and F are conserved by it), so Strang's global error is O(dt^2), Lie's O(dt)
+    n, dx, T = 20, 0.45, 0.16
+    base = inputs.params(n, n, dx, dt=T / 4, c0=25.0, c2=-3.0, gx=1.0, gy=1.2)
+    psi0 = inputs.gaussian(n, n, dx, dx, seed=21, phase_noise=0.5, center=(0.4, -0.3))
+    ref = oracle.step(dict(base, dt=T / 256, split=1), psi0, 256, False)
+    errs = {}
+    for split in (0, 1):
+        errs[split] = []
+        for k in (8, 16, 32):
+            out = oracle.step(dict(base, dt=T / k, split=split), psi0, k, False)
+            errs[split].append(float(np.linalg.norm(out - ref)))
+    r_lie = [errs[0][i] / errs[0][i + 1] for i in range(2)]
+    r_strang = [errs[1][i] / errs[1][i + 1] for i in range(2)]
+    assert all(1.7 < r < 2.4 for r in r_lie), r_lie
+    assert all(3.4 < r < 4.6 for r in r_strang), r_strang
+    assert errs[1][0] < errs[0][0]
+
+
+def test_fixed_magnetisation_projection_conditions():
+    # after the projection: total norm 1, N+ - N- = m, and the component factors obey s+ s- = s0^2
+    n, dx, m = 16, 0.5, 0.35
+    p = inputs.params(n, n, dx, dt=0.01, c0=10.0, c2=-1.0, fix_m=1, magnetization=m)
+    psi = inputs.gaussian(n, n, dx, dx, seed=22, populations=(0.5, 0.2, 0.3))
+    psi *= 1.7
+    before = [float(np.sum(np.abs(psi[c]) ** 2) * dx * dx) for c in range(3)]
+    out = oracle.normalize(p, psi)
+    after = [float(np.sum(np.abs(out[c]) ** 2) * dx * dx) for c in range(3)]
+    s2 = [after[c] / before[c] for c in range(3)]
+    assert abs(sum(after) - 1.0) < 1e-14
+    assert abs(after[0] - after[2] - m) < 1e-14
+    assert abs(math.sqrt(s2[0] * s2[2]) - s2[1]) < 1e-14
+    # each component is only rescaled
+    for c in range(3):
+        assert np.allclose(out[c], psi[c] * math.sqrt(s2[c]), rtol=1e-14, atol=0)
+
+
+def test_fixed_magnetisation_reduces_to_total_norm_at_zero():
+    # N+ = N- and m = 0: the three factors coincide with 1/sqrt(N)
+    n, dx = 16, 0.5
+    psi = inputs.gaussian(n, n, dx, dx, seed=23, populations=(0.3, 0.4, 0.3))
+    psi[2] = psi[0] * np.exp(0.3j)  # equal component norms
+    psi *= 0.8
+    p = inputs.params(n, n, dx, dt=0.01)
+    a = oracle.normalize(p, psi)
+    b = oracle.normalize(dict(p, fix_m=1, magnetization=0.0), psi)
+    assert np.allclose(a, b, rtol=2e-15, atol=0)
+
+
+def test_fixed_magnetisation_imaginary_time_keeps_m():
+    n, dx, m = 32, 0.35, -0.25
+    p = inputs.params(n, n, dx, dt=0.01, c0=40.0, c2=2.0, omega=0.3, fix_m=1, magnetization=m)
+    psi = inputs.gaussian(n, n, dx, dx, seed=24)
+    out = oracle.step(p, psi, 60, True)
+    o = oracle.observables(p, out)
+    assert abs(o["norm_total"] - 1.0) < 1e-13
+    assert abs(o["magnetization"] - m) < 1e-13
+    # the plain renormalisation leaves the magnetisation free (here it drifts from 0)
+    q = dict(p, fix_m=0)
+    o2 = oracle.observables(q, oracle.step(q, psi, 60, True))
+    assert abs(o2["magnetization"] - m) > 0.1
+
+
+def test_anisotropic_harmonic_ground_state():
+    # couplings off: E = lambda_x + lambda_y of the two 1-D grid operators (continuum (gx + gy)/2)
+    nx, ny, dx, gx, gy = 48, 40, 0.25, 1.3, 0.8
+    p = inputs.params(nx, ny, dx, dt=0.005, gx=gx, gy=gy)
+    e_grid = one_d_ground(nx, dx, p["x0"], gx) + one_d_ground(ny, dx, p["y0"], gy)
+    psi = inputs.gaussian(nx, ny, dx, dx, seed=25, phase_noise=0.1)
+    out = oracle.step(p, psi, 3000, True)
+    o = oracle.observables(p, out)
+    assert abs(o["energy"] - e_grid) < 2e-5
+    assert abs(o["energy"] - 0.5 * (gx + gy)) < 5e-3
+    # trap energy of the ground state: half the oscillator energy in each direction (virial)
+    assert abs(o["e_trap"] - 0.5 * o["energy"]) < 5e-3
