@@ -59,9 +59,111 @@ template <typename C> __device__ inline Aff<C> readlane_aff(const Aff<C>& a, int
     return Aff<C>{readlane_c(a.P, l), readlane_c(a.E, l)};
 }
 
+// Inclusive scans within each row of 16 lanes, NQ independent maps at once
+// (their lane moves and compositions interleave).  FWD: lane l holds
+// f_l o f_{l-1} o ... o f_{row start}; backward: f_l o f_{l+1} o ... o f_{row end}.
+template <bool FWD, int NQ, typename C> __device__ inline void row16_incl(Aff<C> (&a)[NQ]) {
+#define GP_STAGE(CTRL)                                                                \
+    {                                                                                 \
+        Aff<C> s[NQ];                                                                 \
+        _Pragma("unroll") for (int q = 0; q < NQ; ++q) s[q] = dpp_aff<CTRL>(a[q]);   \
+        _Pragma("unroll") for (int q = 0; q < NQ; ++q) a[q] = compose(a[q], s[q]);   \
+    }
+    if (FWD) {
+        GP_STAGE(0x111) GP_STAGE(0x112) GP_STAGE(0x114) GP_STAGE(0x118)  // row_shr:1,2,4,8
+    } else {
+        GP_STAGE(0x101) GP_STAGE(0x102) GP_STAGE(0x104) GP_STAGE(0x108)  // row_shl:1,2,4,8
+    }
+#undef GP_STAGE
+}
+
+// Inclusive scan over the 64 lanes of a wave.
+template <bool FWD, int NQ, typename C> __device__ inline void wave_incl(Aff<C> (&a)[NQ], int lane) {
+    row16_incl<FWD, NQ>(a);
+    const int row = lane >> 4;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        Aff<C> pre = aff_id<C>();
+        if (FWD) {
+            // prefix of the rows below: S_1 = T_0, S_2 = T_1 o T_0, S_3 = T_2 o T_1 o T_0
+            const Aff<C> t0 = readlane_aff(a[q], 15), t1 = readlane_aff(a[q], 31), t2 = readlane_aff(a[q], 47);
+            const Aff<C> s2 = compose(t1, t0), s3 = compose(t2, s2);
+            if (row == 1) pre = t0;
+            if (row == 2) pre = s2;
+            if (row == 3) pre = s3;
+        } else {
+            const Aff<C> t1 = readlane_aff(a[q], 16), t2 = readlane_aff(a[q], 32), t3 = readlane_aff(a[q], 48);
+            const Aff<C> s1 = compose(t2, t3), s0 = compose(t1, s1);
+            if (row == 0) pre = s0;
+            if (row == 1) pre = s1;
+            if (row == 2) pre = t3;
+        }
+        a[q] = compose(a[q], pre);
+    }
+}
+
+// Shared memory of one cross-wave scan: for line q, the transfer-map totals
+// of the waves at P[q * 32 + w] and E[q * 32 + 16 + w] (w < 16).  Each scan
+// of a launch gets a region of its own, so no barrier is needed after it.
+template <typename C> struct ScanShm {
+    C* base;
+    __device__ C& P(int q, int w) const { return base[q * 32 + w]; }
+    __device__ C& E(int q, int w) const { return base[q * 32 + 16 + w]; }
+};
+
+// Exclusive scan over the G = 64 * nw threads of one row (thread t = 64 w +
+// lane), NQ lines: out[q] is the composite of the maps before this thread
+// (FWD) or after it (backward) applied to a zero carry.  Every thread of the
+// block must call it (one barrier when nw > 1).
+template <bool FWD, int NQ, typename C>
+__device__ inline void row_scan(const C (&P)[NQ], const C (&E)[NQ], C (&out)[NQ], int lane, int w, int nw,
+                                ScanShm<C> sh) {
+    Aff<C> a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = Aff<C>{P[q], E[q]};
+    wave_incl<FWD, NQ>(a, lane);
+    C din[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) din[q] = zero_c<C>();
+    if (nw > 1) {
+        if (lane == (FWD ? 63 : 0)) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) { sh.P(q, w) = a[q].P; sh.E(q, w) = a[q].E; }
+        }
+        __syncthreads();
+        if (FWD) {
+            for (int v = 0; v < w; ++v)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) din[q] = cfma(din[q], sh.P(q, v), sh.E(q, v));
+        } else {
+            for (int v = nw - 1; v > w; --v)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) din[q] = cfma(din[q], sh.P(q, v), sh.E(q, v));
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const C val = cfma(din[q], a[q].P, a[q].E);  // inclusive map applied to the carry into the wave
+        out[q] = FWD ? dpp_c<0x138>(din[q], val) : dpp_c<0x130>(din[q], val);  // wave_shr:1 / wave_shl:1
+    }
+}
+
+// Exclusive scans across the 16 lanes of a DPP row (segments of one column in
+// the y sweep), NQ lines: no shared memory, no barrier.
+template <bool FWD, int NQ, typename C> __device__ inline void seg16_scan(const C (&P)[NQ], const C (&E)[NQ], C (&out)[NQ]) {
+    Aff<C> a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = Aff<C>{P[q], E[q]};
+    row16_incl<FWD, NQ>(a);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[q] = FWD ? dpp_c<0x111>(zero_c<C>(), a[q].E) : dpp_c<0x101>(zero_c<C>(), a[q].E);
+}
+
+// Single-map forms used by the long-row x sweep (one line at a time; the
+// trailing barrier lets the next line reuse shP / shE).
 // Inclusive scans within each row of 16 lanes.  FWD: lane l holds
 // f_l o f_{l-1} o ... o f_{row start}; backward: f_l o f_{l+1} o ... o f_{row end}.
-template <bool FWD, typename C> __device__ inline Aff<C> row16_incl(Aff<C> a) {
+template <bool FWD, typename C> __device__ inline Aff<C> row16_incl1(Aff<C> a) {
     if (FWD) {
         a = compose(a, dpp_aff<0x111>(a));  // row_shr:1
         a = compose(a, dpp_aff<0x112>(a));  // row_shr:2
@@ -77,8 +179,8 @@ template <bool FWD, typename C> __device__ inline Aff<C> row16_incl(Aff<C> a) {
 }
 
 // Inclusive scan over the 64 lanes of a wave (lane order forward or backward).
-template <bool FWD, typename C> __device__ inline Aff<C> wave_incl(Aff<C> a, int lane) {
-    a = row16_incl<FWD>(a);
+template <bool FWD, typename C> __device__ inline Aff<C> wave_incl1(Aff<C> a, int lane) {
+    a = row16_incl1<FWD>(a);
     const int row = lane >> 4;
     Aff<C> pre = aff_id<C>();
     if (FWD) {
@@ -103,8 +205,8 @@ template <bool FWD, typename C> __device__ inline Aff<C> wave_incl(Aff<C> a, int
 // after it (backward), applied to a zero carry.  shP/shE: >= nw entries of
 // shared memory private to the row.  Every thread of the block must call it.
 template <bool FWD, typename C>
-__device__ inline C row_scan(C P, C E, int lane, int w, int nw, C* shP, C* shE) {
-    const Aff<C> a = wave_incl<FWD>(Aff<C>{P, E}, lane);
+__device__ inline C row_scan1(C P, C E, int lane, int w, int nw, C* shP, C* shE) {
+    const Aff<C> a = wave_incl1<FWD>(Aff<C>{P, E}, lane);
     C din = zero_c<C>();
     if (nw > 1) {
         if (lane == (FWD ? 63 : 0)) { shP[w] = a.P; shE[w] = a.E; }
@@ -118,95 +220,6 @@ __device__ inline C row_scan(C P, C E, int lane, int w, int nw, C* shP, C* shE) 
     }
     const C val = cfma(din, a.P, a.E);  // this thread's inclusive map applied to the carry into the wave
     return FWD ? dpp_c<0x138>(din, val) : dpp_c<0x130>(din, val);  // wave_shr:1 / wave_shl:1
-}
-
-// Exclusive scans of the three eigencomponent lines at once (the three chains
-// are independent, so their lane moves and compositions interleave).
-template <bool FWD, typename C> __device__ inline void row16_incl3(Aff<C> (&a)[3]) {
-#define GP_STAGE(CTRL)                                                        \
-    {                                                                         \
-        Aff<C> s[3];                                                          \
-        _Pragma("unroll") for (int q = 0; q < 3; ++q) s[q] = dpp_aff<CTRL>(a[q]); \
-        _Pragma("unroll") for (int q = 0; q < 3; ++q) a[q] = compose(a[q], s[q]); \
-    }
-    if (FWD) {
-        GP_STAGE(0x111) GP_STAGE(0x112) GP_STAGE(0x114) GP_STAGE(0x118)  // row_shr:1,2,4,8
-    } else {
-        GP_STAGE(0x101) GP_STAGE(0x102) GP_STAGE(0x104) GP_STAGE(0x108)  // row_shl:1,2,4,8
-    }
-#undef GP_STAGE
-}
-
-// Inclusive scan over the 64 lanes of a wave, three maps at once.
-template <bool FWD, typename C> __device__ inline void wave_incl3(Aff<C> (&a)[3], int lane) {
-    row16_incl3<FWD>(a);
-    const int row = lane >> 4;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        Aff<C> pre = aff_id<C>();
-        if (FWD) {
-            // prefix of the rows below: S_1 = T_0, S_2 = T_1 o T_0, S_3 = T_2 o T_1 o T_0
-            const Aff<C> t0 = readlane_aff(a[q], 15), t1 = readlane_aff(a[q], 31), t2 = readlane_aff(a[q], 47);
-            const Aff<C> s2 = compose(t1, t0), s3 = compose(t2, s2);
-            if (row == 1) pre = t0;
-            if (row == 2) pre = s2;
-            if (row == 3) pre = s3;
-        } else {
-            const Aff<C> t1 = readlane_aff(a[q], 16), t2 = readlane_aff(a[q], 32), t3 = readlane_aff(a[q], 48);
-            const Aff<C> s1 = compose(t2, t3), s0 = compose(t1, s1);
-            if (row == 0) pre = s0;
-            if (row == 1) pre = s1;
-            if (row == 2) pre = t3;
-        }
-        a[q] = compose(a[q], pre);
-    }
-}
-
-// Exclusive scan over the G = 64 * nw threads of one row (thread t = 64 w +
-// lane) for the three lines: out[q] is the composite of the maps before this
-// thread (FWD) or after it (backward) applied to a zero carry.  sh: >= 6 nw
-// entries of shared memory private to the row.  Every thread of the block
-// must call it.
-template <bool FWD, typename C>
-__device__ inline void row_scan3(const C (&P)[3], const C (&E)[3], C (&out)[3], int lane, int w, int nw, C* sh) {
-    Aff<C> a[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) a[q] = Aff<C>{P[q], E[q]};
-    wave_incl3<FWD>(a, lane);
-    C din[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
-    if (nw > 1) {
-        if (lane == (FWD ? 63 : 0)) {
-#pragma unroll
-            for (int q = 0; q < 3; ++q) { sh[(2 * q) * nw + w] = a[q].P; sh[(2 * q + 1) * nw + w] = a[q].E; }
-        }
-        __syncthreads();
-        if (FWD) {
-            for (int v = 0; v < w; ++v)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) din[q] = cfma(din[q], sh[(2 * q) * nw + v], sh[(2 * q + 1) * nw + v]);
-        } else {
-            for (int v = nw - 1; v > w; --v)
-#pragma unroll
-                for (int q = 0; q < 3; ++q) din[q] = cfma(din[q], sh[(2 * q) * nw + v], sh[(2 * q + 1) * nw + v]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        const C val = cfma(din[q], a[q].P, a[q].E);  // inclusive map applied to the carry into the wave
-        out[q] = FWD ? dpp_c<0x138>(din[q], val) : dpp_c<0x130>(din[q], val);  // wave_shr:1 / wave_shl:1
-    }
-}
-
-// Exclusive scans across the 16 lanes of a DPP row (segments of one column in
-// the y sweep) for the three lines: no shared memory, no barrier.
-template <bool FWD, typename C> __device__ inline void seg16_scan3(const C (&P)[3], const C (&E)[3], C (&out)[3]) {
-    Aff<C> a[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) a[q] = Aff<C>{P[q], E[q]};
-    row16_incl3<FWD>(a);
-#pragma unroll
-    for (int q = 0; q < 3; ++q) out[q] = FWD ? dpp_c<0x111>(zero_c<C>(), a[q].E) : dpp_c<0x101>(zero_c<C>(), a[q].E);
 }
 
 }  // namespace gp

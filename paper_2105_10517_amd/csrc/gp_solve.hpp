@@ -14,21 +14,70 @@ namespace gp {
 // the elimination is small relative to u and u + delta is rounded once.  (In
 // FP32 the direct form drifts in norm by a few 1e-8 per sweep.)
 //
-// Partitioned Thomas on one line held as K consecutive values per thread
-// (indices i0 .. i0+K-1 of a line of length n; indices outside [0, n) are
-// padding), in place on u[]; left/right are the line values just outside the
-// thread's block.  FS and BS are the forward and backward exclusive scans of
-// the block transfer maps across the threads sharing the line; every thread
-// must reach them (they contain barriers).
+// Partitioned Thomas on NQ lines held as K consecutive values per thread
+// (indices i0 .. i0+K-1 of lines of length n; indices outside [0, n) are
+// padding), in place on u[][]; left/right are the line values just outside
+// the thread's block.  FS and BS are the forward and backward exclusive scans
+// of the block transfer maps across the threads sharing the lines; every
+// thread must reach them (they may contain barriers).
 //
-// Blocks entirely inside the line and past the tabulated transient of the
-// pivots take a fast path with the converged pivots held in registers.
+// Every point takes its pivots from PivSrc: zeros outside the line (which
+// cuts the carries at the line ends), the tabulated transient near the start
+// (from shared memory, staged by the caller, or from the global table), the
+// converged limit elsewhere.  One code path for all threads: no divergence
+// between the threads that hold the start of a line and the others.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG> __device__ inline cx<T> mul_bm1(cx<T> bm1, cx<T> u) {
     // b - 1 = alpha / dx^2: real in imaginary time, imaginary in real time
     return IMAG ? cscale(u, bm1.x) : cscale(ctimes_i(u), bm1.y);
 }
 template <typename C> __device__ inline C cneg(C a) { C z; z.x = -a.x; z.y = -a.y; return z; }
+
+// Where the pivots of (up to) three lines come from: line[q] is the line
+// index in the LineSet; the first kl entries of each line are staged in
+// shared memory (lds[q * kl + i]); the rest of the transient and the limit
+// are read from the LineSet table when a solve needs them.
+template <typename T> struct PivSrc {
+    const Piv<T>* lds;
+    int kl;
+    const Piv<T>* glob;
+    int K;
+    int line[3];
+};
+
+template <typename T>
+__device__ inline PivSrc<T> piv_src(const LineSet<T>& ls, int line0, const Piv<T>* lds, int kl) {
+    PivSrc<T> s;
+    s.lds = lds;
+    s.kl = kl;
+    s.glob = ls.piv;
+    s.K = ls.K;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) s.line[q] = line0 + q;
+    return s;
+}
+
+// Pivots of point i of one line: lim by value (kept in registers), the
+// transient entries from shared memory (tab, kl entries) or the global table
+// (row, K + 1 entries); zeros outside [0, n).
+template <bool LDSPIV, typename T>
+__device__ inline Piv<T> piv_pt(const Piv<T> lim, const Piv<T>* tab, int kl, const Piv<T>* row, int K, int i, int n) {
+    Piv<T> p = lim;
+    if (i < K) {
+        const int ii = i > 0 ? i : 0;
+        const Piv<T>* src = (LDSPIV && ii < kl) ? tab + ii : row + ii;
+        p.m = src->m;
+        p.am = src->am;
+        p.cp = src->cp;
+    }
+    if (i < 0 || i >= n) {
+        p.m = zero_c<cx<T>>();
+        p.am = zero_c<cx<T>>();
+        p.cp = zero_c<cx<T>>();
+    }
+    return p;
+}
+
 template <typename C, int K> __device__ inline C cpow_k(C a) {
     C r = one_c<C>(), b = a;
 #pragma unroll
@@ -39,8 +88,155 @@ template <typename C, int K> __device__ inline C cpow_k(C a) {
     return r;
 }
 
+// Q0: first of the NQ lines within the PivSrc (0 .. 3 - NQ); LDSPIV: take the
+// staged transient from shared memory (else from the global table).  Threads whose K
+// points all lie inside the line and past the pivots' transient take the
+// fast path (the converged pivots, kept in registers, and closed-form block
+// powers); the others (the start and the ragged end of a line, window
+// padding) take pivots point by point.
+template <typename T, int K, bool IMAG, int NQ, int Q0, bool LDSPIV, typename FS, typename BS>
+__device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], const cx<T> (&right)[NQ],
+                                   const LineSet<T>& ls, const PivSrc<T>& ps, int i0, int n, FS fscan, BS bscan) {
+    using C = cx<T>;
+    C a[NQ], e[NQ], nam[NQ], ncp[NQ], lm[NQ];
+    Piv<T> lim[NQ];
+    const Piv<T>* tab[NQ];
+    const Piv<T>* row[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        a[q] = ls.ae[2 * ps.line[Q0 + q]];
+        e[q] = ls.ae[2 * ps.line[Q0 + q] + 1];
+        lim[q] = ps.glob[(size_t)ps.line[Q0 + q] * (ps.K + 1) + ps.K];
+        lm[q] = lim[q].m;
+        nam[q] = cneg(lim[q].am);
+        ncp[q] = cneg(lim[q].cp);
+        tab[q] = ps.lds + (Q0 + q) * ps.kl;
+        row[q] = ps.glob + (size_t)ps.line[Q0 + q] * (ps.K + 1);
+    }
+    const int kl = ps.kl, KP = ps.K;
+    const bool fast = i0 >= KP && i0 + K <= n;
+    // right-hand side of the increment system: r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
+    C r[NQ][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const C um = (k == 0) ? left[q] : u[q][k - 1];
+            const C up = (k == K - 1) ? right[q] : u[q][k + 1];
+            C t = mul_bm1<T, IMAG>(ls.bm1, u[q][k]);
+            t = cfma(um, a[q], t);
+            t = cfma(up, e[q], t);
+            r[q][k] = cscale(t, (T)-2);
+        }
+    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1}
+    C E[NQ], P[NQ], din[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) E[q] = zero_c<C>();
+    if (fast) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                E[q] = cfma(E[q], nam[q], cmul(lm[q], r[q][k]));
+                r[q][k] = E[q];
+            }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) P[q] = cpow_k<C, K>(nam[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) P[q] = one_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const Piv<T> p = piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n);
+                const C na = cneg(p.am);
+                E[q] = cfma(E[q], na, cmul(p.m, r[q][k]));
+                P[q] = cmul(na, P[q]);
+                r[q][k] = E[q];
+            }
+    }
+    fscan(P, E, din);
+    // add the carry that enters the block, times the running product of -am
+    {
+        C Q[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Q[q] = one_c<C>();
+        if (fast) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    Q[q] = cmul(Q[q], nam[q]);
+                    r[q][k] = cfma(din[q], Q[q], r[q][k]);
+                }
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    Q[q] = cmul(Q[q], cneg(piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n).am));
+                    r[q][k] = cfma(din[q], Q[q], r[q][k]);
+                }
+        }
+    }
+    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1}
+    C G[NQ], R[NQ], xin[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) G[q] = zero_c<C>();
+    if (fast) {
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                G[q] = cfma(G[q], ncp[q], r[q][k]);
+                r[q][k] = G[q];
+            }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) R[q] = cpow_k<C, K>(ncp[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) R[q] = one_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const C nc = cneg(piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n).cp);
+                G[q] = cfma(G[q], nc, r[q][k]);
+                R[q] = cmul(nc, R[q]);
+                r[q][k] = G[q];
+            }
+    }
+    bscan(R, G, xin);
+    {
+        C Sx[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) Sx[q] = one_c<C>();
+        if (fast) {
+#pragma unroll
+            for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    Sx[q] = cmul(Sx[q], ncp[q]);
+                    u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
+                }
+        } else {
+#pragma unroll
+            for (int k = K - 1; k >= 0; --k)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    Sx[q] = cmul(Sx[q], cneg(piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n).cp));
+                    u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
+                }
+        }
+    }
+}
+
+// One line with K points per thread for long rows (K s > 32 bytes): the
+// same elimination one line at a time, with the transient pivots read from
+// the global table (keeps the register footprint of the long-row kernels).
 template <typename T, int K, bool IMAG, typename FS, typename BS>
-__device__ inline void block_solve(cx<T> (&u)[K], cx<T> left, cx<T> right, const LineSet<T>& ls, int line, int i0,
+__device__ inline void block_solve1(cx<T> (&u)[K], cx<T> left, cx<T> right, const LineSet<T>& ls, int line, int i0,
                                    int n, FS fscan, BS bscan) {
     using C = cx<T>;
     const C a = ls.ae[2 * line], e = ls.ae[2 * line + 1];
@@ -151,154 +347,6 @@ __device__ inline void block_solve(cx<T> (&u)[K], cx<T> left, cx<T> right, const
     }
 }
 
-template <typename T, int K, bool IMAG, typename FS, typename BS>
-__device__ inline void block_solve3(cx<T> (&u)[3][K], const cx<T> (&left)[3], const cx<T> (&right)[3],
-                                    const LineSet<T>& ls, int line0, int i0, int n, FS fscan, BS bscan) {
-    using C = cx<T>;
-    C a[3], e[3], nam[3], ncp[3], lm[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        a[q] = ls.ae[2 * (line0 + q)];
-        e[q] = ls.ae[2 * (line0 + q) + 1];
-        const Piv<T> lim = ls.piv[(size_t)(line0 + q) * (ls.K + 1) + ls.K];
-        lm[q] = lim.m;
-        nam[q] = cneg(lim.am);
-        ncp[q] = cneg(lim.cp);
-    }
-    const bool fast = i0 >= ls.K && i0 + K <= n;
-    // right-hand side of the increment system: r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
-    C r[3][K];
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const C um = (k == 0) ? left[q] : u[q][k - 1];
-            const C up = (k == K - 1) ? right[q] : u[q][k + 1];
-            C t = mul_bm1<T, IMAG>(ls.bm1, u[q][k]);
-            t = cfma(um, a[q], t);
-            t = cfma(up, e[q], t);
-            r[q][k] = cscale(t, (T)-2);
-        }
-    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1}
-    C E[3], P[3], din[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) E[q] = zero_c<C>();
-    if (fast) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                E[q] = cfma(E[q], nam[q], cmul(lm[q], r[q][k]));
-                r[q][k] = E[q];
-            }
-#pragma unroll
-        for (int q = 0; q < 3; ++q) P[q] = cpow_k<C, K>(nam[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) P[q] = one_c<C>();
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = i0 + k;
-            const bool in = i >= 0 && i < n;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                if (in) {
-                    const Piv<T> pv = piv_at(ls, line0 + q, i);
-                    E[q] = cfma(E[q], cneg(pv.am), cmul(pv.m, r[q][k]));
-                    P[q] = cmul(cneg(pv.am), P[q]);
-                } else {
-                    E[q] = zero_c<C>();
-                    P[q] = zero_c<C>();
-                }
-                r[q][k] = E[q];
-            }
-        }
-    }
-    fscan(P, E, din);
-    // add the carry that enters the block, times the running product of -am
-    if (fast) {
-        C Q[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                Q[q] = cmul(Q[q], nam[q]);
-                r[q][k] = cfma(din[q], Q[q], r[q][k]);
-            }
-    } else {
-        C Q[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = i0 + k;
-            if (i >= 0 && i < n) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    Q[q] = cmul(Q[q], cneg(piv_at(ls, line0 + q, i).am));
-                    r[q][k] = cfma(din[q], Q[q], r[q][k]);
-                }
-            }
-        }
-    }
-    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1}
-    C G[3], R[3], xin[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) G[q] = zero_c<C>();
-    if (fast) {
-#pragma unroll
-        for (int k = K - 1; k >= 0; --k)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                G[q] = cfma(G[q], ncp[q], r[q][k]);
-                r[q][k] = G[q];
-            }
-#pragma unroll
-        for (int q = 0; q < 3; ++q) R[q] = cpow_k<C, K>(ncp[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < 3; ++q) R[q] = one_c<C>();
-#pragma unroll
-        for (int k = K - 1; k >= 0; --k) {
-            const int i = i0 + k;
-            const bool in = i >= 0 && i < n;
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                if (in) {
-                    const C nc = cneg(piv_at(ls, line0 + q, i).cp);
-                    G[q] = cfma(G[q], nc, r[q][k]);
-                    R[q] = cmul(nc, R[q]);
-                } else {
-                    G[q] = zero_c<C>();
-                    R[q] = zero_c<C>();
-                }
-                r[q][k] = G[q];
-            }
-        }
-    }
-    bscan(R, G, xin);
-    if (fast) {
-        C Sx[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
-#pragma unroll
-        for (int k = K - 1; k >= 0; --k)
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                Sx[q] = cmul(Sx[q], ncp[q]);
-                u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
-            }
-    } else {
-        C Sx[3] = {one_c<C>(), one_c<C>(), one_c<C>()};
-#pragma unroll
-        for (int k = K - 1; k >= 0; --k) {
-            const int i = i0 + k;
-            if (i >= 0 && i < n) {
-#pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    Sx[q] = cmul(Sx[q], cneg(piv_at(ls, line0 + q, i).cp));
-                    u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
-                }
-            }
-        }
-    }
-}
 
 // ---------------------------------------------------------------------------
 // Block reduction of one double (all threads call; result valid in thread 0).

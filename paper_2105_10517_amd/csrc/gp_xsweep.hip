@@ -16,8 +16,12 @@ template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE>
 __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
                               const LineSet<T>& ls, const double* __restrict__ scale, int G, int R, int blk) {
     using C = cx<T>;
-    __shared__ C shS[6 * 16];
+    // scan totals: [direction][line][P (16 waves) | E (16 waves)]
+    __shared__ C shS[2 * 3 * 32];
     __shared__ C shN[2 * 3 * 16];
+    // the first pivots of the row's three lines (the transient near the line start)
+    constexpr int KL = 8;
+    __shared__ Piv<T> shT[8 * 3 * KL];
     const int tid = threadIdx.x;
     const int r = tid / G, t = tid - r * G;
     const int lane = t & 63, w = t >> 6, nw = G >> 6;
@@ -26,6 +30,12 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     const int nx = ph.nx;
     const size_t plane = (size_t)ph.nx * ph.ny;
     const int i0 = t * K;
+    const int jl = row_ok ? j : 0;
+    const int kl = ls.K < KL ? ls.K : KL;
+    Piv<T>* tab = shT + (r < 8 ? r : 0) * 3 * KL;
+    if (r < 8)
+        for (int idx = t; idx < 3 * kl; idx += G)
+            tab[idx] = ls.piv[(size_t)(jl * 3 + idx / kl) * (ls.K + 1) + idx % kl];  // visible after the barrier below
     const size_t rowoff = (size_t)(row_ok ? j : 0) * nx;
     const C* rowp = src + rowoff;
     C* rowq = dst + rowoff;
@@ -77,19 +87,24 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
         if (lane == 0) left[q] = (w > 0) ? shN[(nrow + w - 1) * 3 + q] : zero_c<C>();
         if (lane == 63) right[q] = (w + 1 < nw) ? shN[48 + (nrow + w + 1) * 3 + q] : zero_c<C>();
     }
-    const int jl = row_ok ? j : 0;
-    C* ss = shS + 6 * nrow;
+    const PivSrc<T> ps = piv_src(ls, jl * 3, tab, kl);
     if constexpr (sizeof(T) * K <= 32) {
         // the three lines' chains interleaved (fits the register file for small blocks)
-        auto fs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) { row_scan3<true>(P, E, o, lane, w, nw, ss); };
-        auto bs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) { row_scan3<false>(P, E, o, lane, w, nw, ss); };
-        block_solve3<T, K, IMAG>(v, left, right, ls, jl * 3, i0, nx, fs, bs);
+        auto fs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) {
+            row_scan<true, 3>(P, E, o, lane, w, nw, ScanShm<C>{shS + nrow});
+        };
+        auto bs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) {
+            row_scan<false, 3>(P, E, o, lane, w, nw, ScanShm<C>{shS + 3 * 32 + nrow});
+        };
+        block_solve<T, K, IMAG, 3, 0, true>(v, left, right, ls, ps, i0, nx, fs, bs);
     } else {
         // one line after the other
-        auto fs = [&](C P, C E) { return row_scan<true>(P, E, lane, w, nw, ss, ss + nw); };
-        auto bs = [&](C P, C E) { return row_scan<false>(P, E, lane, w, nw, ss, ss + nw); };
+        C* sa = shS + nrow;
+        C* sb = shS + 16 + nrow;
+        auto fs = [&](C P, C E) { return row_scan1<true>(P, E, lane, w, nw, sa, sb); };
+        auto bs = [&](C P, C E) { return row_scan1<false>(P, E, lane, w, nw, sa, sb); };
 #pragma unroll
-        for (int q = 0; q < 3; ++q) block_solve<T, K, IMAG>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, fs, bs);
+        for (int q = 0; q < 3; ++q) block_solve1<T, K, IMAG>(v[q], left[q], right[q], ls, jl * 3 + q, i0, nx, fs, bs);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);

@@ -28,7 +28,9 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
                                 const LineSet<T>& ls, int L, int h, int ncs, NormOut no, int blk) {
     using C = cx<T>;
     constexpr int CPB = 4 * NW;  // columns per block
+    constexpr int KL = 8;
     __shared__ double shr[48];
+    __shared__ Piv<T> shT[CPB * 3 * KL];  // first pivots of the block's lines (windows at the column start)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane & 15, cw = lane >> 4;
     const int cs = blk % ncs, rt = blk / ncs;
@@ -38,6 +40,16 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     const size_t plane = (size_t)nx * ny;
     const int j0 = rt * L;
     const int g0 = j0 - h + seg * KY;  // first row of this lane
+    // windows that reach the start of the columns stage the transient pivots (block-uniform branch)
+    const int kl = (j0 - h < ls.K) ? (ls.K < KL ? ls.K : KL) : 0;
+    if (kl > 0) {
+        for (int idx = threadIdx.x; idx < CPB * 3 * kl; idx += 64 * NW) {
+            const int c = idx / (3 * kl), rem = idx - c * 3 * kl;
+            const int col = cs * CPB + c;
+            shT[idx] = ls.piv[(size_t)((col < nx ? col : 0) * 3 + rem / kl) * (ls.K + 1) + rem % kl];
+        }
+        __syncthreads();
+    }
     C v[3][KY];
 #pragma unroll
     for (int k = 0; k < KY; ++k) {
@@ -57,9 +69,10 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
         dn[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
     }
     const int il = col_ok ? i : 0;
-    auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan3<true>(P, E, o); };
-    auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan3<false>(P, E, o); };
-    block_solve3<T, KY, IMAG>(v, up, dn, ls, il * 3, g0, ny, fs, bs);
+    const PivSrc<T> ps = piv_src(ls, il * 3, shT + (wv * 4 + cw) * 3 * kl, kl);
+    auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
+    auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
+    block_solve<T, KY, IMAG, 3, 0, true>(v, up, dn, ls, ps, g0, ny, fs, bs);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     if (OUTL) {
