@@ -16,7 +16,7 @@ template <> __host__ __device__ constexpr YTile ytile<double>(int t) {
     return t == 0 ? YTile{8, 2} : t == 1 ? YTile{8, 4} : t == 2 ? YTile{4, 4} : YTile{4, 8};
 }
 template <> __host__ __device__ constexpr YTile ytile<float>(int t) {
-    return t == 0 ? YTile{8, 4} : t == 1 ? YTile{16, 2} : t == 2 ? YTile{16, 4} : YTile{8, 8};
+    return t == 0 ? YTile{8, 4} : t == 1 ? YTile{4, 8} : t == 2 ? YTile{4, 4} : YTile{8, 8};
 }
 __host__ __device__ constexpr int ywindow(YTile t) { return 16 * t.KY; }
 
