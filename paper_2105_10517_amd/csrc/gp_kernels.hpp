@@ -41,12 +41,24 @@ struct NormRule {
     double mag;
 };
 
+// The previous y sweep's norm partials, when the x sweep forms the scale
+// factors itself (every block sums them in the same order); partials ==
+// nullptr: the factors are read from `scale`.
+struct NormIn {
+    const double* partials;
+    int n;
+    double dxdy;
+    NormRule rule;
+    int* flag;
+};
+
 template <typename T> struct XLaunch {
     const cx<T>* src;
     cx<T>* dst;
     Phys ph;
     LineSet<T> ls;
     const double* scale;
+    NormIn nin;
     int K, G, R;
     bool imag, local;
 };

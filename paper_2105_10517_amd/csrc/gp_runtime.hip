@@ -557,6 +557,7 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.ph = phys(h->p);
     a.ls = lineset<T>(h->mode[imag].x);
     a.scale = h->d_scale;
+    a.nin = gp::NormIn{nullptr, 0, 0.0, gp::NormRule{0, 0.0}, nullptr};
     const ModeState& ms = h->mode[imag];
     a.K = ms.xK; a.G = ms.xG; a.R = ms.xR;
     a.imag = imag; a.local = local;
@@ -632,11 +633,19 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     const gp::NormRule rule = norm_rule(h->p);
     hipError_t e;
     if (imag && (e = gp::launch_set_scale(h->d_scale, 1.0, st)) != hipSuccess) return hip_fail(h, e, "set_scale");
+    // Imaginary time: the y sweep leaves per-block norm partials.  Where they are
+    // few, every block of the next x sweep sums them itself (no launch in
+    // between); otherwise one block sums them into the scale factors.  The last
+    // step's partials always go through that block (for the final scaling).
+    gp::XLaunch<T> xn = xa;
+    const bool fold = imag && 3 * nyb <= 8 * xa.G * xa.R;
+    if (fold) xn.nin = gp::NormIn{h->d_part, nyb, dxdy, rule, h->d_flag};
     for (int64_t s = 0; s < n; ++s) {
-        if ((e = timed(h, 0, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_x<T>(xa, st, a, b); })) != hipSuccess) return hip_fail(h, e, "x sweep launch");
-        // the y sweep leaves per-block norm partials; one block sums them into the scale
+        const gp::XLaunch<T>& x = s > 0 ? xn : xa;
+        if ((e = timed(h, 0, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_x<T>(x, st, a, b); })) != hipSuccess) return hip_fail(h, e, "x sweep launch");
         if ((e = timed(h, 1, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_y<T>(ya, st, a, b); })) != hipSuccess) return hip_fail(h, e, "y sweep launch");
-        if (imag && (e = timed(h, 2, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_norm_finalize(h->d_part, nyb, dxdy, rule, h->d_scale, h->d_flag, st, a, b); })) != hipSuccess)
+        if (imag && (!fold || s == n - 1) &&
+            (e = timed(h, 2, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_norm_finalize(h->d_part, nyb, dxdy, rule, h->d_scale, h->d_flag, st, a, b); })) != hipSuccess)
             return hip_fail(h, e, "norm launch");
     }
     if (imag) {

@@ -14,7 +14,8 @@ namespace gp {
 // threads per row (threads past G R idle through the barriers).
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE>
 __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
-                              const LineSet<T>& ls, const double* __restrict__ scale, int G, int R, int blk) {
+                              const LineSet<T>& ls, const double* __restrict__ scale, NormIn nin, int G, int R,
+                              int blk) {
     using C = cx<T>;
     // scan totals: [direction][line][P (16 waves) | E (16 waves)]
     __shared__ C shS[2 * 3 * 32];
@@ -53,9 +54,32 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
                 v[m][k] = (row_ok && i0 + k < nx) ? rowp[m * plane + i0 + k] : zero_c<C>();
     }
     if (SCALE) {
+        double sc[3];
+        if (nin.partials != nullptr) {
+            // the scale factors from the previous y sweep's partials (same order in every block)
+            __shared__ double shr3[48];
+            __shared__ double shs[3];
+            double acc[3] = {0, 0, 0};
+            for (int k = tid; k < nin.n; k += blockDim.x)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) acc[m] += nin.partials[3 * k + m];
+            block_sum3(acc, shr3);
+            if (tid == 0) {
+                const double N[3] = {acc[0] * nin.dxdy, acc[1] * nin.dxdy, acc[2] * nin.dxdy};
+                double f[3];
+                if (!norm_scales(N, nin.rule, f)) *nin.flag = 1;
+                shs[0] = f[0]; shs[1] = f[1]; shs[2] = f[2];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sc[m] = shs[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sc[m] = scale[m];
+        }
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const T s = (T)scale[m];
+            const T s = (T)sc[m];
 #pragma unroll
             for (int k = 0; k < K; ++k) v[m][k] = cscale(v[m][k], s);
         }
@@ -124,15 +148,17 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
 __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
-                                               LineSet<T> ls, const double* __restrict__ scale, int G, int R) {
-    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, ph, ls, scale, G, R, (int)blockIdx.x);
+                                               LineSet<T> ls, const double* __restrict__ scale, NormIn nin, int G,
+                                               int R) {
+    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, ph, ls, scale, nin, G, R, (int)blockIdx.x);
 }
 
 template <typename T, bool IMAG, int K, int LB>
 __global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
     const XSlot<T>& s = slots[e >> kMapShift];
-    x_rows<T, IMAG, K, true, IMAG>(s.src, s.dst, s.ph, s.ls, s.scale, s.G, s.R, (int)(e & kMapMask));
+    x_rows<T, IMAG, K, true, IMAG>(s.src, s.dst, s.ph, s.ls, s.scale, NormIn{nullptr, 0, 0.0, NormRule{0, 0.0}, nullptr},
+                                   s.G, s.R, (int)(e & kMapMask));
 }
 
 // ---------------------------------------------------------------------------
@@ -140,17 +166,18 @@ __global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slo
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, bool LOCAL, bool SCALE>
 static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph, const LineSet<T>& ls,
-                             const double* scale, int G, int R, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+                             const double* scale, NormIn nin, int G, int R, hipStream_t st, hipEvent_t e0,
+                             hipEvent_t e1) {
     const int nblk = (ph.ny + R - 1) / R;
     const dim3 grid(nblk), block(G * R);
     if (G * R > xk_bound(K) || G % 64 || G / 64 > 16 || R > 8) return hipErrorInvalidValue;
 
     switch (K) {
-        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
-        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
-        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
-        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
-        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, G, R); break;
+        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
+        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
+        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
+        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
+        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -159,11 +186,11 @@ static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph
 template <typename T>
 hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (a.imag) {
-        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
-        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
     }
-    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
-    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.G, a.R, st, e0, e1);
+    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
 }
 
 template <typename T, bool IMAG>
