@@ -269,3 +269,19 @@ def test_nonfinite_is_reported():
         s.observables(t)
     assert ei.value.status == binding.GP_ENONFINITE
     s.sync()  # the flag was cleared
+
+
+def test_imaginary_time_with_many_y_blocks():
+    # enough y windows that the next x sweep does not sum the norm partials itself
+    # (a separate one-block reduction between the steps)
+    p = all_couplings(256, 4000, 0.1, dy=0.05, dt=0.002, omega=0.3)
+    q = binding.plan_query(p, True)
+    assert q["y_solver"] == binding.GP_YSOLVER_WINDOW
+    # y blocks (32 column strips x windows of y_rows_out rows) far more than the x threads can sum
+    nyb = (256 // q["y_tile_cols"]) * -(-4000 // q["y_rows_out"])
+    assert 3 * nyb > 8 * q["x_threads_per_row"] * q["x_rows_per_block"]
+    psi0 = inputs.gaussian(256, 4000, 0.1, 0.05, x0=p["x0"], y0=p["y0"], seed=12, center=(0.5, 20.0))
+    got, obs = gpu_run(p, psi0, 12, True)
+    want = oracle.step(p, psi0, 12, True)
+    assert rel(got, want) < 1e-11
+    assert abs(obs["norm_total"] - 1.0) < 1e-13
