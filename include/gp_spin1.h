@@ -68,6 +68,14 @@ typedef enum {
     GP_YSOLVER_THOMAS = 2  /* exact per-thread Thomas down whole columns (one thread per column) */
 } gp_ysolver;
 
+/* Choice of the x-sweep line solver. */
+typedef enum {
+    GP_XSOLVER_AUTO = 0,   /* whole-row partitioned Thomas, or the windows when autotuning finds them faster */
+    GP_XSOLVER_SCAN = 1,   /* exact partitioned Thomas over whole rows (scans across the row's threads)     */
+    GP_XSOLVER_WINDOW = 2  /* truncated overlapping windows along the rows (the y sweep's scheme); refused
+                              (GP_EUNSUPPORTED) when the decay bound does not fit any window            */
+} gp_xsolver;
+
 /* Order of the substeps within one step. */
 typedef enum {
     GP_SPLIT_LIE = 0,    /* local substep (dt), x sweep, y sweep: the order the paper's scheme name implies */
@@ -101,6 +109,7 @@ typedef struct {
                                   factors of the normalised gradient flow (Bao and Lim, SIAM J. Sci.
                                   Comput. 30, 2008); needs gamma = rabi = 0 and |magnetization| < 1     */
     double magnetization;
+    int32_t x_solver;        /* gp_xsolver                                                                  */
 } gp_spin1_params;
 
 /* Observables of one wave function (all FP64, rectangle-rule quadrature
@@ -134,6 +143,10 @@ typedef struct {
     int32_t pivots_x, pivots_y;  /* tabulated Thomas pivots per line before the constant limit  */
     double decay_x, decay_y;     /* largest |a m| or |c'| of the converged pivots per direction  */
     int32_t stable;              /* 1 if the mode passed the stability checks                    */
+    int32_t x_solver;            /* GP_XSOLVER_SCAN or GP_XSOLVER_WINDOW                          */
+    int32_t x_halo;              /* windows: points of overlap on each side                       */
+    int32_t x_points_out;        /* windows: points written per window                            */
+    int32_t x_tile;              /* windows: 1..4, same shapes as y_tile (rows per block = 4 per wave) */
 } gp_spin1_plan;
 
 typedef struct gp_spin1 gp_spin1_t;

@@ -18,6 +18,7 @@ LIBPATH = os.path.join(_HERE, "libgp_spin1.so")
 GP_OK, GP_EINVAL, GP_EUNSTABLE, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GP_FP64, GP_FP32 = 0, 1
 GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS = 0, 1, 2
+GP_XSOLVER_AUTO, GP_XSOLVER_SCAN, GP_XSOLVER_WINDOW = 0, 1, 2
 SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
 
 # Every entry point the header declares (checked by the CPU test suite).
@@ -49,7 +50,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("y_solver", ctypes.c_int32),
                 ("x_points", ctypes.c_int32), ("y_tile", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("trap_gx", ctypes.c_double), ("trap_gy", ctypes.c_double), ("split", ctypes.c_int32),
-                ("fix_magnetization", ctypes.c_int32), ("magnetization", ctypes.c_double)]
+                ("fix_magnetization", ctypes.c_int32), ("magnetization", ctypes.c_double),
+                ("x_solver", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -74,7 +76,8 @@ class Plan(ctypes.Structure):
                 ("y_tile", ctypes.c_int32), ("y_tile_cols", ctypes.c_int32), ("y_segments", ctypes.c_int32),
                 ("y_rows_per_thread", ctypes.c_int32), ("pivots_x", ctypes.c_int32),
                 ("pivots_y", ctypes.c_int32), ("decay_x", ctypes.c_double), ("decay_y", ctypes.c_double),
-                ("stable", ctypes.c_int32)]
+                ("stable", ctypes.c_int32), ("x_solver", ctypes.c_int32), ("x_halo", ctypes.c_int32),
+                ("x_points_out", ctypes.c_int32), ("x_tile", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -157,7 +160,7 @@ def load():
 
 
 def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0, y_tile: int = 0,
-                autotune: bool = False) -> Params:
+                autotune: bool = False, x_solver: str = "auto") -> Params:
     """Params from a plain mapping (keys nx, ny, dx, dy, x0, y0, dt, c0, c2,
     gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2;
     optional gx, gy (trap), split (0 Lie, 1 Strang), fix_m and magnetization)."""
@@ -168,7 +171,8 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_poin
                   float(p.get("c0", 0.0)), float(p.get("c2", 0.0)), float(p.get("gamma", 0.0)),
                   int(p.get("eta", 1)), float(p.get("rabi", 0.0)), float(p.get("omega", 0.0)), prec, ys,
                   int(x_points), int(y_tile), int(bool(autotune)), float(p.get("gx", 1.0)), float(p.get("gy", 1.0)),
-                  int(p.get("split", 0)), int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)))
+                  int(p.get("split", 0)), int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)),
+                  {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW}[x_solver])
 
 
 def _obs_dict(o: Obs) -> dict:
@@ -178,12 +182,12 @@ def _obs_dict(o: Obs) -> dict:
 
 
 def plan_query(p: dict, imag: bool, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0,
-               y_tile: int = 0) -> dict:
+               y_tile: int = 0, x_solver: str = "auto") -> dict:
     """Host-only plan (no GPU needed): pivot table lengths, decay factors,
     y solver and stability flag for these parameters."""
     lib = load()
     pl = Plan()
-    pp = make_params(p, precision, y_solver, x_points, y_tile)
+    pp = make_params(p, precision, y_solver, x_points, y_tile, x_solver=x_solver)
     rc = lib.gp_spin1_plan_query(ctypes.byref(pp), int(bool(imag)), ctypes.byref(pl))
     if rc != GP_OK:
         raise GPError(rc, "gp_spin1_plan_query: " + lib.gp_spin1_strerror(rc).decode())
@@ -194,7 +198,7 @@ class Solver:
     """One condensate on one stream: a handle of the C ABI."""
 
     def __init__(self, p: dict, precision: str = "fp64", y_solver: str = "auto", stream=None, x_points: int = 0,
-                 y_tile: int = 0, autotune: bool = False):
+                 y_tile: int = 0, autotune: bool = False, x_solver: str = "auto"):
         import torch
         self._lib = load()
         self.precision = precision
@@ -206,7 +210,7 @@ class Solver:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._h = ctypes.c_void_p()
-        pp = make_params(p, precision, y_solver, x_points, y_tile, autotune)
+        pp = make_params(p, precision, y_solver, x_points, y_tile, autotune, x_solver)
         rc = self._lib.gp_spin1_create(ctypes.byref(pp), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
         if rc != GP_OK:
             raise GPError(rc, "gp_spin1_create: " + self._lib.gp_spin1_strerror(rc).decode())

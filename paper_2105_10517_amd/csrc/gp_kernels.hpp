@@ -61,6 +61,8 @@ template <typename T> struct XLaunch {
     NormIn nin;
     int K, G, R;
     bool imag, local;
+    bool window;    // truncated windows along the rows (tile shapes as the y sweep's) instead of whole rows
+    int L, h, tile;
 };
 
 template <typename T> struct YLaunch {

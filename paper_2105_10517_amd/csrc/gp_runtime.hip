@@ -41,6 +41,8 @@ struct ModeState {
     int h = 0, L = 0;  // halo and rows written per window for the chosen tile
     int xK = 2, xG = 64, xR = 1;  // x sweep: points per thread, threads per row, rows per block
     int ytile = 0;                // windowed y sweep tile shape (0-based)
+    bool xwindow = false;         // x sweep over truncated windows
+    int hhx = 0, hx = 0, Lx = 0, xtile = 0;
     gp_spin1_plan plan{};
 };
 
@@ -246,7 +248,17 @@ struct HostMode {
     bool window = false;
     int hh = 0, h = 0, L = 0;
     int xK = 2, xG = 64, xR = 1, ytile = 0;
+    bool xwindow = false;
+    int hhx = 0, hx = 0, Lx = 0, xtile = 0;
 };
+
+// Halo that makes decay^h fall below the rounding level of T.
+template <typename T> int halo_for(double decay) {
+    const double tolw = sizeof(T) == 8 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -32);
+    if (decay <= 0.0) return 1;
+    if (decay >= 1.0) return 1 << 20;
+    return (int)std::ceil(std::log(tolw) / std::log(decay)) + 1;
+}
 
 // Window of a y tile shape: the whole column fits one window (no halo), or
 // windows of W rows overlap by the halo hh on each side and write W - 2 hh
@@ -305,6 +317,13 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     // launch shapes requested in p, else the defaults (autotuning may replace them)
     hm.xK = p.x_points > 0 ? p.x_points : x_default_k(p.nx);
     x_shape(p.nx, hm.xK, hm.xG, hm.xR);
+    // x windows: only when asked for (autotuning may also choose them)
+    hm.hhx = halo_for<T>(hm.x.decay);
+    hm.xwindow = false;
+    hm.hx = hm.Lx = hm.xtile = 0;
+    if (p.x_solver == GP_XSOLVER_WINDOW)
+        for (int t = 0; t < gp::kNumYTiles && !hm.xwindow; ++t)
+            if (tile_window(p.nx, hm.hhx, gp::ywindow(gp::ytile<T>(t)), hm.hx, hm.Lx)) { hm.xwindow = true; hm.xtile = t; }
 }
 
 template <typename T>
@@ -326,6 +345,10 @@ void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out)
     out->decay_x = hm.x.decay;
     out->decay_y = hm.y.decay;
     out->stable = hm.stable ? 1 : 0;
+    out->x_solver = hm.xwindow ? GP_XSOLVER_WINDOW : GP_XSOLVER_SCAN;
+    out->x_halo = hm.xwindow ? hm.hx : 0;
+    out->x_points_out = hm.xwindow ? hm.Lx : 0;
+    out->x_tile = hm.xwindow ? hm.xtile + 1 : 0;
 }
 
 template <typename T>
@@ -345,6 +368,8 @@ int build_mode(gp_spin1* h, ModeState& ms, bool imag) {
     ms.L = hm.L;
     ms.xK = hm.xK; ms.xG = hm.xG; ms.xR = hm.xR;
     ms.ytile = hm.ytile;
+    ms.xwindow = hm.xwindow;
+    ms.hhx = hm.hhx; ms.hx = hm.hx; ms.Lx = hm.Lx; ms.xtile = hm.xtile;
     fill_plan<T>(p, hm, &ms.plan);
     return GP_OK;
 }
@@ -405,6 +430,7 @@ int validate(const gp_spin1_params* p, std::string& why) {
         why = "trap_gx, trap_gy must be finite and >= 0 (0 selects 1)";
         return GP_EINVAL;
     }
+    if (p->x_solver < GP_XSOLVER_AUTO || p->x_solver > GP_XSOLVER_WINDOW) { why = "unknown x_solver"; return GP_EINVAL; }
     if (p->split != GP_SPLIT_LIE && p->split != GP_SPLIT_STRANG) { why = "split must be GP_SPLIT_LIE or GP_SPLIT_STRANG"; return GP_EINVAL; }
     if (p->fix_magnetization != 0 && p->fix_magnetization != 1) { why = "fix_magnetization must be 0 or 1"; return GP_EINVAL; }
     if (p->fix_magnetization) {
@@ -458,7 +484,7 @@ int autotune_t(gp_spin1* h) {
     for (int m = 0; m < 2 && rc == GP_OK; ++m) {
         ModeState& ms = h->mode[m];
         const bool imag = m == 1;
-        if (p.x_points == 0) {
+        if (p.x_points == 0 && p.x_solver != GP_XSOLVER_WINDOW) {
             float best = 1e30f;
             int bestK = ms.xK;
             for (int idx = 0; idx < gp::kNumXK && rc == GP_OK; ++idx) {
@@ -473,6 +499,40 @@ int autotune_t(gp_spin1* h) {
             }
             ms.xK = bestK;
             x_shape(p.nx, bestK, ms.xG, ms.xR);
+            // windows along the rows, where the decay bound fits a window
+            ms.xwindow = false;
+            if (p.x_solver == GP_XSOLVER_AUTO) {
+                int bestT = -1;
+                for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
+                    if (!tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(t)), ms.hx, ms.Lx)) continue;
+                    ms.xwindow = true;
+                    ms.xtile = t;
+                    const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
+                    float tt = 0.f;
+                    rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
+                    if (rc == GP_OK && tt < best) { best = tt; bestT = t; }
+                }
+                ms.xwindow = bestT >= 0;
+                if (ms.xwindow) {
+                    ms.xtile = bestT;
+                    tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(bestT)), ms.hx, ms.Lx);
+                }
+            }
+        }
+        if (p.x_solver == GP_XSOLVER_WINDOW) {
+            // windows asked for: the fastest tile
+            float best = 1e30f;
+            int bestT = ms.xtile;
+            for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
+                if (!tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(t)), ms.hx, ms.Lx)) continue;
+                ms.xtile = t;
+                const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
+                float tt = 0.f;
+                rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
+                if (rc == GP_OK && tt < best) { best = tt; bestT = t; }
+            }
+            ms.xtile = bestT;
+            tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(bestT)), ms.hx, ms.Lx);
         }
         if (p.y_tile == 0 && ms.window) {
             float best = 1e30f;
@@ -491,6 +551,10 @@ int autotune_t(gp_spin1* h) {
         ms.plan.x_points_per_thread = ms.xK;
         ms.plan.x_threads_per_row = ms.xG;
         ms.plan.x_rows_per_block = ms.xR;
+        ms.plan.x_solver = ms.xwindow ? GP_XSOLVER_WINDOW : GP_XSOLVER_SCAN;
+        ms.plan.x_halo = ms.xwindow ? ms.hx : 0;
+        ms.plan.x_points_out = ms.xwindow ? ms.Lx : 0;
+        ms.plan.x_tile = ms.xwindow ? ms.xtile + 1 : 0;
         const gp::YTile yt = gp::ytile<T>(ms.ytile);
         ms.plan.y_tile = ms.ytile + 1;
         ms.plan.y_tile_cols = 4 * yt.NW;
@@ -521,6 +585,8 @@ int create_t(gp_spin1* h) {
     for (int m = 0; m < 2; ++m) {
         int rc = build_mode<T>(h, h->mode[m], m == 1);
         if (rc) return rc;
+        if (p.x_solver == GP_XSOLVER_WINDOW && !h->mode[m].xwindow)
+            return fail(h, GP_EUNSUPPORTED, "x windows asked for, but the decay of the x lines fits no window");
     }
     size_t need = 1;
     for (auto& m : h->mode) need = std::max(need, max_y_blocks<T>(p, m));
@@ -561,6 +627,7 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     const ModeState& ms = h->mode[imag];
     a.K = ms.xK; a.G = ms.xG; a.R = ms.xR;
     a.imag = imag; a.local = local;
+    a.window = ms.xwindow; a.L = ms.Lx; a.h = ms.hx; a.tile = ms.xtile;
     return a;
 }
 
@@ -638,7 +705,7 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     // between); otherwise one block sums them into the scale factors.  The last
     // step's partials always go through that block (for the final scaling).
     gp::XLaunch<T> xn = xa;
-    const bool fold = imag && 3 * nyb <= 8 * xa.G * xa.R;
+    const bool fold = imag && !xa.window && 3 * nyb <= 8 * xa.G * xa.R;
     if (fold) xn.nin = gp::NormIn{h->d_part, nyb, dxdy, rule, h->d_flag};
     for (int64_t s = 0; s < n; ++s) {
         const gp::XLaunch<T>& x = s > 0 ? xn : xa;

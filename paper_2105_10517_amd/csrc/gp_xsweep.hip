@@ -146,6 +146,102 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     }
 }
 
+// ---------------------------------------------------------------------------
+// x sweep over truncated windows (the y sweep's scheme turned along the rows):
+// a wave holds 4 rows, each DPP row of 16 lanes the 16 segments of one row
+// window, each lane KX consecutive points; windows of 16 KX points overlap by
+// h points on each side and write their middle L = 16 KX - 2 h points, h such
+// that the carries dropped at the window ends have decayed below the rounding
+// level.  No shared-memory scans and no barriers (except the staging of the
+// transient pivots in windows at the row start); the local substep and the
+// pending scale are applied to every point loaded, halo included.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, int KX, int NW, bool LOCAL, bool SCALE>
+__device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
+                                const LineSet<T>& ls, const double* __restrict__ scale, int L, int h, int ncs,
+                                int blk) {
+    using C = cx<T>;
+    constexpr int RPB = 4 * NW;  // rows per block
+    constexpr int KL = 8;
+    __shared__ Piv<T> shT[RPB * 3 * KL];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane & 15, rw = lane >> 4;
+    const int cs = blk % ncs, rt = blk / ncs;
+    const int j = rt * RPB + wv * 4 + rw;
+    const bool row_ok = j < ph.ny;
+    const int nx = ph.nx;
+    const size_t plane = (size_t)nx * ph.ny;
+    const int i0 = cs * L;           // first point written by this window
+    const int g0 = i0 - h + seg * KX;  // first point of this lane
+    const int jl = row_ok ? j : 0;
+    // windows that reach the start of the rows stage the transient pivots (block-uniform branch)
+    const int kl = (i0 - h < ls.K) ? (ls.K < KL ? ls.K : KL) : 0;
+    if (kl > 0) {
+        for (int idx = threadIdx.x; idx < RPB * 3 * kl; idx += 64 * NW) {
+            const int rr = idx / (3 * kl), rem = idx - rr * 3 * kl;
+            const int row = rt * RPB + rr;
+            shT[idx] = ls.piv[(size_t)((row < ph.ny ? row : 0) * 3 + rem / kl) * (ls.K + 1) + rem % kl];
+        }
+        __syncthreads();
+    }
+    const C* rowp = src + (size_t)jl * nx;
+    C v[3][KX];
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+        const int g = g0 + k;
+        const bool ok = row_ok && g >= 0 && g < nx;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? rowp[m * plane + (ok ? g : 0)] : zero_c<C>();
+    }
+    if (SCALE) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const T s = (T)scale[m];
+#pragma unroll
+            for (int k = 0; k < KX; ++k) v[m][k] = cscale(v[m][k], s);
+        }
+    }
+    if (LOCAL) {
+        const T y = (T)(ph.y0 + jl * ph.dy);
+#pragma unroll
+        for (int k = 0; k < KX; ++k) {
+            const T x = (T)(ph.x0 + (g0 + k) * ph.dx);
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], trap_v<T>(ph, x, y), (T)ph.dtl, (T)ph.c0, (T)ph.c2,
+                                   (T)ph.rabi);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < KX; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    // points just left and right of this lane's segment (zeros outside the window)
+    C lf[3], rg[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        lf[q] = dpp_c<0x111>(zero_c<C>(), v[q][KX - 1]);  // row_shr:1
+        rg[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
+    }
+    const PivSrc<T> ps = piv_src(ls, jl * 3, shT + (wv * 4 + rw) * 3 * kl, kl);
+    auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
+    auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
+    block_solve<T, KX, IMAG, 3, 0, true>(v, lf, rg, ls, ps, g0, nx, fs, bs);
+#pragma unroll
+    for (int k = 0; k < KX; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    C* rowq = dst + (size_t)jl * nx;
+#pragma unroll
+    for (int k = 0; k < KX; ++k) {
+        const int g = g0 + k;
+        if (row_ok && g >= i0 && g < i0 + L && g < nx)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) rowq[m * plane + g] = v[m][k];
+    }
+}
+
+template <typename T, bool IMAG, int KX, int NW, bool LOCAL, bool SCALE>
+__global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                      Phys ph, LineSet<T> ls, const double* __restrict__ scale, int L,
+                                                      int h, int ncs) {
+    x_window<T, IMAG, KX, NW, LOCAL, SCALE>(src, dst, ph, ls, scale, L, h, ncs, (int)blockIdx.x);
+}
+
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
 __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
                                                LineSet<T> ls, const double* __restrict__ scale, NormIn nin, int G,
@@ -183,8 +279,35 @@ static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph
     return hipGetLastError();
 }
 
+template <typename T, bool IMAG, bool LOCAL, bool SCALE, int TI>
+static hipError_t launch_xw_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    constexpr YTile xt = ytile<T>(TI);
+    const int ncs = (a.ph.nx + a.L - 1) / a.L;
+    const int nrt = (a.ph.ny + 4 * xt.NW - 1) / (4 * xt.NW);
+    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, LOCAL, SCALE>, dim3(ncs * nrt), dim3(64 * xt.NW), 0, st, e0,
+                          e1, 0, a.src, a.dst, a.ph, a.ls, a.scale, a.L, a.h, ncs);
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG, bool LOCAL, bool SCALE>
+static hipError_t launch_xw(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    switch (a.tile) {
+        case 0: return launch_xw_t<T, IMAG, LOCAL, SCALE, 0>(a, st, e0, e1);
+        case 1: return launch_xw_t<T, IMAG, LOCAL, SCALE, 1>(a, st, e0, e1);
+        case 2: return launch_xw_t<T, IMAG, LOCAL, SCALE, 2>(a, st, e0, e1);
+        case 3: return launch_xw_t<T, IMAG, LOCAL, SCALE, 3>(a, st, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (a.window) {
+        // the windowed kernel takes its scale factors from `scale` (the norm totals are formed beforehand)
+        if (a.nin.partials != nullptr) return hipErrorInvalidValue;
+        if (a.imag) return a.local ? launch_xw<T, true, true, true>(a, st, e0, e1) : launch_xw<T, true, false, false>(a, st, e0, e1);
+        return a.local ? launch_xw<T, false, true, false>(a, st, e0, e1) : launch_xw<T, false, false, false>(a, st, e0, e1);
+    }
     if (a.imag) {
         if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
         return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);

@@ -82,6 +82,49 @@ def test_x_sweep(imag, nx):
 
 
 @pytest.mark.parametrize("imag", [True, False])
+@pytest.mark.parametrize("nx", [3, 53, 128, 131, 700, 1024, 4096])
+def test_x_sweep_windows(imag, nx):
+    # truncated windows along the rows: one window (no halo) up to 16 KX points, overlapping windows beyond
+    p = all_couplings(nx, 5, 0.05, dy=0.2, dt=0.001, eta=-1 if nx % 2 else 1)
+    psi = inputs.random_state(nx, 5, seed=nx + 7)
+    s = binding.Solver(p, x_solver="window")
+    assert s.plan(imag)["x_solver"] == binding.GP_XSOLVER_WINDOW
+    t = dev(psi)
+    s.substep(t, binding.SUB_X, imag)
+    got = host(t)
+    want = oracle.sweep_x(p, psi, imag)
+    assert rel(got, want) < 1e-13, s.plan(imag)
+
+
+@pytest.mark.parametrize("imag", [True, False])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_x_windows_full_steps(imag, precision):
+    # whole steps (local substep and pending scale fused into the windowed x sweep)
+    p = all_couplings(700, 61, 0.06, dy=0.1, dt=0.0015)
+    psi0 = inputs.gaussian(700, 61, 0.06, 0.1, x0=p["x0"], y0=p["y0"], seed=15, center=(4.0, 0.3))
+    s = binding.Solver(p, precision, x_solver="window")
+    assert s.plan(imag)["x_points_out"] < 700  # several windows per row
+    t = dev(psi0, s.dtype)
+    (s.step_imag if imag else s.step_real)(t, 60)
+    s.sync()
+    got = host(t)
+    s.close()
+    want = oracle.step(p, psi0, 60, imag)
+    if precision == "fp64":
+        assert rel(got, want) < 1e-11
+    else:
+        rho_g, rho_w = np.abs(got) ** 2, np.abs(want) ** 2
+        assert float(np.abs(rho_g - rho_w).max() / rho_w.max()) < 1e-5
+
+
+def test_x_windows_refused_when_the_decay_is_slow():
+    p = all_couplings(2000, 5, 0.005, dt=0.01)
+    with pytest.raises(binding.GPError) as ei:
+        binding.Solver(p, x_solver="window")
+    assert ei.value.status == binding.GP_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("imag", [True, False])
 @pytest.mark.parametrize("solver", ["window", "thomas"])
 @pytest.mark.parametrize("ny", [3, 100, 128, 129, 600, 1000])
 def test_y_sweep(imag, solver, ny):
