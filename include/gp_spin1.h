@@ -61,7 +61,7 @@ typedef enum {
 
 typedef enum { GP_FP64 = 0, GP_FP32 = 1 } gp_precision; /* FP32: bulk in FP32, reductions in FP64 */
 
-/* Choice of the y-sweep line solver (the x sweep always uses whole rows). */
+/* Choice of the y-sweep line solver. */
 typedef enum {
     GP_YSOLVER_AUTO = 0,   /* windowed scan when its truncation bound holds, else per-column Thomas */
     GP_YSOLVER_WINDOW = 1, /* windowed partitioned scan over column tiles (2 HBM passes per step) */
@@ -75,6 +75,16 @@ typedef enum {
     GP_XSOLVER_WINDOW = 2  /* truncated overlapping windows along the rows (the y sweep's scheme); refused
                               (GP_EUNSUPPORTED) when the decay bound does not fit any window            */
 } gp_xsolver;
+
+/* Block order of the windowed sweeps.  The chip hands workgroups to its 8
+ * XCDs (each with its own L2) in turn; grouping gives each XCD a contiguous
+ * run of windows instead, so that overlapping halos are read through one L2. */
+typedef enum {
+    GP_ORDER_AUTO = 0,     /* x windows grouped, y windows grouped only on grids of about one wave of blocks;
+                              with autotune, both timed and the faster kept per sweep                       */
+    GP_ORDER_HARDWARE = 1, /* block b processes window b                                                    */
+    GP_ORDER_XCD = 2       /* block b processes window (b mod 8) ceil(n/8) + b div 8 (n windows)            */
+} gp_block_order;
 
 /* Order of the substeps within one step. */
 typedef enum {
@@ -110,6 +120,8 @@ typedef struct {
                                   Comput. 30, 2008); needs gamma = rabi = 0 and |magnetization| < 1     */
     double magnetization;
     int32_t x_solver;        /* gp_xsolver                                                                  */
+    int32_t block_order;     /* gp_block_order: how the windowed sweeps number their blocks (no effect on
+                                results, which are bit-identical in every order)                         */
 } gp_spin1_params;
 
 /* Observables of one wave function (all FP64, rectangle-rule quadrature
@@ -147,6 +159,8 @@ typedef struct {
     int32_t x_halo;              /* windows: points of overlap on each side                       */
     int32_t x_points_out;        /* windows: points written per window                            */
     int32_t x_tile;              /* windows: 1..4, same shapes as y_tile (rows per block = 4 per wave) */
+    int32_t x_block_order;       /* windows: 0 blocks in hardware order, 1 grouped by XCD (each of  */
+    int32_t y_block_order;       /*   the 8 XCDs takes a contiguous run of windows, sharing halos)  */
 } gp_spin1_plan;
 
 typedef struct gp_spin1 gp_spin1_t;

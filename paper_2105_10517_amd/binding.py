@@ -19,6 +19,7 @@ GP_OK, GP_EINVAL, GP_EUNSTABLE, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORT
 GP_FP64, GP_FP32 = 0, 1
 GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS = 0, 1, 2
 GP_XSOLVER_AUTO, GP_XSOLVER_SCAN, GP_XSOLVER_WINDOW = 0, 1, 2
+GP_ORDER_AUTO, GP_ORDER_HARDWARE, GP_ORDER_XCD = 0, 1, 2
 SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
 
 # Every entry point the header declares (checked by the CPU test suite).
@@ -51,7 +52,7 @@ class Params(ctypes.Structure):
                 ("x_points", ctypes.c_int32), ("y_tile", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("trap_gx", ctypes.c_double), ("trap_gy", ctypes.c_double), ("split", ctypes.c_int32),
                 ("fix_magnetization", ctypes.c_int32), ("magnetization", ctypes.c_double),
-                ("x_solver", ctypes.c_int32)]
+                ("x_solver", ctypes.c_int32), ("block_order", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -77,7 +78,8 @@ class Plan(ctypes.Structure):
                 ("y_rows_per_thread", ctypes.c_int32), ("pivots_x", ctypes.c_int32),
                 ("pivots_y", ctypes.c_int32), ("decay_x", ctypes.c_double), ("decay_y", ctypes.c_double),
                 ("stable", ctypes.c_int32), ("x_solver", ctypes.c_int32), ("x_halo", ctypes.c_int32),
-                ("x_points_out", ctypes.c_int32), ("x_tile", ctypes.c_int32)]
+                ("x_points_out", ctypes.c_int32), ("x_tile", ctypes.c_int32),
+                ("x_block_order", ctypes.c_int32), ("y_block_order", ctypes.c_int32)]
 
 
 class BatchInfo(ctypes.Structure):
@@ -160,7 +162,7 @@ def load():
 
 
 def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0, y_tile: int = 0,
-                autotune: bool = False, x_solver: str = "auto") -> Params:
+                autotune: bool = False, x_solver: str = "auto", block_order: str = "auto") -> Params:
     """Params from a plain mapping (keys nx, ny, dx, dy, x0, y0, dt, c0, c2,
     gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2;
     optional gx, gy (trap), split (0 Lie, 1 Strang), fix_m and magnetization)."""
@@ -172,7 +174,8 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_poin
                   int(p.get("eta", 1)), float(p.get("rabi", 0.0)), float(p.get("omega", 0.0)), prec, ys,
                   int(x_points), int(y_tile), int(bool(autotune)), float(p.get("gx", 1.0)), float(p.get("gy", 1.0)),
                   int(p.get("split", 0)), int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)),
-                  {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW}[x_solver])
+                  {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW}[x_solver],
+                  {"auto": GP_ORDER_AUTO, "hardware": GP_ORDER_HARDWARE, "xcd": GP_ORDER_XCD}[block_order])
 
 
 def _obs_dict(o: Obs) -> dict:
@@ -182,12 +185,12 @@ def _obs_dict(o: Obs) -> dict:
 
 
 def plan_query(p: dict, imag: bool, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0,
-               y_tile: int = 0, x_solver: str = "auto") -> dict:
+               y_tile: int = 0, x_solver: str = "auto", block_order: str = "auto") -> dict:
     """Host-only plan (no GPU needed): pivot table lengths, decay factors,
     y solver and stability flag for these parameters."""
     lib = load()
     pl = Plan()
-    pp = make_params(p, precision, y_solver, x_points, y_tile, x_solver=x_solver)
+    pp = make_params(p, precision, y_solver, x_points, y_tile, x_solver=x_solver, block_order=block_order)
     rc = lib.gp_spin1_plan_query(ctypes.byref(pp), int(bool(imag)), ctypes.byref(pl))
     if rc != GP_OK:
         raise GPError(rc, "gp_spin1_plan_query: " + lib.gp_spin1_strerror(rc).decode())
@@ -198,7 +201,7 @@ class Solver:
     """One condensate on one stream: a handle of the C ABI."""
 
     def __init__(self, p: dict, precision: str = "fp64", y_solver: str = "auto", stream=None, x_points: int = 0,
-                 y_tile: int = 0, autotune: bool = False, x_solver: str = "auto"):
+                 y_tile: int = 0, autotune: bool = False, x_solver: str = "auto", block_order: str = "auto"):
         import torch
         self._lib = load()
         self.precision = precision
@@ -210,7 +213,7 @@ class Solver:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._h = ctypes.c_void_p()
-        pp = make_params(p, precision, y_solver, x_points, y_tile, autotune, x_solver)
+        pp = make_params(p, precision, y_solver, x_points, y_tile, autotune, x_solver, block_order)
         rc = self._lib.gp_spin1_create(ctypes.byref(pp), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
         if rc != GP_OK:
             raise GPError(rc, "gp_spin1_create: " + self._lib.gp_spin1_strerror(rc).decode())

@@ -25,6 +25,20 @@ constexpr int kNumXK = 5;
 __host__ __device__ constexpr int xk_value(int idx) { return 1 << idx; }  // 1, 2, 4, 8, 16
 __host__ __device__ constexpr int xk_bound(int K) { return K == 1 ? 1024 : 512; }
 
+// Workgroups are dispatched to the 8 XCDs of the chip in turn (block b to XCD
+// b mod 8), each with its own L2.  The windowed sweeps can renumber their
+// blocks (block order 1) so that every XCD gets a contiguous run of logical
+// blocks: neighbouring windows, whose halos overlap, then share an L2, at the
+// price of eight far-apart streams through HBM instead of one band.  Such
+// launches use 8 ceil(n / 8) blocks; logical numbers >= n exit at once.
+// Block order 0 keeps the hardware order.
+constexpr int kNumXcd = 8;
+__host__ __device__ inline int xcd_blocks(int n) { return (n + kNumXcd - 1) / kNumXcd * kNumXcd; }
+__device__ inline int xcd_logical(int b, int n) {
+    const int q = (n + kNumXcd - 1) / kNumXcd;
+    return (b % kNumXcd) * q + b / kNumXcd;
+}
+
 // Both sweeps run out of place (src -> dst): the y windows overlap, so a
 // window's halo rows must not be rewritten by its neighbour while it reads.
 // Where the y sweep leaves the imaginary-time norm: three partial sums per
@@ -63,6 +77,7 @@ template <typename T> struct XLaunch {
     bool imag, local;
     bool window;    // truncated windows along the rows (tile shapes as the y sweep's) instead of whole rows
     int L, h, tile;
+    int order;      // windows: block order (0 hardware, 1 grouped by XCD)
 };
 
 template <typename T> struct YLaunch {
@@ -74,6 +89,7 @@ template <typename T> struct YLaunch {
     int L, h, tile;
     bool window, imag, norm;
     bool outl;  // second half local substep on the way out (Strang)
+    int order;  // windows: block order (0 hardware, 1 grouped by XCD)
 };
 
 // Batched launches: one descriptor per condensate and one map entry per block,

@@ -43,6 +43,7 @@ struct ModeState {
     int ytile = 0;                // windowed y sweep tile shape (0-based)
     bool xwindow = false;         // x sweep over truncated windows
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
+    int xorder = 1, yorder = 0;   // block orders of the windowed sweeps (0 hardware, 1 grouped by XCD)
     gp_spin1_plan plan{};
 };
 
@@ -73,6 +74,7 @@ struct gp_spin1 {
 namespace {
 
 constexpr double kNu[3] = {1.0, 0.0, -1.0};  // eigenvalue order of the basis changes (+1, 0, -1)
+constexpr int kNumCu = 256;                    // compute units of the chip (one wave of blocks)
 
 int fail(gp_spin1* h, int code, const std::string& msg) {
     if (h) h->err = msg;
@@ -250,6 +252,7 @@ struct HostMode {
     int xK = 2, xG = 64, xR = 1, ytile = 0;
     bool xwindow = false;
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
+    int xorder = 1, yorder = 0;  // block orders of the windowed sweeps
 };
 
 // Halo that makes decay^h fall below the rounding level of T.
@@ -324,6 +327,19 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     if (p.x_solver == GP_XSOLVER_WINDOW)
         for (int t = 0; t < gp::kNumYTiles && !hm.xwindow; ++t)
             if (tile_window(p.nx, hm.hhx, gp::ywindow(gp::ytile<T>(t)), hm.hx, hm.Lx)) { hm.xwindow = true; hm.xtile = t; }
+    // block orders: grouping the x windows by XCD has measured as fast or
+    // faster at every size; the y windows gain from it only while the grid is
+    // about one wave of blocks (on larger grids the eight separate HBM streams
+    // cost more than the shared halos save)
+    hm.xorder = 1;
+    hm.yorder = 0;
+    if (p.block_order != GP_ORDER_AUTO) {
+        hm.xorder = hm.yorder = p.block_order == GP_ORDER_XCD ? 1 : 0;
+    } else if (hm.window) {
+        const gp::YTile yt = gp::ytile<T>(hm.ytile);
+        const long nblk = (long)((p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((p.ny + hm.L - 1) / hm.L);
+        hm.yorder = nblk <= 2 * kNumCu ? 1 : 0;
+    }
 }
 
 template <typename T>
@@ -349,6 +365,8 @@ void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out)
     out->x_halo = hm.xwindow ? hm.hx : 0;
     out->x_points_out = hm.xwindow ? hm.Lx : 0;
     out->x_tile = hm.xwindow ? hm.xtile + 1 : 0;
+    out->x_block_order = hm.xwindow ? hm.xorder : 0;
+    out->y_block_order = hm.window ? hm.yorder : 0;
 }
 
 template <typename T>
@@ -370,6 +388,7 @@ int build_mode(gp_spin1* h, ModeState& ms, bool imag) {
     ms.ytile = hm.ytile;
     ms.xwindow = hm.xwindow;
     ms.hhx = hm.hhx; ms.hx = hm.hx; ms.Lx = hm.Lx; ms.xtile = hm.xtile;
+    ms.xorder = hm.xorder; ms.yorder = hm.yorder;
     fill_plan<T>(p, hm, &ms.plan);
     return GP_OK;
 }
@@ -431,6 +450,7 @@ int validate(const gp_spin1_params* p, std::string& why) {
         return GP_EINVAL;
     }
     if (p->x_solver < GP_XSOLVER_AUTO || p->x_solver > GP_XSOLVER_WINDOW) { why = "unknown x_solver"; return GP_EINVAL; }
+    if (p->block_order < GP_ORDER_AUTO || p->block_order > GP_ORDER_XCD) { why = "unknown block_order"; return GP_EINVAL; }
     if (p->split != GP_SPLIT_LIE && p->split != GP_SPLIT_STRANG) { why = "split must be GP_SPLIT_LIE or GP_SPLIT_STRANG"; return GP_EINVAL; }
     if (p->fix_magnetization != 0 && p->fix_magnetization != 1) { why = "fix_magnetization must be 0 or 1"; return GP_EINVAL; }
     if (p->fix_magnetization) {
@@ -481,6 +501,8 @@ int autotune_t(gp_spin1* h) {
     int rc = GP_OK;
     if ((e = hipMemsetAsync(tmp, 0, bytes, h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
     const int reps = 5;
+    // block orders to time: both, unless p fixes one
+    const int o0 = p.block_order == GP_ORDER_XCD ? 1 : 0, o1 = p.block_order == GP_ORDER_HARDWARE ? 1 : 2;
     for (int m = 0; m < 2 && rc == GP_OK; ++m) {
         ModeState& ms = h->mode[m];
         const bool imag = m == 1;
@@ -502,17 +524,21 @@ int autotune_t(gp_spin1* h) {
             // windows along the rows, where the decay bound fits a window
             ms.xwindow = false;
             if (p.x_solver == GP_XSOLVER_AUTO) {
-                int bestT = -1;
+                int bestT = -1, bestO = ms.xorder;
                 for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
                     if (!tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(t)), ms.hx, ms.Lx)) continue;
-                    ms.xwindow = true;
-                    ms.xtile = t;
-                    const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
-                    float tt = 0.f;
-                    rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
-                    if (rc == GP_OK && tt < best) { best = tt; bestT = t; }
+                    for (int o = o0; o < o1 && rc == GP_OK; ++o) {
+                        ms.xwindow = true;
+                        ms.xtile = t;
+                        ms.xorder = o;
+                        const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
+                        float tt = 0.f;
+                        rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
+                        if (rc == GP_OK && tt < best) { best = tt; bestT = t; bestO = o; }
+                    }
                 }
                 ms.xwindow = bestT >= 0;
+                ms.xorder = bestO;
                 if (ms.xwindow) {
                     ms.xtile = bestT;
                     tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(bestT)), ms.hx, ms.Lx);
@@ -522,30 +548,38 @@ int autotune_t(gp_spin1* h) {
         if (p.x_solver == GP_XSOLVER_WINDOW) {
             // windows asked for: the fastest tile
             float best = 1e30f;
-            int bestT = ms.xtile;
+            int bestT = ms.xtile, bestO = ms.xorder;
             for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
                 if (!tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(t)), ms.hx, ms.Lx)) continue;
-                ms.xtile = t;
-                const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
-                float tt = 0.f;
-                rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
-                if (rc == GP_OK && tt < best) { best = tt; bestT = t; }
+                for (int o = o0; o < o1 && rc == GP_OK; ++o) {
+                    ms.xtile = t;
+                    ms.xorder = o;
+                    const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
+                    float tt = 0.f;
+                    rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
+                    if (rc == GP_OK && tt < best) { best = tt; bestT = t; bestO = o; }
+                }
             }
             ms.xtile = bestT;
+            ms.xorder = bestO;
             tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(bestT)), ms.hx, ms.Lx);
         }
         if (p.y_tile == 0 && ms.window) {
             float best = 1e30f;
-            int bestT = ms.ytile;
+            int bestT = ms.ytile, bestO = ms.yorder;
             for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
                 if (!tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(t)), ms.h, ms.L)) continue;
-                ms.ytile = t;
-                const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag);
-                float tt = 0.f;
-                rc = time_launches(h, [&] { return gp::launch_y<T>(ya, h->stream); }, reps, tt);
-                if (rc == GP_OK && tt < best) { best = tt; bestT = t; }
+                for (int o = o0; o < o1 && rc == GP_OK; ++o) {
+                    ms.ytile = t;
+                    ms.yorder = o;
+                    const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag);
+                    float tt = 0.f;
+                    rc = time_launches(h, [&] { return gp::launch_y<T>(ya, h->stream); }, reps, tt);
+                    if (rc == GP_OK && tt < best) { best = tt; bestT = t; bestO = o; }
+                }
             }
             ms.ytile = bestT;
+            ms.yorder = bestO;
             tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(bestT)), ms.h, ms.L);
         }
         ms.plan.x_points_per_thread = ms.xK;
@@ -555,6 +589,8 @@ int autotune_t(gp_spin1* h) {
         ms.plan.x_halo = ms.xwindow ? ms.hx : 0;
         ms.plan.x_points_out = ms.xwindow ? ms.Lx : 0;
         ms.plan.x_tile = ms.xwindow ? ms.xtile + 1 : 0;
+        ms.plan.x_block_order = ms.xwindow ? ms.xorder : 0;
+        ms.plan.y_block_order = ms.window ? ms.yorder : 0;
         const gp::YTile yt = gp::ytile<T>(ms.ytile);
         ms.plan.y_tile = ms.ytile + 1;
         ms.plan.y_tile_cols = 4 * yt.NW;
@@ -628,6 +664,7 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.K = ms.xK; a.G = ms.xG; a.R = ms.xR;
     a.imag = imag; a.local = local;
     a.window = ms.xwindow; a.L = ms.Lx; a.h = ms.hx; a.tile = ms.xtile;
+    a.order = ms.xorder;
     return a;
 }
 
@@ -643,6 +680,7 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.L = ms.L; a.h = ms.h; a.tile = ms.ytile;
     a.window = ms.window; a.imag = imag; a.norm = norm;
     a.outl = false;
+    a.order = ms.yorder;
     return a;
 }
 

@@ -238,8 +238,10 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
 template <typename T, bool IMAG, int KX, int NW, bool LOCAL, bool SCALE>
 __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                       Phys ph, LineSet<T> ls, const double* __restrict__ scale, int L,
-                                                      int h, int ncs) {
-    x_window<T, IMAG, KX, NW, LOCAL, SCALE>(src, dst, ph, ls, scale, L, h, ncs, (int)blockIdx.x);
+                                                      int h, int ncs, int nblk, int order) {
+    const int lb = order ? xcd_logical((int)blockIdx.x, nblk) : (int)blockIdx.x;
+    if (lb >= nblk) return;
+    x_window<T, IMAG, KX, NW, LOCAL, SCALE>(src, dst, ph, ls, scale, L, h, ncs, lb);
 }
 
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
@@ -284,8 +286,10 @@ static hipError_t launch_xw_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0
     constexpr YTile xt = ytile<T>(TI);
     const int ncs = (a.ph.nx + a.L - 1) / a.L;
     const int nrt = (a.ph.ny + 4 * xt.NW - 1) / (4 * xt.NW);
-    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, LOCAL, SCALE>, dim3(ncs * nrt), dim3(64 * xt.NW), 0, st, e0,
-                          e1, 0, a.src, a.dst, a.ph, a.ls, a.scale, a.L, a.h, ncs);
+    const int nblk = ncs * nrt;
+    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, LOCAL, SCALE>, dim3(a.order ? xcd_blocks(nblk) : nblk),
+                          dim3(64 * xt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.scale, a.L, a.h, ncs, nblk,
+                          a.order);
     return hipGetLastError();
 }
 

@@ -103,8 +103,11 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
 
 template <typename T, bool IMAG, int KY, int NW, bool NORM, bool OUTL>
 __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                                      Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no) {
-    y_window<T, IMAG, KY, NW, NORM, OUTL>(src, dst, ph, ls, L, h, ncs, no, (int)blockIdx.x);
+                                                      Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no,
+                                                      int nblk, int order) {
+    const int lb = order ? xcd_logical((int)blockIdx.x, nblk) : (int)blockIdx.x;
+    if (lb >= nblk) return;
+    y_window<T, IMAG, KY, NW, NORM, OUTL>(src, dst, ph, ls, L, h, ncs, no, lb);
 }
 
 template <typename T, bool IMAG, int KY, int NW>
@@ -203,8 +206,10 @@ static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0
     constexpr YTile yt = ytile<T>(TI);
     const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
-    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, NORM, OUTL>, dim3(ncs * nrt), dim3(64 * yt.NW), 0, st, e0,
-                          e1, 0, a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no);
+    const int nblk = ncs * nrt;
+    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, NORM, OUTL>, dim3(a.order ? xcd_blocks(nblk) : nblk),
+                          dim3(64 * yt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no, nblk,
+                          a.order);
     return hipGetLastError();
 }
 

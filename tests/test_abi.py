@@ -1,5 +1,6 @@
 """C ABI checks that need no GPU: the library loads, exports every entry point
 the header declares, validates parameters and computes its plan on the host."""
+import ctypes
 import math
 import os
 import re
@@ -119,6 +120,24 @@ def test_validation_of_the_next_row_options(change):
     with pytest.raises(binding.GPError) as ei:
         binding.plan_query(p, True)
     assert ei.value.status == binding.GP_EINVAL
+
+
+def test_block_orders_of_the_windowed_sweeps():
+    # default: x windows grouped by XCD, y windows grouped only on grids of about one wave of blocks
+    small = binding.plan_query(inputs.config_c2(), False, x_solver="window")
+    assert small["x_solver"] == binding.GP_XSOLVER_WINDOW and small["x_block_order"] == 1
+    assert small["y_block_order"] == 1
+    big = binding.plan_query(inputs.config_c3(4096), True)
+    assert big["y_solver"] == binding.GP_YSOLVER_WINDOW and big["y_block_order"] == 0
+    assert big["x_block_order"] == 0  # whole-row x sweep: no windows to order
+    for order, want in (("hardware", 0), ("xcd", 1)):
+        for p, imag in ((inputs.config_c2(), False), (inputs.config_c3(4096), True)):
+            pl = binding.plan_query(p, imag, x_solver="window", block_order=order)
+            assert pl["x_block_order"] == want and pl["y_block_order"] == want
+    bad = binding.make_params(BASE)
+    bad.block_order = 3
+    pl = binding.Plan()
+    assert binding.load().gp_spin1_plan_query(ctypes.byref(bad), 1, ctypes.byref(pl)) == binding.GP_EINVAL
 
 
 def test_unit_helper_reproduces_the_printed_couplings():

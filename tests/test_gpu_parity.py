@@ -117,6 +117,29 @@ def test_x_windows_full_steps(imag, precision):
         assert float(np.abs(rho_g - rho_w).max() / rho_w.max()) < 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_block_orders_give_identical_results(precision):
+    # the block order only changes which workgroup computes which window: the
+    # states, and the imaginary-time norm partials (stored per window and summed
+    # in window order), agree to the bit; 700 x 500 spans several windows in both
+    # directions and a ragged last window
+    p = all_couplings(700, 500, 0.06, dy=0.05, dt=0.0015)
+    psi0 = inputs.gaussian(700, 500, 0.06, 0.05, x0=p["x0"], y0=p["y0"], seed=16, center=(3.0, -2.0))
+    for imag in (True, False):
+        out = []
+        for order in ("hardware", "xcd"):
+            s = binding.Solver(p, precision, x_solver="window", block_order=order)
+            pl = s.plan(imag)
+            assert pl["x_points_out"] < 700 and pl["y_rows_out"] < 500
+            assert pl["x_block_order"] == pl["y_block_order"] == (order == "xcd")
+            t = dev(psi0, s.dtype)
+            (s.step_imag if imag else s.step_real)(t, 7)
+            s.sync()
+            out.append(host(t))
+            s.close()
+        assert np.array_equal(out[0], out[1]), imag
+
+
 def test_x_windows_refused_when_the_decay_is_slow():
     p = all_couplings(2000, 5, 0.005, dt=0.01)
     with pytest.raises(binding.GPError) as ei:
