@@ -107,7 +107,7 @@ typedef struct {
     int32_t precision; /* gp_precision                                                         */
     int32_t y_solver;  /* gp_ysolver                                                           */
     int32_t x_points;  /* points per thread of the x sweep: 0 = chosen by the library, else 1, 2, 4, 8 or 16 */
-    int32_t y_tile;    /* tile shape of the windowed y sweep: 0 = chosen by the library, else 1..4            */
+    int32_t y_tile;    /* tile shape of the windowed y sweep: 0 = chosen by the library, else 1..8            */
     int32_t autotune;  /* != 0: time the candidate x and y launch shapes at creation and keep the fastest
                           (only for the fields left at 0); the choice depends on the grid shape only        */
     double trap_gx, trap_gy; /* trap V = (gx^2 x^2 + gy^2 y^2)/2 (Eq. (S.3) with the harmonic trap, optionally
@@ -122,6 +122,8 @@ typedef struct {
     int32_t x_solver;        /* gp_xsolver                                                                  */
     int32_t block_order;     /* gp_block_order: how the windowed sweeps number their blocks (no effect on
                                 results, which are bit-identical in every order)                         */
+    int32_t x_tile;          /* tile shape of the windowed x sweep: 0 = chosen by the library, else 1..8
+                                (the y_tile shapes turned along the rows)                                */
 } gp_spin1_params;
 
 /* Observables of one wave function (all FP64, rectangle-rule quadrature
@@ -148,7 +150,7 @@ typedef struct {
     int32_t y_solver;            /* GP_YSOLVER_WINDOW or GP_YSOLVER_THOMAS                        */
     int32_t y_halo;              /* rows of overlap on each side of a y window                   */
     int32_t y_rows_out;          /* rows written per y window                                    */
-    int32_t y_tile;              /* 1..4, the tile shape below                                     */
+    int32_t y_tile;              /* 1..8, the tile shape below (5..8: lines solved one at a time)  */
     int32_t y_tile_cols;         /* columns per y block (4 per wave)                              */
     int32_t y_segments;          /* segments per column and window (16: one DPP row of lanes)     */
     int32_t y_rows_per_thread;   /* a window spans y_segments * y_rows_per_thread rows            */
@@ -158,7 +160,7 @@ typedef struct {
     int32_t x_solver;            /* GP_XSOLVER_SCAN or GP_XSOLVER_WINDOW                          */
     int32_t x_halo;              /* windows: points of overlap on each side                       */
     int32_t x_points_out;        /* windows: points written per window                            */
-    int32_t x_tile;              /* windows: 1..4, same shapes as y_tile (rows per block = 4 per wave) */
+    int32_t x_tile;              /* windows: 1..8, same shapes as y_tile (rows per block = 4 per wave) */
     int32_t x_block_order;       /* windows: 0 blocks in hardware order, 1 grouped by XCD (each of  */
     int32_t y_block_order;       /*   the 8 XCDs takes a contiguous run of windows, sharing halos)  */
 } gp_spin1_plan;

@@ -52,7 +52,8 @@ class Params(ctypes.Structure):
                 ("x_points", ctypes.c_int32), ("y_tile", ctypes.c_int32), ("autotune", ctypes.c_int32),
                 ("trap_gx", ctypes.c_double), ("trap_gy", ctypes.c_double), ("split", ctypes.c_int32),
                 ("fix_magnetization", ctypes.c_int32), ("magnetization", ctypes.c_double),
-                ("x_solver", ctypes.c_int32), ("block_order", ctypes.c_int32)]
+                ("x_solver", ctypes.c_int32), ("block_order", ctypes.c_int32),
+                ("x_tile", ctypes.c_int32)]
 
 
 class Obs(ctypes.Structure):
@@ -162,7 +163,7 @@ def load():
 
 
 def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0, y_tile: int = 0,
-                autotune: bool = False, x_solver: str = "auto", block_order: str = "auto") -> Params:
+                autotune: bool = False, x_solver: str = "auto", block_order: str = "auto", x_tile: int = 0) -> Params:
     """Params from a plain mapping (keys nx, ny, dx, dy, x0, y0, dt, c0, c2,
     gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2;
     optional gx, gy (trap), split (0 Lie, 1 Strang), fix_m and magnetization)."""
@@ -175,7 +176,8 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_poin
                   int(x_points), int(y_tile), int(bool(autotune)), float(p.get("gx", 1.0)), float(p.get("gy", 1.0)),
                   int(p.get("split", 0)), int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)),
                   {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW}[x_solver],
-                  {"auto": GP_ORDER_AUTO, "hardware": GP_ORDER_HARDWARE, "xcd": GP_ORDER_XCD}[block_order])
+                  {"auto": GP_ORDER_AUTO, "hardware": GP_ORDER_HARDWARE, "xcd": GP_ORDER_XCD}[block_order],
+                  int(x_tile))
 
 
 def _obs_dict(o: Obs) -> dict:
@@ -185,12 +187,13 @@ def _obs_dict(o: Obs) -> dict:
 
 
 def plan_query(p: dict, imag: bool, precision: str = "fp64", y_solver: str = "auto", x_points: int = 0,
-               y_tile: int = 0, x_solver: str = "auto", block_order: str = "auto") -> dict:
+               y_tile: int = 0, x_solver: str = "auto", block_order: str = "auto", x_tile: int = 0) -> dict:
     """Host-only plan (no GPU needed): pivot table lengths, decay factors,
     y solver and stability flag for these parameters."""
     lib = load()
     pl = Plan()
-    pp = make_params(p, precision, y_solver, x_points, y_tile, x_solver=x_solver, block_order=block_order)
+    pp = make_params(p, precision, y_solver, x_points, y_tile, x_solver=x_solver, block_order=block_order,
+                     x_tile=x_tile)
     rc = lib.gp_spin1_plan_query(ctypes.byref(pp), int(bool(imag)), ctypes.byref(pl))
     if rc != GP_OK:
         raise GPError(rc, "gp_spin1_plan_query: " + lib.gp_spin1_strerror(rc).decode())
@@ -201,7 +204,8 @@ class Solver:
     """One condensate on one stream: a handle of the C ABI."""
 
     def __init__(self, p: dict, precision: str = "fp64", y_solver: str = "auto", stream=None, x_points: int = 0,
-                 y_tile: int = 0, autotune: bool = False, x_solver: str = "auto", block_order: str = "auto"):
+                 y_tile: int = 0, autotune: bool = False, x_solver: str = "auto", block_order: str = "auto",
+                 x_tile: int = 0):
         import torch
         self._lib = load()
         self.precision = precision
@@ -213,7 +217,7 @@ class Solver:
             stream = torch.cuda.current_stream()
         self.stream = stream
         self._h = ctypes.c_void_p()
-        pp = make_params(p, precision, y_solver, x_points, y_tile, autotune, x_solver, block_order)
+        pp = make_params(p, precision, y_solver, x_points, y_tile, autotune, x_solver, block_order, x_tile)
         rc = self._lib.gp_spin1_create(ctypes.byref(pp), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
         if rc != GP_OK:
             raise GPError(rc, "gp_spin1_create: " + self._lib.gp_spin1_strerror(rc).decode())

@@ -7,16 +7,22 @@ namespace gp {
 
 constexpr int kObsCount = 13;
 
-// Tile shapes of the windowed y sweep: KY rows per lane, NW waves (4 columns
-// each) per block.  A window spans 16 * KY rows (16 segments per column).
-constexpr int kNumYTiles = 4;
-struct YTile { int KY, NW; };
+// Tile shapes of the windowed sweeps: KY points per lane, NW waves (4 lines
+// each) per block; a window spans 16 * KY points (16 segments per line).
+// Shapes 0..3 solve the three eigen-lines of a window interleaved (one scan
+// for all three); shapes 4..7 are the same shapes solving them one after
+// another (SEQ: about half the registers, so more waves per SIMD, at the price
+// of a longer dependent chain per wave).
+constexpr int kNumYTiles = 8;
+struct YTile { int KY, NW; bool SEQ; };
 template <typename T> __host__ __device__ constexpr YTile ytile(int t);
 template <> __host__ __device__ constexpr YTile ytile<double>(int t) {
-    return t == 0 ? YTile{8, 2} : t == 1 ? YTile{8, 4} : t == 2 ? YTile{4, 4} : YTile{4, 8};
+    return (t & 3) == 0 ? YTile{8, 2, t > 3} : (t & 3) == 1 ? YTile{8, 4, t > 3}
+                        : (t & 3) == 2 ? YTile{4, 4, t > 3} : YTile{4, 8, t > 3};
 }
 template <> __host__ __device__ constexpr YTile ytile<float>(int t) {
-    return t == 0 ? YTile{8, 4} : t == 1 ? YTile{4, 8} : t == 2 ? YTile{4, 4} : YTile{8, 8};
+    return (t & 3) == 0 ? YTile{8, 4, t > 3} : (t & 3) == 1 ? YTile{4, 8, t > 3}
+                        : (t & 3) == 2 ? YTile{4, 4, t > 3} : YTile{8, 8, t > 3};
 }
 __host__ __device__ constexpr int ywindow(YTile t) { return 16 * t.KY; }
 

@@ -324,9 +324,15 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     hm.hhx = halo_for<T>(hm.x.decay);
     hm.xwindow = false;
     hm.hx = hm.Lx = hm.xtile = 0;
-    if (p.x_solver == GP_XSOLVER_WINDOW)
-        for (int t = 0; t < gp::kNumYTiles && !hm.xwindow; ++t)
-            if (tile_window(p.nx, hm.hhx, gp::ywindow(gp::ytile<T>(t)), hm.hx, hm.Lx)) { hm.xwindow = true; hm.xtile = t; }
+    if (p.x_solver == GP_XSOLVER_WINDOW) {
+        if (p.x_tile > 0) {
+            hm.xtile = p.x_tile - 1;
+            hm.xwindow = tile_window(p.nx, hm.hhx, gp::ywindow(gp::ytile<T>(hm.xtile)), hm.hx, hm.Lx);
+        } else {
+            for (int t = 0; t < gp::kNumYTiles && !hm.xwindow; ++t)
+                if (tile_window(p.nx, hm.hhx, gp::ywindow(gp::ytile<T>(t)), hm.hx, hm.Lx)) { hm.xwindow = true; hm.xtile = t; }
+        }
+    }
     // block orders: grouping the x windows by XCD has measured as fast or
     // faster at every size; the y windows gain from it only while the grid is
     // about one wave of blocks (on larger grids the eight separate HBM streams
@@ -451,6 +457,9 @@ int validate(const gp_spin1_params* p, std::string& why) {
     }
     if (p->x_solver < GP_XSOLVER_AUTO || p->x_solver > GP_XSOLVER_WINDOW) { why = "unknown x_solver"; return GP_EINVAL; }
     if (p->block_order < GP_ORDER_AUTO || p->block_order > GP_ORDER_XCD) { why = "unknown block_order"; return GP_EINVAL; }
+    if (p->x_tile < 0 || p->x_tile > gp::kNumYTiles) { why = "x_tile must be 0..8"; return GP_EINVAL; }
+    if (p->y_tile < 0 || p->y_tile > gp::kNumYTiles) { why = "y_tile must be 0..8"; return GP_EINVAL; }
+    if (p->x_tile > 0 && p->x_solver != GP_XSOLVER_WINDOW) { why = "x_tile needs x_solver = GP_XSOLVER_WINDOW"; return GP_EINVAL; }
     if (p->split != GP_SPLIT_LIE && p->split != GP_SPLIT_STRANG) { why = "split must be GP_SPLIT_LIE or GP_SPLIT_STRANG"; return GP_EINVAL; }
     if (p->fix_magnetization != 0 && p->fix_magnetization != 1) { why = "fix_magnetization must be 0 or 1"; return GP_EINVAL; }
     if (p->fix_magnetization) {
@@ -545,7 +554,7 @@ int autotune_t(gp_spin1* h) {
                 }
             }
         }
-        if (p.x_solver == GP_XSOLVER_WINDOW) {
+        if (p.x_solver == GP_XSOLVER_WINDOW && p.x_tile == 0) {
             // windows asked for: the fastest tile
             float best = 1e30f;
             int bestT = ms.xtile, bestO = ms.xorder;
@@ -617,7 +626,7 @@ int create_t(gp_spin1* h) {
         if ((p.x_points & (p.x_points - 1)) || p.x_points > 16 || !x_shape(p.nx, p.x_points, G, R))
             return fail(h, GP_EUNSUPPORTED, "x_points must be 1, 2, 4, 8 or 16 and hold a row in one block");
     }
-    if (p.y_tile < 0 || p.y_tile > gp::kNumYTiles) return fail(h, GP_EINVAL, "y_tile must be 0..4");
+    if (p.y_tile < 0 || p.y_tile > gp::kNumYTiles) return fail(h, GP_EINVAL, "y_tile must be 0..8");
     for (int m = 0; m < 2; ++m) {
         int rc = build_mode<T>(h, h->mode[m], m == 1);
         if (rc) return rc;

@@ -232,6 +232,37 @@ __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], c
     }
 }
 
+// The three eigen-lines of a window held by a DPP row of 16 lanes (K points
+// per lane), solved interleaved through one scan per direction, or (SEQ) one
+// line after another.  The scheduling barriers keep the compiler from
+// re-interleaving the sequential solves, which would undo the register saving.
+template <typename T, int K, bool IMAG, int Q>
+__device__ inline void window_line(cx<T> (&u)[3][K], const cx<T> (&lf)[3], const cx<T> (&rg)[3],
+                                   const LineSet<T>& ls, const PivSrc<T>& ps, int i0, int n) {
+    using C = cx<T>;
+    auto fs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<true, 1>(P, E, o); };
+    auto bs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<false, 1>(P, E, o); };
+    const C l1[1] = {lf[Q]}, r1[1] = {rg[Q]};
+    block_solve<T, K, IMAG, 1, Q, true>(reinterpret_cast<C (&)[1][K]>(u[Q]), l1, r1, ls, ps, i0, n, fs, bs);
+}
+
+template <typename T, int K, bool IMAG, bool SEQ>
+__device__ inline void window_solve(cx<T> (&u)[3][K], const cx<T> (&lf)[3], const cx<T> (&rg)[3],
+                                    const LineSet<T>& ls, const PivSrc<T>& ps, int i0, int n) {
+    using C = cx<T>;
+    if constexpr (SEQ) {
+        window_line<T, K, IMAG, 0>(u, lf, rg, ls, ps, i0, n);
+        __builtin_amdgcn_sched_barrier(0);
+        window_line<T, K, IMAG, 1>(u, lf, rg, ls, ps, i0, n);
+        __builtin_amdgcn_sched_barrier(0);
+        window_line<T, K, IMAG, 2>(u, lf, rg, ls, ps, i0, n);
+    } else {
+        auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
+        auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
+        block_solve<T, K, IMAG, 3, 0, true>(u, lf, rg, ls, ps, i0, n, fs, bs);
+    }
+}
+
 // One line with K points per thread for long rows (K s > 32 bytes): the
 // same elimination one line at a time, with the transient pivots read from
 // the global table (keeps the register footprint of the long-row kernels).

@@ -156,7 +156,7 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 // transient pivots in windows at the row start); the local substep and the
 // pending scale are applied to every point loaded, halo included.
 // ---------------------------------------------------------------------------
-template <typename T, bool IMAG, int KX, int NW, bool LOCAL, bool SCALE>
+template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCALE>
 __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
                                 const LineSet<T>& ls, const double* __restrict__ scale, int L, int h, int ncs,
                                 int blk) {
@@ -220,9 +220,7 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
         rg[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
     }
     const PivSrc<T> ps = piv_src(ls, jl * 3, shT + (wv * 4 + rw) * 3 * kl, kl);
-    auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
-    auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
-    block_solve<T, KX, IMAG, 3, 0, true>(v, lf, rg, ls, ps, g0, nx, fs, bs);
+    window_solve<T, KX, IMAG, SEQ>(v, lf, rg, ls, ps, g0, nx);
 #pragma unroll
     for (int k = 0; k < KX; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
     C* rowq = dst + (size_t)jl * nx;
@@ -235,13 +233,13 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     }
 }
 
-template <typename T, bool IMAG, int KX, int NW, bool LOCAL, bool SCALE>
+template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCALE>
 __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                       Phys ph, LineSet<T> ls, const double* __restrict__ scale, int L,
                                                       int h, int ncs, int nblk, int order) {
     const int lb = order ? xcd_logical((int)blockIdx.x, nblk) : (int)blockIdx.x;
     if (lb >= nblk) return;
-    x_window<T, IMAG, KX, NW, LOCAL, SCALE>(src, dst, ph, ls, scale, L, h, ncs, lb);
+    x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, ph, ls, scale, L, h, ncs, lb);
 }
 
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
@@ -287,7 +285,7 @@ static hipError_t launch_xw_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int ncs = (a.ph.nx + a.L - 1) / a.L;
     const int nrt = (a.ph.ny + 4 * xt.NW - 1) / (4 * xt.NW);
     const int nblk = ncs * nrt;
-    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, LOCAL, SCALE>, dim3(a.order ? xcd_blocks(nblk) : nblk),
+    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, xt.SEQ, LOCAL, SCALE>, dim3(a.order ? xcd_blocks(nblk) : nblk),
                           dim3(64 * xt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.scale, a.L, a.h, ncs, nblk,
                           a.order);
     return hipGetLastError();
@@ -300,6 +298,10 @@ static hipError_t launch_xw(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
         case 1: return launch_xw_t<T, IMAG, LOCAL, SCALE, 1>(a, st, e0, e1);
         case 2: return launch_xw_t<T, IMAG, LOCAL, SCALE, 2>(a, st, e0, e1);
         case 3: return launch_xw_t<T, IMAG, LOCAL, SCALE, 3>(a, st, e0, e1);
+        case 4: return launch_xw_t<T, IMAG, LOCAL, SCALE, 4>(a, st, e0, e1);
+        case 5: return launch_xw_t<T, IMAG, LOCAL, SCALE, 5>(a, st, e0, e1);
+        case 6: return launch_xw_t<T, IMAG, LOCAL, SCALE, 6>(a, st, e0, e1);
+        case 7: return launch_xw_t<T, IMAG, LOCAL, SCALE, 7>(a, st, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }

@@ -23,7 +23,7 @@ namespace gp {
 // norm reduction at the end).  Consecutive windows overlap by h rows on each
 // side and write only their L = 16 KY - 2 h middle rows.
 // ---------------------------------------------------------------------------
-template <typename T, bool IMAG, int KY, int NW, bool NORM, bool OUTL>
+template <typename T, bool IMAG, int KY, int NW, bool SEQ, bool NORM, bool OUTL>
 __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
                                 const LineSet<T>& ls, int L, int h, int ncs, NormOut no, int blk) {
     using C = cx<T>;
@@ -70,9 +70,7 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     }
     const int il = col_ok ? i : 0;
     const PivSrc<T> ps = piv_src(ls, il * 3, shT + (wv * 4 + cw) * 3 * kl, kl);
-    auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
-    auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
-    block_solve<T, KY, IMAG, 3, 0, true>(v, up, dn, ls, ps, g0, ny, fs, bs);
+    window_solve<T, KY, IMAG, SEQ>(v, up, dn, ls, ps, g0, ny);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     if (OUTL) {
@@ -101,21 +99,21 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     if (NORM) store_norm_partials(acc, shr, no, blk);
 }
 
-template <typename T, bool IMAG, int KY, int NW, bool NORM, bool OUTL>
+template <typename T, bool IMAG, int KY, int NW, bool SEQ, bool NORM, bool OUTL>
 __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                       Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no,
                                                       int nblk, int order) {
     const int lb = order ? xcd_logical((int)blockIdx.x, nblk) : (int)blockIdx.x;
     if (lb >= nblk) return;
-    y_window<T, IMAG, KY, NW, NORM, OUTL>(src, dst, ph, ls, L, h, ncs, no, lb);
+    y_window<T, IMAG, KY, NW, SEQ, NORM, OUTL>(src, dst, ph, ls, L, h, ncs, no, lb);
 }
 
-template <typename T, bool IMAG, int KY, int NW>
+template <typename T, bool IMAG, int KY, int NW, bool SEQ>
 __global__ __launch_bounds__(64 * NW) void k_y_batch(const YSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
     const YSlot<T>& s = slots[e >> kMapShift];
-    y_window<T, IMAG, KY, NW, IMAG, false>(s.src, s.dst, s.ph, s.ls, s.L, s.h, s.ncs, NormOut{s.partials},
-                                           (int)(e & kMapMask));
+    y_window<T, IMAG, KY, NW, SEQ, IMAG, false>(s.src, s.dst, s.ph, s.ls, s.L, s.h, s.ncs, NormOut{s.partials},
+                                                (int)(e & kMapMask));
 }
 
 // ---------------------------------------------------------------------------
@@ -207,7 +205,7 @@ static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
     const int nblk = ncs * nrt;
-    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, NORM, OUTL>, dim3(a.order ? xcd_blocks(nblk) : nblk),
+    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, yt.SEQ, NORM, OUTL>, dim3(a.order ? xcd_blocks(nblk) : nblk),
                           dim3(64 * yt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no, nblk,
                           a.order);
     return hipGetLastError();
@@ -220,6 +218,10 @@ static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
         case 1: return launch_yw_t<T, IMAG, NORM, OUTL, 1>(a, st, e0, e1);
         case 2: return launch_yw_t<T, IMAG, NORM, OUTL, 2>(a, st, e0, e1);
         case 3: return launch_yw_t<T, IMAG, NORM, OUTL, 3>(a, st, e0, e1);
+        case 4: return launch_yw_t<T, IMAG, NORM, OUTL, 4>(a, st, e0, e1);
+        case 5: return launch_yw_t<T, IMAG, NORM, OUTL, 5>(a, st, e0, e1);
+        case 6: return launch_yw_t<T, IMAG, NORM, OUTL, 6>(a, st, e0, e1);
+        case 7: return launch_yw_t<T, IMAG, NORM, OUTL, 7>(a, st, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
@@ -260,7 +262,7 @@ hipError_t launch_y(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent
 template <typename T, bool IMAG, int TI>
 static hipError_t launch_y_batch_t(const YSlot<T>* slots, const unsigned* map, int nblk, hipStream_t st) {
     constexpr YTile yt = ytile<T>(TI);
-    hipExtLaunchKernelGGL(k_y_batch<T, IMAG, yt.KY, yt.NW>, dim3(nblk), dim3(64 * yt.NW), 0, st, nullptr, nullptr, 0,
+    hipExtLaunchKernelGGL(k_y_batch<T, IMAG, yt.KY, yt.NW, yt.SEQ>, dim3(nblk), dim3(64 * yt.NW), 0, st, nullptr, nullptr, 0,
                           slots, map);
     return hipGetLastError();
 }
@@ -273,6 +275,10 @@ static hipError_t launch_y_batch_i(const YSlot<T>* slots, const unsigned* map, i
         case 1: return launch_y_batch_t<T, IMAG, 1>(slots, map, nblk, st);
         case 2: return launch_y_batch_t<T, IMAG, 2>(slots, map, nblk, st);
         case 3: return launch_y_batch_t<T, IMAG, 3>(slots, map, nblk, st);
+        case 4: return launch_y_batch_t<T, IMAG, 4>(slots, map, nblk, st);
+        case 5: return launch_y_batch_t<T, IMAG, 5>(slots, map, nblk, st);
+        case 6: return launch_y_batch_t<T, IMAG, 6>(slots, map, nblk, st);
+        case 7: return launch_y_batch_t<T, IMAG, 7>(slots, map, nblk, st);
         default: return hipErrorInvalidValue;
     }
 }

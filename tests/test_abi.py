@@ -140,6 +140,21 @@ def test_block_orders_of_the_windowed_sweeps():
     assert binding.load().gp_spin1_plan_query(ctypes.byref(bad), 1, ctypes.byref(pl)) == binding.GP_EINVAL
 
 
+def test_tile_options():
+    p = dict(BASE, nx=700, ny=600, dx=0.1, dy=0.1)
+    for t in range(1, 9):
+        pl = binding.plan_query(p, True, x_solver="window", x_tile=t, y_tile=t)
+        assert pl["x_tile"] == t and pl["y_tile"] == t
+    lib, pl = binding.load(), binding.Plan()
+    for field, value in (("x_tile", 9), ("x_tile", -1), ("y_tile", 9)):
+        q = binding.make_params(p, x_solver="window")
+        setattr(q, field, value)
+        assert lib.gp_spin1_plan_query(ctypes.byref(q), 1, ctypes.byref(pl)) == binding.GP_EINVAL, (field, value)
+    # a tile for the x windows without the x windows
+    q = binding.make_params(p, x_tile=2)
+    assert lib.gp_spin1_plan_query(ctypes.byref(q), 1, ctypes.byref(pl)) == binding.GP_EINVAL
+
+
 def test_unit_helper_reproduces_the_printed_couplings():
     # Eq. (S.4) with the paper's 87Rb / 23Na inputs (l0 / sqrt(kappa) = 4 micrometres)
     import json

@@ -96,6 +96,31 @@ def test_x_sweep_windows(imag, nx):
     assert rel(got, want) < 1e-13, s.plan(imag)
 
 
+@pytest.mark.parametrize("tile", range(1, 9))
+def test_every_window_tile(tile):
+    # each tile shape of both windowed sweeps (5..8 solve the three lines one at a time), several windows
+    # per line and a ragged last window, both propagation modes
+    for imag in (True, False):
+        p = all_couplings(700, 5, 0.1, dy=0.2, dt=0.001)
+        psi = inputs.random_state(700, 5, seed=40 + tile)
+        s = binding.Solver(p, x_solver="window", x_tile=tile)
+        pl = s.plan(imag)
+        assert pl["x_tile"] == tile and pl["x_points_out"] < 700
+        t = dev(psi)
+        s.substep(t, binding.SUB_X, imag)
+        assert rel(host(t), oracle.sweep_x(p, psi, imag)) < 1e-13, (tile, imag, pl)
+        s.close()
+        q = all_couplings(9, 600, 0.2, dy=0.1, dt=0.001)
+        psi = inputs.random_state(9, 600, seed=50 + tile)
+        s = binding.Solver(q, y_tile=tile)
+        pl = s.plan(imag)
+        assert pl["y_tile"] == tile and pl["y_rows_out"] < 600
+        t = dev(psi)
+        s.substep(t, binding.SUB_Y, imag)
+        assert rel(host(t), oracle.sweep_y(q, psi, imag)) < 1e-13, (tile, imag, pl)
+        s.close()
+
+
 @pytest.mark.parametrize("imag", [True, False])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_x_windows_full_steps(imag, precision):
