@@ -83,7 +83,10 @@ typedef enum {
     GP_ORDER_AUTO = 0,     /* x windows grouped, y windows grouped only on grids of about one wave of blocks;
                               with autotune, both timed and the faster kept per sweep                       */
     GP_ORDER_HARDWARE = 1, /* block b processes window b                                                    */
-    GP_ORDER_XCD = 2       /* block b processes window (b mod 8) ceil(n/8) + b div 8 (n windows)            */
+    GP_ORDER_XCD = 2,      /* block b processes window (b mod 8) ceil(n/8) + b div 8 (n windows)            */
+    GP_ORDER_BANDS = 3     /* y windows: XCD x takes a contiguous range of column strips and walks them down
+                              8 strips at a time (windows above and below each other in flight together);
+                              x windows as GP_ORDER_XCD                                                    */
 } gp_block_order;
 
 /* Order of the substeps within one step. */
@@ -161,8 +164,8 @@ typedef struct {
     int32_t x_halo;              /* windows: points of overlap on each side                       */
     int32_t x_points_out;        /* windows: points written per window                            */
     int32_t x_tile;              /* windows: 1..8, same shapes as y_tile (rows per block = 4 per wave) */
-    int32_t x_block_order;       /* windows: 0 blocks in hardware order, 1 grouped by XCD (each of  */
-    int32_t y_block_order;       /*   the 8 XCDs takes a contiguous run of windows, sharing halos)  */
+    int32_t x_block_order;       /* windows: 0 blocks in hardware order, 1 XCD-contiguous (each of  */
+    int32_t y_block_order;       /*   the 8 XCDs takes a contiguous run of windows), 2 bands (y)    */
 } gp_spin1_plan;
 
 typedef struct gp_spin1 gp_spin1_t;

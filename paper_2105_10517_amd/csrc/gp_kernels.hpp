@@ -32,17 +32,39 @@ __host__ __device__ constexpr int xk_value(int idx) { return 1 << idx; }  // 1, 
 __host__ __device__ constexpr int xk_bound(int K) { return K == 1 ? 1024 : 512; }
 
 // Workgroups are dispatched to the 8 XCDs of the chip in turn (block b to XCD
-// b mod 8), each with its own L2.  The windowed sweeps can renumber their
-// blocks (block order 1) so that every XCD gets a contiguous run of logical
-// blocks: neighbouring windows, whose halos overlap, then share an L2, at the
-// price of eight far-apart streams through HBM instead of one band.  Such
-// launches use 8 ceil(n / 8) blocks; logical numbers >= n exit at once.
-// Block order 0 keeps the hardware order.
+// b mod 8), each with its own L2.  Block orders of the windowed sweeps (the
+// window of logical block lb covers strip lb mod ncs of row tile lb / ncs):
+//   0  hardware order: block b computes window b;
+//   1  XCD-contiguous: XCD x takes the run of windows x ceil(n/8) .. , so
+//      neighbouring windows along a strip, whose halos overlap, share an L2;
+//   2  bands (y sweep): XCD x takes a contiguous range of strips and walks
+//      them down kBand strips at a time, row tile by row tile, so that the
+//      windows above and below each other are in flight together (the halo
+//      rows are read through one L2) while the rows read stay contiguous.
+// Orders 1 and 2 launch more blocks than windows; the extra blocks exit at
+// once (xcd_grid blocks in all, order_logical < 0).
 constexpr int kNumXcd = 8;
+constexpr int kBand = 8;
 __host__ __device__ inline int xcd_blocks(int n) { return (n + kNumXcd - 1) / kNumXcd * kNumXcd; }
-__device__ inline int xcd_logical(int b, int n) {
-    const int q = (n + kNumXcd - 1) / kNumXcd;
-    return (b % kNumXcd) * q + b / kNumXcd;
+__host__ __device__ inline int xcd_grid(int order, int ncs, int nrt) {
+    return order == 0 ? ncs * nrt
+         : order == 1 ? xcd_blocks(ncs * nrt)
+                      : kNumXcd * ((ncs + kNumXcd - 1) / kNumXcd) * nrt;
+}
+__device__ inline int order_logical(int order, int b, int ncs, int nrt) {
+    const int n = ncs * nrt;
+    if (order == 0) return b;
+    const int x = b % kNumXcd, j = b / kNumXcd;
+    if (order == 1) {
+        const int lb = x * ((n + kNumXcd - 1) / kNumXcd) + j;
+        return lb < n ? lb : -1;
+    }
+    const int s0 = x * ncs / kNumXcd, sx = (x + 1) * ncs / kNumXcd - s0;  // this XCD's strips
+    if (j >= sx * nrt) return -1;
+    const int band = j / (kBand * nrt);
+    const int gb = sx - band * kBand < kBand ? sx - band * kBand : kBand;  // strips in this band
+    const int r = j - band * kBand * nrt;
+    return (r / gb) * ncs + s0 + band * kBand + r % gb;
 }
 
 // Both sweeps run out of place (src -> dst): the y windows overlap, so a
@@ -83,7 +105,7 @@ template <typename T> struct XLaunch {
     bool imag, local;
     bool window;    // truncated windows along the rows (tile shapes as the y sweep's) instead of whole rows
     int L, h, tile;
-    int order;      // windows: block order (0 hardware, 1 grouped by XCD)
+    int order;      // windows: block order (0 hardware, 1 XCD-contiguous; 2 is taken as 1)
 };
 
 template <typename T> struct YLaunch {
@@ -95,7 +117,7 @@ template <typename T> struct YLaunch {
     int L, h, tile;
     bool window, imag, norm;
     bool outl;  // second half local substep on the way out (Strang)
-    int order;  // windows: block order (0 hardware, 1 grouped by XCD)
+    int order;  // windows: block order (0 hardware, 1 XCD-contiguous, 2 bands)
 };
 
 // Batched launches: one descriptor per condensate and one map entry per block,

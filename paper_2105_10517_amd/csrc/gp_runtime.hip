@@ -43,7 +43,7 @@ struct ModeState {
     int ytile = 0;                // windowed y sweep tile shape (0-based)
     bool xwindow = false;         // x sweep over truncated windows
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
-    int xorder = 1, yorder = 0;   // block orders of the windowed sweeps (0 hardware, 1 grouped by XCD)
+    int xorder = 1, yorder = 0;   // block orders of the windowed sweeps (0 hardware, 1 XCD-contiguous, 2 bands)
     gp_spin1_plan plan{};
 };
 
@@ -340,7 +340,8 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     hm.xorder = 1;
     hm.yorder = 0;
     if (p.block_order != GP_ORDER_AUTO) {
-        hm.xorder = hm.yorder = p.block_order == GP_ORDER_XCD ? 1 : 0;
+        hm.xorder = p.block_order == GP_ORDER_HARDWARE ? 0 : 1;
+        hm.yorder = p.block_order == GP_ORDER_HARDWARE ? 0 : p.block_order == GP_ORDER_XCD ? 1 : 2;
     } else if (hm.window) {
         const gp::YTile yt = gp::ytile<T>(hm.ytile);
         const long nblk = (long)((p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((p.ny + hm.L - 1) / hm.L);
@@ -456,7 +457,7 @@ int validate(const gp_spin1_params* p, std::string& why) {
         return GP_EINVAL;
     }
     if (p->x_solver < GP_XSOLVER_AUTO || p->x_solver > GP_XSOLVER_WINDOW) { why = "unknown x_solver"; return GP_EINVAL; }
-    if (p->block_order < GP_ORDER_AUTO || p->block_order > GP_ORDER_XCD) { why = "unknown block_order"; return GP_EINVAL; }
+    if (p->block_order < GP_ORDER_AUTO || p->block_order > GP_ORDER_BANDS) { why = "unknown block_order"; return GP_EINVAL; }
     if (p->x_tile < 0 || p->x_tile > gp::kNumYTiles) { why = "x_tile must be 0..8"; return GP_EINVAL; }
     if (p->y_tile < 0 || p->y_tile > gp::kNumYTiles) { why = "y_tile must be 0..8"; return GP_EINVAL; }
     if (p->x_tile > 0 && p->x_solver != GP_XSOLVER_WINDOW) { why = "x_tile needs x_solver = GP_XSOLVER_WINDOW"; return GP_EINVAL; }
@@ -478,6 +479,9 @@ template <typename T> gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void*
 // Mean duration in ms of `reps` launches of f() after two warm-up launches.
 template <typename F>
 int time_launches(gp_spin1* h, F f, int reps, float& ms) {
+    // two untimed launches, then three timed batches of at least ~0.5 ms each
+    // (the first batch sizes the others); the fastest batch counts, which
+    // keeps clock ramps and neighbours' noise out of the comparison
     hipEvent_t a, b;
     hipError_t e;
     if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(h, e, "autotune");
@@ -485,13 +489,23 @@ int time_launches(gp_spin1* h, F f, int reps, float& ms) {
     int rc = GP_OK;
     for (int w = 0; w < 2 && rc == GP_OK; ++w)
         if ((e = f()) != hipSuccess) rc = hip_fail(h, e, "autotune launch");
-    if (rc == GP_OK && (e = hipEventRecord(a, h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
-    for (int r = 0; r < reps && rc == GP_OK; ++r)
-        if ((e = f()) != hipSuccess) rc = hip_fail(h, e, "autotune launch");
-    if (rc == GP_OK && (e = hipEventRecord(b, h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
-    if (rc == GP_OK && (e = hipEventSynchronize(b)) != hipSuccess) rc = hip_fail(h, e, "autotune");
-    if (rc == GP_OK && (e = hipEventElapsedTime(&ms, a, b)) != hipSuccess) rc = hip_fail(h, e, "autotune");
-    ms /= reps;
+    float best = 1e30f;
+    for (int batch = 0; batch < 3 && rc == GP_OK; ++batch) {
+        if ((e = hipEventRecord(a, h->stream)) != hipSuccess) { rc = hip_fail(h, e, "autotune"); break; }
+        for (int r = 0; r < reps && rc == GP_OK; ++r)
+            if ((e = f()) != hipSuccess) rc = hip_fail(h, e, "autotune launch");
+        if (rc != GP_OK) break;
+        float el = 0.f;
+        if ((e = hipEventRecord(b, h->stream)) != hipSuccess || (e = hipEventSynchronize(b)) != hipSuccess ||
+            (e = hipEventElapsedTime(&el, a, b)) != hipSuccess) {
+            rc = hip_fail(h, e, "autotune");
+            break;
+        }
+        el /= reps;
+        if (el < best) best = el;
+        if (batch == 0 && el > 0.f) reps = std::min(200, std::max(reps, (int)std::ceil(0.5f / el)));
+    }
+    ms = best;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return rc;
@@ -510,11 +524,32 @@ int autotune_t(gp_spin1* h) {
     int rc = GP_OK;
     if ((e = hipMemsetAsync(tmp, 0, bytes, h->stream)) != hipSuccess) rc = hip_fail(h, e, "autotune");
     const int reps = 5;
-    // block orders to time: both, unless p fixes one
-    const int o0 = p.block_order == GP_ORDER_XCD ? 1 : 0, o1 = p.block_order == GP_ORDER_HARDWARE ? 1 : 2;
+    // bring the clocks up before the first comparison
+    if (rc == GP_OK) {
+        const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, false, true);
+        float warm = 0.f;
+        rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, warm);
+    }
+    // block orders to time (x windows: hardware, XCD-contiguous; y windows: also bands), unless p fixes one
+    int o0 = 0, o1 = 2, p0 = 0, p1 = 3;
+    if (p.block_order != GP_ORDER_AUTO) {
+        o0 = p.block_order == GP_ORDER_HARDWARE ? 0 : 1; o1 = o0 + 1;
+        p0 = p.block_order == GP_ORDER_HARDWARE ? 0 : p.block_order == GP_ORDER_XCD ? 1 : 2; p1 = p0 + 1;
+    }
     for (int m = 0; m < 2 && rc == GP_OK; ++m) {
         ModeState& ms = h->mode[m];
         const bool imag = m == 1;
+        // every candidate is timed inside x + y pairs with the current choice
+        // for the other sweep, as in a step: a sweep's speed depends on where
+        // the previous kernel left its input (which L2, written back or not)
+        auto pair = [&](float& t) {
+            const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
+            const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag);
+            return time_launches(h, [&] {
+                const hipError_t ex = gp::launch_x<T>(xa, h->stream);
+                return ex != hipSuccess ? ex : gp::launch_y<T>(ya, h->stream);
+            }, reps, t);
+        };
         if (p.x_points == 0 && p.x_solver != GP_XSOLVER_WINDOW) {
             float best = 1e30f;
             int bestK = ms.xK;
@@ -523,9 +558,8 @@ int autotune_t(gp_spin1* h) {
                 int G, R;
                 if (!x_shape(p.nx, K, G, R)) continue;
                 ms.xK = K; ms.xG = G; ms.xR = R;
-                const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
                 float t = 0.f;
-                rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, t);
+                rc = pair(t);
                 if (rc == GP_OK && t < best) { best = t; bestK = K; }
             }
             ms.xK = bestK;
@@ -540,9 +574,8 @@ int autotune_t(gp_spin1* h) {
                         ms.xwindow = true;
                         ms.xtile = t;
                         ms.xorder = o;
-                        const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
                         float tt = 0.f;
-                        rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
+                        rc = pair(tt);
                         if (rc == GP_OK && tt < best) { best = tt; bestT = t; bestO = o; }
                     }
                 }
@@ -563,9 +596,8 @@ int autotune_t(gp_spin1* h) {
                 for (int o = o0; o < o1 && rc == GP_OK; ++o) {
                     ms.xtile = t;
                     ms.xorder = o;
-                    const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
                     float tt = 0.f;
-                    rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, tt);
+                    rc = pair(tt);
                     if (rc == GP_OK && tt < best) { best = tt; bestT = t; bestO = o; }
                 }
             }
@@ -578,12 +610,11 @@ int autotune_t(gp_spin1* h) {
             int bestT = ms.ytile, bestO = ms.yorder;
             for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
                 if (!tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(t)), ms.h, ms.L)) continue;
-                for (int o = o0; o < o1 && rc == GP_OK; ++o) {
+                for (int o = p0; o < p1 && rc == GP_OK; ++o) {
                     ms.ytile = t;
                     ms.yorder = o;
-                    const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag);
                     float tt = 0.f;
-                    rc = time_launches(h, [&] { return gp::launch_y<T>(ya, h->stream); }, reps, tt);
+                    rc = pair(tt);
                     if (rc == GP_OK && tt < best) { best = tt; bestT = t; bestO = o; }
                 }
             }

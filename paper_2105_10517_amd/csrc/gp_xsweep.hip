@@ -237,8 +237,8 @@ template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCAL
 __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                       Phys ph, LineSet<T> ls, const double* __restrict__ scale, int L,
                                                       int h, int ncs, int nblk, int order) {
-    const int lb = order ? xcd_logical((int)blockIdx.x, nblk) : (int)blockIdx.x;
-    if (lb >= nblk) return;
+    const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, ncs, nblk / ncs);
+    if (lb < 0) return;
     x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, ph, ls, scale, L, h, ncs, lb);
 }
 
@@ -285,7 +285,7 @@ static hipError_t launch_xw_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int ncs = (a.ph.nx + a.L - 1) / a.L;
     const int nrt = (a.ph.ny + 4 * xt.NW - 1) / (4 * xt.NW);
     const int nblk = ncs * nrt;
-    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, xt.SEQ, LOCAL, SCALE>, dim3(a.order ? xcd_blocks(nblk) : nblk),
+    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, xt.SEQ, LOCAL, SCALE>, dim3(xcd_grid(a.order ? 1 : 0, ncs, nrt)),
                           dim3(64 * xt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.scale, a.L, a.h, ncs, nblk,
                           a.order);
     return hipGetLastError();

@@ -103,8 +103,8 @@ template <typename T, bool IMAG, int KY, int NW, bool SEQ, bool NORM, bool OUTL>
 __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                       Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no,
                                                       int nblk, int order) {
-    const int lb = order ? xcd_logical((int)blockIdx.x, nblk) : (int)blockIdx.x;
-    if (lb >= nblk) return;
+    const int lb = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
+    if (lb < 0) return;
     y_window<T, IMAG, KY, NW, SEQ, NORM, OUTL>(src, dst, ph, ls, L, h, ncs, no, lb);
 }
 
@@ -205,7 +205,7 @@ static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
     const int nblk = ncs * nrt;
-    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, yt.SEQ, NORM, OUTL>, dim3(a.order ? xcd_blocks(nblk) : nblk),
+    hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, yt.SEQ, NORM, OUTL>, dim3(xcd_grid(a.order, ncs, nrt)),
                           dim3(64 * yt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no, nblk,
                           a.order);
     return hipGetLastError();
