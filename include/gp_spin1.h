@@ -28,8 +28,9 @@
  * second differences, central first differences and psi = 0 on the ghost
  * points just outside the grid.
  *
- * Wave-function layout (every entry point): psi[3][ny][nx], C-contiguous,
- * x fastest, components ordered m = +1, 0, -1, interleaved complex
+ * Wave-function layout (every entry point): psi[3][ny][nx], x fastest, the
+ * component planes plane_stride elements apart (nx ny, i.e. C-contiguous,
+ * unless the parameters set a larger stride), components ordered m = +1, 0, -1, interleaved complex
  * (complex128 for GP_FP64, complex64 for GP_FP32).  Grid: x_i = x0 + i dx,
  * y_j = y0 + j dy.  psi lives in caller-owned device memory; the library
  * borrows it for the duration of a call and never frees it.
@@ -127,6 +128,11 @@ typedef struct {
                                 results, which are bit-identical in every order)                         */
     int32_t x_tile;          /* tile shape of the windowed x sweep: 0 = chosen by the library, else 1..8
                                 (the y_tile shapes turned along the rows)                                */
+    int64_t plane_stride;    /* elements between the component planes of every wave function passed to this
+                                handle (psi_m starts at psi + m plane_stride; rows nx apart, points
+                                contiguous); 0 = nx ny (a contiguous [3][ny][nx] array).  A stride that is
+                                not a power of two apart (e.g. nx ny + 4160) keeps the sweeps' three
+                                streams off the same HBM channels; the gaps are never read or written  */
 } gp_spin1_params;
 
 /* Observables of one wave function (all FP64, rectangle-rule quadrature
@@ -287,8 +293,9 @@ const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b);
  * Serving loop.  Replays a trace of independent solve requests against the
  * clock on one batch: requests are admitted in arrival order while a slot is
  * free and the device-memory budget allows (an admitted condensate is charged
- * 2 * 3 nx ny s bytes for its wave function and work copy, 432 (nx + ny) s
- * for its line tables and 64 KiB of scratch, s = 16 or 8); each round advances every admitted
+ * (2 P + nx ny) s bytes for its wave function, P its plane stride, (2 W + nx ny) s
+ * for the work copy, W = nx ny + 4160, 432 (nx + ny) s for its line tables and
+ * 64 KiB of scratch, s = 16 or 8); each round advances every admitted
  * condensate together by the steps left to the nearest completion (at most
  * chunk_steps), so requests join and leave between rounds.  A request's
  * latency runs from its arrival to the end of the round that completes it.

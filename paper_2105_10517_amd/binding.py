@@ -53,7 +53,7 @@ class Params(ctypes.Structure):
                 ("trap_gx", ctypes.c_double), ("trap_gy", ctypes.c_double), ("split", ctypes.c_int32),
                 ("fix_magnetization", ctypes.c_int32), ("magnetization", ctypes.c_double),
                 ("x_solver", ctypes.c_int32), ("block_order", ctypes.c_int32),
-                ("x_tile", ctypes.c_int32)]
+                ("x_tile", ctypes.c_int32), ("plane_stride", ctypes.c_int64)]
 
 
 class Obs(ctypes.Structure):
@@ -178,7 +178,41 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_poin
                   {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW}[x_solver],
                   {"auto": GP_ORDER_AUTO, "hardware": GP_ORDER_HARDWARE, "xcd": GP_ORDER_XCD,
                    "bands": GP_ORDER_BANDS}[block_order],
-                  int(x_tile))
+                  int(x_tile), int(p.get("plane_stride", 0)))
+
+
+def plane_stride(p: dict) -> int:
+    """Elements between the component planes of the wave functions of p."""
+    return int(p.get("plane_stride", 0)) or int(p["nx"]) * int(p["ny"])
+
+
+def check_psi(t, dtype, p: dict, what: str = "psi"):
+    """Device pointer of a (3, ny, nx) CUDA tensor whose rows are contiguous
+    and whose planes are plane_stride(p) elements apart (contiguous when p
+    has no plane_stride)."""
+    nx, ny = int(p["nx"]), int(p["ny"])
+    if t.dtype != dtype or tuple(t.shape) != (3, ny, nx) or not t.is_cuda or \
+            tuple(t.stride()) != (plane_stride(p), nx, 1):
+        raise ValueError(f"{what} must be a CUDA {dtype} tensor of shape (3, {ny}, {nx}) with strides "
+                         f"({plane_stride(p)}, {nx}, 1)")
+    return t.data_ptr()
+
+
+PLANE_PAD = 4160  # elements of padding between planes that padded_psi adds
+
+
+def padded_psi(psi, p: dict, dtype, device="cuda"):
+    """Copy of psi (array-like (3, ny, nx)) on the device with planes
+    nx ny + PLANE_PAD elements apart, and p updated with that plane_stride.
+    Planes a power of two apart make a sweep's three read (and three write)
+    streams fall on the same HBM channels; the pad spreads them."""
+    import torch
+    nx, ny = int(p["nx"]), int(p["ny"])
+    stride = nx * ny + PLANE_PAD
+    buf = torch.zeros(2 * stride + nx * ny, dtype=dtype, device=device)
+    t = torch.as_strided(buf, (3, ny, nx), (stride, nx, 1))
+    t.copy_(torch.as_tensor(psi).to(dtype))
+    return t, dict(p, plane_stride=stride)
 
 
 def _obs_dict(o: Obs) -> dict:
@@ -229,10 +263,7 @@ class Solver:
             raise GPError(rc, f"{what}: {self._lib.gp_spin1_strerror(rc).decode()}: {msg}")
 
     def _psi(self, psi):
-        if psi.dtype != self.dtype or tuple(psi.shape) != (3, self.ny, self.nx) or not psi.is_contiguous() \
-                or not psi.is_cuda:
-            raise ValueError(f"psi must be a contiguous CUDA {self.dtype} tensor of shape (3, {self.ny}, {self.nx})")
-        return ctypes.c_void_p(psi.data_ptr())
+        return ctypes.c_void_p(check_psi(psi, self.dtype, self.params))
 
     def step_imag(self, psi, nsteps: int):
         self._check(self._lib.gp_spin1_step_imag(self._h, self._psi(psi), int(nsteps)), "step_imag")
@@ -332,10 +363,7 @@ class Batch:
         p = self.params[slot]
         if p is None:
             return psi.data_ptr()  # the library reports the empty slot
-        shape = (3, int(p["ny"]), int(p["nx"]))
-        if psi.dtype != self.dtype or tuple(psi.shape) != shape or not psi.is_contiguous() or not psi.is_cuda:
-            raise ValueError(f"slot {slot}: psi must be a contiguous CUDA {self.dtype} tensor of shape {shape}")
-        return psi.data_ptr()
+        return check_psi(psi, self.dtype, p, f"slot {slot}: psi")
 
     def step(self, psis, nsteps, modes, active=None):
         """psis[s]: tensor or None (slot skipped); nsteps[s] >= 0; modes[s] in
@@ -403,11 +431,9 @@ def serve(requests, precision: str = "fp32", max_slots: int = 64, hbm_budget_byt
     for k, r in enumerate(requests):
         p = r["params"]
         t = r["psi"]
-        if t.dtype != dtype or tuple(t.shape) != (3, int(p["ny"]), int(p["nx"])) or not t.is_contiguous() \
-                or not t.is_cuda:
-            raise ValueError(f"request {k}: psi must be a contiguous CUDA {dtype} tensor of shape (3, ny, nx)")
+        ptr = check_psi(t, dtype, p, f"request {k}: psi")
         arr[k] = Request(float(r["arrival"]), make_params(p, precision), int(r["nsteps"]), MODES[r["mode"]],
-                         ctypes.c_void_p(t.data_ptr()))
+                         ctypes.c_void_p(ptr))
     cfg = ServeConfig(int(max_slots), float(hbm_budget_bytes), int(chunk_steps), float(time_scale))
     out = (RequestResult * n)()
     st = ServeStats()

@@ -106,6 +106,7 @@ template <typename T> struct XLaunch {
     bool window;    // truncated windows along the rows (tile shapes as the y sweep's) instead of whole rows
     int L, h, tile;
     int order;      // windows: block order (0 hardware, 1 XCD-contiguous; 2 is taken as 1)
+    size_t sp, dp;  // plane strides (elements between the component planes) of src and dst
 };
 
 template <typename T> struct YLaunch {
@@ -118,6 +119,7 @@ template <typename T> struct YLaunch {
     bool window, imag, norm;
     bool outl;  // second half local substep on the way out (Strang)
     int order;  // windows: block order (0 hardware, 1 XCD-contiguous, 2 bands)
+    size_t sp, dp;  // plane strides of src and dst
 };
 
 // Batched launches: one descriptor per condensate and one map entry per block,
@@ -134,6 +136,7 @@ template <typename T> struct XSlot {
     LineSet<T> ls;
     const double* scale;
     int G, R;
+    size_t sp, dp;
 };
 
 template <typename T> struct YSlot {
@@ -143,6 +146,7 @@ template <typename T> struct YSlot {
     LineSet<T> ls;
     double* partials;
     int L, h, ncs;
+    size_t sp, dp;
 };
 
 struct NSlot {
@@ -156,7 +160,8 @@ struct NSlot {
 
 template <typename T> struct SSlot {
     cx<T>* psi;
-    size_t plane;
+    size_t n;       // points per component plane
+    size_t stride;  // elements between the planes
     const double* scale;
 };
 
@@ -172,20 +177,22 @@ hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0 = nullptr
 template <typename T>
 hipError_t launch_y(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T> int y_blocks(const YLaunch<T>& a);
-template <typename T> hipError_t launch_local(cx<T>* psi, const Phys& ph, bool imag, hipStream_t st);
-// psi[m][plane] *= scale[m] (three factors, one per component)
+// The single-condensate kernels below address component m of point idx at
+// psi[m sp + idx] (sp: the plane stride, at least nx ny).
+template <typename T> hipError_t launch_local(cx<T>* psi, size_t sp, const Phys& ph, bool imag, hipStream_t st);
+// psi[m][0 .. n) *= scale[m] (three factors, one per component)
 template <typename T>
-hipError_t launch_scale(cx<T>* psi, size_t plane, const double* scale, hipStream_t st, hipEvent_t e0 = nullptr,
+hipError_t launch_scale(cx<T>* psi, size_t n, size_t sp, const double* scale, hipStream_t st, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr);
 template <typename T>
-hipError_t launch_norm_partials(const cx<T>* psi, size_t plane, double* partials, int nblk, hipStream_t st);
+hipError_t launch_norm_partials(const cx<T>* psi, size_t n, size_t sp, double* partials, int nblk, hipStream_t st);
 hipError_t launch_set_scale(double* scale, double v, hipStream_t st);
 // n blocks' worth of partials (3 n values) -> scale[3], flag
 hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, NormRule rule, double* scale, int* flag,
                                 hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 template <typename T>
-hipError_t launch_obs(const cx<T>* psi, const Phys& ph, const ObsLaunch& o, T* dens, double* partials, int nblk,
-                      hipStream_t st);
+hipError_t launch_obs(const cx<T>* psi, size_t sp, const Phys& ph, const ObsLaunch& o, T* dens, double* partials,
+                      int nblk, hipStream_t st);
 hipError_t launch_obs_finalize(const double* partials, int nblk, double* out, hipStream_t st);
 
 // Batched forms: the x sweep (local substep fused; imaginary time also applies

@@ -10,34 +10,36 @@ namespace gp {
 // Small kernels.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG>
-__global__ __launch_bounds__(256) void k_local(cx<T>* __restrict__ psi, Phys ph) {
-    const size_t plane = (size_t)ph.nx * ph.ny;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane; idx += (size_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(256) void k_local(cx<T>* __restrict__ psi, size_t sp, Phys ph) {
+    const size_t n = (size_t)ph.nx * ph.ny;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(idx % ph.nx), j = (int)(idx / ph.nx);
         const T x = (T)(ph.x0 + i * ph.dx), y = (T)(ph.y0 + j * ph.dy);
-        cx<T> p = psi[idx], z = psi[plane + idx], m = psi[2 * plane + idx];
+        cx<T> p = psi[idx], z = psi[sp + idx], m = psi[2 * sp + idx];
         local_substep<T, IMAG>(p, z, m, trap_v<T>(ph, x, y), (T)ph.dt, (T)ph.c0, (T)ph.c2, (T)ph.rabi);
-        psi[idx] = p; psi[plane + idx] = z; psi[2 * plane + idx] = m;
+        psi[idx] = p; psi[sp + idx] = z; psi[2 * sp + idx] = m;
     }
 }
 
-// psi[m][.] *= scale[m]
+// psi[m][0 .. n) *= scale[m] (the gaps between padded planes are not touched)
 template <typename T>
-__global__ __launch_bounds__(256) void k_scale(cx<T>* __restrict__ psi, size_t plane, const double* __restrict__ scale) {
+__global__ __launch_bounds__(256) void k_scale(cx<T>* __restrict__ psi, size_t n, size_t sp,
+                                              const double* __restrict__ scale) {
     const T s[3] = {(T)scale[0], (T)scale[1], (T)scale[2]};
-    const size_t n = 3 * plane;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x)
-        psi[idx] = cscale(psi[idx], s[idx / plane]);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) psi[m * sp + idx] = cscale(psi[m * sp + idx], s[m]);
 }
 
 // Per-block partial component norms (partials[3 b + m]).
 template <typename T>
-__global__ __launch_bounds__(256) void k_norm_partials(const cx<T>* __restrict__ psi, size_t plane, double* __restrict__ partials) {
+__global__ __launch_bounds__(256) void k_norm_partials(const cx<T>* __restrict__ psi, size_t n, size_t sp,
+                                                      double* __restrict__ partials) {
     __shared__ double shr[48];
     double acc[3] = {0, 0, 0};
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane; idx += (size_t)gridDim.x * blockDim.x)
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x)
 #pragma unroll
-        for (int m = 0; m < 3; ++m) acc[m] += (double)cnorm2(psi[m * plane + idx]);
+        for (int m = 0; m < 3; ++m) acc[m] += (double)cnorm2(psi[m * sp + idx]);
     store_norm_partials(acc, shr, NormOut{partials}, (int)blockIdx.x);
 }
 
@@ -77,7 +79,7 @@ struct ObsArgs {
 };
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_obs(const cx<T>* __restrict__ psi, Phys ph, ObsArgs oa,
+__global__ __launch_bounds__(256) void k_obs(const cx<T>* __restrict__ psi, size_t sp, Phys ph, ObsArgs oa,
                                             T* __restrict__ dens, double* __restrict__ partials) {
     __shared__ double shr[16];
     const int nx = ph.nx, ny = ph.ny;
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(256) void k_obs(const cx<T>* __restrict__ psi, Phys
     for (int q = 0; q < kObsCount; ++q) acc[q] = 0;
     auto ld = [&](int m, int j, int i) -> double2 {
         if (i < 0 || i >= nx || j < 0 || j >= ny) return make_double2(0.0, 0.0);
-        const cx<T> z = psi[m * plane + (size_t)j * nx + i];
+        const cx<T> z = psi[m * sp + (size_t)j * nx + i];
         return make_double2((double)z.x, (double)z.y);
     };
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < plane; idx += (size_t)gridDim.x * blockDim.x) {
@@ -192,11 +194,13 @@ __global__ __launch_bounds__(256) void k_scale_batch(const SSlot<T>* __restrict_
     const unsigned e = map[blockIdx.x];
     const SSlot<T>& s = slots[e >> kMapShift];
     const size_t base = (size_t)(e & kMapMask) * kScaleChunk;
-    const size_t n = 3 * s.plane;
     const T f[3] = {(T)s.scale[0], (T)s.scale[1], (T)s.scale[2]};
     for (int k = threadIdx.x; k < kScaleChunk; k += blockDim.x) {
         const size_t i = base + k;
-        if (i < n) s.psi[i] = cscale(s.psi[i], f[i / s.plane]);
+        if (i < 3 * s.n) {
+            const size_t m = i / s.n, o = m * s.stride + (i - m * s.n);
+            s.psi[o] = cscale(s.psi[o], f[m]);
+        }
     }
 }
 
@@ -204,25 +208,25 @@ __global__ __launch_bounds__(256) void k_scale_batch(const SSlot<T>* __restrict_
 // Launchers.
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t launch_local(cx<T>* psi, const Phys& ph, bool imag, hipStream_t st) {
+hipError_t launch_local(cx<T>* psi, size_t sp, const Phys& ph, bool imag, hipStream_t st) {
     const size_t n = (size_t)ph.nx * ph.ny;
     const int nblk = (int)((n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536);
-    if (imag) k_local<T, true><<<nblk, 256, 0, st>>>(psi, ph);
-    else k_local<T, false><<<nblk, 256, 0, st>>>(psi, ph);
+    if (imag) k_local<T, true><<<nblk, 256, 0, st>>>(psi, sp, ph);
+    else k_local<T, false><<<nblk, 256, 0, st>>>(psi, sp, ph);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_scale(cx<T>* psi, size_t plane, const double* scale, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    const size_t n = 3 * plane;
+hipError_t launch_scale(cx<T>* psi, size_t n, size_t sp, const double* scale, hipStream_t st, hipEvent_t e0,
+                        hipEvent_t e1) {
     const int nblk = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
-    hipExtLaunchKernelGGL(k_scale<T>, dim3(nblk), dim3(256), 0, st, e0, e1, 0, psi, plane, scale);
+    hipExtLaunchKernelGGL(k_scale<T>, dim3(nblk), dim3(256), 0, st, e0, e1, 0, psi, n, sp, scale);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_norm_partials(const cx<T>* psi, size_t plane, double* partials, int nblk, hipStream_t st) {
-    k_norm_partials<T><<<nblk, 256, 0, st>>>(psi, plane, partials);
+hipError_t launch_norm_partials(const cx<T>* psi, size_t n, size_t sp, double* partials, int nblk, hipStream_t st) {
+    k_norm_partials<T><<<nblk, 256, 0, st>>>(psi, n, sp, partials);
     return hipGetLastError();
 }
 
@@ -238,10 +242,10 @@ hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, Norm
 }
 
 template <typename T>
-hipError_t launch_obs(const cx<T>* psi, const Phys& ph, const ObsLaunch& o, T* dens, double* partials, int nblk,
-                      hipStream_t st) {
+hipError_t launch_obs(const cx<T>* psi, size_t sp, const Phys& ph, const ObsLaunch& o, T* dens, double* partials,
+                      int nblk, hipStream_t st) {
     ObsArgs oa{o.c0, o.c2, o.rabi, o.gamma, o.omega, o.eta};
-    k_obs<T><<<nblk, 256, 0, st>>>(psi, ph, oa, dens, partials);
+    k_obs<T><<<nblk, 256, 0, st>>>(psi, sp, ph, oa, dens, partials);
     return hipGetLastError();
 }
 
@@ -270,10 +274,12 @@ hipError_t launch_scale_batch(const SSlot<T>* slots, const unsigned* map, int nb
 }
 
 #define GP_INST(T)                                                                                             \
-    template hipError_t launch_local<T>(cx<T>*, const Phys&, bool, hipStream_t);                               \
-    template hipError_t launch_scale<T>(cx<T>*, size_t, const double*, hipStream_t, hipEvent_t, hipEvent_t);   \
-    template hipError_t launch_norm_partials<T>(const cx<T>*, size_t, double*, int, hipStream_t);              \
-    template hipError_t launch_obs<T>(const cx<T>*, const Phys&, const ObsLaunch&, T*, double*, int, hipStream_t); \
+    template hipError_t launch_local<T>(cx<T>*, size_t, const Phys&, bool, hipStream_t);                       \
+    template hipError_t launch_scale<T>(cx<T>*, size_t, size_t, const double*, hipStream_t, hipEvent_t,        \
+                                        hipEvent_t);                                                           \
+    template hipError_t launch_norm_partials<T>(const cx<T>*, size_t, size_t, double*, int, hipStream_t);      \
+    template hipError_t launch_obs<T>(const cx<T>*, size_t, const Phys&, const ObsLaunch&, T*, double*, int,     \
+                                      hipStream_t);                                                               \
     template hipError_t launch_scale_batch<T>(const SSlot<T>*, const unsigned*, int, hipStream_t);
 GP_INST(double)
 GP_INST(float)

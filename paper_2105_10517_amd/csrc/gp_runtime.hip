@@ -61,6 +61,7 @@ struct gp_spin1 {
     double* d_obs = nullptr;
     int obs_blocks = 0;
     void* d_work = nullptr;  // a second wave function: the x sweep writes it, the y sweep reads it
+    size_t psp = 0, wsp = 0;  // plane strides (elements) of the caller's wave functions and of d_work
     // optional per-kernel timing: pairs of events around launches of kind k
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -75,6 +76,13 @@ namespace {
 
 constexpr double kNu[3] = {1.0, 0.0, -1.0};  // eigenvalue order of the basis changes (+1, 0, -1)
 constexpr int kNumCu = 256;                    // compute units of the chip (one wave of blocks)
+// Padding of the work buffer's component planes.  With planes exactly a
+// power of two apart (every 2^k x 2^k grid), the three streams a sweep reads
+// and the three it writes fall on the same HBM channels at the same time; a
+// pad of 4160 elements (65 KiB in FP64, a multiple of 256 B) spreads them.
+constexpr size_t kPlanePad = 4160;
+size_t work_stride(const gp_spin1_params& p) { return (size_t)p.nx * p.ny + kPlanePad; }
+size_t psi_stride(const gp_spin1_params& p) { return p.plane_stride > 0 ? (size_t)p.plane_stride : (size_t)p.nx * p.ny; }
 
 int fail(gp_spin1* h, int code, const std::string& msg) {
     if (h) h->err = msg;
@@ -446,6 +454,10 @@ int validate(const gp_spin1_params* p, std::string& why) {
         why = "x0, y0 must be finite (or NaN for the default)";
         return GP_EINVAL;
     }
+    if (p->plane_stride != 0 && (p->plane_stride < (int64_t)p->nx * p->ny || p->plane_stride > ((int64_t)1 << 40))) {
+        why = "plane_stride must be 0 or at least nx * ny";
+        return GP_EINVAL;
+    }
     if (p->eta != 1 && p->eta != -1) { why = "eta must be +1 (Rashba) or -1 (Dresselhaus)"; return GP_EINVAL; }
     if (p->precision != GP_FP64 && p->precision != GP_FP32) { why = "precision must be GP_FP64 or GP_FP32"; return GP_EINVAL; }
     if (p->y_solver < GP_YSOLVER_AUTO || p->y_solver > GP_YSOLVER_THOMAS) { why = "unknown y_solver"; return GP_EINVAL; }
@@ -473,8 +485,10 @@ int validate(const gp_spin1_params* p, std::string& why) {
     return GP_OK;
 }
 
-template <typename T> gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool local);
-template <typename T> gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool norm);
+template <typename T>
+gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool local, size_t sp, size_t dp);
+template <typename T>
+gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool norm, size_t sp, size_t dp);
 
 // Mean duration in ms of `reps` launches of f() after two warm-up launches.
 template <typename F>
@@ -517,7 +531,7 @@ int time_launches(gp_spin1* h, F f, int reps, float& ms) {
 template <typename T>
 int autotune_t(gp_spin1* h) {
     const gp_spin1_params& p = h->p;
-    const size_t bytes = (size_t)3 * p.nx * p.ny * sizeof(gp::cx<T>);
+    const size_t bytes = (2 * h->psp + (size_t)p.nx * p.ny) * sizeof(gp::cx<T>);  // laid out as the caller's
     void* tmp = nullptr;
     hipError_t e = hipMalloc(&tmp, bytes);
     if (e != hipSuccess) return fail(h, GP_ENOMEM, "autotune buffer allocation failed");
@@ -526,7 +540,7 @@ int autotune_t(gp_spin1* h) {
     const int reps = 5;
     // bring the clocks up before the first comparison
     if (rc == GP_OK) {
-        const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, false, true);
+        const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, false, true, h->psp, h->wsp);
         float warm = 0.f;
         rc = time_launches(h, [&] { return gp::launch_x<T>(xa, h->stream); }, reps, warm);
     }
@@ -543,8 +557,8 @@ int autotune_t(gp_spin1* h) {
         // for the other sweep, as in a step: a sweep's speed depends on where
         // the previous kernel left its input (which L2, written back or not)
         auto pair = [&](float& t) {
-            const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true);
-            const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag);
+            const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true, h->psp, h->wsp);
+            const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag, h->wsp, h->psp);
             return time_launches(h, [&] {
                 const hipError_t ex = gp::launch_x<T>(xa, h->stream);
                 return ex != hipSuccess ? ex : gp::launch_y<T>(ya, h->stream);
@@ -676,7 +690,9 @@ int create_t(gp_spin1* h) {
     if (hipMalloc(&h->d_scale, 3 * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_flag, sizeof(int)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
     if (hipMalloc(&h->d_obs, gp::kObsCount * sizeof(double)) != hipSuccess) return fail(h, GP_ENOMEM, "scratch allocation failed");
-    if (hipMalloc(&h->d_work, (size_t)3 * p.nx * p.ny * sizeof(gp::cx<T>)) != hipSuccess)
+    h->psp = psi_stride(p);
+    h->wsp = work_stride(p);
+    if (hipMalloc(&h->d_work, (2 * h->wsp + npts) * sizeof(gp::cx<T>)) != hipSuccess)
         return fail(h, GP_ENOMEM, "work buffer allocation failed");
     const double one = 1.0;
     const int zero = 0;
@@ -692,10 +708,12 @@ int create_t(gp_spin1* h) {
 }
 
 template <typename T>
-gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool local) {
+gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool local, size_t sp, size_t dp) {
     gp::XLaunch<T> a;
     a.src = (const gp::cx<T>*)src;
     a.dst = (gp::cx<T>*)dst;
+    a.sp = sp;
+    a.dp = dp;
     a.ph = phys(h->p);
     a.ls = lineset<T>(h->mode[imag].x);
     a.scale = h->d_scale;
@@ -709,7 +727,7 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
 }
 
 template <typename T>
-gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool norm) {
+gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool norm, size_t sp, size_t dp) {
     const ModeState& ms = h->mode[imag];
     gp::YLaunch<T> a;
     a.src = (const gp::cx<T>*)src;
@@ -721,6 +739,8 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.window = ms.window; a.imag = imag; a.norm = norm;
     a.outl = false;
     a.order = ms.yorder;
+    a.sp = sp;
+    a.dp = dp;
     return a;
 }
 
@@ -770,8 +790,8 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     if (!ms.stable) return fail(h, GP_EUNSTABLE, ms.why);
     if (n == 0) return GP_OK;
     hipStream_t st = h->stream;
-    const gp::XLaunch<T> xa = xlaunch<T>(h, psi, h->d_work, imag, true);
-    gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, psi, imag, imag);
+    const gp::XLaunch<T> xa = xlaunch<T>(h, psi, h->d_work, imag, true, h->psp, h->wsp);
+    gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, psi, imag, imag, h->wsp, h->psp);
     ya.outl = h->p.split == GP_SPLIT_STRANG;
     const int nyb = gp::y_blocks<T>(ya);
     const double dxdy = h->p.dx * h->p.dy;
@@ -794,8 +814,8 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
             return hip_fail(h, e, "norm launch");
     }
     if (imag) {
-        const size_t plane = (size_t)h->p.nx * h->p.ny;
-        if ((e = timed(h, 3, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_scale<T>((gp::cx<T>*)psi, plane, h->d_scale, st, a, b); })) != hipSuccess)
+        const size_t npts = (size_t)h->p.nx * h->p.ny;
+        if ((e = timed(h, 3, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_scale<T>((gp::cx<T>*)psi, npts, h->psp, h->d_scale, st, a, b); })) != hipSuccess)
             return hip_fail(h, e, "scale launch");
     }
     return GP_OK;
@@ -805,26 +825,26 @@ template <typename T>
 int substep_t(gp_spin1* h, void* psi, int which, bool imag) {
     hipStream_t st = h->stream;
     hipError_t e = hipSuccess;
-    const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
+    const size_t npts = (size_t)h->p.nx * h->p.ny;
+    const size_t cs = sizeof(gp::cx<T>);
     switch (which) {
-        case 0: e = gp::launch_local<T>((gp::cx<T>*)psi, phys(h->p), imag, st); break;
+        case 0: e = gp::launch_local<T>((gp::cx<T>*)psi, h->psp, phys(h->p), imag, st); break;
         case 1:
         case 2: {
-            // out of place into the work buffer, then back
-            if (which == 1) e = gp::launch_x<T>(xlaunch<T>(h, psi, h->d_work, imag, false), st);
-            else e = gp::launch_y<T>(ylaunch<T>(h, psi, h->d_work, imag, false), st);
+            // out of place into the work buffer, then back plane by plane
+            if (which == 1) e = gp::launch_x<T>(xlaunch<T>(h, psi, h->d_work, imag, false, h->psp, h->wsp), st);
+            else e = gp::launch_y<T>(ylaunch<T>(h, psi, h->d_work, imag, false, h->psp, h->wsp), st);
             if (e != hipSuccess) break;
-            e = hipMemcpyAsync(psi, h->d_work, n3 * sizeof(gp::cx<T>), hipMemcpyDeviceToDevice, st);
+            e = hipMemcpy2DAsync(psi, h->psp * cs, h->d_work, h->wsp * cs, npts * cs, 3, hipMemcpyDeviceToDevice, st);
             break;
         }
         case 3: {
-            const int nblk = (int)std::min<size_t>(1024, (n3 + 255) / 256);
-            const size_t plane = n3 / 3;
-            if ((e = gp::launch_norm_partials<T>((const gp::cx<T>*)psi, plane, h->d_part, nblk, st)) != hipSuccess) break;
+            const int nblk = (int)std::min<size_t>(1024, (3 * npts + 255) / 256);
+            if ((e = gp::launch_norm_partials<T>((const gp::cx<T>*)psi, npts, h->psp, h->d_part, nblk, st)) != hipSuccess) break;
             if ((e = gp::launch_norm_finalize(h->d_part, nblk, h->p.dx * h->p.dy, norm_rule(h->p), h->d_scale, h->d_flag,
                                               st)) != hipSuccess)
                 break;
-            e = gp::launch_scale<T>((gp::cx<T>*)psi, plane, h->d_scale, st);
+            e = gp::launch_scale<T>((gp::cx<T>*)psi, npts, h->psp, h->d_scale, st);
             break;
         }
         default: return fail(h, GP_EINVAL, "substep: which must be 0..3");
@@ -838,7 +858,7 @@ int obs_t(gp_spin1* h, const void* psi, gp_spin1_obs* out, void* dens) {
     hipStream_t st = h->stream;
     gp::ObsLaunch o{h->p.c0, h->p.c2, h->p.rabi, h->p.gamma, h->p.omega, h->p.eta};
     hipError_t e;
-    if ((e = gp::launch_obs<T>((const gp::cx<T>*)psi, phys(h->p), o, (T*)dens, h->d_part, h->obs_blocks, st)) != hipSuccess)
+    if ((e = gp::launch_obs<T>((const gp::cx<T>*)psi, h->psp, phys(h->p), o, (T*)dens, h->d_part, h->obs_blocks, st)) != hipSuccess)
         return hip_fail(h, e, "observables launch");
     if ((e = gp::launch_obs_finalize(h->d_part, h->obs_blocks, h->d_obs, st)) != hipSuccess)
         return hip_fail(h, e, "observables finalize launch");
@@ -1050,10 +1070,12 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
                 const int nyb = ncs * ((h->p.ny + L - 1) / L);
                 const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
                 const int nsb = (int)((n3 + gp::kScaleChunk - 1) / gp::kScaleChunk);
-                xs.push_back(gp::XSlot<T>{(const C*)psi[s], (C*)h->d_work, phys(h->p), lineset<T>(ms.x), h->d_scale, G, R});
-                ys.push_back(gp::YSlot<T>{(const C*)h->d_work, (C*)psi[s], phys(h->p), lineset<T>(ms.y), h->d_part, L, hh, ncs});
+                xs.push_back(gp::XSlot<T>{(const C*)psi[s], (C*)h->d_work, phys(h->p), lineset<T>(ms.x), h->d_scale, G, R,
+                                          h->psp, h->wsp});
+                ys.push_back(gp::YSlot<T>{(const C*)h->d_work, (C*)psi[s], phys(h->p), lineset<T>(ms.y), h->d_part, L, hh, ncs,
+                                          h->wsp, h->psp});
                 ns.push_back(gp::NSlot{h->d_part, nyb, h->p.dx * h->p.dy, h->d_scale, h->d_flag, norm_rule(h->p)});
-                ss.push_back(gp::SSlot<T>{(C*)psi[s], n3 / 3, h->d_scale});
+                ss.push_back(gp::SSlot<T>{(C*)psi[s], n3 / 3, h->psp, h->d_scale});
                 for (int k = 0; k < (h->p.ny + R - 1) / R; ++k) xm.push_back((id << gp::kMapShift) | (unsigned)k);
                 for (int k = 0; k < nyb; ++k) ym.push_back((id << gp::kMapShift) | (unsigned)k);
                 for (int k = 0; k < nsb; ++k) sm.push_back((id << gp::kMapShift) | (unsigned)k);
@@ -1144,9 +1166,10 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
 // work copy and the per-line tables (pivots + coefficients, both directions).
 size_t request_bytes(const gp_spin1_params& p) {
     const size_t s = p.precision == GP_FP64 ? 16 : 8;
-    const size_t state = (size_t)3 * p.nx * p.ny * s;
+    const size_t n = (size_t)p.nx * p.ny;
+    const size_t state = (2 * psi_stride(p) + n) * s, work = (2 * work_stride(p) + n) * s;
     const size_t tables = (size_t)2 * 3 * ((size_t)p.nx + p.ny) * 72 * s;  // generous bound
-    return 2 * state + tables + (1u << 16);
+    return state + work + tables + (1u << 16);
 }
 
 double seconds_since(const std::chrono::steady_clock::time_point& t0) {

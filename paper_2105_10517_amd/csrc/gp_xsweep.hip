@@ -13,7 +13,7 @@ namespace gp {
 // One block of the x sweep: rows blk R .. blk R + R - 1 of one condensate, G
 // threads per row (threads past G R idle through the barriers).
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE>
-__device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
+__device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp, const Phys& ph,
                               const LineSet<T>& ls, const double* __restrict__ scale, NormIn nin, int G, int R,
                               int blk) {
     using C = cx<T>;
@@ -29,7 +29,6 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     const int j = blk * R + r;
     const bool row_ok = r < R && j < ph.ny;
     const int nx = ph.nx;
-    const size_t plane = (size_t)ph.nx * ph.ny;
     const int i0 = t * K;
     const int jl = row_ok ? j : 0;
     const int kl = ls.K < KL ? ls.K : KL;
@@ -45,13 +44,13 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int k = 0; k < K; ++k) v[m][k] = rowp[m * plane + i0 + k];
+            for (int k = 0; k < K; ++k) v[m][k] = rowp[m * sp + i0 + k];
     } else {
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                v[m][k] = (row_ok && i0 + k < nx) ? rowp[m * plane + i0 + k] : zero_c<C>();
+                v[m][k] = (row_ok && i0 + k < nx) ? rowp[m * sp + i0 + k] : zero_c<C>();
     }
     if (SCALE) {
         double sc[3];
@@ -136,13 +135,13 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
-            for (int k = 0; k < K; ++k) rowq[m * plane + i0 + k] = v[m][k];
+            for (int k = 0; k < K; ++k) rowq[m * dp + i0 + k] = v[m][k];
     } else if (row_ok) {
 #pragma unroll
         for (int m = 0; m < 3; ++m)
 #pragma unroll
             for (int k = 0; k < K; ++k)
-                if (i0 + k < nx) rowq[m * plane + i0 + k] = v[m][k];
+                if (i0 + k < nx) rowq[m * dp + i0 + k] = v[m][k];
     }
 }
 
@@ -157,7 +156,7 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 // pending scale are applied to every point loaded, halo included.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCALE>
-__device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
+__device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp, const Phys& ph,
                                 const LineSet<T>& ls, const double* __restrict__ scale, int L, int h, int ncs,
                                 int blk) {
     using C = cx<T>;
@@ -170,7 +169,6 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     const int j = rt * RPB + wv * 4 + rw;
     const bool row_ok = j < ph.ny;
     const int nx = ph.nx;
-    const size_t plane = (size_t)nx * ph.ny;
     const int i0 = cs * L;           // first point written by this window
     const int g0 = i0 - h + seg * KX;  // first point of this lane
     const int jl = row_ok ? j : 0;
@@ -191,7 +189,7 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
         const int g = g0 + k;
         const bool ok = row_ok && g >= 0 && g < nx;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) v[m][k] = ok ? rowp[m * plane + (ok ? g : 0)] : zero_c<C>();
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? rowp[m * sp + (ok ? g : 0)] : zero_c<C>();
     }
     if (SCALE) {
 #pragma unroll
@@ -229,31 +227,32 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
         const int g = g0 + k;
         if (row_ok && g >= i0 && g < i0 + L && g < nx)
 #pragma unroll
-            for (int m = 0; m < 3; ++m) rowq[m * plane + g] = v[m][k];
+            for (int m = 0; m < 3; ++m) rowq[m * dp + g] = v[m][k];
     }
 }
 
 template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCALE>
 __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                                      Phys ph, LineSet<T> ls, const double* __restrict__ scale, int L,
+                                                      size_t sp, size_t dp, Phys ph, LineSet<T> ls, const double* __restrict__ scale, int L,
                                                       int h, int ncs, int nblk, int order) {
     const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, ncs, nblk / ncs);
     if (lb < 0) return;
-    x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, ph, ls, scale, L, h, ncs, lb);
+    x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, L, h, ncs, lb);
 }
 
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
-__global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
+__global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
+                                               size_t dp, Phys ph,
                                                LineSet<T> ls, const double* __restrict__ scale, NormIn nin, int G,
                                                int R) {
-    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, ph, ls, scale, nin, G, R, (int)blockIdx.x);
+    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, nin, G, R, (int)blockIdx.x);
 }
 
 template <typename T, bool IMAG, int K, int LB>
 __global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
     const XSlot<T>& s = slots[e >> kMapShift];
-    x_rows<T, IMAG, K, true, IMAG>(s.src, s.dst, s.ph, s.ls, s.scale, NormIn{nullptr, 0, 0.0, NormRule{0, 0.0}, nullptr},
+    x_rows<T, IMAG, K, true, IMAG>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.scale, NormIn{nullptr, 0, 0.0, NormRule{0, 0.0}, nullptr},
                                    s.G, s.R, (int)(e & kMapMask));
 }
 
@@ -261,7 +260,7 @@ __global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slo
 // Launchers.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, bool LOCAL, bool SCALE>
-static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph, const LineSet<T>& ls,
+static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, size_t sp, size_t dp, const Phys& ph, const LineSet<T>& ls,
                              const double* scale, NormIn nin, int G, int R, hipStream_t st, hipEvent_t e0,
                              hipEvent_t e1) {
     const int nblk = (ph.ny + R - 1) / R;
@@ -269,11 +268,11 @@ static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, const Phys& ph
     if (G * R > xk_bound(K) || G % 64 || G / 64 > 16 || R > 8) return hipErrorInvalidValue;
 
     switch (K) {
-        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
-        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
-        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
-        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
-        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, ph, ls, scale, nin, G, R); break;
+        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
+        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
+        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
+        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
+        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -286,7 +285,7 @@ static hipError_t launch_xw_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int nrt = (a.ph.ny + 4 * xt.NW - 1) / (4 * xt.NW);
     const int nblk = ncs * nrt;
     hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, xt.SEQ, LOCAL, SCALE>, dim3(xcd_grid(a.order ? 1 : 0, ncs, nrt)),
-                          dim3(64 * xt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.scale, a.L, a.h, ncs, nblk,
+                          dim3(64 * xt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.L, a.h, ncs, nblk,
                           a.order);
     return hipGetLastError();
 }
@@ -315,11 +314,11 @@ hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent
         return a.local ? launch_xw<T, false, true, false>(a, st, e0, e1) : launch_xw<T, false, false, false>(a, st, e0, e1);
     }
     if (a.imag) {
-        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
-        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
     }
-    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
-    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
 }
 
 template <typename T, bool IMAG>

@@ -24,7 +24,7 @@ namespace gp {
 // side and write only their L = 16 KY - 2 h middle rows.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, int KY, int NW, bool SEQ, bool NORM, bool OUTL>
-__device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, const Phys& ph,
+__device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp, const Phys& ph,
                                 const LineSet<T>& ls, int L, int h, int ncs, NormOut no, int blk) {
     using C = cx<T>;
     constexpr int CPB = 4 * NW;  // columns per block
@@ -37,7 +37,6 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     const int i = cs * CPB + wv * 4 + cw;
     const bool col_ok = i < ph.nx;
     const int nx = ph.nx, ny = ph.ny;
-    const size_t plane = (size_t)nx * ny;
     const int j0 = rt * L;
     const int g0 = j0 - h + seg * KY;  // first row of this lane
     // windows that reach the start of the columns stage the transient pivots (block-uniform branch)
@@ -57,7 +56,7 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
         const bool ok = col_ok && g >= 0 && g < ny;
         const size_t o = (size_t)(ok ? g : 0) * nx + (col_ok ? i : 0);
 #pragma unroll
-        for (int m = 0; m < 3; ++m) v[m][k] = ok ? src[m * plane + o] : zero_c<C>();
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? src[m * sp + o] : zero_c<C>();
     }
 #pragma unroll
     for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
@@ -91,7 +90,7 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
             const size_t o = (size_t)g * nx + i;
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                dst[m * plane + o] = v[m][k];
+                dst[m * dp + o] = v[m][k];
                 if (NORM) acc[m] += (double)cnorm2(v[m][k]);
             }
         }
@@ -101,18 +100,18 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
 
 template <typename T, bool IMAG, int KY, int NW, bool SEQ, bool NORM, bool OUTL>
 __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                                      Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no,
+                                                      size_t sp, size_t dp, Phys ph, LineSet<T> ls, int L, int h, int ncs, NormOut no,
                                                       int nblk, int order) {
     const int lb = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
     if (lb < 0) return;
-    y_window<T, IMAG, KY, NW, SEQ, NORM, OUTL>(src, dst, ph, ls, L, h, ncs, no, lb);
+    y_window<T, IMAG, KY, NW, SEQ, NORM, OUTL>(src, dst, sp, dp, ph, ls, L, h, ncs, no, lb);
 }
 
 template <typename T, bool IMAG, int KY, int NW, bool SEQ>
 __global__ __launch_bounds__(64 * NW) void k_y_batch(const YSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
     const YSlot<T>& s = slots[e >> kMapShift];
-    y_window<T, IMAG, KY, NW, SEQ, IMAG, false>(s.src, s.dst, s.ph, s.ls, s.L, s.h, s.ncs, NormOut{s.partials},
+    y_window<T, IMAG, KY, NW, SEQ, IMAG, false>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.L, s.h, s.ncs, NormOut{s.partials},
                                                 (int)(e & kMapMask));
 }
 
@@ -121,13 +120,13 @@ __global__ __launch_bounds__(64 * NW) void k_y_batch(const YSlot<T>* __restrict_
 // forward eliminations go to dst, the back substitution re-reads src.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, bool NORM, bool OUTL>
-__global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, Phys ph,
+__global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
+                                                 size_t dp, Phys ph,
                                                  LineSet<T> ls, NormOut no) {
     using C = cx<T>;
     __shared__ double shr[48];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int nx = ph.nx, ny = ph.ny;
-    const size_t plane = (size_t)nx * ny;
     double acc[3] = {0, 0, 0};
     if (i < nx) {
         C a[3], e[3];
@@ -141,7 +140,7 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
         auto load_sx = [&](int g, C (&o)[3]) {
             if (g >= 0 && g < ny) {
 #pragma unroll
-                for (int m = 0; m < 3; ++m) o[m] = src[m * plane + (size_t)g * nx + i];
+                for (int m = 0; m < 3; ++m) o[m] = src[m * sp + (size_t)g * nx + i];
                 to_sx<C, T>(o[0], o[1], o[2]);
             } else {
 #pragma unroll
@@ -166,13 +165,13 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
                 cur[q] = nxt[q];
             }
 #pragma unroll
-            for (int m = 0; m < 3; ++m) dst[m * plane + (size_t)g * nx + i] = d[m];
+            for (int m = 0; m < 3; ++m) dst[m * dp + (size_t)g * nx + i] = d[m];
         }
         C x[3] = {zero_c<C>(), zero_c<C>(), zero_c<C>()};
         for (int g = ny - 1; g >= 0; --g) {
             C o[3], uu[3];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) o[m] = dst[m * plane + (size_t)g * nx + i];
+            for (int m = 0; m < 3; ++m) o[m] = dst[m * dp + (size_t)g * nx + i];
             load_sx(g, uu);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
@@ -188,7 +187,7 @@ __global__ __launch_bounds__(256) void k_y_thomas(const cx<T>* __restrict__ src,
             }
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                dst[m * plane + (size_t)g * nx + i] = o[m];
+                dst[m * dp + (size_t)g * nx + i] = o[m];
                 if (NORM) acc[m] += (double)cnorm2(o[m]);
             }
         }
@@ -206,7 +205,7 @@ static hipError_t launch_yw_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
     const int nblk = ncs * nrt;
     hipExtLaunchKernelGGL(k_y_window<T, IMAG, yt.KY, yt.NW, yt.SEQ, NORM, OUTL>, dim3(xcd_grid(a.order, ncs, nrt)),
-                          dim3(64 * yt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.L, a.h, ncs, a.no, nblk,
+                          dim3(64 * yt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.L, a.h, ncs, a.no, nblk,
                           a.order);
     return hipGetLastError();
 }
@@ -239,7 +238,7 @@ int y_blocks(const YLaunch<T>& a) {
 template <typename T, bool IMAG, bool NORM, bool OUTL>
 static hipError_t launch_yt(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     const dim3 grid((a.ph.nx + 255) / 256), block(256);
-    hipExtLaunchKernelGGL(k_y_thomas<T, IMAG, NORM, OUTL>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.ph, a.ls, a.no);
+    hipExtLaunchKernelGGL(k_y_thomas<T, IMAG, NORM, OUTL>, grid, block, 0, st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.no);
     return hipGetLastError();
 }
 

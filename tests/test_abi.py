@@ -155,6 +155,16 @@ def test_tile_options():
     assert lib.gp_spin1_plan_query(ctypes.byref(q), 1, ctypes.byref(pl)) == binding.GP_EINVAL
 
 
+def test_plane_stride_validation():
+    n = BASE["nx"] * BASE["ny"]
+    for stride in (0, n, n + 4160):
+        binding.plan_query(dict(BASE, plane_stride=stride), True)
+    for stride in (n - 1, -5):
+        with pytest.raises(binding.GPError) as ei:
+            binding.plan_query(dict(BASE, plane_stride=stride), True)
+        assert ei.value.status == binding.GP_EINVAL
+
+
 def test_unit_helper_reproduces_the_printed_couplings():
     # Eq. (S.4) with the paper's 87Rb / 23Na inputs (l0 / sqrt(kappa) = 4 micrometres)
     import json

@@ -74,8 +74,10 @@ def test_served_states_equal_solo_runs(precision):
 
 
 def charge(p, s=8):
-    """Device bytes the serving loop charges an admitted condensate."""
-    return 2 * 3 * p["nx"] * p["ny"] * s + 432 * (p["nx"] + p["ny"]) * s + 65536
+    """Device bytes the serving loop charges an admitted condensate: its wave
+    function, the work copy (planes padded by 4160 points), line tables, scratch."""
+    n = p["nx"] * p["ny"]
+    return 3 * n * s + (3 * n + 2 * 4160) * s + 432 * (p["nx"] + p["ny"]) * s + 65536
 
 
 def test_memory_budget_limits_admission():
