@@ -85,9 +85,13 @@ typedef enum {
                               with autotune, both timed and the faster kept per sweep                       */
     GP_ORDER_HARDWARE = 1, /* block b processes window b                                                    */
     GP_ORDER_XCD = 2,      /* block b processes window (b mod 8) ceil(n/8) + b div 8 (n windows)            */
-    GP_ORDER_BANDS = 3     /* y windows: XCD x takes a contiguous range of column strips and walks them down
+    GP_ORDER_BANDS = 3,    /* y windows: XCD x takes a contiguous range of column strips and walks them down
                               8 strips at a time (windows above and below each other in flight together);
                               x windows as GP_ORDER_XCD                                                    */
+    GP_ORDER_ROWS = 4      /* row bands for small grids: XCD x owns the y row tiles [x nrt/8, (x+1) nrt/8)
+                              (nrt row tiles) in both sweeps - their y windows and the x rows they cover -
+                              so that each sweep reads from its own L2 what the other wrote; needs y
+                              windows (else x windows as GP_ORDER_XCD, whole rows in hardware order)    */
 } gp_block_order;
 
 /* Order of the substeps within one step. */
@@ -170,8 +174,8 @@ typedef struct {
     int32_t x_halo;              /* windows: points of overlap on each side                       */
     int32_t x_points_out;        /* windows: points written per window                            */
     int32_t x_tile;              /* windows: 1..8, same shapes as y_tile (rows per block = 4 per wave) */
-    int32_t x_block_order;       /* windows: 0 blocks in hardware order, 1 XCD-contiguous (each of  */
-    int32_t y_block_order;       /*   the 8 XCDs takes a contiguous run of windows), 2 bands (y)    */
+    int32_t x_block_order;       /* 0 blocks in hardware order, 1 XCD-contiguous windows (each of   */
+    int32_t y_block_order;       /*   the 8 XCDs a contiguous run), 2 bands (y), 3 row bands        */
 } gp_spin1_plan;
 
 typedef struct gp_spin1 gp_spin1_t;

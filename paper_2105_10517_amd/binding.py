@@ -19,7 +19,7 @@ GP_OK, GP_EINVAL, GP_EUNSTABLE, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORT
 GP_FP64, GP_FP32 = 0, 1
 GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS = 0, 1, 2
 GP_XSOLVER_AUTO, GP_XSOLVER_SCAN, GP_XSOLVER_WINDOW = 0, 1, 2
-GP_ORDER_AUTO, GP_ORDER_HARDWARE, GP_ORDER_XCD, GP_ORDER_BANDS = 0, 1, 2, 3
+GP_ORDER_AUTO, GP_ORDER_HARDWARE, GP_ORDER_XCD, GP_ORDER_BANDS, GP_ORDER_ROWS = 0, 1, 2, 3, 4
 SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
 
 # Every entry point the header declares (checked by the CPU test suite).
@@ -177,7 +177,7 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_poin
                   int(p.get("split", 0)), int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)),
                   {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW}[x_solver],
                   {"auto": GP_ORDER_AUTO, "hardware": GP_ORDER_HARDWARE, "xcd": GP_ORDER_XCD,
-                   "bands": GP_ORDER_BANDS}[block_order],
+                   "bands": GP_ORDER_BANDS, "rows": GP_ORDER_ROWS}[block_order],
                   int(x_tile), int(p.get("plane_stride", 0)))
 
 

@@ -43,7 +43,7 @@ struct ModeState {
     int ytile = 0;                // windowed y sweep tile shape (0-based)
     bool xwindow = false;         // x sweep over truncated windows
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
-    int xorder = 1, yorder = 0;   // block orders of the windowed sweeps (0 hardware, 1 XCD-contiguous, 2 bands)
+    int xorder = 1, yorder = 0;   // block orders (x windows 0/1, x rows 0/3; y windows 0..3), see gp_kernels.hpp
     gp_spin1_plan plan{};
 };
 
@@ -348,8 +348,9 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     hm.xorder = 1;
     hm.yorder = 0;
     if (p.block_order != GP_ORDER_AUTO) {
-        hm.xorder = p.block_order == GP_ORDER_HARDWARE ? 0 : 1;
-        hm.yorder = p.block_order == GP_ORDER_HARDWARE ? 0 : p.block_order == GP_ORDER_XCD ? 1 : 2;
+        hm.xorder = p.block_order == GP_ORDER_HARDWARE ? 0 : p.block_order == GP_ORDER_ROWS ? 3 : 1;
+        hm.yorder = p.block_order == GP_ORDER_HARDWARE ? 0 : p.block_order == GP_ORDER_XCD ? 1
+                  : p.block_order == GP_ORDER_BANDS ? 2 : 3;
     } else if (hm.window) {
         const gp::YTile yt = gp::ytile<T>(hm.ytile);
         const long nblk = (long)((p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((p.ny + hm.L - 1) / hm.L);
@@ -380,7 +381,7 @@ void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out)
     out->x_halo = hm.xwindow ? hm.hx : 0;
     out->x_points_out = hm.xwindow ? hm.Lx : 0;
     out->x_tile = hm.xwindow ? hm.xtile + 1 : 0;
-    out->x_block_order = hm.xwindow ? hm.xorder : 0;
+    out->x_block_order = hm.xorder == 3 && !hm.window ? (hm.xwindow ? 1 : 0) : hm.xwindow || hm.xorder == 3 ? hm.xorder : 0;
     out->y_block_order = hm.window ? hm.yorder : 0;
 }
 
@@ -469,7 +470,7 @@ int validate(const gp_spin1_params* p, std::string& why) {
         return GP_EINVAL;
     }
     if (p->x_solver < GP_XSOLVER_AUTO || p->x_solver > GP_XSOLVER_WINDOW) { why = "unknown x_solver"; return GP_EINVAL; }
-    if (p->block_order < GP_ORDER_AUTO || p->block_order > GP_ORDER_BANDS) { why = "unknown block_order"; return GP_EINVAL; }
+    if (p->block_order < GP_ORDER_AUTO || p->block_order > GP_ORDER_ROWS) { why = "unknown block_order"; return GP_EINVAL; }
     if (p->x_tile < 0 || p->x_tile > gp::kNumYTiles) { why = "x_tile must be 0..8"; return GP_EINVAL; }
     if (p->y_tile < 0 || p->y_tile > gp::kNumYTiles) { why = "y_tile must be 0..8"; return GP_EINVAL; }
     if (p->x_tile > 0 && p->x_solver != GP_XSOLVER_WINDOW) { why = "x_tile needs x_solver = GP_XSOLVER_WINDOW"; return GP_EINVAL; }
@@ -548,7 +549,9 @@ int autotune_t(gp_spin1* h) {
     int o0 = 0, o1 = 2, p0 = 0, p1 = 3;
     if (p.block_order != GP_ORDER_AUTO) {
         o0 = p.block_order == GP_ORDER_HARDWARE ? 0 : 1; o1 = o0 + 1;
-        p0 = p.block_order == GP_ORDER_HARDWARE ? 0 : p.block_order == GP_ORDER_XCD ? 1 : 2; p1 = p0 + 1;
+        p0 = p.block_order == GP_ORDER_HARDWARE ? 0 : p.block_order == GP_ORDER_XCD ? 1
+           : p.block_order == GP_ORDER_BANDS ? 2 : 3;
+        p1 = p0 + 1;
     }
     for (int m = 0; m < 2 && rc == GP_OK; ++m) {
         ModeState& ms = h->mode[m];
@@ -636,6 +639,18 @@ int autotune_t(gp_spin1* h) {
             ms.yorder = bestO;
             tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(bestT)), ms.h, ms.L);
         }
+        if (p.block_order == GP_ORDER_ROWS) ms.xorder = 3;
+        // row bands for both sweeps (only as a pair: each sweep then reads what the
+        // other wrote on the same XCD), where the y sweep has windows
+        if (rc == GP_OK && ms.window && p.block_order == GP_ORDER_AUTO) {
+            const int kx = ms.xorder, ky = ms.yorder;
+            float tc = 0.f, tb = 0.f;
+            rc = pair(tc);
+            ms.xorder = 3;
+            ms.yorder = 3;
+            if (rc == GP_OK) rc = pair(tb);
+            if (rc != GP_OK || !(tb < tc)) { ms.xorder = kx; ms.yorder = ky; }
+        }
         ms.plan.x_points_per_thread = ms.xK;
         ms.plan.x_threads_per_row = ms.xG;
         ms.plan.x_rows_per_block = ms.xR;
@@ -643,7 +658,7 @@ int autotune_t(gp_spin1* h) {
         ms.plan.x_halo = ms.xwindow ? ms.hx : 0;
         ms.plan.x_points_out = ms.xwindow ? ms.Lx : 0;
         ms.plan.x_tile = ms.xwindow ? ms.xtile + 1 : 0;
-        ms.plan.x_block_order = ms.xwindow ? ms.xorder : 0;
+        ms.plan.x_block_order = ms.xorder == 3 && !ms.window ? (ms.xwindow ? 1 : 0) : ms.xwindow || ms.xorder == 3 ? ms.xorder : 0;
         ms.plan.y_block_order = ms.window ? ms.yorder : 0;
         const gp::YTile yt = gp::ytile<T>(ms.ytile);
         ms.plan.y_tile = ms.ytile + 1;
@@ -723,6 +738,9 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.imag = imag; a.local = local;
     a.window = ms.xwindow; a.L = ms.Lx; a.h = ms.hx; a.tile = ms.xtile;
     a.order = ms.xorder;
+    // row bands follow the y sweep's row tiles (none without y windows)
+    a.bL = ms.window ? ms.L : 0;
+    a.bnrt = ms.window ? (h->p.ny + ms.L - 1) / ms.L : 0;
     return a;
 }
 

@@ -6,16 +6,18 @@
 // rows of many condensates (a block map names each block's condensate).
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "gp_solve.hpp"
 
 namespace gp {
 
-// One block of the x sweep: rows blk R .. blk R + R - 1 of one condensate, G
-// threads per row (threads past G R idle through the barriers).
+// One block of the x sweep: rows row0 .. row0 + R - 1 below rlim of one
+// condensate, G threads per row (threads past G R idle through the barriers).
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE>
 __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp, const Phys& ph,
                               const LineSet<T>& ls, const double* __restrict__ scale, NormIn nin, int G, int R,
-                              int blk) {
+                              int row0, int rlim) {
     using C = cx<T>;
     // scan totals: [direction][line][P (16 waves) | E (16 waves)]
     __shared__ C shS[2 * 3 * 32];
@@ -26,8 +28,8 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     const int tid = threadIdx.x;
     const int r = tid / G, t = tid - r * G;
     const int lane = t & 63, w = t >> 6, nw = G >> 6;
-    const int j = blk * R + r;
-    const bool row_ok = r < R && j < ph.ny;
+    const int j = row0 + r;
+    const bool row_ok = r < R && j < rlim;
     const int nx = ph.nx;
     const int i0 = t * K;
     const int jl = row_ok ? j : 0;
@@ -157,17 +159,16 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCALE>
 __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp, const Phys& ph,
-                                const LineSet<T>& ls, const double* __restrict__ scale, int L, int h, int ncs,
-                                int blk) {
+                                const LineSet<T>& ls, const double* __restrict__ scale, int L, int h, int cs, int rt,
+                                int rlo, int rhi) {
     using C = cx<T>;
     constexpr int RPB = 4 * NW;  // rows per block
     constexpr int KL = 8;
     __shared__ Piv<T> shT[RPB * 3 * KL];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane & 15, rw = lane >> 4;
-    const int cs = blk % ncs, rt = blk / ncs;
     const int j = rt * RPB + wv * 4 + rw;
-    const bool row_ok = j < ph.ny;
+    const bool row_ok = j >= rlo && j < rhi;  // rows of this block's group that it owns
     const int nx = ph.nx;
     const int i0 = cs * L;           // first point written by this window
     const int g0 = i0 - h + seg * KX;  // first point of this lane
@@ -234,18 +235,42 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
 template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCALE>
 __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                       size_t sp, size_t dp, Phys ph, LineSet<T> ls, const double* __restrict__ scale, int L,
-                                                      int h, int ncs, int nblk, int order) {
-    const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, ncs, nblk / ncs);
-    if (lb < 0) return;
-    x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, L, h, ncs, lb);
+                                                      int h, int ncs, int nblk, int order, int bL, int bnrt) {
+    constexpr int RPB = 4 * NW;
+    int cs, rt, rlo = 0, rhi = ph.ny;
+    if (order == 3 && bL > 0) {
+        // row bands: XCD (b mod 8) takes the row groups overlapping its rows, all windows of each,
+        // and computes only its own rows of a group shared with the next band
+        const int jb = (int)blockIdx.x / kNumXcd;
+        band_rows((int)blockIdx.x % kNumXcd, bnrt, bL, ph.ny, rlo, rhi);
+        const int g0 = rlo / RPB, g1 = (rhi + RPB - 1) / RPB;
+        if (jb >= (g1 - g0) * ncs) return;
+        rt = g0 + jb / ncs;
+        cs = jb % ncs;
+    } else {
+        const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, ncs, nblk / ncs);
+        if (lb < 0) return;
+        cs = lb % ncs;
+        rt = lb / ncs;
+    }
+    x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, L, h, cs, rt, rlo, rhi);
 }
 
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
 __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
                                                size_t dp, Phys ph,
                                                LineSet<T> ls, const double* __restrict__ scale, NormIn nin, int G,
-                                               int R) {
-    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, nin, G, R, (int)blockIdx.x);
+                                               int R, int bL, int bnrt) {
+    int row0 = (int)blockIdx.x * R, rlim = ph.ny;
+    if (bL > 0) {
+        // row bands: XCD (b mod 8) takes the rows of its y row tiles, R at a time
+        int r0, r1;
+        band_rows((int)blockIdx.x % kNumXcd, bnrt, bL, ph.ny, r0, r1);
+        row0 = r0 + (int)blockIdx.x / kNumXcd * R;
+        rlim = r1;
+        if (row0 >= rlim) return;
+    }
+    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, nin, G, R, row0, rlim);
 }
 
 template <typename T, bool IMAG, int K, int LB>
@@ -253,7 +278,7 @@ __global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slo
     const unsigned e = map[blockIdx.x];
     const XSlot<T>& s = slots[e >> kMapShift];
     x_rows<T, IMAG, K, true, IMAG>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.scale, NormIn{nullptr, 0, 0.0, NormRule{0, 0.0}, nullptr},
-                                   s.G, s.R, (int)(e & kMapMask));
+                                   s.G, s.R, (int)(e & kMapMask) * s.R, s.ph.ny);
 }
 
 // ---------------------------------------------------------------------------
@@ -261,18 +286,28 @@ __global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slo
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, bool LOCAL, bool SCALE>
 static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, size_t sp, size_t dp, const Phys& ph, const LineSet<T>& ls,
-                             const double* scale, NormIn nin, int G, int R, hipStream_t st, hipEvent_t e0,
-                             hipEvent_t e1) {
-    const int nblk = (ph.ny + R - 1) / R;
+                             const double* scale, NormIn nin, int G, int R, int bL, int bnrt, hipStream_t st,
+                             hipEvent_t e0, hipEvent_t e1) {
+    int nblk = (ph.ny + R - 1) / R;
+    if (bL > 0) {
+        if (bnrt <= 0 || (long)bL * bnrt < ph.ny) return hipErrorInvalidValue;
+        int most = 0;
+        for (int x = 0; x < kNumXcd; ++x) {
+            int r0, r1;
+            band_rows(x, bnrt, bL, ph.ny, r0, r1);
+            most = std::max(most, (r1 - r0 + R - 1) / R);
+        }
+        nblk = kNumXcd * std::max(most, 1);
+    }
     const dim3 grid(nblk), block(G * R);
     if (G * R > xk_bound(K) || G % 64 || G / 64 > 16 || R > 8) return hipErrorInvalidValue;
 
     switch (K) {
-        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
-        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
-        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
-        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
-        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R); break;
+        case 1: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 1, LOCAL, SCALE, xk_bound(1)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R, bL, bnrt); break;
+        case 2: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 2, LOCAL, SCALE, xk_bound(2)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R, bL, bnrt); break;
+        case 4: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 4, LOCAL, SCALE, xk_bound(4)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R, bL, bnrt); break;
+        case 8: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 8, LOCAL, SCALE, xk_bound(8)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R, bL, bnrt); break;
+        case 16: hipExtLaunchKernelGGL(k_x_scan<T, IMAG, 16, LOCAL, SCALE, xk_bound(16)>, grid, block, 0, st, e0, e1, 0, src, dst, sp, dp, ph, ls, scale, nin, G, R, bL, bnrt); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -284,9 +319,21 @@ static hipError_t launch_xw_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int ncs = (a.ph.nx + a.L - 1) / a.L;
     const int nrt = (a.ph.ny + 4 * xt.NW - 1) / (4 * xt.NW);
     const int nblk = ncs * nrt;
-    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, xt.SEQ, LOCAL, SCALE>, dim3(xcd_grid(a.order ? 1 : 0, ncs, nrt)),
+    const bool bands = a.order == 3 && a.bL > 0;
+    int grid = xcd_grid(a.order ? 1 : 0, ncs, nrt);
+    if (bands) {
+        if (a.bnrt <= 0 || (long)a.bL * a.bnrt < a.ph.ny) return hipErrorInvalidValue;
+        int most = 0;
+        for (int x = 0; x < kNumXcd; ++x) {
+            int r0, r1;
+            band_rows(x, a.bnrt, a.bL, a.ph.ny, r0, r1);
+            most = std::max(most, (r1 + 4 * xt.NW - 1) / (4 * xt.NW) - r0 / (4 * xt.NW));
+        }
+        grid = kNumXcd * std::max(most, 1) * ncs;
+    }
+    hipExtLaunchKernelGGL(k_x_window<T, IMAG, xt.KY, xt.NW, xt.SEQ, LOCAL, SCALE>, dim3(grid),
                           dim3(64 * xt.NW), 0, st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.L, a.h, ncs, nblk,
-                          a.order);
+                          a.order, a.bL, a.bnrt);
     return hipGetLastError();
 }
 
@@ -314,11 +361,11 @@ hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent
         return a.local ? launch_xw<T, false, true, false>(a, st, e0, e1) : launch_xw<T, false, false, false>(a, st, e0, e1);
     }
     if (a.imag) {
-        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
-        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+        if (a.local) return launch_x_k<T, true, true, true>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, a.order == 3 ? a.bL : 0, a.bnrt, st, e0, e1);
+        return launch_x_k<T, true, false, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, a.order == 3 ? a.bL : 0, a.bnrt, st, e0, e1);
     }
-    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
-    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, st, e0, e1);
+    if (a.local) return launch_x_k<T, false, true, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, a.order == 3 ? a.bL : 0, a.bnrt, st, e0, e1);
+    return launch_x_k<T, false, false, false>(a.K, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.G, a.R, a.order == 3 ? a.bL : 0, a.bnrt, st, e0, e1);
 }
 
 template <typename T, bool IMAG>

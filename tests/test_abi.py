@@ -130,12 +130,15 @@ def test_block_orders_of_the_windowed_sweeps():
     big = binding.plan_query(inputs.config_c3(4096), True)
     assert big["y_solver"] == binding.GP_YSOLVER_WINDOW and big["y_block_order"] == 0
     assert big["x_block_order"] == 0  # whole-row x sweep: no windows to order
-    for order, wx, wy in (("hardware", 0, 0), ("xcd", 1, 1), ("bands", 1, 2)):
+    for order, wx, wy in (("hardware", 0, 0), ("xcd", 1, 1), ("bands", 1, 2), ("rows", 3, 3)):
         for p, imag in ((inputs.config_c2(), False), (inputs.config_c3(4096), True)):
             pl = binding.plan_query(p, imag, x_solver="window", block_order=order)
             assert pl["x_block_order"] == wx and pl["y_block_order"] == wy
+    # row bands on the whole-row x sweep
+    pl = binding.plan_query(inputs.config_c2(), False, block_order="rows")
+    assert pl["x_solver"] == binding.GP_XSOLVER_SCAN and pl["x_block_order"] == 3 and pl["y_block_order"] == 3
     bad = binding.make_params(BASE)
-    bad.block_order = 4
+    bad.block_order = 5
     pl = binding.Plan()
     assert binding.load().gp_spin1_plan_query(ctypes.byref(bad), 1, ctypes.byref(pl)) == binding.GP_EINVAL
 

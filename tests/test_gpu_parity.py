@@ -150,19 +150,22 @@ def test_block_orders_give_identical_results(precision):
     # directions and a ragged last window
     p = all_couplings(700, 500, 0.06, dy=0.05, dt=0.0015)
     psi0 = inputs.gaussian(700, 500, 0.06, 0.05, x0=p["x0"], y0=p["y0"], seed=16, center=(3.0, -2.0))
-    for imag in (True, False):
+    for imag, xs in ((True, "window"), (False, "window"), (True, "scan"), (False, "scan")):
         out = []
-        for order, wy in (("hardware", 0), ("xcd", 1), ("bands", 2)):
-            s = binding.Solver(p, precision, x_solver="window", block_order=order)
+        for order, wy in (("hardware", 0), ("xcd", 1), ("bands", 2), ("rows", 3)):
+            s = binding.Solver(p, precision, x_solver=xs, block_order=order)
             pl = s.plan(imag)
-            assert pl["x_points_out"] < 700 and pl["y_rows_out"] < 500
-            assert pl["x_block_order"] == (order != "hardware") and pl["y_block_order"] == wy
+            assert pl["y_rows_out"] < 500 and pl["y_block_order"] == wy
+            if xs == "window":
+                assert pl["x_points_out"] < 700 and pl["x_block_order"] == {"hardware": 0, "rows": 3}.get(order, 1)
+            else:
+                assert pl["x_block_order"] == (3 if order == "rows" else 0)
             t = dev(psi0, s.dtype)
             (s.step_imag if imag else s.step_real)(t, 7)
             s.sync()
             out.append(host(t))
             s.close()
-        assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2]), imag
+        assert all(np.array_equal(out[0], o) for o in out[1:]), (imag, xs)
 
 
 def test_x_windows_refused_when_the_decay_is_slow():
