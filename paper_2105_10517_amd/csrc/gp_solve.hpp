@@ -78,6 +78,24 @@ __device__ inline Piv<T> piv_pt(const Piv<T> lim, const Piv<T>* tab, int kl, con
     return p;
 }
 
+// Per-line coefficients of a solve: sub- and super-diagonal (a, e) and the
+// converged pivots.  Loaded by the caller, so that a kernel can issue these
+// loads together with its wave-function loads, ahead of any barrier.
+template <typename T> struct LineCoef {
+    cx<T> a, e;
+    Piv<T> lim;
+};
+template <typename T, int NQ, int Q0>
+__device__ inline void line_coefs(const LineSet<T>& ls, const PivSrc<T>& ps, LineCoef<T> (&cf)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int line = ps.line[Q0 + q];
+        cf[q].a = ls.ae[2 * line];
+        cf[q].e = ls.ae[2 * line + 1];
+        cf[q].lim = ps.glob[(size_t)line * (ps.K + 1) + ps.K];
+    }
+}
+
 template <typename C, int K> __device__ inline C cpow_k(C a) {
     C r = one_c<C>(), b = a;
 #pragma unroll
@@ -96,7 +114,8 @@ template <typename C, int K> __device__ inline C cpow_k(C a) {
 // padding) take pivots point by point.
 template <typename T, int K, bool IMAG, int NQ, int Q0, bool LDSPIV, typename FS, typename BS>
 __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], const cx<T> (&right)[NQ],
-                                   const LineSet<T>& ls, const PivSrc<T>& ps, int i0, int n, FS fscan, BS bscan) {
+                                   const LineSet<T>& ls, const PivSrc<T>& ps, const LineCoef<T> (&cf)[NQ], int i0,
+                                   int n, FS fscan, BS bscan) {
     using C = cx<T>;
     C a[NQ], e[NQ], nam[NQ], ncp[NQ], lm[NQ];
     Piv<T> lim[NQ];
@@ -104,9 +123,9 @@ __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], c
     const Piv<T>* row[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        a[q] = ls.ae[2 * ps.line[Q0 + q]];
-        e[q] = ls.ae[2 * ps.line[Q0 + q] + 1];
-        lim[q] = ps.glob[(size_t)ps.line[Q0 + q] * (ps.K + 1) + ps.K];
+        a[q] = cf[q].a;
+        e[q] = cf[q].e;
+        lim[q] = cf[q].lim;
         lm[q] = lim[q].m;
         nam[q] = cneg(lim[q].am);
         ncp[q] = cneg(lim[q].cp);
@@ -243,7 +262,9 @@ __device__ inline void window_line(cx<T> (&u)[3][K], const cx<T> (&lf)[3], const
     auto fs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<true, 1>(P, E, o); };
     auto bs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<false, 1>(P, E, o); };
     const C l1[1] = {lf[Q]}, r1[1] = {rg[Q]};
-    block_solve<T, K, IMAG, 1, Q, true>(reinterpret_cast<C (&)[1][K]>(u[Q]), l1, r1, ls, ps, i0, n, fs, bs);
+    LineCoef<T> cf[1];
+    line_coefs<T, 1, Q>(ls, ps, cf);
+    block_solve<T, K, IMAG, 1, Q, true>(reinterpret_cast<C (&)[1][K]>(u[Q]), l1, r1, ls, ps, cf, i0, n, fs, bs);
 }
 
 template <typename T, int K, bool IMAG, bool SEQ>
@@ -259,7 +280,9 @@ __device__ inline void window_solve(cx<T> (&u)[3][K], const cx<T> (&lf)[3], cons
     } else {
         auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
         auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
-        block_solve<T, K, IMAG, 3, 0, true>(u, lf, rg, ls, ps, i0, n, fs, bs);
+        LineCoef<T> cf[3];
+        line_coefs<T, 3, 0>(ls, ps, cf);
+        block_solve<T, K, IMAG, 3, 0, true>(u, lf, rg, ls, ps, cf, i0, n, fs, bs);
     }
 }
 

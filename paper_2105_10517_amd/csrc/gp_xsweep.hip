@@ -54,6 +54,9 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
             for (int k = 0; k < K; ++k)
                 v[m][k] = (row_ok && i0 + k < nx) ? rowp[m * sp + i0 + k] : zero_c<C>();
     }
+    // the lines' coefficients, loaded with the row (before the barriers below)
+    LineCoef<T> cf[3];
+    line_coefs<T, 3, 0>(ls, piv_src(ls, jl * 3, tab, kl), cf);
     if (SCALE) {
         double sc[3];
         if (nin.partials != nullptr) {
@@ -121,7 +124,7 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
         auto bs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) {
             row_scan<false, 3>(P, E, o, lane, w, nw, ScanShm<C>{shS + 3 * 32 + nrow});
         };
-        block_solve<T, K, IMAG, 3, 0, true>(v, left, right, ls, ps, i0, nx, fs, bs);
+        block_solve<T, K, IMAG, 3, 0, true>(v, left, right, ls, ps, cf, i0, nx, fs, bs);
     } else {
         // one line after the other
         C* sa = shS + nrow;
