@@ -56,6 +56,15 @@ def kernel_roofline(timing, npts, prec):
             "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in rows.items()}}
 
 
+TILES = {"fp64": [(8, 2), (8, 4), (4, 4), (4, 8)], "fp32": [(8, 4), (4, 8), (4, 4), (8, 8)]}
+
+
+def tile_args(prec, tile):
+    """Template arguments (points per lane, waves, lines one at a time) of window tile 1..8."""
+    kk, nw = TILES[prec][(tile - 1) & 3]
+    return f"{kk}, {nw}, {'true' if (tile - 1) & 4 else 'false'}, "
+
+
 def traffic_for(roof, prec, imag, plan, workload):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when there is none for these kernel sources."""
@@ -64,9 +73,12 @@ def traffic_for(roof, prec, imag, plan, workload):
     T = "double" if prec == "fp64" else "float"
     im = "true" if imag else "false"
     if roof["kernel"] == "x_sweep":
-        prefix = f"gp::k_x_scan<{T}, {im}, {plan['x_points_per_thread']}, "
+        if plan["x_solver"] == 2:
+            prefix = f"gp::k_x_window<{T}, {im}, " + tile_args(prec, plan["x_tile"])
+        else:
+            prefix = f"gp::k_x_scan<{T}, {im}, {plan['x_points_per_thread']}, "
     else:
-        prefix = f"gp::k_y_window<{T}, {im}, {plan['y_rows_per_thread']}, {plan['y_tile_cols'] // 4}, "
+        prefix = f"gp::k_y_window<{T}, {im}, " + tile_args(prec, plan["y_tile"])
     for k, v in t.items():
         if k.startswith(prefix):
             return v

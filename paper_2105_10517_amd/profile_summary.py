@@ -47,14 +47,22 @@ def find(d: str, suffix: str) -> str:
     return hits[0]
 
 
-def counters(d: str, counter: str) -> dict:
-    """Mean value per dispatch of one counter, per kernel."""
+def counters(d: str, counter: str, last: int = 0) -> dict:
+    """Mean value per dispatch of one counter, per kernel; with last > 0 over
+    each kernel's last `last` dispatches only (the timed steps of a run whose
+    launch shapes were tuned first, not the tuner's candidates)."""
     acc = {}
     for row in csv.DictReader(open(find(d, "counter_collection.csv"))):
         if row["Counter_Name"] != counter:
             continue
-        acc.setdefault(short(row["Kernel_Name"]), []).append(float(row["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in acc.items()}
+        acc.setdefault(short(row["Kernel_Name"]), []).append((int(row["Dispatch_Id"]), float(row["Counter_Value"])))
+    out = {}
+    for k, v in acc.items():
+        v = [x for _, x in sorted(v)]
+        if last > 0:
+            v = v[-last:]
+        out[k] = sum(v) / len(v)
+    return out
 
 
 def cmd_stats(a):
@@ -75,8 +83,8 @@ def cmd_traffic(a):
     ck = max(cf, key=cf.get)  # the copy kernel reads the most
     f_scale = copy_bytes / (cf[ck] * 1024.0)
     w_scale = copy_bytes / (cw[max(cw, key=cw.get)] * 1024.0)
-    fetch = counters(a.fetch, "FETCH_SIZE")
-    write = counters(a.write, "WRITE_SIZE")
+    fetch = counters(a.fetch, "FETCH_SIZE", a.last)
+    write = counters(a.write, "WRITE_SIZE", a.last)
     s = 16 if a.precision == "fp64" else 8
     algo = 3 * s * a.points  # read or write of one sweep kernel, bytes per launch
     lines = [f"# HBM traffic per launch: {a.title}", "", "Commands (one counter per pass):", "", "```",
@@ -86,7 +94,9 @@ def cmd_traffic(a):
              f"WRITE_SIZE = {cw[max(cw, key=cw.get)]:.0f} KiB per dispatch: fetch factor {f_scale:.3f}, "
              f"write factor {w_scale:.3f}.", "",
              f"Algorithmic bytes per sweep launch: read {algo} B + write {algo} B "
-             f"(3 complex values of {s} B per point, {a.points} points).", "",
+             f"(3 complex values of {s} B per point, {a.points} points)."
+             + (f"  Per kernel, the mean over its last {a.last} dispatches (the timed steps after"
+                f" the launch shapes were tuned)." if a.last else ""), "",
              "| kernel | fetch B | write B | traffic B | fetch / algo | write / algo |",
              "|---|---:|---:|---:|---:|---:|"]
     for k in sorted(set(fetch) & set(write)):
@@ -129,6 +139,7 @@ def main():
     t.add_argument("--copy-mib", type=int, required=True)
     t.add_argument("--points", type=int, required=True, help="grid points nx ny of the workload")
     t.add_argument("--precision", choices=("fp64", "fp32"), required=True)
+    t.add_argument("--last", type=int, default=0, help="use each kernel's last N dispatches only")
     t.add_argument("--command", required=True)
     t.add_argument("--title", default="")
     t.add_argument("--out", required=True)
