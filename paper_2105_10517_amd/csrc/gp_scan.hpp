@@ -9,8 +9,9 @@
 // that enters each thread's block.
 //
 // Inside a wave the scans use DPP lane moves (row_shr / row_shl within rows of
-// 16 lanes, readlane across the four rows, wave_shr / wave_shl for the final
-// shift); across the waves of a row they go through shared memory.
+// 16 lanes, row broadcasts or ds_bpermute gathers across the four rows,
+// wave_shr / wave_shl for the final shift); across the waves of a row they go
+// through shared memory.
 #pragma once
 
 #include "gp_device.hpp"
@@ -41,9 +42,24 @@ template <int CTRL, int RM> __device__ inline double dpp_r(double old, double v)
 template <int CTRL, int RM = 0xF, typename C> __device__ inline C dpp_c(C old, C v) {
     C z; z.x = dpp_r<CTRL, RM>(old.x, v.x); z.y = dpp_r<CTRL, RM>(old.y, v.y); return z;
 }
-template <int CTRL, typename C> __device__ inline Aff<C> dpp_aff(const Aff<C>& a) {
+template <int CTRL, int RM = 0xF, typename C> __device__ inline Aff<C> dpp_aff(const Aff<C>& a) {
     const Aff<C> id = aff_id<C>();
-    return Aff<C>{dpp_c<CTRL>(id.P, a.P), dpp_c<CTRL>(id.E, a.E)};
+    return Aff<C>{dpp_c<CTRL, RM>(id.P, a.P), dpp_c<CTRL, RM>(id.E, a.E)};
+}
+
+// --- lane gathers through the LDS crossbar (ds_bpermute: no LDS memory) -----
+__device__ inline int bperm_i(int v, int src) { return __builtin_amdgcn_ds_bpermute(src << 2, v); }
+__device__ inline float bperm_r(float v, int src) { return __int_as_float(bperm_i(__float_as_int(v), src)); }
+__device__ inline double bperm_r(double v, int src) {
+    const long long x = __double_as_longlong(v);
+    const int lo = bperm_i((int)x, src), hi = bperm_i((int)(x >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename C> __device__ inline C bperm_c(C v, int src) {
+    C z; z.x = bperm_r(v.x, src); z.y = bperm_r(v.y, src); return z;
+}
+template <typename C> __device__ inline Aff<C> bperm_aff(const Aff<C>& a, int src) {
+    return Aff<C>{bperm_c(a.P, src), bperm_c(a.E, src)};
 }
 
 __device__ inline float readlane_r(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
@@ -77,28 +93,36 @@ template <bool FWD, int NQ, typename C> __device__ inline void row16_incl(Aff<C>
 #undef GP_STAGE
 }
 
-// Inclusive scan over the 64 lanes of a wave.
+// Inclusive scan over the 64 lanes of a wave: the rows' scans, then two
+// stages across rows.  Forward: DPP row broadcasts (row_bcast:15 into rows 1
+// and 3, then row_bcast:31 into rows 2 and 3), the values stay in VGPRs.
+// Backward (the maps of the rows above): two ds_bpermute gathers, from the
+// first lane of the next row (rows 0 and 2), then from lane 32 (rows 0, 1).
 template <bool FWD, int NQ, typename C> __device__ inline void wave_incl(Aff<C> (&a)[NQ], int lane) {
     row16_incl<FWD, NQ>(a);
-    const int row = lane >> 4;
+    if (FWD) {
+        Aff<C> s[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        Aff<C> pre = aff_id<C>();
-        if (FWD) {
-            // prefix of the rows below: S_1 = T_0, S_2 = T_1 o T_0, S_3 = T_2 o T_1 o T_0
-            const Aff<C> t0 = readlane_aff(a[q], 15), t1 = readlane_aff(a[q], 31), t2 = readlane_aff(a[q], 47);
-            const Aff<C> s2 = compose(t1, t0), s3 = compose(t2, s2);
-            if (row == 1) pre = t0;
-            if (row == 2) pre = s2;
-            if (row == 3) pre = s3;
-        } else {
-            const Aff<C> t1 = readlane_aff(a[q], 16), t2 = readlane_aff(a[q], 32), t3 = readlane_aff(a[q], 48);
-            const Aff<C> s1 = compose(t2, t3), s0 = compose(t1, s1);
-            if (row == 0) pre = s0;
-            if (row == 1) pre = s1;
-            if (row == 2) pre = t3;
-        }
-        a[q] = compose(a[q], pre);
+        for (int q = 0; q < NQ; ++q) s[q] = dpp_aff<0x142, 0xA>(a[q]);  // row_bcast:15, rows 1 and 3
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = compose(a[q], s[q]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s[q] = dpp_aff<0x143, 0xC>(a[q]);  // row_bcast:31, rows 2 and 3
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = compose(a[q], s[q]);
+    } else {
+        const int row = lane >> 4;
+        const int src1 = (row & 1) ? lane : (lane & ~15) + 16;
+        const int src2 = row >= 2 ? lane : 32;
+        Aff<C> s[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s[q] = bperm_aff(a[q], src1);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = compose(a[q], (row & 1) ? aff_id<C>() : s[q]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s[q] = bperm_aff(a[q], src2);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) a[q] = compose(a[q], row >= 2 ? aff_id<C>() : s[q]);
     }
 }
 
@@ -180,24 +204,9 @@ template <bool FWD, typename C> __device__ inline Aff<C> row16_incl1(Aff<C> a) {
 
 // Inclusive scan over the 64 lanes of a wave (lane order forward or backward).
 template <bool FWD, typename C> __device__ inline Aff<C> wave_incl1(Aff<C> a, int lane) {
-    a = row16_incl1<FWD>(a);
-    const int row = lane >> 4;
-    Aff<C> pre = aff_id<C>();
-    if (FWD) {
-        // prefix of the rows below: S_1 = T_0, S_2 = T_1 o T_0, S_3 = T_2 o T_1 o T_0
-        const Aff<C> t0 = readlane_aff(a, 15), t1 = readlane_aff(a, 31), t2 = readlane_aff(a, 47);
-        const Aff<C> s2 = compose(t1, t0), s3 = compose(t2, s2);
-        if (row == 1) pre = t0;
-        if (row == 2) pre = s2;
-        if (row == 3) pre = s3;
-    } else {
-        const Aff<C> t1 = readlane_aff(a, 16), t2 = readlane_aff(a, 32), t3 = readlane_aff(a, 48);
-        const Aff<C> s1 = compose(t2, t3), s0 = compose(t1, s1);
-        if (row == 0) pre = s0;
-        if (row == 1) pre = s1;
-        if (row == 2) pre = t3;
-    }
-    return compose(a, pre);
+    Aff<C> b[1] = {a};
+    wave_incl<FWD, 1>(b, lane);
+    return b[0];
 }
 
 // Exclusive scan over the G = 64 * nw threads of one row (thread t = 64 w +
