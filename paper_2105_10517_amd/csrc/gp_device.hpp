@@ -68,6 +68,15 @@ template <typename T> struct LineSet {
     const cx<T>* ae;     // [lines][2] : a, e of each line
     cx<T> bm1;           // diagonal minus one, b - 1 (same for every line of the set)
     int K;               // pivots tabulated before the limit
+    // Line-start correction of the solves that use the converged pivots from
+    // the first point on.  Those factor the matrix A_inf whose first diagonal
+    // entry is the limit pivot w instead of b: A = A_inf + (b - w) e0 e0^T, so
+    // (Sherman-Morrison) A^{-1} r = z - gc (z_0) g with z = A_inf^{-1} r,
+    // g = A_inf^{-1} e0 and gc = (b - w) / (1 + (b - w) g_0).  g decays like
+    // the pivots' transient; it is tabulated up to Kg points.
+    const cx<T>* g;      // [lines][Kg]
+    const cx<T>* gc;     // [lines]
+    int Kg;
 };
 
 template <typename T> __device__ inline Piv<T> piv_at(const LineSet<T>& ls, int line, int k) {

@@ -30,6 +30,9 @@ struct DirTable {
     bool dominant = true;
     void* d_piv = nullptr;
     void* d_ae = nullptr;
+    int Kg = 0;
+    void* d_g = nullptr;   // line-start correction vectors [lines][Kg]
+    void* d_gc = nullptr;  // and coefficients [lines]
 };
 
 struct ModeState {
@@ -123,6 +126,8 @@ struct HostDir {
     double decay = 0.0;
     bool dominant = true;
     std::vector<zd> A, E, W;
+    int Kg = 1;            // points of the line-start correction
+    std::vector<zd> G, GC; // [lines][Kg] and [lines]
 };
 
 // Round a complex coefficient to the storage precision T and back.
@@ -165,6 +170,35 @@ void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
         d.decay = std::max(d.decay, std::max(std::abs(a / wl), std::abs(e / wl)));
     }
     d.K = std::min(K, n);
+    // Line-start correction: g = A_inf^{-1} e0 on the n points of a line
+    // (Thomas with the limit pivots throughout), kept while |g_k| is above
+    // the rounding level of T relative to |g_0| (the same bound as the halo)
+    const double tolg = sizeof(T) == 8 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -32);
+    std::vector<std::vector<zd>> gl(lines);
+    int Kg = 1;
+    for (int l = 0; l < lines; ++l) {
+        const zd w = d.W[l], m = 1.0 / w, am = d.A[l] * m, cp = d.E[l] * m;
+        // y = L^{-1} e0 decays geometrically; past the point where it is far
+        // below the rounding level it is taken as zero (exact for short lines)
+        std::vector<zd> y(1, m);
+        while ((int)y.size() < n && std::abs(y.back()) > 1e-27 * std::abs(m)) y.push_back(-am * y.back());
+        const int M = (int)y.size();
+        std::vector<zd> g(M);
+        g[M - 1] = y[M - 1];
+        for (int k = M - 2; k >= 0; --k) g[k] = y[k] - cp * g[k + 1];
+        int kg = M;
+        while (kg > 1 && std::abs(g[kg - 1]) < tolg * std::abs(g[0])) --kg;
+        Kg = std::max(Kg, kg);
+        gl[l] = std::move(g);
+    }
+    d.Kg = Kg;
+    d.G.assign((size_t)lines * Kg, zd());
+    d.GC.assign(lines, zd());
+    for (int l = 0; l < lines; ++l) {
+        for (int k = 0; k < Kg && k < (int)gl[l].size(); ++k) d.G[(size_t)l * Kg + k] = gl[l][k];
+        const zd bw = d.b - d.W[l];
+        d.GC[l] = bw / (1.0 + bw * gl[l][0]);
+    }
 }
 
 template <typename T>
@@ -199,6 +233,17 @@ int upload_dir(gp_spin1* h, const HostDir& hd, DirTable& d) {
     if (e3 != hipSuccess) return hip_fail(h, e3, "pivot table upload");
     hipError_t e4 = hipMemcpy(d.d_ae, ae.data(), ae.size() * sizeof(gp::cx<T>), hipMemcpyHostToDevice);
     if (e4 != hipSuccess) return hip_fail(h, e4, "coefficient table upload");
+    d.Kg = hd.Kg;
+    std::vector<gp::cx<T>> g(hd.G.size()), gc(hd.GC.size());
+    for (size_t i = 0; i < g.size(); ++i) g[i] = to_dev<T>(hd.G[i]);
+    for (size_t i = 0; i < gc.size(); ++i) gc[i] = to_dev<T>(hd.GC[i]);
+    if (hipMalloc(&d.d_g, g.size() * sizeof(gp::cx<T>)) != hipSuccess ||
+        hipMalloc(&d.d_gc, gc.size() * sizeof(gp::cx<T>)) != hipSuccess)
+        return fail(h, GP_ENOMEM, "correction table allocation failed");
+    hipError_t e5 = hipMemcpy(d.d_g, g.data(), g.size() * sizeof(gp::cx<T>), hipMemcpyHostToDevice);
+    if (e5 != hipSuccess) return hip_fail(h, e5, "correction table upload");
+    hipError_t e6 = hipMemcpy(d.d_gc, gc.data(), gc.size() * sizeof(gp::cx<T>), hipMemcpyHostToDevice);
+    if (e6 != hipSuccess) return hip_fail(h, e6, "correction table upload");
     return GP_OK;
 }
 
@@ -209,6 +254,9 @@ gp::LineSet<T> lineset(const DirTable& d) {
     ls.ae = (const gp::cx<T>*)d.d_ae;
     ls.bm1 = to_dev<T>(d.bm1);
     ls.K = d.K;
+    ls.g = (const gp::cx<T>*)d.d_g;
+    ls.gc = (const gp::cx<T>*)d.d_gc;
+    ls.Kg = d.Kg;
     return ls;
 }
 
@@ -238,13 +286,22 @@ bool x_shape(int nx, int K, int& G, int& R) {
     return true;
 }
 
+// Whether the whole-row x sweep can run K points per thread: the row fits a
+// block, and where the three lines are solved together (K s <= 32 bytes,
+// s = sizeof(T)) the line-start correction of Kg points lies in the row's
+// first wave (the long-row path with K s > 32 takes the tabulated transient
+// pivots itself and needs no correction).
+bool x_shape_ok(int nx, int K, int Kg, size_t s, int& G, int& R) {
+    return x_shape(nx, K, G, R) && (s * K > 32 || Kg <= 64 * K);
+}
+
 // Default x shape before any tuning: the fewest points per thread (at least
 // two) that keep a row within 512 threads.
-int x_default_k(int nx) {
+int x_default_k(int nx, int Kg, size_t s) {
     for (int idx = 1; idx < gp::kNumXK; ++idx) {
         const int K = gp::xk_value(idx);
         int G, R;
-        if (x_shape(nx, K, G, R) && G <= 512) return K;
+        if (x_shape_ok(nx, K, Kg, s, G, R) && G <= 512) return K;
     }
     return 16;
 }
@@ -312,6 +369,8 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     if (hm.y.decay <= 0.0) hm.hh = 1;
     else if (hm.y.decay >= 1.0) hm.hh = 1 << 20;
     else hm.hh = (int)std::ceil(std::log(tolw) / std::log(hm.y.decay)) + 1;
+    // the first window must write every point the line-start correction touches
+    hm.hh = std::max(hm.hh, hm.y.Kg);
     hm.window = false;
     hm.h = 0;
     hm.L = 0;
@@ -326,10 +385,10 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
         }
     }
     // launch shapes requested in p, else the defaults (autotuning may replace them)
-    hm.xK = p.x_points > 0 ? p.x_points : x_default_k(p.nx);
+    hm.xK = p.x_points > 0 ? p.x_points : x_default_k(p.nx, hm.x.Kg, sizeof(T));
     x_shape(p.nx, hm.xK, hm.xG, hm.xR);
     // x windows: only when asked for (autotuning may also choose them)
-    hm.hhx = halo_for<T>(hm.x.decay);
+    hm.hhx = std::max(halo_for<T>(hm.x.decay), hm.x.Kg);
     hm.xwindow = false;
     hm.hx = hm.Lx = hm.xtile = 0;
     if (p.x_solver == GP_XSOLVER_WINDOW) {
@@ -426,6 +485,8 @@ size_t max_y_blocks(const gp_spin1_params& p, const ModeState& ms) {
 void free_dir(DirTable& d) {
     if (d.d_piv) (void)hipFree(d.d_piv);
     if (d.d_ae) (void)hipFree(d.d_ae);
+    if (d.d_g) (void)hipFree(d.d_g);
+    if (d.d_gc) (void)hipFree(d.d_gc);
     d.d_piv = d.d_ae = nullptr;
 }
 
@@ -573,7 +634,7 @@ int autotune_t(gp_spin1* h) {
             for (int idx = 0; idx < gp::kNumXK && rc == GP_OK; ++idx) {
                 const int K = gp::xk_value(idx);
                 int G, R;
-                if (!x_shape(p.nx, K, G, R)) continue;
+                if (!x_shape_ok(p.nx, K, ms.x.Kg, sizeof(T), G, R)) continue;
                 ms.xK = K; ms.xG = G; ms.xR = R;
                 float t = 0.f;
                 rc = pair(t);
@@ -644,12 +705,24 @@ int autotune_t(gp_spin1* h) {
         // other wrote on the same XCD), where the y sweep has windows
         if (rc == GP_OK && ms.window && p.block_order == GP_ORDER_AUTO) {
             const int kx = ms.xorder, ky = ms.yorder;
-            float tc = 0.f, tb = 0.f;
-            rc = pair(tc);
-            ms.xorder = 3;
-            ms.yorder = 3;
-            if (rc == GP_OK) rc = pair(tb);
-            if (rc != GP_OK || !(tb < tc)) { ms.xorder = kx; ms.yorder = ky; }
+            const bool kw = ms.xwindow;
+            float best = 0.f;
+            rc = pair(best);
+            int bx = kx, by = ky;
+            bool bw = kw;
+            // with the chosen x sweep, and (where windows won) with the fastest whole-row shape
+            for (int v = 0; v < 2 && rc == GP_OK; ++v) {
+                if (v == 1 && (!kw || p.x_solver == GP_XSOLVER_WINDOW)) continue;
+                ms.xwindow = v == 0 ? kw : false;
+                ms.xorder = 3;
+                ms.yorder = 3;
+                float tb = 0.f;
+                rc = pair(tb);
+                if (rc == GP_OK && tb < best) { best = tb; bx = 3; by = 3; bw = ms.xwindow; }
+            }
+            ms.xorder = bx;
+            ms.yorder = by;
+            ms.xwindow = bw;
         }
         ms.plan.x_points_per_thread = ms.xK;
         ms.plan.x_threads_per_row = ms.xG;
@@ -690,6 +763,10 @@ int create_t(gp_spin1* h) {
     for (int m = 0; m < 2; ++m) {
         int rc = build_mode<T>(h, h->mode[m], m == 1);
         if (rc) return rc;
+        int G, R;
+        if (p.x_points > 0 && !h->mode[m].xwindow &&
+            !x_shape_ok(p.nx, p.x_points, h->mode[m].x.Kg, sizeof(T), G, R))
+            return fail(h, GP_EUNSUPPORTED, "x_points too small for the line-start correction of these lines");
         if (p.x_solver == GP_XSOLVER_WINDOW && !h->mode[m].xwindow)
             return fail(h, GP_EUNSUPPORTED, "x windows asked for, but the decay of the x lines fits no window");
     }
@@ -980,8 +1057,12 @@ template <typename T>
 BatchShape batch_shape(const std::vector<gp_spin1*>& hs, bool imag) {
     BatchShape bs;
     int nxmax = 3;
-    for (gp_spin1* h : hs) nxmax = std::max(nxmax, h->p.nx);
-    bs.K = x_default_k(nxmax);
+    int kgmax = 1;
+    for (gp_spin1* h : hs) {
+        nxmax = std::max(nxmax, h->p.nx);
+        kgmax = std::max(kgmax, h->mode[imag].x.Kg);
+    }
+    bs.K = x_default_k(nxmax, kgmax, sizeof(T));
     int G, R;
     x_shape(nxmax, bs.K, G, R);
     bs.block = G;
@@ -1035,7 +1116,7 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
         int hh, L, G, R;
         // Strang slots need the y sweep's output substep, which the batched kernel does not carry
         const bool ok = h->p.split == GP_SPLIT_LIE && ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
-                        x_shape(h->p.nx, shape[im].K, G, R) && G <= shape[im].block;
+                        x_shape_ok(h->p.nx, shape[im].K, ms.x.Kg, sizeof(T), G, R) && G <= shape[im].block;
         if (ok) {
             grouped[im].push_back(s);
             maxn = std::max(maxn, nsteps[s]);

@@ -21,62 +21,19 @@ namespace gp {
 // of the block transfer maps across the threads sharing the lines; every
 // thread must reach them (they may contain barriers).
 //
-// Every point takes its pivots from PivSrc: zeros outside the line (which
-// cuts the carries at the line ends), the tabulated transient near the start
-// (from shared memory, staged by the caller, or from the global table), the
-// converged limit elsewhere.  One code path for all threads: no divergence
-// between the threads that hold the start of a line and the others.
+// Every point uses the converged pivots (kept in registers): that factors the
+// matrix A_inf whose first diagonal entry is the limit pivot instead of b.
+// The carries are cut at the line ends (the forward carry into point 0, the
+// backward carry into point n - 1), so the result is z = A_inf^{-1} r; the
+// caller turns it into A^{-1} r with line_start_fix (a rank-one correction
+// of the first LineSet::Kg points).  One code path for every thread: no
+// divergence between the threads that hold the start of a line and the rest.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG> __device__ inline cx<T> mul_bm1(cx<T> bm1, cx<T> u) {
     // b - 1 = alpha / dx^2: real in imaginary time, imaginary in real time
     return IMAG ? cscale(u, bm1.x) : cscale(ctimes_i(u), bm1.y);
 }
 template <typename C> __device__ inline C cneg(C a) { C z; z.x = -a.x; z.y = -a.y; return z; }
-
-// Where the pivots of (up to) three lines come from: line[q] is the line
-// index in the LineSet; the first kl entries of each line are staged in
-// shared memory (lds[q * kl + i]); the rest of the transient and the limit
-// are read from the LineSet table when a solve needs them.
-template <typename T> struct PivSrc {
-    const Piv<T>* lds;
-    int kl;
-    const Piv<T>* glob;
-    int K;
-    int line[3];
-};
-
-template <typename T>
-__device__ inline PivSrc<T> piv_src(const LineSet<T>& ls, int line0, const Piv<T>* lds, int kl) {
-    PivSrc<T> s;
-    s.lds = lds;
-    s.kl = kl;
-    s.glob = ls.piv;
-    s.K = ls.K;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) s.line[q] = line0 + q;
-    return s;
-}
-
-// Pivots of point i of one line: lim by value (kept in registers), the
-// transient entries from shared memory (tab, kl entries) or the global table
-// (row, K + 1 entries); zeros outside [0, n).
-template <bool LDSPIV, typename T>
-__device__ inline Piv<T> piv_pt(const Piv<T> lim, const Piv<T>* tab, int kl, const Piv<T>* row, int K, int i, int n) {
-    Piv<T> p = lim;
-    if (i < K) {
-        const int ii = i > 0 ? i : 0;
-        const Piv<T>* src = (LDSPIV && ii < kl) ? tab + ii : row + ii;
-        p.m = src->m;
-        p.am = src->am;
-        p.cp = src->cp;
-    }
-    if (i < 0 || i >= n) {
-        p.m = zero_c<cx<T>>();
-        p.am = zero_c<cx<T>>();
-        p.cp = zero_c<cx<T>>();
-    }
-    return p;
-}
 
 // Per-line coefficients of a solve: sub- and super-diagonal (a, e) and the
 // converged pivots.  Loaded by the caller, so that a kernel can issue these
@@ -85,14 +42,14 @@ template <typename T> struct LineCoef {
     cx<T> a, e;
     Piv<T> lim;
 };
-template <typename T, int NQ, int Q0>
-__device__ inline void line_coefs(const LineSet<T>& ls, const PivSrc<T>& ps, LineCoef<T> (&cf)[NQ]) {
+template <typename T, int NQ>
+__device__ inline void line_coefs(const LineSet<T>& ls, int line0, LineCoef<T> (&cf)[NQ]) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        const int line = ps.line[Q0 + q];
+        const int line = line0 + q;
         cf[q].a = ls.ae[2 * line];
         cf[q].e = ls.ae[2 * line + 1];
-        cf[q].lim = ps.glob[(size_t)line * (ps.K + 1) + ps.K];
+        cf[q].lim = ls.piv[(size_t)line * (ls.K + 1) + ls.K];
     }
 }
 
@@ -106,34 +63,21 @@ template <typename C, int K> __device__ inline C cpow_k(C a) {
     return r;
 }
 
-// Q0: first of the NQ lines within the PivSrc (0 .. 3 - NQ); LDSPIV: take the
-// staged transient from shared memory (else from the global table).  Threads whose K
-// points all lie inside the line and past the pivots' transient take the
-// fast path (the converged pivots, kept in registers, and closed-form block
-// powers); the others (the start and the ragged end of a line, window
-// padding) take pivots point by point.
-template <typename T, int K, bool IMAG, int NQ, int Q0, bool LDSPIV, typename FS, typename BS>
+// dk: the increment at the thread's point kpick (the caller's index of line
+// point 0, for the line-start correction; kpick < 0: none).
+template <typename T, int K, bool IMAG, int NQ, typename FS, typename BS>
 __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], const cx<T> (&right)[NQ],
-                                   const LineSet<T>& ls, const PivSrc<T>& ps, const LineCoef<T> (&cf)[NQ], int i0,
-                                   int n, FS fscan, BS bscan) {
+                                   const LineSet<T>& ls, const LineCoef<T> (&cf)[NQ], int i0, int n, FS fscan,
+                                   BS bscan, int kpick, cx<T> (&dk)[NQ]) {
     using C = cx<T>;
-    C a[NQ], e[NQ], nam[NQ], ncp[NQ], lm[NQ];
-    Piv<T> lim[NQ];
-    const Piv<T>* tab[NQ];
-    const Piv<T>* row[NQ];
+    C nam[NQ], ncp[NQ], lm[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-        a[q] = cf[q].a;
-        e[q] = cf[q].e;
-        lim[q] = cf[q].lim;
-        lm[q] = lim[q].m;
-        nam[q] = cneg(lim[q].am);
-        ncp[q] = cneg(lim[q].cp);
-        tab[q] = ps.lds + (Q0 + q) * ps.kl;
-        row[q] = ps.glob + (size_t)ps.line[Q0 + q] * (ps.K + 1);
+        lm[q] = cf[q].lim.m;
+        nam[q] = cneg(cf[q].lim.am);
+        ncp[q] = cneg(cf[q].lim.cp);
+        dk[q] = zero_c<C>();
     }
-    const int kl = ps.kl, KP = ps.K;
-    const bool fast = i0 >= KP && i0 + K <= n;
     // right-hand side of the increment system: r = -2 ((b - 1) u_k + a u_{k-1} + e u_{k+1})
     C r[NQ][K];
 #pragma unroll
@@ -143,37 +87,25 @@ __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], c
             const C um = (k == 0) ? left[q] : u[q][k - 1];
             const C up = (k == K - 1) ? right[q] : u[q][k + 1];
             C t = mul_bm1<T, IMAG>(ls.bm1, u[q][k]);
-            t = cfma(um, a[q], t);
-            t = cfma(up, e[q], t);
+            t = cfma(um, cf[q].a, t);
+            t = cfma(up, cf[q].e, t);
             r[q][k] = cscale(t, (T)-2);
         }
-    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1}
+    // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1};
+    // points i <= 0 take no carry (the line starts at 0)
     C E[NQ], P[NQ], din[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) E[q] = zero_c<C>();
-    if (fast) {
+    for (int q = 0; q < NQ; ++q) { E[q] = zero_c<C>(); P[q] = one_c<C>(); }
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+    for (int k = 0; k < K; ++k) {
+        const bool cut = i0 + k <= 0;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                E[q] = cfma(E[q], nam[q], cmul(lm[q], r[q][k]));
-                r[q][k] = E[q];
-            }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) P[q] = cpow_k<C, K>(nam[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) P[q] = one_c<C>();
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const Piv<T> p = piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n);
-                const C na = cneg(p.am);
-                E[q] = cfma(E[q], na, cmul(p.m, r[q][k]));
-                P[q] = cmul(na, P[q]);
-                r[q][k] = E[q];
-            }
+        for (int q = 0; q < NQ; ++q) {
+            const C na = cut ? zero_c<C>() : nam[q];
+            E[q] = cfma(E[q], na, cmul(lm[q], r[q][k]));
+            P[q] = cmul(P[q], na);
+            r[q][k] = E[q];
+        }
     }
     fscan(P, E, din);
     // add the carry that enters the block, times the running product of -am
@@ -181,108 +113,117 @@ __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], c
         C Q[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) Q[q] = one_c<C>();
-        if (fast) {
 #pragma unroll
-            for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+            const bool cut = i0 + k <= 0;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    Q[q] = cmul(Q[q], nam[q]);
-                    r[q][k] = cfma(din[q], Q[q], r[q][k]);
-                }
-        } else {
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    Q[q] = cmul(Q[q], cneg(piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n).am));
-                    r[q][k] = cfma(din[q], Q[q], r[q][k]);
-                }
+            for (int q = 0; q < NQ; ++q) {
+                Q[q] = cmul(Q[q], cut ? zero_c<C>() : nam[q]);
+                r[q][k] = cfma(din[q], Q[q], r[q][k]);
+            }
         }
     }
-    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1}
+    // back substitution over the block from a zero carry: G_k = r_k - cp G_{k+1};
+    // points i >= n - 1 take no carry (the line ends at n - 1)
     C G[NQ], R[NQ], xin[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) G[q] = zero_c<C>();
-    if (fast) {
+    for (int q = 0; q < NQ; ++q) { G[q] = zero_c<C>(); R[q] = one_c<C>(); }
 #pragma unroll
-        for (int k = K - 1; k >= 0; --k)
+    for (int k = K - 1; k >= 0; --k) {
+        const bool cut = i0 + k >= n - 1;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                G[q] = cfma(G[q], ncp[q], r[q][k]);
-                r[q][k] = G[q];
-            }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) R[q] = cpow_k<C, K>(ncp[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) R[q] = one_c<C>();
-#pragma unroll
-        for (int k = K - 1; k >= 0; --k)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                const C nc = cneg(piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n).cp);
-                G[q] = cfma(G[q], nc, r[q][k]);
-                R[q] = cmul(nc, R[q]);
-                r[q][k] = G[q];
-            }
+        for (int q = 0; q < NQ; ++q) {
+            const C nc = cut ? zero_c<C>() : ncp[q];
+            G[q] = cfma(G[q], nc, r[q][k]);
+            R[q] = cmul(nc, R[q]);
+            r[q][k] = G[q];
+        }
     }
     bscan(R, G, xin);
     {
         C Sx[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) Sx[q] = one_c<C>();
-        if (fast) {
 #pragma unroll
-            for (int k = K - 1; k >= 0; --k)
+        for (int k = K - 1; k >= 0; --k) {
+            const bool cut = i0 + k >= n - 1;
 #pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    Sx[q] = cmul(Sx[q], ncp[q]);
-                    u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
-                }
-        } else {
-#pragma unroll
-            for (int k = K - 1; k >= 0; --k)
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    Sx[q] = cmul(Sx[q], cneg(piv_pt<LDSPIV>(lim[q], tab[q], kl, row[q], KP, i0 + k, n).cp));
-                    u[q][k] = cadd(u[q][k], cfma(xin[q], Sx[q], r[q][k]));
-                }
+            for (int q = 0; q < NQ; ++q) {
+                Sx[q] = cmul(Sx[q], cut ? zero_c<C>() : ncp[q]);
+                const C d = cfma(xin[q], Sx[q], r[q][k]);
+                if (k == kpick) dk[q] = d;
+                u[q][k] = cadd(u[q][k], d);
+            }
         }
     }
 }
 
+
+// Line-start correction (Sherman-Morrison, see LineSet): the points
+// i0 .. i0 + K - 1 of line `line` lose gc d0 g_i, d0 being the increment the
+// solve gave line point 0.
+template <typename T, int K>
+__device__ inline void line_start_fix(cx<T> (&u)[K], const LineSet<T>& ls, int line, cx<T> d0, int i0) {
+    if (i0 >= ls.Kg || i0 + K <= 0) return;
+    const cx<T> f = cmul(ls.gc[line], d0);
+    const cx<T>* g = ls.g + (size_t)line * ls.Kg;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = i0 + k;
+        if (i >= 0 && i < ls.Kg) u[k] = csub(u[k], cmul(f, g[i]));
+    }
+}
+
 // The three eigen-lines of a window held by a DPP row of 16 lanes (K points
-// per lane), solved interleaved through one scan per direction, or (SEQ) one
-// line after another.  The scheduling barriers keep the compiler from
-// re-interleaving the sequential solves, which would undo the register saving.
+// per lane, lines line0 .. line0 + 2 of the LineSet), solved interleaved
+// through one scan per direction, or (SEQ) one line after another.  The
+// scheduling barriers keep the compiler from re-interleaving the sequential
+// solves, which would undo the register saving.  first: the window holds line
+// point 0 (in segment seg0, at point k0 of that lane); then the line-start
+// correction is applied with the increment at that point, gathered from its
+// lane of the DPP row (every lane of the wave takes part in the gather).
 template <typename T, int K, bool IMAG, int Q>
 __device__ inline void window_line(cx<T> (&u)[3][K], const cx<T> (&lf)[3], const cx<T> (&rg)[3],
-                                   const LineSet<T>& ls, const PivSrc<T>& ps, int i0, int n) {
+                                   const LineSet<T>& ls, int line0, int i0, int n, int k0, cx<T> (&d)[3]) {
     using C = cx<T>;
     auto fs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<true, 1>(P, E, o); };
     auto bs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<false, 1>(P, E, o); };
     const C l1[1] = {lf[Q]}, r1[1] = {rg[Q]};
     LineCoef<T> cf[1];
-    line_coefs<T, 1, Q>(ls, ps, cf);
-    block_solve<T, K, IMAG, 1, Q, true>(reinterpret_cast<C (&)[1][K]>(u[Q]), l1, r1, ls, ps, cf, i0, n, fs, bs);
+    line_coefs<T, 1>(ls, line0 + Q, cf);
+    C d1[1];
+    block_solve<T, K, IMAG, 1>(reinterpret_cast<C (&)[1][K]>(u[Q]), l1, r1, ls, cf, i0, n, fs, bs, k0, d1);
+    d[Q] = d1[0];
 }
 
 template <typename T, int K, bool IMAG, bool SEQ>
 __device__ inline void window_solve(cx<T> (&u)[3][K], const cx<T> (&lf)[3], const cx<T> (&rg)[3],
-                                    const LineSet<T>& ls, const PivSrc<T>& ps, int i0, int n) {
+                                    const LineSet<T>& ls, int line0, int i0, int n, bool first, int seg0, int k0,
+                                    int lane) {
     using C = cx<T>;
+    C d[3];
+    const int kp = first ? k0 : -1;
     if constexpr (SEQ) {
-        window_line<T, K, IMAG, 0>(u, lf, rg, ls, ps, i0, n);
+        window_line<T, K, IMAG, 0>(u, lf, rg, ls, line0, i0, n, kp, d);
         __builtin_amdgcn_sched_barrier(0);
-        window_line<T, K, IMAG, 1>(u, lf, rg, ls, ps, i0, n);
+        window_line<T, K, IMAG, 1>(u, lf, rg, ls, line0, i0, n, kp, d);
         __builtin_amdgcn_sched_barrier(0);
-        window_line<T, K, IMAG, 2>(u, lf, rg, ls, ps, i0, n);
+        window_line<T, K, IMAG, 2>(u, lf, rg, ls, line0, i0, n, kp, d);
     } else {
         auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
         auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
         LineCoef<T> cf[3];
-        line_coefs<T, 3, 0>(ls, ps, cf);
-        block_solve<T, K, IMAG, 3, 0, true>(u, lf, rg, ls, ps, cf, i0, n, fs, bs);
+        line_coefs<T, 3>(ls, line0, cf);
+        block_solve<T, K, IMAG, 3>(u, lf, rg, ls, cf, i0, n, fs, bs, kp, d);
+    }
+    if (first) {
+        // the increment at line point 0, from lane seg0 of this DPP row
+        const int src = (lane & ~15) + seg0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const C d0 = bperm_c(d[q], src);
+            line_start_fix<T, K>(u[q], ls, line0 + q, d0, i0);
+        }
     }
 }
 

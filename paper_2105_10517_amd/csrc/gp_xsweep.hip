@@ -22,9 +22,6 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     // scan totals: [direction][line][P (16 waves) | E (16 waves)]
     __shared__ C shS[2 * 3 * 32];
     __shared__ C shN[2 * 3 * 16];
-    // the first pivots of the row's three lines (the transient near the line start)
-    constexpr int KL = 8;
-    __shared__ Piv<T> shT[8 * 3 * KL];
     const int tid = threadIdx.x;
     const int r = tid / G, t = tid - r * G;
     const int lane = t & 63, w = t >> 6, nw = G >> 6;
@@ -33,11 +30,6 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     const int nx = ph.nx;
     const int i0 = t * K;
     const int jl = row_ok ? j : 0;
-    const int kl = ls.K < KL ? ls.K : KL;
-    Piv<T>* tab = shT + (r < 8 ? r : 0) * 3 * KL;
-    if (r < 8)
-        for (int idx = t; idx < 3 * kl; idx += G)
-            tab[idx] = ls.piv[(size_t)(jl * 3 + idx / kl) * (ls.K + 1) + idx % kl];  // visible after the barrier below
     const size_t rowoff = (size_t)(row_ok ? j : 0) * nx;
     const C* rowp = src + rowoff;
     C* rowq = dst + rowoff;
@@ -56,7 +48,7 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     }
     // the lines' coefficients, loaded with the row (before the barriers below)
     LineCoef<T> cf[3];
-    line_coefs<T, 3, 0>(ls, piv_src(ls, jl * 3, tab, kl), cf);
+    line_coefs<T, 3>(ls, jl * 3, cf);
     if (SCALE) {
         double sc[3];
         if (nin.partials != nullptr) {
@@ -115,7 +107,6 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
         if (lane == 0) left[q] = (w > 0) ? shN[(nrow + w - 1) * 3 + q] : zero_c<C>();
         if (lane == 63) right[q] = (w + 1 < nw) ? shN[48 + (nrow + w + 1) * 3 + q] : zero_c<C>();
     }
-    const PivSrc<T> ps = piv_src(ls, jl * 3, tab, kl);
     if constexpr (sizeof(T) * K <= 32) {
         // the three lines' chains interleaved (fits the register file for small blocks)
         auto fs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) {
@@ -124,7 +115,15 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
         auto bs = [&](const C (&P)[3], const C (&E)[3], C (&o)[3]) {
             row_scan<false, 3>(P, E, o, lane, w, nw, ScanShm<C>{shS + 3 * 32 + nrow});
         };
-        block_solve<T, K, IMAG, 3, 0, true>(v, left, right, ls, ps, cf, i0, nx, fs, bs);
+        C d[3];
+        block_solve<T, K, IMAG, 3>(v, left, right, ls, cf, i0, nx, fs, bs, 0, d);
+        // line-start correction with the increment at point 0 (thread 0 of the row);
+        // the host keeps every corrected point in the row's first wave (Kg <= 64 K)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const C d0 = bperm_c(d[q], 0);  // lane 0 of this wave
+            if (w == 0) line_start_fix<T, K>(v[q], ls, jl * 3 + q, d0, i0);
+        }
     } else {
         // one line after the other
         C* sa = shS + nrow;
@@ -166,8 +165,6 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
                                 int rlo, int rhi) {
     using C = cx<T>;
     constexpr int RPB = 4 * NW;  // rows per block
-    constexpr int KL = 8;
-    __shared__ Piv<T> shT[RPB * 3 * KL];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane & 15, rw = lane >> 4;
     const int j = rt * RPB + wv * 4 + rw;
@@ -176,16 +173,6 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     const int i0 = cs * L;           // first point written by this window
     const int g0 = i0 - h + seg * KX;  // first point of this lane
     const int jl = row_ok ? j : 0;
-    // windows that reach the start of the rows stage the transient pivots (block-uniform branch)
-    const int kl = (i0 - h < ls.K) ? (ls.K < KL ? ls.K : KL) : 0;
-    if (kl > 0) {
-        for (int idx = threadIdx.x; idx < RPB * 3 * kl; idx += 64 * NW) {
-            const int rr = idx / (3 * kl), rem = idx - rr * 3 * kl;
-            const int row = rt * RPB + rr;
-            shT[idx] = ls.piv[(size_t)((row < ph.ny ? row : 0) * 3 + rem / kl) * (ls.K + 1) + rem % kl];
-        }
-        __syncthreads();
-    }
     const C* rowp = src + (size_t)jl * nx;
     C v[3][KX];
 #pragma unroll
@@ -221,8 +208,9 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
         lf[q] = dpp_c<0x111>(zero_c<C>(), v[q][KX - 1]);  // row_shr:1
         rg[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
     }
-    const PivSrc<T> ps = piv_src(ls, jl * 3, shT + (wv * 4 + rw) * 3 * kl, kl);
-    window_solve<T, KX, IMAG, SEQ>(v, lf, rg, ls, ps, g0, nx);
+    // the window holding point 0 of its rows applies the line-start correction
+    // (block-uniform: the first window of the rows, cs == 0)
+    window_solve<T, KX, IMAG, SEQ>(v, lf, rg, ls, jl * 3, g0, nx, i0 - h <= 0, h / KX, h % KX, lane);
 #pragma unroll
     for (int k = 0; k < KX; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
     C* rowq = dst + (size_t)jl * nx;
@@ -291,6 +279,8 @@ template <typename T, bool IMAG, bool LOCAL, bool SCALE>
 static hipError_t launch_x_k(int K, const cx<T>* src, cx<T>* dst, size_t sp, size_t dp, const Phys& ph, const LineSet<T>& ls,
                              const double* scale, NormIn nin, int G, int R, int bL, int bnrt, hipStream_t st,
                              hipEvent_t e0, hipEvent_t e1) {
+    // the line-start correction of the three-line path must lie in each row's first wave
+    if (sizeof(T) * K <= 32 && ls.Kg > 64 * K) return hipErrorInvalidValue;
     int nblk = (ph.ny + R - 1) / R;
     if (bL > 0) {
         if (bnrt <= 0 || (long)bL * bnrt < ph.ny) return hipErrorInvalidValue;

@@ -28,9 +28,7 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
                                 const LineSet<T>& ls, int L, int h, int ncs, NormOut no, int blk) {
     using C = cx<T>;
     constexpr int CPB = 4 * NW;  // columns per block
-    constexpr int KL = 8;
     __shared__ double shr[48];
-    __shared__ Piv<T> shT[CPB * 3 * KL];  // first pivots of the block's lines (windows at the column start)
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int seg = lane & 15, cw = lane >> 4;
     const int cs = blk % ncs, rt = blk / ncs;
@@ -39,16 +37,6 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     const int nx = ph.nx, ny = ph.ny;
     const int j0 = rt * L;
     const int g0 = j0 - h + seg * KY;  // first row of this lane
-    // windows that reach the start of the columns stage the transient pivots (block-uniform branch)
-    const int kl = (j0 - h < ls.K) ? (ls.K < KL ? ls.K : KL) : 0;
-    if (kl > 0) {
-        for (int idx = threadIdx.x; idx < CPB * 3 * kl; idx += 64 * NW) {
-            const int c = idx / (3 * kl), rem = idx - c * 3 * kl;
-            const int col = cs * CPB + c;
-            shT[idx] = ls.piv[(size_t)((col < nx ? col : 0) * 3 + rem / kl) * (ls.K + 1) + rem % kl];
-        }
-        __syncthreads();
-    }
     C v[3][KY];
 #pragma unroll
     for (int k = 0; k < KY; ++k) {
@@ -68,8 +56,9 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
         dn[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
     }
     const int il = col_ok ? i : 0;
-    const PivSrc<T> ps = piv_src(ls, il * 3, shT + (wv * 4 + cw) * 3 * kl, kl);
-    window_solve<T, KY, IMAG, SEQ>(v, up, dn, ls, ps, g0, ny);
+    // the window holding row 0 of its columns applies the line-start correction
+    // (block-uniform: the first row tile, rt == 0)
+    window_solve<T, KY, IMAG, SEQ>(v, up, dn, ls, il * 3, g0, ny, j0 - h <= 0, h / KY, h % KY, lane);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     if (OUTL) {
