@@ -93,6 +93,8 @@ __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], c
         }
     // forward elimination over the block from a zero carry: E_k = m r_k - am E_{k-1};
     // points i <= 0 take no carry (the line starts at 0)
+    // (the block's product of -am: a running product for short blocks, fewer
+    // registers; closed-form powers for K >= 8, a shorter dependent chain)
     C E[NQ], P[NQ], din[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) { E[q] = zero_c<C>(); P[q] = one_c<C>(); }
@@ -103,9 +105,13 @@ __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], c
         for (int q = 0; q < NQ; ++q) {
             const C na = cut ? zero_c<C>() : nam[q];
             E[q] = cfma(E[q], na, cmul(lm[q], r[q][k]));
-            P[q] = cmul(P[q], na);
+            if constexpr (K < 8) P[q] = cmul(P[q], na);
             r[q][k] = E[q];
         }
+    }
+    if constexpr (K >= 8) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) P[q] = i0 <= 0 ? zero_c<C>() : cpow_k<C, K>(nam[q]);
     }
     fscan(P, E, din);
     // add the carry that enters the block, times the running product of -am
@@ -135,9 +141,13 @@ __device__ inline void block_solve(cx<T> (&u)[NQ][K], const cx<T> (&left)[NQ], c
         for (int q = 0; q < NQ; ++q) {
             const C nc = cut ? zero_c<C>() : ncp[q];
             G[q] = cfma(G[q], nc, r[q][k]);
-            R[q] = cmul(nc, R[q]);
+            if constexpr (K < 8) R[q] = cmul(nc, R[q]);
             r[q][k] = G[q];
         }
+    }
+    if constexpr (K >= 8) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) R[q] = i0 + K >= n ? zero_c<C>() : cpow_k<C, K>(ncp[q]);
     }
     bscan(R, G, xin);
     {
