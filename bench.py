@@ -128,17 +128,50 @@ def c2_initial_state(torch, binding, inputs):
 
 
 def cpu_baseline(p, psi0, seconds):
+    """The oracle on all host threads for about `seconds`, and on one thread
+    for a fifth of that."""
     import oracle
-    t0 = time.perf_counter()
-    psi = oracle.step(p, psi0, 1, False)
-    t1 = time.perf_counter() - t0
-    n = max(1, int(seconds / max(t1, 1e-6)))
-    t0 = time.perf_counter()
-    oracle.step(p, psi, n, False)
-    dt = time.perf_counter() - t0
-    return {"value": p["nx"] * p["ny"] * n / dt, "unit": UNIT, "cores": oracle.get_threads(), "kind": "oracle",
+    threads = oracle.get_threads()
+
+    def rate(budget):
+        t0 = time.perf_counter()
+        psi = oracle.step(p, psi0, 1, False)
+        t1 = time.perf_counter() - t0
+        n = max(1, int(budget / max(t1, 1e-6)))
+        t0 = time.perf_counter()
+        oracle.step(p, psi, n, False)
+        dt = time.perf_counter() - t0
+        return p["nx"] * p["ny"] * n / dt, n, dt
+
+    v, n, dt = rate(seconds)
+    oracle.set_threads(1)
+    v1, n1, dt1 = rate(seconds / 5)
+    oracle.set_threads(threads)
+    return {"value": v, "unit": UNIT, "cores": threads, "kind": "oracle",
             "sample": f"{n} real-time FP64 steps of the {p['nx']}x{p['ny']} workload (block-Thomas oracle, "
-                      f"{dt:.1f} s)"}
+                      f"{dt:.1f} s)",
+            "value_1_core": v1, "sample_1_core": f"{n1} steps on one thread ({dt1:.1f} s)"}
+
+
+def copy_rate(torch, nbytes, reps=50):
+    """Bytes moved per second by a plain device copy of nbytes (read + write),
+    the practical ceiling beside the 8 TB/s peak."""
+    a = torch.ones(nbytes // 16, dtype=torch.complex128, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+        a.copy_(b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+        a.copy_(b)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / (2 * reps)
+    del a, b
+    return 2 * nbytes / sec
 
 
 def batch_c4(torch, binding, inputs, nsteps):
@@ -250,6 +283,9 @@ def main():
         tim = kernel_timing(s, t, args.timing_steps, False)
         roof = kernel_roofline(tim, npts, prec)
         roof["traffic"] = traffic_for(roof, prec, False, s.plan(False), "c2_512")
+        cp = copy_rate(torch, 3 * npts * bytes_per_complex(prec))
+        roof["copy_GBps"] = round(cp / 1e9, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] * 1e9 / cp, 4)
         val = npts * args.steps / (ms / 1e3)
         step_bytes = 12 * bytes_per_complex(prec) * npts
         results[prec] = {"value": val, "ms_per_step": ms / args.steps, "roofline": roof,
@@ -275,6 +311,9 @@ def main():
             tim = kernel_timing(s, t, max(10, args.c3_steps // 5), True)
             roof = kernel_roofline(tim, n3, prec)
             roof["traffic"] = traffic_for(roof, prec, True, s.plan(True), "c3_4096")
+            cp = copy_rate(torch, 3 * n3 * bytes_per_complex(prec), reps=10)
+            roof["copy_GBps"] = round(cp / 1e9, 1)
+            roof["frac_of_copy"] = round(roof["achieved"] * 1e9 / cp, 4)
             val = n3 * args.c3_steps / (ms / 1e3)
             step_bytes = 12 * bytes_per_complex(prec) * n3
             c3[prec] = {"value": val, "ms_per_step": ms / args.c3_steps, "roofline": roof,
@@ -293,7 +332,8 @@ def main():
     cpu = None
     if args.cpu_seconds > 0:
         cpu = cpu_baseline(p, psi0, args.cpu_seconds)
-        log(f"[bench] CPU oracle baseline: {cpu['value']:.3e} pt-steps/s on {cpu['cores']} threads")
+        log(f"[bench] CPU oracle baseline: {cpu['value']:.3e} pt-steps/s on {cpu['cores']} threads, "
+            f"{cpu['value_1_core']:.3e} on one")
 
     r = results["fp64"]
     line = {
