@@ -186,53 +186,58 @@ __device__ inline void line_start_fix(cx<T> (&u)[K], const LineSet<T>& ls, int l
 
 // The three eigen-lines of a window held by a DPP row of 16 lanes (K points
 // per lane, lines line0 .. line0 + 2 of the LineSet), solved interleaved
-// through one scan per direction, or (SEQ) one line after another.  The
-// scheduling barriers keep the compiler from re-interleaving the sequential
-// solves, which would undo the register saving.  first: the window holds line
-// point 0 (in segment seg0, at point k0 of that lane); then the line-start
-// correction is applied with the increment at that point, gathered from its
-// lane of the DPP row (every lane of the wave takes part in the gather).
+// through one scan per direction, or (SEQ) one line after another, each with
+// its own segment neighbours and line-start correction (so that only one
+// line's extras are live at a time).  The scheduling barriers keep the
+// compiler from re-interleaving the sequential solves, which would undo the
+// register saving.  The points just before and after a lane's segment come
+// from the neighbouring lanes of the DPP row (zeros outside the window).
+// first: the window holds line point 0 (in segment seg0, at point k0 of that
+// lane); then the line-start correction is applied with the increment at that
+// point, gathered from its lane of the DPP row (every lane of the wave takes
+// part in the gather).
 template <typename T, int K, bool IMAG, int Q>
-__device__ inline void window_line(cx<T> (&u)[3][K], const cx<T> (&lf)[3], const cx<T> (&rg)[3],
-                                   const LineSet<T>& ls, int line0, int i0, int n, int k0, cx<T> (&d)[3]) {
+__device__ inline void window_line(cx<T> (&u)[3][K], const LineSet<T>& ls, int line0, int i0, int n, bool first,
+                                   int seg0, int k0, int lane) {
     using C = cx<T>;
     auto fs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<true, 1>(P, E, o); };
     auto bs = [](const C (&P)[1], const C (&E)[1], C (&o)[1]) { seg16_scan<false, 1>(P, E, o); };
-    const C l1[1] = {lf[Q]}, r1[1] = {rg[Q]};
+    const C l1[1] = {dpp_c<0x111>(zero_c<C>(), u[Q][K - 1])};  // row_shr:1
+    const C r1[1] = {dpp_c<0x101>(zero_c<C>(), u[Q][0])};      // row_shl:1
     LineCoef<T> cf[1];
     line_coefs<T, 1>(ls, line0 + Q, cf);
     C d1[1];
-    block_solve<T, K, IMAG, 1>(reinterpret_cast<C (&)[1][K]>(u[Q]), l1, r1, ls, cf, i0, n, fs, bs, k0, d1);
-    d[Q] = d1[0];
+    block_solve<T, K, IMAG, 1>(reinterpret_cast<C (&)[1][K]>(u[Q]), l1, r1, ls, cf, i0, n, fs, bs, first ? k0 : -1, d1);
+    if (first) line_start_fix<T, K>(u[Q], ls, line0 + Q, bperm_c(d1[0], (lane & ~15) + seg0), i0);
 }
 
 template <typename T, int K, bool IMAG, bool SEQ>
-__device__ inline void window_solve(cx<T> (&u)[3][K], const cx<T> (&lf)[3], const cx<T> (&rg)[3],
-                                    const LineSet<T>& ls, int line0, int i0, int n, bool first, int seg0, int k0,
-                                    int lane) {
+__device__ inline void window_solve(cx<T> (&u)[3][K], const LineSet<T>& ls, int line0, int i0, int n, bool first,
+                                    int seg0, int k0, int lane) {
     using C = cx<T>;
-    C d[3];
-    const int kp = first ? k0 : -1;
     if constexpr (SEQ) {
-        window_line<T, K, IMAG, 0>(u, lf, rg, ls, line0, i0, n, kp, d);
+        window_line<T, K, IMAG, 0>(u, ls, line0, i0, n, first, seg0, k0, lane);
         __builtin_amdgcn_sched_barrier(0);
-        window_line<T, K, IMAG, 1>(u, lf, rg, ls, line0, i0, n, kp, d);
+        window_line<T, K, IMAG, 1>(u, ls, line0, i0, n, first, seg0, k0, lane);
         __builtin_amdgcn_sched_barrier(0);
-        window_line<T, K, IMAG, 2>(u, lf, rg, ls, line0, i0, n, kp, d);
+        window_line<T, K, IMAG, 2>(u, ls, line0, i0, n, first, seg0, k0, lane);
     } else {
+        C lf[3], rg[3], d[3];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            lf[q] = dpp_c<0x111>(zero_c<C>(), u[q][K - 1]);  // row_shr:1
+            rg[q] = dpp_c<0x101>(zero_c<C>(), u[q][0]);       // row_shl:1
+        }
         auto fs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<true, 3>(P, E, o); };
         auto bs = [](const C (&P)[3], const C (&E)[3], C (&o)[3]) { seg16_scan<false, 3>(P, E, o); };
         LineCoef<T> cf[3];
         line_coefs<T, 3>(ls, line0, cf);
-        block_solve<T, K, IMAG, 3>(u, lf, rg, ls, cf, i0, n, fs, bs, kp, d);
-    }
-    if (first) {
-        // the increment at line point 0, from lane seg0 of this DPP row
-        const int src = (lane & ~15) + seg0;
+        block_solve<T, K, IMAG, 3>(u, lf, rg, ls, cf, i0, n, fs, bs, first ? k0 : -1, d);
+        if (first) {
+            // the increment at line point 0, from lane seg0 of this DPP row
+            const int src = (lane & ~15) + seg0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const C d0 = bperm_c(d[q], src);
-            line_start_fix<T, K>(u[q], ls, line0 + q, d0, i0);
+            for (int q = 0; q < 3; ++q) line_start_fix<T, K>(u[q], ls, line0 + q, bperm_c(d[q], src), i0);
         }
     }
 }

@@ -201,16 +201,9 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     }
 #pragma unroll
     for (int k = 0; k < KX; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
-    // points just left and right of this lane's segment (zeros outside the window)
-    C lf[3], rg[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        lf[q] = dpp_c<0x111>(zero_c<C>(), v[q][KX - 1]);  // row_shr:1
-        rg[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
-    }
     // the window holding point 0 of its rows applies the line-start correction
     // (block-uniform: the first window of the rows, cs == 0)
-    window_solve<T, KX, IMAG, SEQ>(v, lf, rg, ls, jl * 3, g0, nx, i0 - h <= 0, h / KX, h % KX, lane);
+    window_solve<T, KX, IMAG, SEQ>(v, ls, jl * 3, g0, nx, i0 - h <= 0, h / KX, h % KX, lane);
 #pragma unroll
     for (int k = 0; k < KX; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
     C* rowq = dst + (size_t)jl * nx;

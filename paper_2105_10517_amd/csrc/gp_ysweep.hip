@@ -48,17 +48,10 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     }
 #pragma unroll
     for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
-    // rows just above and below this lane's segment (zeros outside the window)
-    C up[3], dn[3];
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        up[q] = dpp_c<0x111>(zero_c<C>(), v[q][KY - 1]);  // row_shr:1
-        dn[q] = dpp_c<0x101>(zero_c<C>(), v[q][0]);       // row_shl:1
-    }
     const int il = col_ok ? i : 0;
     // the window holding row 0 of its columns applies the line-start correction
     // (block-uniform: the first row tile, rt == 0)
-    window_solve<T, KY, IMAG, SEQ>(v, up, dn, ls, il * 3, g0, ny, j0 - h <= 0, h / KY, h % KY, lane);
+    window_solve<T, KY, IMAG, SEQ>(v, ls, il * 3, g0, ny, j0 - h <= 0, h / KY, h % KY, lane);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     if (OUTL) {
