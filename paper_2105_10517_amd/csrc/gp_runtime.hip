@@ -554,10 +554,10 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
 
 // Mean duration in ms of `reps` launches of f() after two warm-up launches.
 template <typename F>
-int time_launches(gp_spin1* h, F f, int reps, float& ms) {
-    // two untimed launches, then three timed batches of at least ~0.5 ms each
-    // (the first batch sizes the others); the fastest batch counts, which
-    // keeps clock ramps and neighbours' noise out of the comparison
+int time_launches(gp_spin1* h, F f, int reps, float& ms, int batches = 3, float batch_ms = 0.5f) {
+    // two untimed launches, then timed batches of at least batch_ms each (the
+    // first batch sizes the others); the fastest batch counts, which keeps
+    // clock ramps and neighbours' noise out of the comparison
     hipEvent_t a, b;
     hipError_t e;
     if ((e = hipEventCreate(&a)) != hipSuccess) return hip_fail(h, e, "autotune");
@@ -566,7 +566,7 @@ int time_launches(gp_spin1* h, F f, int reps, float& ms) {
     for (int w = 0; w < 2 && rc == GP_OK; ++w)
         if ((e = f()) != hipSuccess) rc = hip_fail(h, e, "autotune launch");
     float best = 1e30f;
-    for (int batch = 0; batch < 3 && rc == GP_OK; ++batch) {
+    for (int batch = 0; batch < batches && rc == GP_OK; ++batch) {
         if ((e = hipEventRecord(a, h->stream)) != hipSuccess) { rc = hip_fail(h, e, "autotune"); break; }
         for (int r = 0; r < reps && rc == GP_OK; ++r)
             if ((e = f()) != hipSuccess) rc = hip_fail(h, e, "autotune launch");
@@ -579,7 +579,7 @@ int time_launches(gp_spin1* h, F f, int reps, float& ms) {
         }
         el /= reps;
         if (el < best) best = el;
-        if (batch == 0 && el > 0.f) reps = std::min(200, std::max(reps, (int)std::ceil(0.5f / el)));
+        if (batch == 0 && el > 0.f) reps = std::min(1000, std::max(reps, (int)std::ceil(batch_ms / el)));
     }
     ms = best;
     (void)hipEventDestroy(a);
@@ -620,13 +620,13 @@ int autotune_t(gp_spin1* h) {
         // every candidate is timed inside x + y pairs with the current choice
         // for the other sweep, as in a step: a sweep's speed depends on where
         // the previous kernel left its input (which L2, written back or not)
-        auto pair = [&](float& t) {
+        auto pair = [&](float& t, int batches = 3, float batch_ms = 0.5f) {
             const gp::XLaunch<T> xa = xlaunch<T>(h, tmp, h->d_work, imag, true, h->psp, h->wsp);
             const gp::YLaunch<T> ya = ylaunch<T>(h, h->d_work, tmp, imag, imag, h->wsp, h->psp);
             return time_launches(h, [&] {
                 const hipError_t ex = gp::launch_x<T>(xa, h->stream);
                 return ex != hipSuccess ? ex : gp::launch_y<T>(ya, h->stream);
-            }, reps, t);
+            }, reps, t, batches, batch_ms);
         };
         if (p.x_points == 0 && p.x_solver != GP_XSOLVER_WINDOW) {
             float best = 1e30f;
@@ -706,8 +706,9 @@ int autotune_t(gp_spin1* h) {
         if (rc == GP_OK && ms.window && p.block_order == GP_ORDER_AUTO) {
             const int kx = ms.xorder, ky = ms.yorder;
             const bool kw = ms.xwindow;
+            // (the final choice: longer measurements than the sweeps above)
             float best = 0.f;
-            rc = pair(best);
+            rc = pair(best, 5, 2.0f);
             int bx = kx, by = ky;
             bool bw = kw;
             // with the chosen x sweep, and (where windows won) with the fastest whole-row shape
@@ -717,7 +718,7 @@ int autotune_t(gp_spin1* h) {
                 ms.xorder = 3;
                 ms.yorder = 3;
                 float tb = 0.f;
-                rc = pair(tb);
+                rc = pair(tb, 5, 2.0f);
                 if (rc == GP_OK && tb < best) { best = tb; bx = 3; by = 3; bw = ms.xwindow; }
             }
             ms.xorder = bx;
