@@ -168,6 +168,23 @@ def test_block_orders_give_identical_results(precision):
         assert all(np.array_equal(out[0], o) for o in out[1:]), (imag, xs)
 
 
+@pytest.mark.parametrize("imag", [True, False])
+def test_slowly_decaying_rows(imag):
+    # the pivots' transient spans hundreds of points: the whole-row sweep takes a
+    # shape whose line-start correction fits (or the long-row path), and refuses
+    # a requested shape where it would not
+    p = all_couplings(2000, 5, 0.005, dt=0.01)
+    psi = inputs.random_state(2000, 5, seed=77)
+    s = binding.Solver(p)
+    t = dev(psi)
+    s.substep(t, binding.SUB_X, imag)
+    assert rel(host(t), oracle.sweep_x(p, psi, imag)) < 1e-12, s.plan(imag)
+    s.close()
+    with pytest.raises(binding.GPError) as ei:
+        binding.Solver(p, x_points=2)
+    assert ei.value.status == binding.GP_EUNSUPPORTED
+
+
 def test_x_windows_refused_when_the_decay_is_slow():
     p = all_couplings(2000, 5, 0.005, dt=0.01)
     with pytest.raises(binding.GPError) as ei:
