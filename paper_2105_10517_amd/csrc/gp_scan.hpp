@@ -62,19 +62,6 @@ template <typename C> __device__ inline Aff<C> bperm_aff(const Aff<C>& a, int sr
     return Aff<C>{bperm_c(a.P, src), bperm_c(a.E, src)};
 }
 
-__device__ inline float readlane_r(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
-__device__ inline double readlane_r(double v, int l) {
-    const long long x = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)x, l), hi = __builtin_amdgcn_readlane((int)(x >> 32), l);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-template <typename C> __device__ inline C readlane_c(C v, int l) {
-    C z; z.x = readlane_r(v.x, l); z.y = readlane_r(v.y, l); return z;
-}
-template <typename C> __device__ inline Aff<C> readlane_aff(const Aff<C>& a, int l) {
-    return Aff<C>{readlane_c(a.P, l), readlane_c(a.E, l)};
-}
-
 // Inclusive scans within each row of 16 lanes, NQ independent maps at once
 // (their lane moves and compositions interleave).  FWD: lane l holds
 // f_l o f_{l-1} o ... o f_{row start}; backward: f_l o f_{l+1} o ... o f_{row end}.
@@ -185,24 +172,8 @@ template <bool FWD, int NQ, typename C> __device__ inline void seg16_scan(const 
 
 // Single-map forms used by the long-row x sweep (one line at a time; the
 // trailing barrier lets the next line reuse shP / shE).
-// Inclusive scans within each row of 16 lanes.  FWD: lane l holds
-// f_l o f_{l-1} o ... o f_{row start}; backward: f_l o f_{l+1} o ... o f_{row end}.
-template <bool FWD, typename C> __device__ inline Aff<C> row16_incl1(Aff<C> a) {
-    if (FWD) {
-        a = compose(a, dpp_aff<0x111>(a));  // row_shr:1
-        a = compose(a, dpp_aff<0x112>(a));  // row_shr:2
-        a = compose(a, dpp_aff<0x114>(a));  // row_shr:4
-        a = compose(a, dpp_aff<0x118>(a));  // row_shr:8
-    } else {
-        a = compose(a, dpp_aff<0x101>(a));  // row_shl:1
-        a = compose(a, dpp_aff<0x102>(a));  // row_shl:2
-        a = compose(a, dpp_aff<0x104>(a));  // row_shl:4
-        a = compose(a, dpp_aff<0x108>(a));  // row_shl:8
-    }
-    return a;
-}
-
-// Inclusive scan over the 64 lanes of a wave (lane order forward or backward).
+// Inclusive scan of one map over the wave.  FWD: lane l holds
+// f_l o f_{l-1} o ... o f_0; backward: f_l o f_{l+1} o ... o f_63.
 template <bool FWD, typename C> __device__ inline Aff<C> wave_incl1(Aff<C> a, int lane) {
     Aff<C> b[1] = {a};
     wave_incl<FWD, 1>(b, lane);

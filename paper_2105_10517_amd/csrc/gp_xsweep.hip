@@ -155,9 +155,9 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 // window, each lane KX consecutive points; windows of 16 KX points overlap by
 // h points on each side and write their middle L = 16 KX - 2 h points, h such
 // that the carries dropped at the window ends have decayed below the rounding
-// level.  No shared-memory scans and no barriers (except the staging of the
-// transient pivots in windows at the row start); the local substep and the
-// pending scale are applied to every point loaded, halo included.
+// level.  No shared memory and no barriers; the windows at the row start
+// apply the line-start correction.  The local substep and the pending scale
+// are applied to every point loaded, halo included.
 // ---------------------------------------------------------------------------
 template <typename T, bool IMAG, int KX, int NW, bool SEQ, bool LOCAL, bool SCALE>
 __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp, const Phys& ph,
