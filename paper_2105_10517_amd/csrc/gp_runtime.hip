@@ -1116,8 +1116,19 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
         const ModeState& ms = h->mode[im];
         int hh, L, G, R;
         // Strang slots need the y sweep's output substep, which the batched kernel does not carry
-        const bool ok = h->p.split == GP_SPLIT_LIE && ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
-                        x_shape_ok(h->p.nx, shape[im].K, ms.x.Kg, sizeof(T), G, R) && G <= shape[im].block;
+        bool ok = h->p.split == GP_SPLIT_LIE && ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
+                  x_shape_ok(h->p.nx, shape[im].K, ms.x.Kg, sizeof(T), G, R) && G <= shape[im].block;
+        if (ok) {
+            // every block of a grouped condensate is named by a map entry with
+            // kMapShift bits of block index: larger condensates run alone
+            const gp::YTile yt = gp::ytile<T>(shape[im].tile);
+            const int64_t rb = std::max(1, std::min(8, shape[im].block / G));
+            const int64_t xb = (h->p.ny + rb - 1) / rb;
+            const int64_t yb = (int64_t)((h->p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((h->p.ny + L - 1) / L);
+            const int64_t sb = ((int64_t)3 * h->p.nx * h->p.ny + gp::kScaleChunk - 1) / gp::kScaleChunk;
+            const int64_t lim = (int64_t)gp::kMapMask + 1;
+            ok = xb <= lim && yb <= lim && sb <= lim;
+        }
         if (ok) {
             grouped[im].push_back(s);
             maxn = std::max(maxn, nsteps[s]);

@@ -181,3 +181,38 @@ def test_batch_scan_workload_sample():
         want = alone(ps[k], psi0[k], 20, "imag", "fp32", info, torch.complex64)
         assert same(ts[k].cpu(), want, "fp32")[0]
     b.close()
+
+
+def test_condensate_beyond_the_block_map_runs_alone():
+    # a 3 x 8.4M grid needs more x-sweep blocks (8 rows each) than the 20 bits of
+    # block index a batched map entry carries; the batch runs it on its own plan
+    small = inputs.params(48, 48, 0.3, dt=0.009, c0=20.0, c2=-1.0, gamma=0.4, eta=1, rabi=0.1, omega=0.3)
+    nx, ny = 3, 8_400_000
+    huge = inputs.params(nx, ny, 0.1, dt=5e-4, c0=10.0, c2=1.0, gamma=0.2, eta=-1, rabi=0.1)
+    assert (ny + 7) // 8 > (1 << 20)
+    if binding.plan_query(huge, True)["y_solver"] != binding.GP_YSOLVER_WINDOW:
+        pytest.skip("the tall grid does not window here")
+    # a Gaussian strip about the centre; zero elsewhere
+    psi = np.zeros((3, ny, nx), np.complex64)
+    j = np.arange(ny // 2 - 400, ny // 2 + 400)
+    y = (j - ny // 2) * 0.1
+    x = (np.arange(nx) - nx // 2) * 0.1
+    g = np.exp(-0.5 * (y[:, None] ** 2 + x[None, :] ** 2))
+    rng = np.random.default_rng(70)
+    for m, w in enumerate((0.25, 0.5, 0.25)):
+        psi[m, j, :] = np.sqrt(w) * g * np.exp(1j * rng.uniform(-np.pi, np.pi, g.shape))
+    psi /= np.sqrt((np.abs(psi.astype(np.complex128)) ** 2).sum() * 0.01)
+    b = binding.Batch([small, huge], "fp32")
+    ts = [dev(initial(small, 71), torch.complex64), torch.from_numpy(psi).cuda()]
+    b.step(ts, [3, 3], ["imag", "imag"])
+    b.sync()
+    info = b.info()
+    assert info["individual"] == 1 and info["grouped"] == 1
+    s = binding.Solver(huge, "fp32")
+    t = torch.from_numpy(psi).cuda()
+    s.step_imag(t, 3)
+    s.sync()
+    assert torch.equal(ts[1], t)  # the same kernels and plan: bit for bit
+    assert abs(s.observables(t)["norm_total"] - 1.0) < 1e-6
+    s.close()
+    b.close()
