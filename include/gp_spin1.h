@@ -54,7 +54,7 @@ typedef enum {
     GP_OK = 0,
     GP_EINVAL = -1,        /* bad argument: non-finite value, n < 3, d <= 0, dt <= 0, |eta| != 1, NULL */
     GP_EUNSTABLE = -2,     /* the requested propagation fails the create-time stability checks */
-    GP_ENOMEM = -3,        /* a device allocation failed */
+    GP_ENOMEM = -3,        /* a device or host allocation failed */
     GP_EHIP = -4,          /* a HIP runtime call failed; gp_spin1_last_error has the message */
     GP_ENONFINITE = -5,    /* a NaN or Inf was met in a norm or an observable */
     GP_EUNSUPPORTED = -6   /* a size or option this build does not handle */

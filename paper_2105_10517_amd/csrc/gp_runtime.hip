@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <thread>
 #include <vector>
@@ -990,7 +991,12 @@ int make_handle(const gp_spin1_params* p, hipStream_t st, gp_spin1** out) {
     if (std::isnan(h->p.y0)) h->p.y0 = -0.5 * h->p.ny * h->p.dy;
     h->stream = st;
     if (hipGetDevice(&h->device) != hipSuccess) { destroy_all(h); return GP_EHIP; }
-    rc = h->p.precision == GP_FP64 ? create_t<double>(h) : create_t<float>(h);
+    try {
+        rc = h->p.precision == GP_FP64 ? create_t<double>(h) : create_t<float>(h);
+    } catch (...) {
+        destroy_all(h);
+        throw;
+    }
     if (rc) { destroy_all(h); return rc; }
     *out = h;
     return GP_OK;
@@ -1413,12 +1419,42 @@ int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& c
     return GP_OK;
 }
 
+// No C++ exception leaves the library: a failed host allocation (tables,
+// launch maps, messages) becomes GP_ENOMEM, anything else GP_EUNSUPPORTED.
+// err: where the handle keeps its last message (nullable).
+template <typename F>
+int no_throw(F&& f, std::string* err = nullptr) noexcept {
+    int rc;
+    const char* what;
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        rc = GP_ENOMEM;
+        what = "host allocation failed";
+    } catch (const std::length_error&) {
+        rc = GP_ENOMEM;
+        what = "host allocation failed (size beyond a container's limit)";
+    } catch (...) {
+        rc = GP_EUNSUPPORTED;
+        what = "unexpected C++ exception";
+    }
+    if (err) {
+        try {
+            *err = what;
+        } catch (...) {
+        }
+    }
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
 
 int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out) {
-    return make_handle(p, (hipStream_t)hip_stream, out);
+    return no_throw([&]() -> int {
+        return make_handle(p, (hipStream_t)hip_stream, out);
+    });
 }
 
 int gp_spin1_destroy(gp_spin1_t* h) {
@@ -1428,42 +1464,52 @@ int gp_spin1_destroy(gp_spin1_t* h) {
 }
 
 int gp_spin1_step_imag(gp_spin1_t* h, void* psi, int64_t nsteps) {
-    if (!h) return GP_EINVAL;
-    if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
-    return h->p.precision == GP_FP64 ? steps_t<double>(h, psi, nsteps, true) : steps_t<float>(h, psi, nsteps, true);
+    return no_throw([&]() -> int {
+        if (!h) return GP_EINVAL;
+        if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
+        return h->p.precision == GP_FP64 ? steps_t<double>(h, psi, nsteps, true) : steps_t<float>(h, psi, nsteps, true);
+    }, h ? &h->err : nullptr);
 }
 
 int gp_spin1_step_real(gp_spin1_t* h, void* psi, int64_t nsteps) {
-    if (!h) return GP_EINVAL;
-    if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
-    return h->p.precision == GP_FP64 ? steps_t<double>(h, psi, nsteps, false) : steps_t<float>(h, psi, nsteps, false);
+    return no_throw([&]() -> int {
+        if (!h) return GP_EINVAL;
+        if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
+        return h->p.precision == GP_FP64 ? steps_t<double>(h, psi, nsteps, false) : steps_t<float>(h, psi, nsteps, false);
+    }, h ? &h->err : nullptr);
 }
 
 int gp_spin1_substep(gp_spin1_t* h, void* psi, int32_t which, int32_t imag) {
-    if (!h) return GP_EINVAL;
-    if (!psi) return fail(h, GP_EINVAL, "psi is NULL");
-    return h->p.precision == GP_FP64 ? substep_t<double>(h, psi, which, imag != 0)
-                                     : substep_t<float>(h, psi, which, imag != 0);
+    return no_throw([&]() -> int {
+        if (!h) return GP_EINVAL;
+        if (!psi) return fail(h, GP_EINVAL, "psi is NULL");
+        return h->p.precision == GP_FP64 ? substep_t<double>(h, psi, which, imag != 0)
+                                         : substep_t<float>(h, psi, which, imag != 0);
+    }, h ? &h->err : nullptr);
 }
 
 int gp_spin1_observables(gp_spin1_t* h, const void* psi, gp_spin1_obs* out, void* dens) {
-    if (!h) return GP_EINVAL;
-    if (!psi || !out) return fail(h, GP_EINVAL, "psi or out is NULL");
-    return h->p.precision == GP_FP64 ? obs_t<double>(h, psi, out, dens) : obs_t<float>(h, psi, out, dens);
+    return no_throw([&]() -> int {
+        if (!h) return GP_EINVAL;
+        if (!psi || !out) return fail(h, GP_EINVAL, "psi or out is NULL");
+        return h->p.precision == GP_FP64 ? obs_t<double>(h, psi, out, dens) : obs_t<float>(h, psi, out, dens);
+    }, h ? &h->err : nullptr);
 }
 
 int gp_spin1_sync(gp_spin1_t* h) {
-    if (!h) return GP_EINVAL;
-    hipError_t e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) return hip_fail(h, e, "sync");
-    int flag = 0;
-    if ((e = hipMemcpy(&flag, h->d_flag, sizeof flag, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(h, e, "flag read");
-    if (flag) {
-        const int zero = 0;
-        if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "flag clear");
-        return fail(h, GP_ENONFINITE, "an imaginary-time norm was not finite");
-    }
-    return GP_OK;
+    return no_throw([&]() -> int {
+        if (!h) return GP_EINVAL;
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return hip_fail(h, e, "sync");
+        int flag = 0;
+        if ((e = hipMemcpy(&flag, h->d_flag, sizeof flag, hipMemcpyDeviceToHost)) != hipSuccess) return hip_fail(h, e, "flag read");
+        if (flag) {
+            const int zero = 0;
+            if ((e = hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(h, e, "flag clear");
+            return fail(h, GP_ENONFINITE, "an imaginary-time norm was not finite");
+        }
+        return GP_OK;
+    }, h ? &h->err : nullptr);
 }
 
 int gp_spin1_get_plan(const gp_spin1_t* h, int32_t imag, gp_spin1_plan* out) {
@@ -1473,39 +1519,45 @@ int gp_spin1_get_plan(const gp_spin1_t* h, int32_t imag, gp_spin1_plan* out) {
 }
 
 int gp_spin1_plan_query(const gp_spin1_params* p, int32_t imag, gp_spin1_plan* out) {
-    if (!out) return GP_EINVAL;
-    std::string why;
-    int rc = validate(p, why);
-    if (rc) return rc;
-    gp_spin1_params q = *p;
-    if (std::isnan(q.x0)) q.x0 = -0.5 * q.nx * q.dx;
-    if (std::isnan(q.y0)) q.y0 = -0.5 * q.ny * q.dy;
-    HostMode hm;
-    if (q.precision == GP_FP64) {
-        host_mode<double>(q, imag != 0, hm);
-        fill_plan<double>(q, hm, out);
-    } else {
-        host_mode<float>(q, imag != 0, hm);
-        fill_plan<float>(q, hm, out);
-    }
-    return GP_OK;
+    return no_throw([&]() -> int {
+        if (!out) return GP_EINVAL;
+        std::string why;
+        int rc = validate(p, why);
+        if (rc) return rc;
+        gp_spin1_params q = *p;
+        if (std::isnan(q.x0)) q.x0 = -0.5 * q.nx * q.dx;
+        if (std::isnan(q.y0)) q.y0 = -0.5 * q.ny * q.dy;
+        HostMode hm;
+        if (q.precision == GP_FP64) {
+            host_mode<double>(q, imag != 0, hm);
+            fill_plan<double>(q, hm, out);
+        } else {
+            host_mode<float>(q, imag != 0, hm);
+            fill_plan<float>(q, hm, out);
+        }
+        return GP_OK;
+    });
 }
 
 int gp_spin1_timing_enable(gp_spin1_t* h, int32_t enable) {
-    if (!h) return GP_EINVAL;
-    hipError_t e = timing_drain(h);
-    if (e != hipSuccess) return hip_fail(h, e, "timing");
-    h->timing = enable != 0;
-    for (int k = 0; k < 4; ++k) { h->t_launches[k] = 0; h->t_ms[k] = 0.0; }
-    return GP_OK;
+    return no_throw([&]() -> int {
+        if (!h) return GP_EINVAL;
+        hipError_t e = timing_drain(h);
+        if (e != hipSuccess) return hip_fail(h, e, "timing");
+        h->timing = enable != 0;
+        for (int k = 0; k < 4; ++k) { h->t_launches[k] = 0; h->t_ms[k] = 0.0; }
+        return GP_OK;
+    }, h ? &h->err : nullptr);
 }
 
 int gp_spin1_timing_read(gp_spin1_t* h, gp_spin1_timing* out) {
-    if (!h || !out) return GP_EINVAL;
-    hipError_t e = timing_drain(h);
-    if (e != hipSuccess) return hip_fail(h, e, "timing");
-    for (int k = 0; k < 4; ++k) { out->launches[k] = h->t_launches[k]; out->ms[k] = h->t_ms[k]; }
-    return GP_OK;
+    return no_throw([&]() -> int {
+        if (!h || !out) return GP_EINVAL;
+        hipError_t e = timing_drain(h);
+        if (e != hipSuccess) return hip_fail(h, e, "timing");
+        for (int k = 0; k < 4; ++k) { out->launches[k] = h->t_launches[k]; out->ms[k] = h->t_ms[k]; }
+        return GP_OK;
+    }, h ? &h->err : nullptr);
 }
 
 const char* gp_spin1_strerror(int status) {
@@ -1513,7 +1565,7 @@ const char* gp_spin1_strerror(int status) {
         case GP_OK: return "success";
         case GP_EINVAL: return "invalid argument";
         case GP_EUNSTABLE: return "parameters fail the stability checks for this propagation";
-        case GP_ENOMEM: return "device allocation failed";
+        case GP_ENOMEM: return "allocation failed (device or host memory)";
         case GP_EHIP: return "HIP runtime error";
         case GP_ENONFINITE: return "non-finite value";
         case GP_EUNSUPPORTED: return "unsupported size or option";
@@ -1528,74 +1580,89 @@ const char* gp_spin1_last_error(const gp_spin1_t* h) {
 
 
 int gp_spin1_batch_create(const gp_spin1_params* p, int32_t n, void* hip_stream, gp_spin1_batch_t** out) {
-    if (!out || !p || n < 1 || n > 65536) return GP_EINVAL;
-    for (int s = 1; s < n; ++s)
-        if (p[s].precision != p[0].precision) return GP_EINVAL;
-    if (p[0].precision != GP_FP64 && p[0].precision != GP_FP32) return GP_EINVAL;
-    gp_spin1_batch* b = new (std::nothrow) gp_spin1_batch();
-    if (!b) return GP_ENOMEM;
-    b->n = n;
-    b->precision = p[0].precision;
-    b->stream = (hipStream_t)hip_stream;
-    b->slot.assign(n, nullptr);
-    if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) { batch_free(b); return GP_EHIP; }
-    for (int s = 0; s < n; ++s) {
-        if (p[s].nx == 0) continue;  // empty slot
-        int rc = make_handle(&p[s], b->stream, &b->slot[s]);
-        if (rc) { batch_free(b); return rc; }
-    }
-    *out = b;
-    return GP_OK;
+    return no_throw([&]() -> int {
+        if (!out || !p || n < 1 || n > 65536) return GP_EINVAL;
+        for (int s = 1; s < n; ++s)
+            if (p[s].precision != p[0].precision) return GP_EINVAL;
+        if (p[0].precision != GP_FP64 && p[0].precision != GP_FP32) return GP_EINVAL;
+        gp_spin1_batch* b = new (std::nothrow) gp_spin1_batch();
+        if (!b) return GP_ENOMEM;
+        b->n = n;
+        b->precision = p[0].precision;
+        b->stream = (hipStream_t)hip_stream;
+        b->slot.assign(n, nullptr);
+        if (hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess) { batch_free(b); return GP_EHIP; }
+        try {
+            for (int s = 0; s < n; ++s) {
+                if (p[s].nx == 0) continue;  // empty slot
+                int rc = make_handle(&p[s], b->stream, &b->slot[s]);
+                if (rc) { batch_free(b); return rc; }
+            }
+        } catch (...) {
+            batch_free(b);
+            throw;
+        }
+        *out = b;
+        return GP_OK;
+    });
 }
 
 int gp_spin1_batch_set_slot(gp_spin1_batch_t* b, int32_t slot, const gp_spin1_params* p) {
-    if (!b) return GP_EINVAL;
-    if (slot < 0 || slot >= b->n) return bfail(b, GP_EINVAL, "slot out of range");
-    if (p && p->nx != 0 && p->precision != b->precision) return bfail(b, GP_EINVAL, "precision differs from the batch");
-    gp_spin1* h = nullptr;
-    if (p && p->nx != 0) {
-        int rc = make_handle(p, b->stream, &h);
-        if (rc) return bfail(b, rc, "slot " + std::to_string(slot) + ": invalid or unsupported parameters");
-    }
-    if (b->slot[slot]) {
-        // the stream may still use the old slot's tables
-        hipError_t e = hipStreamSynchronize(b->stream);
-        if (e != hipSuccess) {
-            if (h) destroy_all(h);
-            return bhip(b, e, "set_slot");
+    return no_throw([&]() -> int {
+        if (!b) return GP_EINVAL;
+        if (slot < 0 || slot >= b->n) return bfail(b, GP_EINVAL, "slot out of range");
+        if (p && p->nx != 0 && p->precision != b->precision) return bfail(b, GP_EINVAL, "precision differs from the batch");
+        gp_spin1* h = nullptr;
+        if (p && p->nx != 0) {
+            int rc = make_handle(p, b->stream, &h);
+            if (rc) return bfail(b, rc, "slot " + std::to_string(slot) + ": invalid or unsupported parameters");
         }
-        destroy_all(b->slot[slot]);
-    }
-    b->slot[slot] = h;
-    return GP_OK;
+        if (b->slot[slot]) {
+            // the stream may still use the old slot's tables
+            hipError_t e = hipStreamSynchronize(b->stream);
+            if (e != hipSuccess) {
+                if (h) destroy_all(h);
+                return bhip(b, e, "set_slot");
+            }
+            destroy_all(b->slot[slot]);
+        }
+        b->slot[slot] = h;
+        return GP_OK;
+    }, b ? &b->err : nullptr);
 }
 
 int gp_spin1_batch_step(gp_spin1_batch_t* b, void* const* psi_dev, const int64_t* nsteps, const int32_t* mode,
                         const uint8_t* active) {
-    if (!b) return GP_EINVAL;
-    if (!psi_dev || !nsteps || !mode) return bfail(b, GP_EINVAL, "psi_dev, nsteps and mode are required");
-    return b->precision == GP_FP64 ? batch_step_t<double>(b, psi_dev, nsteps, mode, active)
-                                   : batch_step_t<float>(b, psi_dev, nsteps, mode, active);
+    return no_throw([&]() -> int {
+        if (!b) return GP_EINVAL;
+        if (!psi_dev || !nsteps || !mode) return bfail(b, GP_EINVAL, "psi_dev, nsteps and mode are required");
+        return b->precision == GP_FP64 ? batch_step_t<double>(b, psi_dev, nsteps, mode, active)
+                                       : batch_step_t<float>(b, psi_dev, nsteps, mode, active);
+    }, b ? &b->err : nullptr);
 }
 
 int gp_spin1_batch_sync(gp_spin1_batch_t* b) {
-    if (!b) return GP_EINVAL;
-    hipError_t e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) return bhip(b, e, "sync");
-    for (int s = 0; s < b->n; ++s) {
-        if (!b->slot[s]) continue;
-        int rc = gp_spin1_sync(b->slot[s]);
-        if (rc) return bfail(b, rc, "slot " + std::to_string(s) + ": " + b->slot[s]->err);
-    }
-    return GP_OK;
+    return no_throw([&]() -> int {
+        if (!b) return GP_EINVAL;
+        hipError_t e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return bhip(b, e, "sync");
+        for (int s = 0; s < b->n; ++s) {
+            if (!b->slot[s]) continue;
+            int rc = gp_spin1_sync(b->slot[s]);
+            if (rc) return bfail(b, rc, "slot " + std::to_string(s) + ": " + b->slot[s]->err);
+        }
+        return GP_OK;
+    }, b ? &b->err : nullptr);
 }
 
 int gp_spin1_batch_observables(gp_spin1_batch_t* b, int32_t slot, const void* psi, gp_spin1_obs* out, void* dens) {
-    if (!b) return GP_EINVAL;
-    if (slot < 0 || slot >= b->n || !b->slot[slot]) return bfail(b, GP_EINVAL, "slot out of range or empty");
-    int rc = gp_spin1_observables(b->slot[slot], psi, out, dens);
-    if (rc) return bfail(b, rc, "slot " + std::to_string(slot) + ": " + b->slot[slot]->err);
-    return GP_OK;
+    return no_throw([&]() -> int {
+        if (!b) return GP_EINVAL;
+        if (slot < 0 || slot >= b->n || !b->slot[slot]) return bfail(b, GP_EINVAL, "slot out of range or empty");
+        int rc = gp_spin1_observables(b->slot[slot], psi, out, dens);
+        if (rc) return bfail(b, rc, "slot " + std::to_string(slot) + ": " + b->slot[slot]->err);
+        return GP_OK;
+    }, b ? &b->err : nullptr);
 }
 
 int gp_spin1_batch_info_read(const gp_spin1_batch_t* b, gp_spin1_batch_info* out) {
@@ -1618,15 +1685,17 @@ const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b) {
 
 int gp_spin1_serve(const gp_spin1_request* req, int32_t n, const gp_spin1_serve_config* cfg, void* hip_stream,
                    gp_spin1_request_result* out, gp_spin1_serve_stats* stats) {
-    if (!req || n < 1 || !cfg || !out || !stats) return GP_EINVAL;
-    if (cfg->max_slots < 1 || cfg->max_slots > gp::kMaxBatchSlots || !(cfg->hbm_budget_bytes > 0) ||
-        !(cfg->time_scale >= 0) || cfg->chunk_steps < 0)
-        return GP_EINVAL;
-    for (int k = 0; k < n; ++k) out[k].start = out[k].finish = -1.0;
-    std::string err;
-    const int rc = serve_run(req, n, *cfg, (hipStream_t)hip_stream, out, stats, err);
-    if (rc) std::fprintf(stderr, "gp_spin1_serve: %s\n", err.c_str());
-    return rc;
+    return no_throw([&]() -> int {
+        if (!req || n < 1 || !cfg || !out || !stats) return GP_EINVAL;
+        if (cfg->max_slots < 1 || cfg->max_slots > gp::kMaxBatchSlots || !(cfg->hbm_budget_bytes > 0) ||
+            !(cfg->time_scale >= 0) || cfg->chunk_steps < 0)
+            return GP_EINVAL;
+        for (int k = 0; k < n; ++k) out[k].start = out[k].finish = -1.0;
+        std::string err;
+        const int rc = serve_run(req, n, *cfg, (hipStream_t)hip_stream, out, stats, err);
+        if (rc) std::fprintf(stderr, "gp_spin1_serve: %s\n", err.c_str());
+        return rc;
+    });
 }
 
 }  // extern "C"

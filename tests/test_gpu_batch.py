@@ -184,14 +184,23 @@ def test_batch_scan_workload_sample():
 
 
 def test_condensate_beyond_the_block_map_runs_alone():
-    # a 3 x 8.4M grid needs more x-sweep blocks (8 rows each) than the 20 bits of
-    # block index a batched map entry carries; the batch runs it on its own plan
+    # a grouped condensate's blocks are named by map entries with 20 bits of
+    # block index; beside a 48-point-wide slot the x sweep takes one row per
+    # block, so 3 x 1.2M points need more blocks than that and run on their own
+    # plan, while the same shape 2000 rows tall is grouped
     small = inputs.params(48, 48, 0.3, dt=0.009, c0=20.0, c2=-1.0, gamma=0.4, eta=1, rabi=0.1, omega=0.3)
-    nx, ny = 3, 8_400_000
-    huge = inputs.params(nx, ny, 0.1, dt=5e-4, c0=10.0, c2=1.0, gamma=0.2, eta=-1, rabi=0.1)
-    assert (ny + 7) // 8 > (1 << 20)
+    nx, ny = 3, 1_200_000
+    kw = dict(dt=5e-4, c0=10.0, c2=1.0, gamma=0.2, eta=-1, rabi=0.1)
+    huge = inputs.params(nx, ny, 0.1, **kw)
+    short = inputs.params(nx, 2000, 0.1, **kw)
+    assert ny > (1 << 20)
     if binding.plan_query(huge, True)["y_solver"] != binding.GP_YSOLVER_WINDOW:
         pytest.skip("the tall grid does not window here")
+    b = binding.Batch([small, short], "fp32")
+    b.step([dev(initial(small, 71), torch.complex64), dev(initial(short, 72), torch.complex64)], [2, 2], ["imag", "imag"])
+    b.sync()
+    assert b.info()["grouped"] == 2
+    b.close()
     # a Gaussian strip about the centre; zero elsewhere
     psi = np.zeros((3, ny, nx), np.complex64)
     j = np.arange(ny // 2 - 400, ny // 2 + 400)
