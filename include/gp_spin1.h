@@ -252,8 +252,8 @@ const char* gp_spin1_last_error(const gp_spin1_t* h); /* per-handle message of t
  * gp_spin1_step_real; results equal those of a single handle created with
  * the batch's x_points and y_tile (gp_spin1_batch_info) bit for bit.
  *
- * gp_spin1_batch_create: p is an array of n parameter sets (n >= 1), one per
- *   slot; an entry with nx == 0 leaves its slot empty.  Every entry carries
+ * gp_spin1_batch_create: p is an array of n parameter sets (1 <= n <= 65536),
+ *   one per slot; an entry with nx == 0 leaves its slot empty.  Every entry carries
  *   the same precision.  Each slot owns the tables and scratch of a single
  *   handle (allocated here, freed by set_slot / destroy).  Work runs on
  *   hip_stream.  GP_EINVAL / GP_EUNSUPPORTED as gp_spin1_create.
@@ -264,8 +264,9 @@ const char* gp_spin1_last_error(const gp_spin1_t* h); /* per-handle message of t
  *   the layout above (complex128 / complex64 by the batch precision);
  *   nsteps[s] >= 0 steps in mode[s] (0 imaginary time, renormalised every
  *   step; 1 real time); active (nullable) masks slots out.  Slots whose
- *   windowed y sweep does not fit the batch tile run on their own, on the
- *   same stream.  Asynchronous like gp_spin1_step_*; psi_dev arrays may be
+ *   windowed y sweep does not fit the batch tile, that need more than 2^20
+ *   blocks in a sweep, or beyond the first 4096 of one mode, run on their
+ *   own, on the same stream.  Asynchronous like gp_spin1_step_*; psi_dev arrays may be
  *   reused as soon as the call returns.  Calls that overlap on one batch are
  *   not allowed (a batch is not thread-safe).
  * gp_spin1_batch_sync: waits for the stream; GP_ENONFINITE names the slot

@@ -1135,6 +1135,8 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
             const int64_t lim = (int64_t)gp::kMapMask + 1;
             ok = xb <= lim && yb <= lim && sb <= lim;
         }
+        // and the map names at most kMaxBatchSlots condensates per launch
+        if (ok && (int)grouped[im].size() >= gp::kMaxBatchSlots) ok = false;
         if (ok) {
             grouped[im].push_back(s);
             maxn = std::max(maxn, nsteps[s]);

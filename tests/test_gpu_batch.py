@@ -225,3 +225,28 @@ def test_condensate_beyond_the_block_map_runs_alone():
     assert abs(s.observables(t)["norm_total"] - 1.0) < 1e-6
     s.close()
     b.close()
+
+
+def test_more_condensates_than_one_launch_names():
+    # a launch's map names at most 4096 condensates; the rest of the batch run
+    # on their own plans
+    n = 4100
+    p = inputs.params(8, 8, 0.5, dt=0.02, c0=5.0, c2=0.5, gamma=0.3, eta=1, rabi=0.1)
+    b = binding.Batch([p] * n, "fp32")
+    psi = [initial(p, 80 + k % 7) for k in range(n)]
+    ts = [dev(a, torch.complex64) for a in psi]
+    b.step(ts, [2] * n, ["imag"] * n)
+    b.sync()
+    info = b.info()
+    assert info["grouped"] == 4096 and info["individual"] == n - 4096
+    for k in (0, 4095):
+        ok, err = same(ts[k].cpu(), alone(p, psi[k], 2, "imag", "fp32", info, torch.complex64), "fp32")
+        assert ok, f"slot {k}: relative L2 {err:.3e}"
+    s = binding.Solver(p, "fp32")
+    for k in (4096, n - 1):
+        t = dev(psi[k], torch.complex64)
+        s.step_imag(t, 2)
+        s.sync()
+        assert torch.equal(ts[k], t), k  # its own plan: bit for bit
+    s.close()
+    b.close()
