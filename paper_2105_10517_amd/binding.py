@@ -186,15 +186,17 @@ def plane_stride(p: dict) -> int:
     return int(p.get("plane_stride", 0)) or int(p["nx"]) * int(p["ny"])
 
 
-def check_psi(t, dtype, p: dict, what: str = "psi"):
+def check_psi(t, dtype, p: dict, what: str = "psi", device=None):
     """Device pointer of a (3, ny, nx) CUDA tensor whose rows are contiguous
     and whose planes are plane_stride(p) elements apart (contiguous when p
-    has no plane_stride)."""
+    has no plane_stride), on GPU `device` when given (the handle's)."""
     nx, ny = int(p["nx"]), int(p["ny"])
     if t.dtype != dtype or tuple(t.shape) != (3, ny, nx) or not t.is_cuda or \
             tuple(t.stride()) != (plane_stride(p), nx, 1):
         raise ValueError(f"{what} must be a CUDA {dtype} tensor of shape (3, {ny}, {nx}) with strides "
                          f"({plane_stride(p)}, {nx}, 1)")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{what} is on cuda:{t.device.index}, the handle on cuda:{device}")
     return t.data_ptr()
 
 
@@ -251,6 +253,7 @@ class Solver:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.device = torch.cuda.current_device()  # the handle's GPU (current at creation)
         self._h = ctypes.c_void_p()
         pp = make_params(p, precision, y_solver, x_points, y_tile, autotune, x_solver, block_order, x_tile)
         rc = self._lib.gp_spin1_create(ctypes.byref(pp), ctypes.c_void_p(stream.cuda_stream), ctypes.byref(self._h))
@@ -263,7 +266,7 @@ class Solver:
             raise GPError(rc, f"{what}: {self._lib.gp_spin1_strerror(rc).decode()}: {msg}")
 
     def _psi(self, psi):
-        return ctypes.c_void_p(check_psi(psi, self.dtype, self.params))
+        return ctypes.c_void_p(check_psi(psi, self.dtype, self.params, device=self.device))
 
     def step_imag(self, psi, nsteps: int):
         self._check(self._lib.gp_spin1_step_imag(self._h, self._psi(psi), int(nsteps)), "step_imag")
@@ -278,8 +281,10 @@ class Solver:
         o = Obs()
         dp = None
         if dens is not None:
-            if dens.dtype != self.real_dtype or tuple(dens.shape) != (3, self.ny, self.nx) or not dens.is_contiguous():
-                raise ValueError("dens must be a contiguous real tensor of shape (3, ny, nx) in the solver precision")
+            if dens.dtype != self.real_dtype or tuple(dens.shape) != (3, self.ny, self.nx) or not dens.is_contiguous() \
+                    or not dens.is_cuda or dens.device.index != self.device:
+                raise ValueError("dens must be a contiguous real CUDA tensor of shape (3, ny, nx) in the solver "
+                                 "precision, on the handle's device")
             dp = ctypes.c_void_p(dens.data_ptr())
         self._check(self._lib.gp_spin1_observables(self._h, self._psi(psi), ctypes.byref(o), dp), "observables")
         return _obs_dict(o)
@@ -335,6 +340,7 @@ class Batch:
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
+        self.device = torch.cuda.current_device()
         self.params = [dict(p) if p is not None else None for p in params]
         arr = (Params * self.n)(*[self._mk(p) for p in params])
         self._h = ctypes.c_void_p()
@@ -363,7 +369,7 @@ class Batch:
         p = self.params[slot]
         if p is None:
             return psi.data_ptr()  # the library reports the empty slot
-        return check_psi(psi, self.dtype, p, f"slot {slot}: psi")
+        return check_psi(psi, self.dtype, p, f"slot {slot}: psi", device=self.device)
 
     def step(self, psis, nsteps, modes, active=None):
         """psis[s]: tensor or None (slot skipped); nsteps[s] >= 0; modes[s] in

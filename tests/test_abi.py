@@ -181,3 +181,12 @@ def test_unit_helper_reproduces_the_printed_couplings():
             assert round(c2, c["c2_digits"]) == c["c2_printed"]
     # oscillator length of 87Rb in a 2 pi x 20 Hz trap: about 2.4 micrometres
     assert abs(units.oscillator_length(86.909 * 1.66053906660e-27, 2 * math.pi * 20.0) - 2.41e-6) < 0.02e-6
+
+
+def test_check_psi_refuses_host_and_misshaped_tensors():
+    torch = pytest.importorskip("torch")
+    p = {"nx": 8, "ny": 6}
+    with pytest.raises(ValueError):
+        binding.check_psi(torch.zeros((3, 6, 8), dtype=torch.complex128), torch.complex128, p)
+    with pytest.raises(ValueError):
+        binding.check_psi(torch.zeros((3, 8, 6), dtype=torch.complex128), torch.complex128, p)

@@ -375,6 +375,20 @@ def test_unstable_parameters_are_refused():
     assert ei.value.status == binding.GP_EUNSTABLE
 
 
+def test_host_buffers_are_refused_before_any_launch():
+    # the binding hands the library device pointers only
+    p = inputs.params(32, 24, 0.3, dt=0.01)
+    s = binding.Solver(p)
+    host = torch.zeros((3, 24, 32), dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        s.step_imag(host, 1)
+    t = dev(inputs.gaussian(32, 24, 0.3, 0.3, seed=1))
+    with pytest.raises(ValueError):
+        s.observables(t, torch.zeros((3, 24, 32), dtype=torch.float64))
+    s.observables(t, torch.zeros((3, 24, 32), dtype=torch.float64, device=DEV))
+    s.close()
+
+
 def test_nonfinite_is_reported():
     p = all_couplings(40, 40, 0.3)
     psi = inputs.gaussian(40, 40, 0.3, 0.3, seed=1)
