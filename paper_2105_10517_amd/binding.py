@@ -434,10 +434,11 @@ def serve(requests, precision: str = "fp32", max_slots: int = 64, hbm_budget_byt
     n = len(requests)
     arr = (Request * n)()
     dtype = torch.complex128 if precision == "fp64" else torch.complex64
+    device = torch.cuda.current_device()
     for k, r in enumerate(requests):
         p = r["params"]
         t = r["psi"]
-        ptr = check_psi(t, dtype, p, f"request {k}: psi")
+        ptr = check_psi(t, dtype, p, f"request {k}: psi", device=device)
         arr[k] = Request(float(r["arrival"]), make_params(p, precision), int(r["nsteps"]), MODES[r["mode"]],
                          ctypes.c_void_p(ptr))
     cfg = ServeConfig(int(max_slots), float(hbm_budget_bytes), int(chunk_steps), float(time_scale))
