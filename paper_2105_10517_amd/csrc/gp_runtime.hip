@@ -338,6 +338,24 @@ bool tile_window(int ny, int hh, int W, int& h, int& L) {
     return false;
 }
 
+// Row tile of the y windows as launched.  Under row bands (order 3) each XCD
+// owns a contiguous range of row tiles, and ny / L tiles rarely split evenly
+// over the 8 XCDs (512 rows of 42: 13 tiles, so some XCDs hold twice the
+// rows of others, in both sweeps).  There the tile shrinks to the height that
+// gives 8 m tiles, m = ceil(nrt / 8); the window keeps its span W, and the rows
+// it no longer writes widen its halo on both sides.
+void band_tile(int ny, int order, int W, int h, int L, int& hb, int& Lb) {
+    hb = h;
+    Lb = L;
+    if (order != 3 || ny <= W) return;
+    const int nrt = (ny + L - 1) / L;
+    const int m = (nrt + gp::kNumXcd - 1) / gp::kNumXcd;
+    const int Le = (ny + gp::kNumXcd * m - 1) / (gp::kNumXcd * m);
+    if (Le >= L) return;
+    Lb = Le;
+    hb = (W - Le) / 2;  // >= h, as Le < L = W - 2 h; the lower halo is W - Le - hb >= hb
+}
+
 template <typename T>
 void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     const zd alpha = imag ? zd(0.5 * p.dt, 0.0) : zd(0.0, 0.5 * p.dt);
@@ -425,9 +443,8 @@ void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out)
     out->x_threads_per_row = hm.xG;
     out->x_rows_per_block = hm.xR;
     out->y_solver = hm.window ? GP_YSOLVER_WINDOW : GP_YSOLVER_THOMAS;
-    out->y_halo = hm.h;
-    out->y_rows_out = hm.L;
     const gp::YTile yt = gp::ytile<T>(hm.ytile);
+    band_tile(p.ny, hm.window ? hm.yorder : 0, gp::ywindow(yt), hm.h, hm.L, out->y_halo, out->y_rows_out);
     out->y_tile = hm.ytile + 1;
     out->y_tile_cols = 4 * yt.NW;
     out->y_segments = 16;
@@ -478,7 +495,8 @@ size_t max_y_blocks(const gp_spin1_params& p, const ModeState& ms) {
         const gp::YTile yt = gp::ytile<T>(t);
         int h, L;
         if (!tile_window(p.ny, ms.hh, gp::ywindow(yt), h, L)) continue;
-        best = std::max(best, (size_t)((p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((p.ny + L - 1) / L));
+        // (+7: the row-band tiles, at most 8 ceil(nrt / 8) of them)
+        best = std::max(best, (size_t)((p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((p.ny + L - 1) / L + 7));
     }
     return best;
 }
@@ -740,8 +758,7 @@ int autotune_t(gp_spin1* h) {
         ms.plan.y_tile_cols = 4 * yt.NW;
         ms.plan.y_segments = 16;
         ms.plan.y_rows_per_thread = yt.KY;
-        ms.plan.y_halo = ms.h;
-        ms.plan.y_rows_out = ms.L;
+        band_tile(p.ny, ms.window ? ms.yorder : 0, gp::ywindow(yt), ms.h, ms.L, ms.plan.y_halo, ms.plan.y_rows_out);
     }
     const double one = 1.0;
     const int zero = 0;
@@ -818,8 +835,10 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.window = ms.xwindow; a.L = ms.Lx; a.h = ms.hx; a.tile = ms.xtile;
     a.order = ms.xorder;
     // row bands follow the y sweep's row tiles (none without y windows)
-    a.bL = ms.window ? ms.L : 0;
-    a.bnrt = ms.window ? (h->p.ny + ms.L - 1) / ms.L : 0;
+    int hb = 0, Lb = 0;
+    if (ms.window) band_tile(h->p.ny, ms.yorder, gp::ywindow(gp::ytile<T>(ms.ytile)), ms.h, ms.L, hb, Lb);
+    a.bL = Lb;
+    a.bnrt = ms.window ? (h->p.ny + Lb - 1) / Lb : 0;
     return a;
 }
 
@@ -833,6 +852,7 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.ls = lineset<T>(ms.y);
     a.no.partials = h->d_part;
     a.L = ms.L; a.h = ms.h; a.tile = ms.ytile;
+    if (ms.window) band_tile(h->p.ny, ms.yorder, gp::ywindow(gp::ytile<T>(ms.ytile)), ms.h, ms.L, a.h, a.L);
     a.window = ms.window; a.imag = imag; a.norm = norm;
     a.outl = false;
     a.order = ms.yorder;

@@ -190,3 +190,22 @@ def test_check_psi_refuses_host_and_misshaped_tensors():
         binding.check_psi(torch.zeros((3, 6, 8), dtype=torch.complex128), torch.complex128, p)
     with pytest.raises(ValueError):
         binding.check_psi(torch.zeros((3, 8, 6), dtype=torch.complex128), torch.complex128, p)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_row_band_tiles_split_evenly_over_the_xcds(precision):
+    # under row bands the y row tile shrinks so that the number of row tiles is
+    # a multiple of the 8 XCDs; the window span stays, the halo grows
+    for n in (512, 700, 2048):
+        p = inputs.params(n, n, 0.05, dt=1e-4, c0=200.0, c2=5.0, gamma=1.0, eta=-1, rabi=0.2, omega=0.9)
+        for imag in (False, True):
+            base = binding.plan_query(p, imag, precision=precision, block_order="hardware")
+            rows = binding.plan_query(p, imag, precision=precision, block_order="rows")
+            if base["y_solver"] != binding.GP_YSOLVER_WINDOW or base["y_rows_out"] >= n:
+                continue
+            nrt = -(-n // rows["y_rows_out"])
+            assert nrt % 8 == 0 or nrt < 8, (n, imag, rows["y_rows_out"])
+            assert rows["y_rows_out"] <= base["y_rows_out"] and rows["y_halo"] >= base["y_halo"]
+            span = 16 * rows["y_rows_per_thread"]
+            assert rows["y_halo"] + rows["y_rows_out"] <= span
+            assert span - rows["y_halo"] - rows["y_rows_out"] >= base["y_halo"]

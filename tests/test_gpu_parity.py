@@ -144,10 +144,12 @@ def test_x_windows_full_steps(imag, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_block_orders_give_identical_results(precision):
-    # the block order only changes which workgroup computes which window: the
-    # states, and the imaginary-time norm partials (stored per window and summed
-    # in window order), agree to the bit; 700 x 500 spans several windows in both
-    # directions and a ragged last window
+    # orders 0-2 only change which workgroup computes which window: the states,
+    # and the imaginary-time norm partials (stored per window and summed in
+    # window order), agree to the bit; row bands also shorten the y row tile so
+    # that the tiles split evenly over the XCDs (other window ends: agreement to
+    # rounding); 700 x 500 spans several windows in both directions and a
+    # ragged last window
     p = all_couplings(700, 500, 0.06, dy=0.05, dt=0.0015)
     psi0 = inputs.gaussian(700, 500, 0.06, 0.05, x0=p["x0"], y0=p["y0"], seed=16, center=(3.0, -2.0))
     for imag, xs in ((True, "window"), (False, "window"), (True, "scan"), (False, "scan")):
@@ -165,7 +167,9 @@ def test_block_orders_give_identical_results(precision):
             s.sync()
             out.append(host(t))
             s.close()
-        assert all(np.array_equal(out[0], o) for o in out[1:]), (imag, xs)
+        assert all(np.array_equal(out[0], o) for o in out[1:3]), (imag, xs)
+        err = np.linalg.norm(out[3] - out[0]) / np.linalg.norm(out[0])
+        assert err < (1e-13 if precision == "fp64" else 2e-6), (imag, xs, err)
 
 
 @pytest.mark.parametrize("imag", [True, False])
