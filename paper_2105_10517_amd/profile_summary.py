@@ -1,6 +1,6 @@
 """Text summaries of rocprofv3 output for ``profiles/``.
 
-    python3 paper_2105_10517_amd/profile_summary.py stats RUN_DIR --command "..." --out profiles/NAME.md
+    python3 paper_2105_10517_amd/profile_summary.py stats RUN_DIR [--last N] --command "..." --out profiles/NAME.md
     python3 paper_2105_10517_amd/profile_summary.py traffic --fetch DIR --write DIR --copy-fetch DIR \
         --copy-write DIR --copy-mib 512 --command "..." --out profiles/NAME.md
 
@@ -65,14 +65,43 @@ def counters(d: str, counter: str, last: int = 0) -> dict:
     return out
 
 
+def last_means(d: str, last: int) -> dict:
+    """Per kernel, from the kernel trace: its most frequent launch shape (grid
+    size; one workload's timed steps, as tuning candidates and other workloads
+    launch other shapes), that shape's dispatch count, and the mean duration in
+    us of its last `last` dispatches."""
+    acc = {}
+    for row in csv.DictReader(open(find(d, "kernel_trace.csv"))):
+        acc.setdefault(short(row["Kernel_Name"]), {}).setdefault(int(row["Grid_Size_X"]), []).append(
+            (int(row["Dispatch_Id"]), int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
+    out = {}
+    for k, shapes in acc.items():
+        grid, v = max(shapes.items(), key=lambda kv: len(kv[1]))
+        t = [x for _, x in sorted(v)][-last:]
+        out[k] = (grid, len(v), sum(t) / len(t) / 1e3)
+    return out
+
+
 def cmd_stats(a):
     rows = list(csv.DictReader(open(find(a.run_dir, "kernel_stats.csv"))))
+    tail = last_means(a.run_dir, a.last) if a.last else {}
     lines = [f"# Kernel durations: {a.title}", "", "Command:", "", "```", a.command, "```", "",
-             f"Kernel sources: `{kernel_source_hash()}`", "",
-             "| kernel | calls | mean us | min us | max us | share |", "|---|---:|---:|---:|---:|---:|"]
+             f"Kernel sources: `{kernel_source_hash()}`", ""]
+    if a.last:
+        lines += [f"Last columns: each kernel's most frequent launch shape (grid size in work-items), its "
+                  f"dispatches, and their mean over the last {a.last} (one workload's timed steps; tuning "
+                  f"candidates and other workloads launch other shapes).", ""]
+    lines += ["| kernel | calls | mean us | min us | max us | share |" + (
+              f" main grid | its calls | its last {a.last} mean us |" if a.last else ""),
+              "|---|---:|---:|---:|---:|---:|" + ("---:|---:|---:|" if a.last else "")]
     for r in rows:
-        lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
-                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}% |")
+        k = short(r["Name"])
+        extra = ""
+        if a.last:
+            extra = f" {tail[k][0]} | {tail[k][1]} | {tail[k][2]:.2f} |" if k in tail else " | | |"
+        lines.append(f"| `{k}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f}% |"
+                     + extra)
     open(a.out, "w").write("\n".join(lines) + "\n")
 
 
@@ -132,6 +161,7 @@ def main():
     s.add_argument("run_dir")
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="")
+    s.add_argument("--last", type=int, default=0, help="add each kernel's main launch shape and its mean over its last N dispatches")
     s.add_argument("--out", required=True)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy_fetch", "copy_write"):
