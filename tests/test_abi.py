@@ -209,3 +209,14 @@ def test_row_band_tiles_split_evenly_over_the_xcds(precision):
             span = 16 * rows["y_rows_per_thread"]
             assert rows["y_halo"] + rows["y_rows_out"] <= span
             assert span - rows["y_halo"] - rows["y_rows_out"] >= base["y_halo"]
+
+
+def test_size_limits():
+    # the longest row the whole-row x sweep holds on chip is 8192 points; a grid
+    # of more than 4e9 values (3 nx ny) is refused
+    ok = inputs.params(8192, 16, 0.01, dt=1e-5)
+    assert binding.plan_query(ok, True)["stable"] == 1
+    for nx, ny in ((8193, 16), (8192, 170000)):
+        with pytest.raises(binding.GPError) as ei:
+            binding.plan_query(inputs.params(nx, ny, 0.01, dt=1e-5), True)
+        assert ei.value.status == binding.GP_EUNSUPPORTED

@@ -68,7 +68,7 @@ def test_local_substep(imag):
 
 
 @pytest.mark.parametrize("imag", [True, False])
-@pytest.mark.parametrize("nx", [3, 53, 128, 130, 700, 1024, 1500, 4096, 5000])
+@pytest.mark.parametrize("nx", [3, 53, 128, 130, 700, 1024, 1500, 4096, 5000, 8192])
 def test_x_sweep(imag, nx):
     ny = 5
     p = all_couplings(nx, ny, 24.0 / nx + 0.001, dy=0.2, dt=0.004, eta=-1 if nx % 2 else 1)
@@ -377,6 +377,15 @@ def test_unstable_parameters_are_refused():
     with pytest.raises(binding.GPError) as ei:
         s.step_imag(t, 1)
     assert ei.value.status == binding.GP_EUNSTABLE
+
+
+@pytest.mark.parametrize("imag", [True, False])
+def test_longest_row_full_steps(imag):
+    # 8192-point rows (the longest the build holds) through whole steps
+    p = all_couplings(8192, 12, 0.0015, dy=0.3, dt=2e-5)
+    psi0 = inputs.random_state(8192, 12, seed=91, scale=0.4)
+    got, _ = gpu_run(p, psi0, 3, imag)
+    assert rel(got, oracle.step(p, psi0, 3, imag)) < 1e-12
 
 
 def test_host_buffers_are_refused_before_any_launch():
