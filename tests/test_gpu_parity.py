@@ -354,6 +354,17 @@ def test_c2_full_size_steps(precision):
     assert abs(s.observables(t)["norm_total"] - 1.0) < (1e-11 if precision == "fp64" else 1e-6)
 
 
+def test_c2_full_size_1000_steps():
+    # the bar of 1e-10 relative L2 after 1000 FP64 steps, on the full 512^2
+    # real-time workload in the benchmark's launch configuration (tuned shapes)
+    p = inputs.config_c2()
+    psi0 = inputs.add_noise(inputs.gaussian(512, 512, 0.05, 0.05, seed=2), 0.05, 0.05, 1e-3, seed=3)
+    got, obs = gpu_run(p, psi0, 1000, False, autotune=True)
+    want = oracle.step(p, psi0, 1000, False)
+    assert rel(got, want) < 1e-10
+    assert abs(obs["norm_total"] - 1.0) < 1e-12
+
+
 @pytest.mark.parametrize("n", [2048, 4096])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_c3_full_size_steps(precision, n):
