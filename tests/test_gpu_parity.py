@@ -399,6 +399,31 @@ def test_longest_row_full_steps(imag):
     assert rel(got, oracle.step(p, psi0, 3, imag)) < 1e-12
 
 
+def test_zero_steps_and_invalid_counts():
+    # zero steps leave psi untouched (imaginary time included: no pending scale
+    # is applied); negative counts and unknown substeps are refused
+    p = all_couplings(40, 30, 0.3, dt=0.01)
+    psi0 = inputs.gaussian(40, 30, 0.3, 0.3, seed=5)
+    s = binding.Solver(p)
+    for step in (s.step_imag, s.step_real):
+        t = dev(psi0)
+        step(t, 0)
+        s.sync()
+        assert np.array_equal(host(t), psi0)
+        with pytest.raises(binding.GPError) as ei:
+            step(t, -1)
+        assert ei.value.status == binding.GP_EINVAL
+    t = dev(psi0)
+    with pytest.raises(binding.GPError) as ei:
+        s.substep(t, 4, True)
+    assert ei.value.status == binding.GP_EINVAL
+    s.step_imag(t, 1)
+    one = host(t)
+    s.step_imag(t, 0)
+    assert np.array_equal(host(t), one)
+    s.close()
+
+
 def test_host_buffers_are_refused_before_any_launch():
     # the binding hands the library device pointers only
     p = inputs.params(32, 24, 0.3, dt=0.01)
