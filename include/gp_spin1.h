@@ -161,7 +161,7 @@ typedef struct {
     int32_t x_threads_per_row;   /* threads cooperating on one row                               */
     int32_t x_rows_per_block;
     int32_t y_solver;            /* GP_YSOLVER_WINDOW or GP_YSOLVER_THOMAS                        */
-    int32_t y_halo;              /* rows of overlap on each side of a y window                   */
+    int32_t y_halo;              /* rows read above a y window's output (at least as many below) */
     int32_t y_rows_out;          /* rows written per y window                                    */
     int32_t y_tile;              /* 1..8, the tile shape below (5..8: lines solved one at a time)  */
     int32_t y_tile_cols;         /* columns per y block (4 per wave)                              */
