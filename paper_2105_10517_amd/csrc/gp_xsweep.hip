@@ -14,7 +14,9 @@ namespace gp {
 
 // One block of the x sweep: rows row0 .. row0 + R - 1 below rlim of one
 // condensate, G threads per row (threads past G R idle through the barriers).
-template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE>
+// PF: load the line-start correction's factors before the solve (more
+// registers, no load at the end of the row's chain).
+template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, bool PF>
 __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp, const Phys& ph,
                               const LineSet<T>& ls, const double* __restrict__ scale, NormIn nin, int G, int R,
                               int row0, int rlim) {
@@ -91,6 +93,24 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    // the line-start correction's factors, loaded before the solve (wave 0
+    // holds every corrected point), so that the fix after it waits on no load
+    C gcf[3], gk[3][K];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        gcf[q] = zero_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) gk[q][k] = zero_c<C>();
+    }
+    if (PF && sizeof(T) * K <= 32 && w == 0 && i0 < ls.Kg) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            gcf[q] = ls.gc[jl * 3 + q];
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+                if (i0 + k < ls.Kg) gk[q][k] = ls.g[(size_t)(jl * 3 + q) * ls.Kg + i0 + k];
+        }
+    }
     // neighbours of the block ends for all three components (ghost zeros beyond the row)
     C left[3], right[3];
     const int nrow = r * nw;  // first wave of this row in the block
@@ -122,7 +142,16 @@ __device__ inline void x_rows(const cx<T>* __restrict__ src, cx<T>* __restrict__
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             const C d0 = bperm_c(d[q], 0);  // lane 0 of this wave
-            if (w == 0) line_start_fix<T, K>(v[q], ls, jl * 3 + q, d0, i0);
+            if (PF) {
+                if (w == 0 && i0 < ls.Kg) {
+                    const C f = cmul(gcf[q], d0);
+#pragma unroll
+                    for (int k = 0; k < K; ++k)
+                        if (i0 + k < ls.Kg) v[q][k] = csub(v[q][k], cmul(f, gk[q][k]));
+                }
+            } else if (w == 0) {
+                line_start_fix<T, K>(v[q], ls, jl * 3 + q, d0, i0);
+            }
         }
     } else {
         // one line after the other
@@ -254,14 +283,15 @@ __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx
         rlim = r1;
         if (row0 >= rlim) return;
     }
-    x_rows<T, IMAG, K, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, nin, G, R, row0, rlim);
+    x_rows<T, IMAG, K, LOCAL, SCALE, true>(src, dst, sp, dp, ph, ls, scale, nin, G, R, row0, rlim);
 }
 
 template <typename T, bool IMAG, int K, int LB>
 __global__ __launch_bounds__(LB) void k_x_batch(const XSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
     const XSlot<T>& s = slots[e >> kMapShift];
-    x_rows<T, IMAG, K, true, IMAG>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.scale, NormIn{nullptr, 0, 0.0, NormRule{0, 0.0}, nullptr},
+    // (many condensates fill the chip: the batch keeps the smaller register footprint)
+    x_rows<T, IMAG, K, true, IMAG, false>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.scale, NormIn{nullptr, 0, 0.0, NormRule{0, 0.0}, nullptr},
                                    s.G, s.R, (int)(e & kMapMask) * s.R, s.ph.ny);
 }
 
