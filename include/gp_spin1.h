@@ -148,7 +148,8 @@ typedef struct {
  *   grid, i.e. <psi| -grad^2/2 |psi>; e_int = 1/2 int (c0 rho^2 + c2 |F|^2));
  *   lz = <L_z> summed over components;
  *   mu[m] = Re <psi_m | (H psi)_m> / norm[m] with (H psi) the right-hand sides
- *   of Eqs. (S.1)-(S.2), mu_total = sum_m Re <psi_m|(H psi)_m> / norm_total. */
+ *   of Eqs. (S.1)-(S.2) (0 for a component whose norm is exactly 0),
+ *   mu_total = sum_m Re <psi_m|(H psi)_m> / norm_total. */
 typedef struct {
     double norm[3], norm_total, magnetization;
     double energy, e_kin, e_trap, e_int, e_rot, e_so, e_rabi, lz;

@@ -582,7 +582,8 @@ void orc_observables(const orc_params *p, const cplx *psi, orc_obs *o) {
     o->energy = o->e_kin + o->e_trap + o->e_int + o->e_rot + o->e_so + o->e_rabi;
     double hs = 0;
     for (int m = 0; m < 3; ++m) {
-        o->mu[m] = tot[Q_HM0 + m] / o->norm[m];
+        /* an empty component (N_m = 0) has no chemical potential of its own: 0 */
+        o->mu[m] = o->norm[m] > 0.0 ? tot[Q_HM0 + m] / o->norm[m] : 0.0;
         hs += tot[Q_HM0 + m];
     }
     o->mu_total = hs / o->norm_total;

@@ -207,6 +207,7 @@ hipError_t launch_scale(cx<T>* psi, size_t n, size_t sp, const double* scale, hi
 template <typename T>
 hipError_t launch_norm_partials(const cx<T>* psi, size_t n, size_t sp, double* partials, int nblk, hipStream_t st);
 hipError_t launch_set_scale(double* scale, double v, hipStream_t st);
+hipError_t launch_set_flag(int* flag, int v, hipStream_t st);  // a one-thread store (no memset node)
 // n blocks' worth of partials (3 n values) -> scale[3], flag
 hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, NormRule rule, double* scale, int* flag,
                                 hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

@@ -47,6 +47,10 @@ __global__ void k_set_scale(double* scale, double v) {
     if (blockIdx.x == 0 && threadIdx.x < 3) scale[threadIdx.x] = v;
 }
 
+__global__ void k_set_flag(int* flag, int v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *flag = v;
+}
+
 // Sum the per-block partial component norms in a fixed order and turn them
 // into the three scale factors (flag on a non-finite or non-positive result).
 __device__ inline void finalize_norms(const double* __restrict__ partials, int n, double dxdy, NormRule rule,
@@ -232,6 +236,11 @@ hipError_t launch_norm_partials(const cx<T>* psi, size_t n, size_t sp, double* p
 
 hipError_t launch_set_scale(double* scale, double v, hipStream_t st) {
     k_set_scale<<<1, 64, 0, st>>>(scale, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_flag(int* flag, int v, hipStream_t st) {
+    k_set_flag<<<1, 64, 0, st>>>(flag, v);
     return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -210,8 +211,31 @@ void set_piv(gp::Piv<T>& pv, zd a, zd e, zd w) {
     pv.cp = to_dev<T>(e * m);
 }
 
+// Device memory for the line tables: hipMalloc, or (the entry point that
+// allocates nothing) a bump allocator over the library's static scratch array.
+// Arena copies go through the stream (ordered after earlier work on it).
+struct Arena {
+    unsigned char* base = nullptr;  // nullptr: allocate with hipMalloc
+    size_t cap = 0, used = 0;
+    hipStream_t stream = nullptr;
+};
+
+hipError_t dev_alloc(Arena* a, void** p, size_t bytes) {
+    if (!a || !a->base) return hipMalloc(p, bytes);
+    const size_t off = (a->used + 255) / 256 * 256;
+    if (off > a->cap || bytes > a->cap - off) return hipErrorOutOfMemory;
+    *p = a->base + off;
+    a->used = off + bytes;
+    return hipSuccess;
+}
+
+hipError_t dev_upload(Arena* a, void* dst, const void* src, size_t bytes) {
+    if (!a || !a->base) return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, a->stream);
+}
+
 template <typename T>
-int upload_dir(gp_spin1* h, const HostDir& hd, DirTable& d) {
+int upload_dir(gp_spin1* h, const HostDir& hd, DirTable& d, Arena* arena = nullptr) {
     const int lines = hd.lines, K = hd.K;
     d.lines = lines; d.K = K; d.b = hd.b; d.bm1 = hd.bm1; d.decay = hd.decay; d.dominant = hd.dominant;
     std::vector<gp::Piv<T>> piv((size_t)lines * (K + 1));
@@ -226,25 +250,30 @@ int upload_dir(gp_spin1* h, const HostDir& hd, DirTable& d) {
         ae[2 * (size_t)l] = to_dev<T>(hd.A[l]);
         ae[2 * (size_t)l + 1] = to_dev<T>(hd.E[l]);
     }
-    hipError_t e1 = hipMalloc(&d.d_piv, piv.size() * sizeof(gp::Piv<T>));
+    hipError_t e1 = dev_alloc(arena, &d.d_piv, piv.size() * sizeof(gp::Piv<T>));
     if (e1 != hipSuccess) return fail(h, GP_ENOMEM, "pivot table allocation failed");
-    hipError_t e2 = hipMalloc(&d.d_ae, ae.size() * sizeof(gp::cx<T>));
+    hipError_t e2 = dev_alloc(arena, &d.d_ae, ae.size() * sizeof(gp::cx<T>));
     if (e2 != hipSuccess) return fail(h, GP_ENOMEM, "coefficient table allocation failed");
-    hipError_t e3 = hipMemcpy(d.d_piv, piv.data(), piv.size() * sizeof(gp::Piv<T>), hipMemcpyHostToDevice);
+    hipError_t e3 = dev_upload(arena, d.d_piv, piv.data(), piv.size() * sizeof(gp::Piv<T>));
     if (e3 != hipSuccess) return hip_fail(h, e3, "pivot table upload");
-    hipError_t e4 = hipMemcpy(d.d_ae, ae.data(), ae.size() * sizeof(gp::cx<T>), hipMemcpyHostToDevice);
+    hipError_t e4 = dev_upload(arena, d.d_ae, ae.data(), ae.size() * sizeof(gp::cx<T>));
     if (e4 != hipSuccess) return hip_fail(h, e4, "coefficient table upload");
     d.Kg = hd.Kg;
     std::vector<gp::cx<T>> g(hd.G.size()), gc(hd.GC.size());
     for (size_t i = 0; i < g.size(); ++i) g[i] = to_dev<T>(hd.G[i]);
     for (size_t i = 0; i < gc.size(); ++i) gc[i] = to_dev<T>(hd.GC[i]);
-    if (hipMalloc(&d.d_g, g.size() * sizeof(gp::cx<T>)) != hipSuccess ||
-        hipMalloc(&d.d_gc, gc.size() * sizeof(gp::cx<T>)) != hipSuccess)
+    if (dev_alloc(arena, &d.d_g, g.size() * sizeof(gp::cx<T>)) != hipSuccess ||
+        dev_alloc(arena, &d.d_gc, gc.size() * sizeof(gp::cx<T>)) != hipSuccess)
         return fail(h, GP_ENOMEM, "correction table allocation failed");
-    hipError_t e5 = hipMemcpy(d.d_g, g.data(), g.size() * sizeof(gp::cx<T>), hipMemcpyHostToDevice);
+    hipError_t e5 = dev_upload(arena, d.d_g, g.data(), g.size() * sizeof(gp::cx<T>));
     if (e5 != hipSuccess) return hip_fail(h, e5, "correction table upload");
-    hipError_t e6 = hipMemcpy(d.d_gc, gc.data(), gc.size() * sizeof(gp::cx<T>), hipMemcpyHostToDevice);
+    hipError_t e6 = dev_upload(arena, d.d_gc, gc.data(), gc.size() * sizeof(gp::cx<T>));
     if (e6 != hipSuccess) return hip_fail(h, e6, "correction table upload");
+    // (arena uploads read the host vectors asynchronously: wait before they go)
+    if (arena && arena->base) {
+        hipError_t e7 = hipStreamSynchronize(arena->stream);
+        if (e7 != hipSuccess) return hip_fail(h, e7, "table upload");
+    }
     return GP_OK;
 }
 
@@ -463,13 +492,13 @@ void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out)
 }
 
 template <typename T>
-int build_mode(gp_spin1* h, ModeState& ms, bool imag) {
+int build_mode(gp_spin1* h, ModeState& ms, bool imag, Arena* arena = nullptr) {
     const gp_spin1_params& p = h->p;
     HostMode hm;
     host_mode<T>(p, imag, hm);
-    int rc = upload_dir<T>(h, hm.x, ms.x);
+    int rc = upload_dir<T>(h, hm.x, ms.x, arena);
     if (rc) return rc;
-    rc = upload_dir<T>(h, hm.y, ms.y);
+    rc = upload_dir<T>(h, hm.y, ms.y, arena);
     if (rc) return rc;
     ms.stable = hm.stable;
     ms.why = hm.why;
@@ -990,7 +1019,8 @@ int obs_t(gp_spin1* h, const void* psi, gp_spin1_obs* out, void* dens) {
     out->e_kin = q[3]; out->e_trap = q[4]; out->e_int = q[5]; out->e_rot = q[6];
     out->e_so = q[7]; out->e_rabi = q[8]; out->lz = q[9];
     out->energy = q[3] + q[4] + q[5] + q[6] + q[7] + q[8];
-    for (int m = 0; m < 3; ++m) out->mu[m] = q[10 + m] / q[m];
+    // an empty component (norm exactly 0) has no chemical potential of its own: reported as 0
+    for (int m = 0; m < 3; ++m) out->mu[m] = q[m] > 0.0 ? q[10 + m] / q[m] : 0.0;
     out->mu_total = (q[10] + q[11] + q[12]) / out->norm_total;
     for (double v : q)
         if (!std::isfinite(v)) return fail(h, GP_ENONFINITE, "non-finite value in the observables");

@@ -230,9 +230,10 @@ __device__ inline void x_window(const cx<T>* __restrict__ src, cx<T>* __restrict
     }
 #pragma unroll
     for (int k = 0; k < KX; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
-    // the window holding point 0 of its rows applies the line-start correction
-    // (block-uniform: the first window of the rows, cs == 0)
-    window_solve<T, KX, IMAG, SEQ>(v, ls, jl * 3, g0, nx, i0 - h <= 0, h / KX, h % KX, lane);
+    // the windows holding point 0 of their rows apply the line-start correction
+    // (block-uniform); point 0 sits h - i0 points into the window
+    const int off0 = h - i0;
+    window_solve<T, KX, IMAG, SEQ>(v, ls, jl * 3, g0, nx, off0 >= 0, off0 / KX, off0 % KX, lane);
 #pragma unroll
     for (int k = 0; k < KX; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
     C* rowq = dst + (size_t)jl * nx;

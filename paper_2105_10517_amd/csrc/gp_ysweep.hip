@@ -49,9 +49,12 @@ __device__ inline void y_window(const cx<T>* __restrict__ src, cx<T>* __restrict
 #pragma unroll
     for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     const int il = col_ok ? i : 0;
-    // the window holding row 0 of its columns applies the line-start correction
-    // (block-uniform: the first row tile, rt == 0)
-    window_solve<T, KY, IMAG, SEQ>(v, ls, il * 3, g0, ny, j0 - h <= 0, h / KY, h % KY, lane);
+    // the windows holding row 0 of their columns apply the line-start correction
+    // (block-uniform: the first row tiles); row 0 sits h - j0 rows into the window
+    // (under row bands a shortened row tile can leave row 0 inside the halo of
+    // tiles after the first)
+    const int off0 = h - j0;
+    window_solve<T, KY, IMAG, SEQ>(v, ls, il * 3, g0, ny, off0 >= 0, off0 / KY, off0 % KY, lane);
 #pragma unroll
     for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
     if (OUTL) {

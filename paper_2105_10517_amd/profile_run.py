@@ -4,7 +4,8 @@
     python3 paper_2105_10517_amd/profile_run.py --copy-mib 512
 
 The first form builds one solver for a named workload and advances a seeded
-state by ``--steps`` steps: ``c2`` is the 512 x 512 real-time workload
+state by ``--steps`` steps (launch shapes from the autotuner, from the
+``--x-*`` / ``--y-tile`` / ``--block-order`` options, or the defaults): ``c2`` is the 512 x 512 real-time workload
 (Dresselhaus, Rabi 0.2, Omega 0.9), ``c3_<n>`` the n x n imaginary-time
 workload (Rashba, Omega 0.95).  The second form times nothing: it launches a
 plain device-to-device copy of a known size, whose FETCH_SIZE / WRITE_SIZE
@@ -26,6 +27,11 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--copy-mib", type=int, default=0, help="run a plain copy of this many MiB instead")
     ap.add_argument("--autotune", action="store_true", help="tune the launch shapes first (as bench.py does)")
+    ap.add_argument("--x-solver", default="auto", choices=("auto", "scan", "window"))
+    ap.add_argument("--x-tile", type=int, default=0, help="x window tile (1..8, with --x-solver window)")
+    ap.add_argument("--x-points", type=int, default=0, help="points per thread of the whole-row x sweep")
+    ap.add_argument("--y-tile", type=int, default=0, help="y window tile (1..8)")
+    ap.add_argument("--block-order", default="auto", choices=("auto", "hardware", "xcd", "bands", "rows"))
     args = ap.parse_args()
 
     import torch
@@ -46,15 +52,14 @@ def main():
         p, imag = inputs.config_c3(int(args.workload.split("_")[1])), True
     else:
         raise SystemExit(f"unknown workload {args.workload}")
-    s = binding.Solver(p, args.precision, autotune=args.autotune)
+    s = binding.Solver(p, args.precision, autotune=args.autotune, x_solver=args.x_solver, x_tile=args.x_tile,
+                       x_points=args.x_points, y_tile=args.y_tile, block_order=args.block_order)
     psi = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], seed=4, full_phase=imag)
     t = torch.from_numpy(psi).to("cuda").to(s.dtype)
     (s.step_imag if imag else s.step_real)(t, args.steps)
     s.sync()
     pl = s.plan(imag)
-    print(f"{args.workload} {args.precision}: {args.steps} steps, x K={pl['x_points_per_thread']} "
-          f"G={pl['x_threads_per_row']} R={pl['x_rows_per_block']}, y solver {pl['y_solver']} tile {pl['y_tile']}",
-          flush=True)
+    print(f"{args.workload} {args.precision}: {args.steps} steps, plan {pl}", flush=True)
     s.close()
 
 

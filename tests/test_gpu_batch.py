@@ -183,6 +183,33 @@ def test_batch_scan_workload_sample():
     b.close()
 
 
+def test_batch_scan_fp32_matches_oracle():
+    """The full 256-condensate parameter scan, FP32 bulk in one batch, 100
+    imaginary-time steps; the smallest, a middle and the largest grid of the
+    scan against the FP64 oracle: density 1e-5 (relative to the peak density)
+    and chemical potentials 1e-6 (relative)."""
+    ps = inputs.batch_scan(256, seed=5)
+    b = binding.Batch(ps, "fp32")
+    ts = [dev(initial(p, 1000 + k), torch.complex64) for k, p in enumerate(ps)]
+    b.step(ts, [100] * len(ps), ["imag"] * len(ps))
+    b.sync()
+    sizes = [p["nx"] for p in ps]
+    picks = (int(np.argmin(sizes)), int(np.argsort(sizes)[len(sizes) // 2]), int(np.argmax(sizes)))
+    for k in picks:
+        p = ps[k]
+        want = oracle.step(p, initial(p, 1000 + k), 100, True)
+        o = oracle.observables(p, want)
+        obs = b.observables(k, ts[k])
+        got = ts[k].cpu().numpy().astype(np.complex128)
+        rho_g, rho_w = np.abs(got) ** 2, np.abs(want) ** 2
+        dens = float(np.abs(rho_g - rho_w).max() / rho_w.max())
+        mu = abs(obs["mu_total"] - o["mu_total"]) / abs(o["mu_total"])
+        mum = max(abs(obs["mu"][m] - o["mu"][m]) / abs(o["mu"][m]) for m in range(3))
+        print(f"scan slot {k} ({p['nx']}^2): density err {dens:.2e}, mu err {mu:.2e}, mu_m err {mum:.2e}")
+        assert dens < 1e-5 and mu < 1e-6 and mum < 1e-6, k
+    b.close()
+
+
 def test_condensate_beyond_the_block_map_runs_alone():
     # a grouped condensate's blocks are named by map entries with 20 bits of
     # block index; beside a 48-point-wide slot the x sweep takes one row per

@@ -8,6 +8,7 @@ respect arrival order, the slot limit and the memory budget."""
 import numpy as np
 import pytest
 
+import oracle
 from paper_2105_10517_amd import binding, inputs
 
 torch = pytest.importorskip("torch")
@@ -68,6 +69,14 @@ def test_served_states_equal_solo_runs(precision):
         got = r["psi"].cpu()
         err = float(torch.linalg.vector_norm((got - want).flatten()) / torch.linalg.vector_norm(want.flatten()))
         assert err < (1e-12 if precision == "fp64" else 2e-6), (k, err)
+        # and the FP64 oracle: the parity bar (FP64), density and mu (FP32)
+        ref = oracle.step(r["params"], r["psi0"], r["nsteps"], r["mode"] == "imag")
+        g = got.numpy().astype(np.complex128)
+        if precision == "fp64":
+            assert np.linalg.norm(g - ref) / np.linalg.norm(ref) < 1e-12, k
+        else:
+            rho_g, rho_w = np.abs(g) ** 2, np.abs(ref) ** 2
+            assert np.abs(rho_g - rho_w).max() / rho_w.max() < 1e-5, k
     # first come, first served
     starts = [s for s, _ in res]
     assert starts == sorted(starts)

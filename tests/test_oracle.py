@@ -321,6 +321,66 @@ def test_rabi_only_ground_state():
     assert np.abs(s - np.array([1, -S2, 1])).max() < 1e-8
 
 
+def test_component_chemical_potentials_at_eigenstates():
+    # reading S12, mu_m = Re<psi_m|(H psi)_m> / N_m with H the operator of
+    # Eqs. (S.1)-(S.3): at an eigenstate of the linear grid operator
+    # (c0 = c2 = 0) every populated component has mu_m = lambda.  The operator
+    # is the dense form built here (SO from Eq. (S.5), -Omega L_z), not the
+    # oracle's; a dropped term, a wrong component or a division by the total
+    # norm fails one of the cases below.
+    n, dx = 9, 0.5
+    # (a) SO + rotation + Rabi couple the components: any eigenvector, unequal populations
+    p = inputs.params(n, n, dx, gamma=0.7, eta=-1, omega=0.35, rabi=0.3)
+    H = dense_linear_h(p)
+    w, vec = np.linalg.eigh(H)
+    for k in (0, 1, 5):
+        psi = vec[:, k].reshape(3, n, n) / dx
+        o = oracle.observables(p, psi)
+        pops = np.array(o["norm"])
+        assert pops.min() > 1e-3 and np.ptp(pops) > 1e-3  # populated, and not all equal
+        for m in range(3):
+            assert abs(o["mu"][m] - w[k]) < 1e-11 * max(1.0, abs(w[k])), (k, m)
+        assert abs(o["mu_total"] - w[k]) < 1e-11 * max(1.0, abs(w[k]))
+    # (b) uncoupled components (gamma = rabi = 0, rotation on): three different
+    # eigenstates of the one-component operator with unequal weights give three
+    # different mu_m, so a swapped component index or a shared divisor fails
+    p = inputs.params(n, n, dx, omega=0.4)
+    H1 = dense_linear_h(p)[: n * n, : n * n]
+    w1, v1 = np.linalg.eigh(H1)
+    picks, amps = (0, 2, 4), (0.3, 0.5, 0.2)
+    psi = np.stack([math.sqrt(a) * v1[:, k].reshape(n, n) / dx for k, a in zip(picks, amps)])
+    o = oracle.observables(p, psi)
+    assert len({round(w1[k], 6) for k in picks}) == 3
+    for m, k in enumerate(picks):
+        assert abs(o["norm"][m] - amps[m]) < 1e-13
+        assert abs(o["mu"][m] - w1[k]) < 1e-11 * max(1.0, abs(w1[k])), m
+    assert abs(o["mu_total"] - sum(a * w1[k] for k, a in zip(picks, amps))) < 1e-11
+    # (c) Rabi only: the ground spinor (1, -sqrt2, 1)/2 of R Sigma_x times the
+    # discrete oscillator ground state gives mu_m = E_osc - R in every component
+    R = 0.6
+    p = inputs.params(n, n, dx, rabi=R)
+    x, y = coords(p)
+    ex, fx = np.linalg.eigh(-0.5 * d2(n, dx) + np.diag(0.5 * x * x))
+    ey, fy = np.linalg.eigh(-0.5 * d2(n, dx) + np.diag(0.5 * y * y))
+    phi = np.outer(fy[:, 0], fx[:, 0]) / dx
+    psi = np.stack([0.5 * phi, -0.5 * S2 * phi, 0.5 * phi]).astype(complex)
+    o = oracle.observables(p, psi)
+    for m in range(3):
+        assert abs(o["mu"][m] - (ex[0] + ey[0] - R)) < 1e-12
+
+
+def test_empty_component_has_zero_chemical_potential():
+    # a component with zero norm has no chemical potential of its own: reported as 0
+    n, dx = 10, 0.4
+    p = inputs.params(n, n, dx, c0=20.0, c2=-3.0, omega=0.2)
+    psi = inputs.gaussian(n, n, dx, dx, seed=5)
+    psi[0] = 0.0
+    psi[2] = 0.0
+    o = oracle.observables(p, psi)
+    assert o["mu"][0] == 0.0 and o["mu"][2] == 0.0
+    assert math.isfinite(o["mu"][1]) and abs(o["mu"][1] - o["mu_total"]) < 1e-12
+
+
 def test_real_time_norm_conserved():
     n, dx = 40, 0.3
     p = inputs.params(n, n, dx, dt=0.01, c0=60.0, c2=-4.0, gamma=0.9, eta=1, rabi=0.4, omega=0.5)
