@@ -66,15 +66,21 @@ typedef enum { GP_FP64 = 0, GP_FP32 = 1 } gp_precision; /* FP32: bulk in FP32, r
 typedef enum {
     GP_YSOLVER_AUTO = 0,   /* windowed scan when its truncation bound holds, else per-column Thomas */
     GP_YSOLVER_WINDOW = 1, /* windowed partitioned scan over column tiles (2 HBM passes per step) */
-    GP_YSOLVER_THOMAS = 2  /* exact per-thread Thomas down whole columns (one thread per column) */
+    GP_YSOLVER_THOMAS = 2, /* exact per-thread Thomas down whole columns (one thread per column) */
+    GP_YSOLVER_CHAIN = 3   /* windows as GP_YSOLVER_WINDOW, each segment's carry formed from the ceil(h / K)
+                              segments before and after it instead of a scan of the whole window (their
+                              carries are attenuated below the same rounding bound as the window ends);
+                              y_tile then names a chain tile */
 } gp_ysolver;
 
 /* Choice of the x-sweep line solver. */
 typedef enum {
     GP_XSOLVER_AUTO = 0,   /* whole-row partitioned Thomas, or the windows when autotuning finds them faster */
     GP_XSOLVER_SCAN = 1,   /* exact partitioned Thomas over whole rows (scans across the row's threads)     */
-    GP_XSOLVER_WINDOW = 2  /* truncated overlapping windows along the rows (the y sweep's scheme); refused
+    GP_XSOLVER_WINDOW = 2, /* truncated overlapping windows along the rows (the y sweep's scheme); refused
                               (GP_EUNSUPPORTED) when the decay bound does not fit any window            */
+    GP_XSOLVER_CHAIN = 3   /* windows of one row segment per wave (64 K points) with carries over ceil(h / K)
+                              lanes (as GP_YSOLVER_CHAIN); x_tile then names a chain tile               */
 } gp_xsolver;
 
 /* Block order of the windowed sweeps.  The chip hands workgroups to its 8
@@ -131,7 +137,8 @@ typedef struct {
     int32_t block_order;     /* gp_block_order: how the windowed sweeps number their blocks (no effect on
                                 results, which are bit-identical in every order)                         */
     int32_t x_tile;          /* tile shape of the windowed x sweep: 0 = chosen by the library, else 1..8
-                                (the y_tile shapes turned along the rows)                                */
+                                (the y_tile shapes turned along the rows; chain tiles with
+                                GP_XSOLVER_CHAIN)                                                        */
     int64_t plane_stride;    /* elements between the component planes of every wave function passed to this
                                 handle (psi_m starts at psi + m plane_stride; rows nx apart, points
                                 contiguous); 0 = nx ny (a contiguous [3][ny][nx] array).  A stride that is
@@ -161,7 +168,7 @@ typedef struct {
     int32_t x_points_per_thread; /* K of the x kernel: each thread holds K consecutive points   */
     int32_t x_threads_per_row;   /* threads cooperating on one row                               */
     int32_t x_rows_per_block;
-    int32_t y_solver;            /* GP_YSOLVER_WINDOW or GP_YSOLVER_THOMAS                        */
+    int32_t y_solver;            /* GP_YSOLVER_WINDOW, GP_YSOLVER_CHAIN or GP_YSOLVER_THOMAS      */
     int32_t y_halo;              /* rows read above a y window's output (at least as many below) */
     int32_t y_rows_out;          /* rows written per y window                                    */
     int32_t y_tile;              /* 1..8, the tile shape below (5..8: lines solved one at a time)  */
@@ -171,7 +178,7 @@ typedef struct {
     int32_t pivots_x, pivots_y;  /* tabulated Thomas pivots per line before the constant limit  */
     double decay_x, decay_y;     /* largest |a m| or |c'| of the converged pivots per direction  */
     int32_t stable;              /* 1 if the mode passed the stability checks                    */
-    int32_t x_solver;            /* GP_XSOLVER_SCAN or GP_XSOLVER_WINDOW                          */
+    int32_t x_solver;            /* GP_XSOLVER_SCAN, GP_XSOLVER_WINDOW or GP_XSOLVER_CHAIN        */
     int32_t x_halo;              /* windows: points of overlap on each side                       */
     int32_t x_points_out;        /* windows: points written per window                            */
     int32_t x_tile;              /* windows: 1..8, same shapes as y_tile (rows per block = 4 per wave) */

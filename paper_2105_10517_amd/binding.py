@@ -17,8 +17,8 @@ LIBPATH = os.path.join(_HERE, "libgp_spin1.so")
 
 GP_OK, GP_EINVAL, GP_EUNSTABLE, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GP_FP64, GP_FP32 = 0, 1
-GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS = 0, 1, 2
-GP_XSOLVER_AUTO, GP_XSOLVER_SCAN, GP_XSOLVER_WINDOW = 0, 1, 2
+GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS, GP_YSOLVER_CHAIN = 0, 1, 2, 3
+GP_XSOLVER_AUTO, GP_XSOLVER_SCAN, GP_XSOLVER_WINDOW, GP_XSOLVER_CHAIN = 0, 1, 2, 3
 GP_ORDER_AUTO, GP_ORDER_HARDWARE, GP_ORDER_XCD, GP_ORDER_BANDS, GP_ORDER_ROWS = 0, 1, 2, 3, 4
 SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
 
@@ -168,14 +168,16 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_poin
     gamma, eta, rabi, omega; missing x0/y0 select the default -n d / 2;
     optional gx, gy (trap), split (0 Lie, 1 Strang), fix_m and magnetization)."""
     prec = {"fp64": GP_FP64, "fp32": GP_FP32}[precision]
-    ys = {"auto": GP_YSOLVER_AUTO, "window": GP_YSOLVER_WINDOW, "thomas": GP_YSOLVER_THOMAS}[y_solver]
+    ys = {"auto": GP_YSOLVER_AUTO, "window": GP_YSOLVER_WINDOW, "thomas": GP_YSOLVER_THOMAS,
+          "chain": GP_YSOLVER_CHAIN}[y_solver]
     return Params(int(p["nx"]), int(p["ny"]), float(p["dx"]), float(p.get("dy", p["dx"])),
                   float(p.get("x0", math.nan)), float(p.get("y0", math.nan)), float(p["dt"]),
                   float(p.get("c0", 0.0)), float(p.get("c2", 0.0)), float(p.get("gamma", 0.0)),
                   int(p.get("eta", 1)), float(p.get("rabi", 0.0)), float(p.get("omega", 0.0)), prec, ys,
                   int(x_points), int(y_tile), int(bool(autotune)), float(p.get("gx", 1.0)), float(p.get("gy", 1.0)),
                   int(p.get("split", 0)), int(bool(p.get("fix_m", 0))), float(p.get("magnetization", 0.0)),
-                  {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW}[x_solver],
+                  {"auto": GP_XSOLVER_AUTO, "scan": GP_XSOLVER_SCAN, "window": GP_XSOLVER_WINDOW,
+                   "chain": GP_XSOLVER_CHAIN}[x_solver],
                   {"auto": GP_ORDER_AUTO, "hardware": GP_ORDER_HARDWARE, "xcd": GP_ORDER_XCD,
                    "bands": GP_ORDER_BANDS, "rows": GP_ORDER_ROWS}[block_order],
                   int(x_tile), int(p.get("plane_stride", 0)))

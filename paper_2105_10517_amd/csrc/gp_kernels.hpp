@@ -26,6 +26,33 @@ template <> __host__ __device__ constexpr YTile ytile<float>(int t) {
 }
 __host__ __device__ constexpr int ywindow(YTile t) { return 16 * t.KY; }
 
+// Tile shapes of the chain windows: K points per lane, NW waves per block,
+// SEQ as for the scanned windows.  x windows: one row per wave (64 K
+// points); y windows: four columns per wave, 16 segments each (16 K rows).
+constexpr int kNumChainTiles = 8;
+struct ChainTile { int K, NW; bool SEQ; };
+template <typename T> __host__ __device__ constexpr ChainTile xchain_tile(int t);
+template <> __host__ __device__ constexpr ChainTile xchain_tile<double>(int t) {
+    return (t & 3) == 0 ? ChainTile{4, 4, t > 3} : (t & 3) == 1 ? ChainTile{8, 2, t > 3}
+                        : (t & 3) == 2 ? ChainTile{2, 4, t > 3} : ChainTile{4, 2, t > 3};
+}
+template <> __host__ __device__ constexpr ChainTile xchain_tile<float>(int t) {
+    return (t & 3) == 0 ? ChainTile{4, 4, t > 3} : (t & 3) == 1 ? ChainTile{8, 4, t > 3}
+                        : (t & 3) == 2 ? ChainTile{8, 2, t > 3} : ChainTile{16, 2, t > 3};
+}
+template <typename T> __host__ __device__ constexpr ChainTile ychain_tile(int t);
+template <> __host__ __device__ constexpr ChainTile ychain_tile<double>(int t) {
+    return (t & 3) == 0 ? ChainTile{8, 2, t > 3} : (t & 3) == 1 ? ChainTile{8, 4, t > 3}
+                        : (t & 3) == 2 ? ChainTile{4, 4, t > 3} : ChainTile{7, 4, t > 3};
+}
+template <> __host__ __device__ constexpr ChainTile ychain_tile<float>(int t) {
+    return (t & 3) == 0 ? ChainTile{8, 4, t > 3} : (t & 3) == 1 ? ChainTile{8, 8, t > 3}
+                        : (t & 3) == 2 ? ChainTile{4, 4, t > 3} : ChainTile{16, 2, t > 3};
+}
+
+// Carry lanes of a chain window for a halo of h points: nc = ceil(h / K).
+__host__ __device__ inline int chain_lanes(int h, int K) { return h <= K ? 1 : (h + K - 1) / K; }
+
 // x sweep: K consecutive points per thread; the launch bound of each K.
 constexpr int kNumXK = 5;
 __host__ __device__ constexpr int xk_value(int idx) { return 1 << idx; }  // 1, 2, 4, 8, 16
@@ -123,6 +150,7 @@ template <typename T> struct XLaunch {
     int K, G, R;
     bool imag, local;
     bool window;    // truncated windows along the rows (tile shapes as the y sweep's) instead of whole rows
+    bool chain = false;  // chain windows (gp_chain.hpp): one row segment of 64 K points per wave
     int L, h, tile;
     int order;      // block order: windows 0 hardware, 1 XCD-contiguous (2, 3 taken as 1); rows 0 or 3
     int bL, bnrt;   // order 3 on rows: the y sweep's row tile (rows) and number of row tiles
@@ -137,6 +165,7 @@ template <typename T> struct YLaunch {
     NormOut no;
     int L, h, tile;
     bool window, imag, norm;
+    bool chain = false;  // chain windows (gp_chain.hpp) instead of the scanned windows
     bool outl;  // second half local substep on the way out (Strang)
     int order;  // windows: block order (0 hardware, 1 XCD-contiguous, 2 bands, 3 row bands)
     size_t sp, dp;  // plane strides of src and dst

@@ -66,10 +66,35 @@ __device__ inline void finalize_norms(const double* __restrict__ partials, int n
     }
 }
 
-__global__ __launch_bounds__(256) void k_norm_finalize(const double* __restrict__ partials, int n, double dxdy,
-                                                      NormRule rule, double* __restrict__ scale, int* __restrict__ flag) {
+// One block of 1024 threads; each thread keeps four independent sums per
+// component, so that sixteen loads are in flight per thread (the partials of
+// a 4096^2 grid are about 60 thousand triples).  The order of the additions
+// depends only on n.
+__global__ __launch_bounds__(1024) void k_norm_finalize(const double* __restrict__ partials, int n, double dxdy,
+                                                       NormRule rule, double* __restrict__ scale, int* __restrict__ flag) {
     __shared__ double shr[48];
-    finalize_norms(partials, n, dxdy, rule, scale, flag, shr);
+    constexpr int U = 4;
+    const int nt = blockDim.x;
+    double a[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u][0] = a[u][1] = a[u][2] = 0.0;
+    int k = threadIdx.x;
+    for (; k + (U - 1) * nt < n; k += U * nt)
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) a[u][m] += partials[3 * (k + u * nt) + m];
+    for (; k < n; k += nt)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) a[0][m] += partials[3 * k + m];
+    double acc[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) acc[m] = (a[0][m] + a[1][m]) + (a[2][m] + a[3][m]);
+    block_sum3(acc, shr);
+    if (threadIdx.x == 0) {
+        const double N[3] = {acc[0] * dxdy, acc[1] * dxdy, acc[2] * dxdy};
+        if (!norm_scales(N, rule, scale)) *flag = 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -246,7 +271,7 @@ hipError_t launch_set_flag(int* flag, int v, hipStream_t st) {
 
 hipError_t launch_norm_finalize(const double* partials, int n, double dxdy, NormRule rule, double* scale, int* flag,
                                 hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-    hipExtLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(256), 0, st, e0, e1, 0, partials, n, dxdy, rule, scale, flag);
+    hipExtLaunchKernelGGL(k_norm_finalize, dim3(1), dim3(1024), 0, st, e0, e1, 0, partials, n, dxdy, rule, scale, flag);
     return hipGetLastError();
 }
 

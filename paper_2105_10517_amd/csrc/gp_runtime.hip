@@ -49,6 +49,9 @@ struct ModeState {
     bool xwindow = false;         // x sweep over truncated windows
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
     int xorder = 1, yorder = 0;   // block orders (x windows 0/1, x rows 0/3; y windows 0..3), see gp_kernels.hpp
+    bool xchain = false, ychain = false;  // chain windows (gp_chain.hpp) for the x / y sweep
+    int xctile = 0, hcx = 0, Lcx = 0;     // x chain tile, halo points, points written per window
+    int yctile = 0, hcy = 0, Lcy = 0;     // y chain tile, halo rows, rows written per window
     gp_spin1_plan plan{};
 };
 
@@ -348,6 +351,8 @@ struct HostMode {
     bool xwindow = false;
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
     int xorder = 1, yorder = 0;  // block orders of the windowed sweeps
+    bool xchain = false, ychain = false;
+    int xctile = 0, hcx = 0, Lcx = 0, yctile = 0, hcy = 0, Lcy = 0;
 };
 
 // Halo that makes decay^h fall below the rounding level of T.
@@ -365,6 +370,23 @@ bool tile_window(int ny, int hh, int W, int& h, int& L) {
     if (ny <= W) { h = 0; L = W; return true; }
     if (2 * hh <= W / 2) { h = hh; L = W - 2 * hh; return true; }
     return false;
+}
+
+// Chain windows (gp_chain.hpp): a window of W points (64 K along x, 16 K
+// along y) writes L = W - 2 h of them, h the halo the decay bound asks for;
+// the first window writes every point of the line-start correction.  Along y
+// the kernels address a plane with 32-bit byte offsets.
+template <typename T> bool xchain_fits(int hh, int Kg, int t, int& h, int& L) {
+    const gp::ChainTile ct = gp::xchain_tile<T>(t);
+    h = std::max(hh, 1);
+    L = 64 * ct.K - 2 * h;
+    return L > 0 && Kg <= L;
+}
+template <typename T> bool ychain_fits(int nx, int ny, int hh, int Kg, int t, int& h, int& L) {
+    const gp::ChainTile ct = gp::ychain_tile<T>(t);
+    h = std::max(hh, 1);
+    L = 16 * ct.K - 2 * h;
+    return L > 0 && Kg <= L && (double)nx * ny * sizeof(gp::cx<T>) < 4294967296.0;
 }
 
 // Row tile of the y windows as launched.  Under row bands (order 3) each XCD
@@ -424,7 +446,7 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     hm.L = 0;
     hm.ytile = 0;
     if (p.y_solver != GP_YSOLVER_THOMAS) {
-        if (p.y_tile > 0) {
+        if (p.y_tile > 0 && p.y_solver != GP_YSOLVER_CHAIN) {
             hm.ytile = p.y_tile - 1;
             hm.window = tile_window(p.ny, hm.hh, gp::ywindow(gp::ytile<T>(hm.ytile)), hm.h, hm.L);
         } else {
@@ -448,6 +470,20 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
                 if (tile_window(p.nx, hm.hhx, gp::ywindow(gp::ytile<T>(t)), hm.hx, hm.Lx)) { hm.xwindow = true; hm.xtile = t; }
         }
     }
+    // chain windows: only when asked for (autotuning may also choose them)
+    hm.xchain = hm.ychain = false;
+    if (p.x_solver == GP_XSOLVER_CHAIN) {
+        for (int t = p.x_tile > 0 ? p.x_tile - 1 : 0; t < gp::kNumChainTiles && !hm.xchain; ++t) {
+            if (xchain_fits<T>(hm.hhx, hm.x.Kg, t, hm.hcx, hm.Lcx)) { hm.xchain = true; hm.xctile = t; }
+            if (p.x_tile > 0) break;
+        }
+    }
+    if (p.y_solver == GP_YSOLVER_CHAIN) {
+        for (int t = p.y_tile > 0 ? p.y_tile - 1 : 0; t < gp::kNumChainTiles && !hm.ychain; ++t) {
+            if (ychain_fits<T>(p.nx, p.ny, hm.hh, hm.y.Kg, t, hm.hcy, hm.Lcy)) { hm.ychain = true; hm.yctile = t; }
+            if (p.y_tile > 0) break;
+        }
+    }
     // block orders: grouping the x windows by XCD has measured as fast or
     // faster at every size; the y windows gain from it only while the grid is
     // about one wave of blocks (on larger grids the eight separate HBM streams
@@ -465,31 +501,54 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     }
 }
 
+// The plan a mode's launches follow (gp_spin1_get_plan).
 template <typename T>
-void fill_plan(const gp_spin1_params& p, const HostMode& hm, gp_spin1_plan* out) {
+void fill_plan(const gp_spin1_params& p, ModeState& ms) {
+    gp_spin1_plan* out = &ms.plan;
     std::memset(out, 0, sizeof *out);
-    out->x_points_per_thread = hm.xK;
-    out->x_threads_per_row = hm.xG;
-    out->x_rows_per_block = hm.xR;
-    out->y_solver = hm.window ? GP_YSOLVER_WINDOW : GP_YSOLVER_THOMAS;
-    const gp::YTile yt = gp::ytile<T>(hm.ytile);
-    band_tile(p.ny, hm.window ? hm.yorder : 0, gp::ywindow(yt), hm.h, hm.L, out->y_halo, out->y_rows_out);
-    out->y_tile = hm.ytile + 1;
-    out->y_tile_cols = 4 * yt.NW;
+    out->x_points_per_thread = ms.xchain ? gp::xchain_tile<T>(ms.xctile).K : ms.xK;
+    out->x_threads_per_row = ms.xG;
+    out->x_rows_per_block = ms.xR;
+    const gp::YTile yt = gp::ytile<T>(ms.ytile);
+    if (ms.ychain) {
+        const gp::ChainTile ct = gp::ychain_tile<T>(ms.yctile);
+        out->y_solver = GP_YSOLVER_CHAIN;
+        out->y_halo = ms.hcy;
+        out->y_rows_out = ms.Lcy;
+        out->y_tile = ms.yctile + 1;
+        out->y_tile_cols = 4 * ct.NW;
+        out->y_rows_per_thread = ct.K;
+    } else {
+        out->y_solver = ms.window ? GP_YSOLVER_WINDOW : GP_YSOLVER_THOMAS;
+        band_tile(p.ny, ms.window ? ms.yorder : 0, gp::ywindow(yt), ms.h, ms.L, out->y_halo, out->y_rows_out);
+        out->y_tile = ms.ytile + 1;
+        out->y_tile_cols = 4 * yt.NW;
+        out->y_rows_per_thread = yt.KY;
+    }
     out->y_segments = 16;
-    out->y_rows_per_thread = yt.KY;
-    out->pivots_x = hm.x.K;
-    out->pivots_y = hm.y.K;
-    out->decay_x = hm.x.decay;
-    out->decay_y = hm.y.decay;
-    out->stable = hm.stable ? 1 : 0;
-    out->x_solver = hm.xwindow ? GP_XSOLVER_WINDOW : GP_XSOLVER_SCAN;
-    out->x_halo = hm.xwindow ? hm.hx : 0;
-    out->x_points_out = hm.xwindow ? hm.Lx : 0;
-    out->x_tile = hm.xwindow ? hm.xtile + 1 : 0;
-    out->x_block_order = hm.xorder == 3 && !hm.window ? (hm.xwindow ? 1 : 0) : hm.xwindow || hm.xorder == 3 ? hm.xorder : 0;
-    out->y_block_order = hm.window ? hm.yorder : 0;
+    out->pivots_x = ms.x.K;
+    out->pivots_y = ms.y.K;
+    out->decay_x = ms.x.decay;
+    out->decay_y = ms.y.decay;
+    out->stable = ms.stable ? 1 : 0;
+    if (ms.xchain) {
+        out->x_solver = GP_XSOLVER_CHAIN;
+        out->x_halo = ms.hcx;
+        out->x_points_out = ms.Lcx;
+        out->x_tile = ms.xctile + 1;
+        out->x_block_order = ms.xorder ? 1 : 0;
+    } else {
+        out->x_solver = ms.xwindow ? GP_XSOLVER_WINDOW : GP_XSOLVER_SCAN;
+        out->x_halo = ms.xwindow ? ms.hx : 0;
+        out->x_points_out = ms.xwindow ? ms.Lx : 0;
+        out->x_tile = ms.xwindow ? ms.xtile + 1 : 0;
+        out->x_block_order = ms.xorder == 3 && !ms.window ? (ms.xwindow ? 1 : 0) : ms.xwindow || ms.xorder == 3 ? ms.xorder : 0;
+    }
+    out->y_block_order = ms.window || ms.ychain ? ms.yorder : 0;
 }
+
+template <typename T>
+void copy_plan(const gp_spin1_params& p, const HostMode& hm, ModeState& ms);
 
 template <typename T>
 int build_mode(gp_spin1* h, ModeState& ms, bool imag, Arena* arena = nullptr) {
@@ -500,6 +559,15 @@ int build_mode(gp_spin1* h, ModeState& ms, bool imag, Arena* arena = nullptr) {
     if (rc) return rc;
     rc = upload_dir<T>(h, hm.y, ms.y, arena);
     if (rc) return rc;
+    copy_plan<T>(p, hm, ms);
+    return GP_OK;
+}
+
+// The launch choices of a host-side mode (tables excepted), and the plan.
+template <typename T>
+void copy_plan(const gp_spin1_params& p, const HostMode& hm, ModeState& ms) {
+    ms.x.K = hm.x.K; ms.x.decay = hm.x.decay; ms.x.Kg = hm.x.Kg;
+    ms.y.K = hm.y.K; ms.y.decay = hm.y.decay; ms.y.Kg = hm.y.Kg;
     ms.stable = hm.stable;
     ms.why = hm.why;
     ms.window = hm.window;
@@ -511,15 +579,23 @@ int build_mode(gp_spin1* h, ModeState& ms, bool imag, Arena* arena = nullptr) {
     ms.xwindow = hm.xwindow;
     ms.hhx = hm.hhx; ms.hx = hm.hx; ms.Lx = hm.Lx; ms.xtile = hm.xtile;
     ms.xorder = hm.xorder; ms.yorder = hm.yorder;
-    fill_plan<T>(p, hm, &ms.plan);
-    return GP_OK;
+    ms.xchain = hm.xchain; ms.xctile = hm.xctile; ms.hcx = hm.hcx; ms.Lcx = hm.Lcx;
+    ms.ychain = hm.ychain; ms.yctile = hm.yctile; ms.hcy = hm.hcy; ms.Lcy = hm.Lcy;
+    fill_plan<T>(p, ms);
 }
 
 // Blocks of the y sweep for the largest grid of any tile shape (partials).
 template <typename T>
 size_t max_y_blocks(const gp_spin1_params& p, const ModeState& ms) {
-    if (!ms.window) return (size_t)(p.nx + 255) / 256;
-    size_t best = 1;
+    size_t best = (size_t)(p.nx + 255) / 256;  // per-column Thomas
+    // chain tiles (any may be chosen by the autotuner)
+    for (int t = 0; t < gp::kNumChainTiles; ++t) {
+        int h, L;
+        if (!ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, h, L)) continue;
+        const gp::ChainTile ct = gp::ychain_tile<T>(t);
+        best = std::max(best, (size_t)((p.nx + 4 * ct.NW - 1) / (4 * ct.NW)) * ((p.ny + L - 1) / L));
+    }
+    if (!ms.window) return best;
     for (int t = 0; t < gp::kNumYTiles; ++t) {
         const gp::YTile yt = gp::ytile<T>(t);
         int h, L;
@@ -570,7 +646,7 @@ int validate(const gp_spin1_params* p, std::string& why) {
     }
     if (p->eta != 1 && p->eta != -1) { why = "eta must be +1 (Rashba) or -1 (Dresselhaus)"; return GP_EINVAL; }
     if (p->precision != GP_FP64 && p->precision != GP_FP32) { why = "precision must be GP_FP64 or GP_FP32"; return GP_EINVAL; }
-    if (p->y_solver < GP_YSOLVER_AUTO || p->y_solver > GP_YSOLVER_THOMAS) { why = "unknown y_solver"; return GP_EINVAL; }
+    if (p->y_solver < GP_YSOLVER_AUTO || p->y_solver > GP_YSOLVER_CHAIN) { why = "unknown y_solver"; return GP_EINVAL; }
     const int nmax = 8192;
     if (p->nx > nmax) { why = "nx above the largest row this build holds on chip"; return GP_EUNSUPPORTED; }
     if ((double)p->nx * (double)p->ny * 3.0 > 4.0e9) { why = "grid too large"; return GP_EUNSUPPORTED; }
@@ -578,11 +654,14 @@ int validate(const gp_spin1_params* p, std::string& why) {
         why = "trap_gx, trap_gy must be finite and >= 0 (0 selects 1)";
         return GP_EINVAL;
     }
-    if (p->x_solver < GP_XSOLVER_AUTO || p->x_solver > GP_XSOLVER_WINDOW) { why = "unknown x_solver"; return GP_EINVAL; }
+    if (p->x_solver < GP_XSOLVER_AUTO || p->x_solver > GP_XSOLVER_CHAIN) { why = "unknown x_solver"; return GP_EINVAL; }
     if (p->block_order < GP_ORDER_AUTO || p->block_order > GP_ORDER_ROWS) { why = "unknown block_order"; return GP_EINVAL; }
     if (p->x_tile < 0 || p->x_tile > gp::kNumYTiles) { why = "x_tile must be 0..8"; return GP_EINVAL; }
     if (p->y_tile < 0 || p->y_tile > gp::kNumYTiles) { why = "y_tile must be 0..8"; return GP_EINVAL; }
-    if (p->x_tile > 0 && p->x_solver != GP_XSOLVER_WINDOW) { why = "x_tile needs x_solver = GP_XSOLVER_WINDOW"; return GP_EINVAL; }
+    if (p->x_tile > 0 && p->x_solver != GP_XSOLVER_WINDOW && p->x_solver != GP_XSOLVER_CHAIN) {
+        why = "x_tile needs x_solver = GP_XSOLVER_WINDOW or GP_XSOLVER_CHAIN";
+        return GP_EINVAL;
+    }
     if (p->split != GP_SPLIT_LIE && p->split != GP_SPLIT_STRANG) { why = "split must be GP_SPLIT_LIE or GP_SPLIT_STRANG"; return GP_EINVAL; }
     if (p->fix_magnetization != 0 && p->fix_magnetization != 1) { why = "fix_magnetization must be 0 or 1"; return GP_EINVAL; }
     if (p->fix_magnetization) {
@@ -676,7 +755,7 @@ int autotune_t(gp_spin1* h) {
                 return ex != hipSuccess ? ex : gp::launch_y<T>(ya, h->stream);
             }, reps, t, batches, batch_ms);
         };
-        if (p.x_points == 0 && p.x_solver != GP_XSOLVER_WINDOW) {
+        if (p.x_points == 0 && p.x_solver != GP_XSOLVER_WINDOW && p.x_solver != GP_XSOLVER_CHAIN) {
             float best = 1e30f;
             int bestK = ms.xK;
             for (int idx = 0; idx < gp::kNumXK && rc == GP_OK; ++idx) {
@@ -731,7 +810,35 @@ int autotune_t(gp_spin1* h) {
             ms.xorder = bestO;
             tile_window(p.nx, ms.hhx, gp::ywindow(gp::ytile<T>(bestT)), ms.hx, ms.Lx);
         }
-        if (p.y_tile == 0 && ms.window) {
+        // x chain windows: against the choice above (AUTO), or the fastest chain tile (CHAIN)
+        if (rc == GP_OK && ((p.x_solver == GP_XSOLVER_AUTO && p.x_points == 0) ||
+                            (p.x_solver == GP_XSOLVER_CHAIN && p.x_tile == 0))) {
+            float best = 1e30f;
+            if (p.x_solver == GP_XSOLVER_AUTO) {
+                ms.xchain = false;
+                rc = pair(best);
+            }
+            const bool k0 = ms.xchain;
+            const int kt = ms.xctile, ko = ms.xorder;
+            bool bestC = k0;
+            int bestT = kt, bestO = ko;
+            for (int t = 0; t < gp::kNumChainTiles && rc == GP_OK; ++t) {
+                if (!xchain_fits<T>(ms.hhx, ms.x.Kg, t, ms.hcx, ms.Lcx)) continue;
+                for (int o = o0; o < o1 && rc == GP_OK; ++o) {
+                    ms.xchain = true;
+                    ms.xctile = t;
+                    ms.xorder = o;
+                    float tt = 0.f;
+                    rc = pair(tt);
+                    if (rc == GP_OK && tt < best) { best = tt; bestC = true; bestT = t; bestO = o; }
+                }
+            }
+            ms.xchain = bestC;
+            ms.xctile = bestT;
+            ms.xorder = bestO;
+            if (ms.xchain) xchain_fits<T>(ms.hhx, ms.x.Kg, bestT, ms.hcx, ms.Lcx);
+        }
+        if (p.y_tile == 0 && ms.window && p.y_solver != GP_YSOLVER_CHAIN) {
             float best = 1e30f;
             int bestT = ms.ytile, bestO = ms.yorder;
             for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
@@ -748,10 +855,35 @@ int autotune_t(gp_spin1* h) {
             ms.yorder = bestO;
             tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(bestT)), ms.h, ms.L);
         }
+        // y chain windows: against the choice above (AUTO), or the fastest chain tile (CHAIN)
+        if (rc == GP_OK && p.y_tile == 0 && (p.y_solver == GP_YSOLVER_AUTO || p.y_solver == GP_YSOLVER_CHAIN)) {
+            float best = 1e30f;
+            if (p.y_solver == GP_YSOLVER_AUTO) {
+                ms.ychain = false;
+                rc = pair(best);
+            }
+            bool bestC = ms.ychain;
+            int bestT = ms.yctile, bestO = ms.yorder;
+            for (int t = 0; t < gp::kNumChainTiles && rc == GP_OK; ++t) {
+                if (!ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, ms.hcy, ms.Lcy)) continue;
+                for (int o = p0; o < std::min(p1, 3) && rc == GP_OK; ++o) {
+                    ms.ychain = true;
+                    ms.yctile = t;
+                    ms.yorder = o;
+                    float tt = 0.f;
+                    rc = pair(tt);
+                    if (rc == GP_OK && tt < best) { best = tt; bestC = true; bestT = t; bestO = o; }
+                }
+            }
+            ms.ychain = bestC;
+            ms.yctile = bestT;
+            ms.yorder = bestO;
+            if (ms.ychain) ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, bestT, ms.hcy, ms.Lcy);
+        }
         if (p.block_order == GP_ORDER_ROWS) ms.xorder = 3;
         // row bands for both sweeps (only as a pair: each sweep then reads what the
         // other wrote on the same XCD), where the y sweep has windows
-        if (rc == GP_OK && ms.window && p.block_order == GP_ORDER_AUTO) {
+        if (rc == GP_OK && ms.window && !ms.ychain && !ms.xchain && p.block_order == GP_ORDER_AUTO) {
             const int kx = ms.xorder, ky = ms.yorder;
             const bool kw = ms.xwindow;
             // (the final choice: longer measurements than the sweeps above)
@@ -773,21 +905,7 @@ int autotune_t(gp_spin1* h) {
             ms.yorder = by;
             ms.xwindow = bw;
         }
-        ms.plan.x_points_per_thread = ms.xK;
-        ms.plan.x_threads_per_row = ms.xG;
-        ms.plan.x_rows_per_block = ms.xR;
-        ms.plan.x_solver = ms.xwindow ? GP_XSOLVER_WINDOW : GP_XSOLVER_SCAN;
-        ms.plan.x_halo = ms.xwindow ? ms.hx : 0;
-        ms.plan.x_points_out = ms.xwindow ? ms.Lx : 0;
-        ms.plan.x_tile = ms.xwindow ? ms.xtile + 1 : 0;
-        ms.plan.x_block_order = ms.xorder == 3 && !ms.window ? (ms.xwindow ? 1 : 0) : ms.xwindow || ms.xorder == 3 ? ms.xorder : 0;
-        ms.plan.y_block_order = ms.window ? ms.yorder : 0;
-        const gp::YTile yt = gp::ytile<T>(ms.ytile);
-        ms.plan.y_tile = ms.ytile + 1;
-        ms.plan.y_tile_cols = 4 * yt.NW;
-        ms.plan.y_segments = 16;
-        ms.plan.y_rows_per_thread = yt.KY;
-        band_tile(p.ny, ms.window ? ms.yorder : 0, gp::ywindow(yt), ms.h, ms.L, ms.plan.y_halo, ms.plan.y_rows_out);
+        fill_plan<T>(p, ms);
     }
     const double one = 1.0;
     const int zero = 0;
@@ -817,6 +935,10 @@ int create_t(gp_spin1* h) {
             return fail(h, GP_EUNSUPPORTED, "x_points too small for the line-start correction of these lines");
         if (p.x_solver == GP_XSOLVER_WINDOW && !h->mode[m].xwindow)
             return fail(h, GP_EUNSUPPORTED, "x windows asked for, but the decay of the x lines fits no window");
+        if (p.x_solver == GP_XSOLVER_CHAIN && !h->mode[m].xchain)
+            return fail(h, GP_EUNSUPPORTED, "x chain windows asked for, but the decay of the x lines fits no such tile");
+        if (p.y_solver == GP_YSOLVER_CHAIN && !h->mode[m].ychain)
+            return fail(h, GP_EUNSUPPORTED, "y chain windows asked for, but no such tile fits these columns");
     }
     size_t need = 1;
     for (auto& m : h->mode) need = std::max(need, max_y_blocks<T>(p, m));
@@ -863,6 +985,8 @@ gp::XLaunch<T> xlaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.imag = imag; a.local = local;
     a.window = ms.xwindow; a.L = ms.Lx; a.h = ms.hx; a.tile = ms.xtile;
     a.order = ms.xorder;
+    a.chain = ms.xchain;
+    if (ms.xchain) { a.window = false; a.L = ms.Lcx; a.h = ms.hcx; a.tile = ms.xctile; }
     // row bands follow the y sweep's row tiles (none without y windows)
     int hb = 0, Lb = 0;
     if (ms.window) band_tile(h->p.ny, ms.yorder, gp::ywindow(gp::ytile<T>(ms.ytile)), ms.h, ms.L, hb, Lb);
@@ -885,6 +1009,8 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.window = ms.window; a.imag = imag; a.norm = norm;
     a.outl = false;
     a.order = ms.yorder;
+    a.chain = ms.ychain;
+    if (ms.ychain) { a.L = ms.Lcy; a.h = ms.hcy; a.tile = ms.yctile; }
     a.sp = sp;
     a.dp = dp;
     return a;
@@ -949,7 +1075,7 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     // between); otherwise one block sums them into the scale factors.  The last
     // step's partials always go through that block (for the final scaling).
     gp::XLaunch<T> xn = xa;
-    const bool fold = imag && !xa.window && 3 * nyb <= 8 * xa.G * xa.R;
+    const bool fold = imag && !xa.window && !xa.chain && 3 * nyb <= 8 * xa.G * xa.R;
     if (fold) xn.nin = gp::NormIn{h->d_part, nyb, dxdy, rule, h->d_flag};
     for (int64_t s = 0; s < n; ++s) {
         const gp::XLaunch<T>& x = s > 0 ? xn : xa;
@@ -1580,13 +1706,15 @@ int gp_spin1_plan_query(const gp_spin1_params* p, int32_t imag, gp_spin1_plan* o
         if (std::isnan(q.x0)) q.x0 = -0.5 * q.nx * q.dx;
         if (std::isnan(q.y0)) q.y0 = -0.5 * q.ny * q.dy;
         HostMode hm;
+        ModeState ms;
         if (q.precision == GP_FP64) {
             host_mode<double>(q, imag != 0, hm);
-            fill_plan<double>(q, hm, out);
+            copy_plan<double>(q, hm, ms);
         } else {
             host_mode<float>(q, imag != 0, hm);
-            fill_plan<float>(q, hm, out);
+            copy_plan<float>(q, hm, ms);
         }
+        *out = ms.plan;
         return GP_OK;
     });
 }

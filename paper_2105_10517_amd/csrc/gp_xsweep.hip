@@ -7,8 +7,9 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <climits>
 
-#include "gp_solve.hpp"
+#include "gp_chain.hpp"
 
 namespace gp {
 
@@ -270,6 +271,80 @@ __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ 
     x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, L, h, cs, rt, rlo, rhi);
 }
 
+// ---------------------------------------------------------------------------
+// x sweep over chain windows (gp_chain.hpp): one row segment of W = 64 K
+// points per wave, K consecutive points per lane, carries over nc lanes; the
+// window starting at point cs L - h writes the points [cs L, cs L + L),
+// L = W - 2 h.  Windows at the row ends take the EDGE path; the first window
+// of a row also applies the line-start correction (point 0 is the window's
+// point h).  Waves are independent (no shared memory, no barrier): wave w of
+// logical block lb takes window lb NW + w of the row-major window list.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, int K, int NW, bool SEQ, bool LOCAL, bool SCALE>
+__global__ __launch_bounds__(64 * NW) void k_x_chain(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                     size_t sp, size_t dp, Phys ph, LineSet<T> ls,
+                                                     const double* __restrict__ scale, int h, int nc, int L, int nwin,
+                                                     int nblk, int order) {
+    using C = cx<T>;
+    const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, nblk, 1);
+    if (lb < 0) return;
+    const int lane = threadIdx.x & 63;
+    const int gw = lb * NW + (int)(threadIdx.x >> 6);
+    const int nx = ph.nx;
+    if (gw >= nwin * ph.ny) return;  // whole waves
+    const int j = gw / nwin, cs = gw - j * nwin;
+    const int i0 = cs * L;           // first point written
+    const int s0 = i0 - h;           // first point of the window
+    const int g0 = s0 + lane * K;    // first point of this lane
+    const C* rowp = src + (size_t)j * nx;
+    const bool edge = s0 < 0 || s0 + 64 * K > nx;  // wave-uniform
+    C v[3][K];
+    if (!edge) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) v[m][k] = rowp[m * sp + g0 + k];
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int g = g0 + k;
+            const bool ok = g >= 0 && g < nx;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) v[m][k] = ok ? rowp[m * sp + (ok ? g : 0)] : zero_c<C>();
+        }
+    }
+    if (SCALE) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const T sc = (T)scale[m];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[m][k] = cscale(v[m][k], sc);
+        }
+    }
+    if (LOCAL) {
+        const T y = (T)(ph.y0 + j * ph.dy);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const T x = (T)(ph.x0 + (g0 + k) * ph.dx);
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], trap_v<T>(ph, x, y), (T)ph.dtl, (T)ph.c0, (T)ph.c2,
+                                   (T)ph.rabi);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) to_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    if (!edge) chain_lines<T, K, IMAG, true, false, SEQ>(v, ls, j * 3, nc, g0, nx, false, 0, 0);
+    else chain_lines<T, K, IMAG, true, true, SEQ>(v, ls, j * 3, nc, g0, nx, cs == 0, h / K, h % K);
+#pragma unroll
+    for (int k = 0; k < K; ++k) from_sy<C, T>(v[0][k], v[1][k], v[2][k]);
+    C* rowq = dst + (size_t)j * nx;
+    const int i1 = min(i0 + L, nx);
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        if (g0 + k >= i0 && g0 + k < i1)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) rowq[m * dp + g0 + k] = v[m][k];
+}
+
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
 __global__ __launch_bounds__(LB) void k_x_scan(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
                                                size_t dp, Phys ph,
@@ -369,8 +444,45 @@ static hipError_t launch_xw(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
     }
 }
 
+template <typename T, bool IMAG, bool LOCAL, bool SCALE, int TI>
+static hipError_t launch_xc_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    constexpr ChainTile ct = xchain_tile<T>(TI);
+    // the window (64 K points) writes L = 64 K - 2 h of them; the first window holds the corrected points
+    if (a.h < 1 || a.L != 64 * ct.K - 2 * a.h || a.L <= 0 || a.ls.Kg > a.L) return hipErrorInvalidValue;
+    const int nwin = (a.ph.nx + a.L - 1) / a.L;
+    const long nwav = (long)nwin * a.ph.ny;
+    if ((nwav + ct.NW - 1) / ct.NW > INT_MAX / 2) return hipErrorInvalidValue;
+    const int nblk = (int)((nwav + ct.NW - 1) / ct.NW);
+    const int grid = a.order ? xcd_blocks(nblk) : nblk;
+    hipExtLaunchKernelGGL(k_x_chain<T, IMAG, ct.K, ct.NW, ct.SEQ, LOCAL, SCALE>, dim3(grid), dim3(64 * ct.NW), 0, st, e0,
+                          e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.h, chain_lanes(a.h, ct.K), a.L, nwin,
+                          nblk, a.order);
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG, bool LOCAL, bool SCALE>
+static hipError_t launch_xc(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    switch (a.tile) {
+        case 0: return launch_xc_t<T, IMAG, LOCAL, SCALE, 0>(a, st, e0, e1);
+        case 1: return launch_xc_t<T, IMAG, LOCAL, SCALE, 1>(a, st, e0, e1);
+        case 2: return launch_xc_t<T, IMAG, LOCAL, SCALE, 2>(a, st, e0, e1);
+        case 3: return launch_xc_t<T, IMAG, LOCAL, SCALE, 3>(a, st, e0, e1);
+        case 4: return launch_xc_t<T, IMAG, LOCAL, SCALE, 4>(a, st, e0, e1);
+        case 5: return launch_xc_t<T, IMAG, LOCAL, SCALE, 5>(a, st, e0, e1);
+        case 6: return launch_xc_t<T, IMAG, LOCAL, SCALE, 6>(a, st, e0, e1);
+        case 7: return launch_xc_t<T, IMAG, LOCAL, SCALE, 7>(a, st, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (a.chain) {
+        // (the scale factors come from `scale`)
+        if (a.nin.partials != nullptr) return hipErrorInvalidValue;
+        if (a.imag) return a.local ? launch_xc<T, true, true, true>(a, st, e0, e1) : launch_xc<T, true, false, false>(a, st, e0, e1);
+        return a.local ? launch_xc<T, false, true, false>(a, st, e0, e1) : launch_xc<T, false, false, false>(a, st, e0, e1);
+    }
     if (a.window) {
         // the windowed kernel takes its scale factors from `scale` (the norm totals are formed beforehand)
         if (a.nin.partials != nullptr) return hipErrorInvalidValue;

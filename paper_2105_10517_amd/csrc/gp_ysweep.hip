@@ -10,7 +10,7 @@
 //                column, forward eliminations stored in place).
 #include <hip/hip_ext.h>
 
-#include "gp_solve.hpp"
+#include "gp_chain.hpp"
 
 namespace gp {
 
@@ -90,6 +90,85 @@ __global__ __launch_bounds__(64 * NW) void k_y_window(const cx<T>* __restrict__ 
     const int lb = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
     if (lb < 0) return;
     y_window<T, IMAG, KY, NW, SEQ, NORM, OUTL>(src, dst, sp, dp, ph, ls, L, h, ncs, no, lb);
+}
+
+// ---------------------------------------------------------------------------
+// y sweep over chain windows (gp_chain.hpp): 4 columns per wave, 16 segments
+// of KY rows per column (one DPP row of lanes), carries over nc segments
+// within the DPP row; the window starting at row rt L - h writes the rows
+// [rt L, rt L + L), L = 16 KY - 2 h.  Norm partials and the Strang half
+// substep as in y_window.  Addresses are 32-bit byte offsets within a plane
+// from the planes' base pointers (one offset per row serves all three
+// components); the host keeps a plane below 2^32 bytes.
+// ---------------------------------------------------------------------------
+template <typename T, bool IMAG, int KY, int NW, bool SEQ, bool NORM, bool OUTL>
+__global__ __launch_bounds__(64 * NW) void k_y_chain(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                     size_t sp, size_t dp, Phys ph, LineSet<T> ls, int L, int h, int nc,
+                                                     int ncs, NormOut no, int nblk, int order) {
+    using C = cx<T>;
+    constexpr int CPB = 4 * NW;  // columns per block
+    __shared__ double shr[48];
+    const int blk = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
+    if (blk < 0) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int seg = lane & 15, cw = lane >> 4;
+    const int cs = blk % ncs, rt = blk / ncs;
+    const int i = cs * CPB + wv * 4 + cw;
+    const bool col_ok = i < ph.nx;
+    const int nx = ph.nx, ny = ph.ny;
+    const int j0 = rt * L;             // first row written
+    const int s0 = j0 - h;             // first row of the window
+    const int g0 = s0 + seg * KY;      // first row of this lane
+    const bool edge = s0 < 0 || s0 + 16 * KY > ny;  // block-uniform
+    const unsigned col = col_ok ? (unsigned)i : 0u;
+    const unsigned pb = (unsigned)nx * (unsigned)ny * (unsigned)sizeof(C);  // bytes of a plane
+    __amdgpu_buffer_rsrc_t rs[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) rs[m] = plane_rsrc(src + m * sp, pb);
+    C v[3][KY];
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        const bool ok = col_ok && (!edge || (g >= 0 && g < ny));
+        const unsigned o = ((unsigned)(ok ? g : 0) * (unsigned)nx + col) * (unsigned)sizeof(C);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? buf_load<C>(rs[m], o) : zero_c<C>();
+    }
+#pragma unroll
+    for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    const int line0 = (int)col * 3;
+    if (!edge) chain_lines<T, KY, IMAG, false, false, SEQ>(v, ls, line0, nc, g0, ny, false, 0, 0);
+    else chain_lines<T, KY, IMAG, false, true, SEQ>(v, ls, line0, nc, g0, ny, rt == 0, (lane & ~15) + h / KY, h % KY);
+#pragma unroll
+    for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    if (OUTL) {
+        // Strang: the second half local substep, on the way out
+        const T x = (T)(ph.x0 + (int)col * ph.dx);
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            const T y = (T)(ph.y0 + (g0 + k) * ph.dy);
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], trap_v<T>(ph, x, y), (T)ph.dtl, (T)ph.c0, (T)ph.c2,
+                                   (T)ph.rabi);
+        }
+    }
+    __amdgpu_buffer_rsrc_t rd[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) rd[m] = plane_rsrc(dst + m * dp, pb);
+    const int j1 = min(j0 + L, ny);
+    double acc[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        if (col_ok && g >= j0 && g < j1) {
+            const unsigned o = ((unsigned)g * (unsigned)nx + col) * (unsigned)sizeof(C);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                buf_store(v[m][k], rd[m], o);
+                if (NORM) acc[m] += (double)cnorm2(v[m][k]);
+            }
+        }
+    }
+    if (NORM) store_norm_partials(acc, shr, no, blk);
 }
 
 template <typename T, bool IMAG, int KY, int NW, bool SEQ>
@@ -210,8 +289,46 @@ static hipError_t launch_yw(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
     }
 }
 
+template <typename T, bool IMAG, bool NORM, bool OUTL, int TI>
+static hipError_t launch_yc_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    constexpr ChainTile ct = ychain_tile<T>(TI);
+    // the window (16 KY rows) writes L = 16 KY - 2 h rows; the first window holds the corrected rows;
+    // byte offsets within a plane fit 32 bits
+    if (a.h < 1 || a.L != 16 * ct.K - 2 * a.h || a.L <= 0 || a.ls.Kg > a.L ||
+        (double)a.ph.nx * a.ph.ny * sizeof(cx<T>) >= 4294967296.0)
+        return hipErrorInvalidValue;
+    const int ncs = (a.ph.nx + 4 * ct.NW - 1) / (4 * ct.NW);
+    const int nrt = (a.ph.ny + a.L - 1) / a.L;
+    const int nblk = ncs * nrt;
+    hipExtLaunchKernelGGL(k_y_chain<T, IMAG, ct.K, ct.NW, ct.SEQ, NORM, OUTL>, dim3(xcd_grid(a.order, ncs, nrt)),
+                          dim3(64 * ct.NW), 0, st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.L, a.h,
+                          chain_lanes(a.h, ct.K), ncs, a.no, nblk, a.order);
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG, bool NORM, bool OUTL>
+static hipError_t launch_yc(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (a.order == 3) return hipErrorInvalidValue;  // (row bands: scanned windows only)
+    switch (a.tile) {
+        case 0: return launch_yc_t<T, IMAG, NORM, OUTL, 0>(a, st, e0, e1);
+        case 1: return launch_yc_t<T, IMAG, NORM, OUTL, 1>(a, st, e0, e1);
+        case 2: return launch_yc_t<T, IMAG, NORM, OUTL, 2>(a, st, e0, e1);
+        case 3: return launch_yc_t<T, IMAG, NORM, OUTL, 3>(a, st, e0, e1);
+        case 4: return launch_yc_t<T, IMAG, NORM, OUTL, 4>(a, st, e0, e1);
+        case 5: return launch_yc_t<T, IMAG, NORM, OUTL, 5>(a, st, e0, e1);
+        case 6: return launch_yc_t<T, IMAG, NORM, OUTL, 6>(a, st, e0, e1);
+        case 7: return launch_yc_t<T, IMAG, NORM, OUTL, 7>(a, st, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 int y_blocks(const YLaunch<T>& a) {
+    if (a.chain) {
+        const ChainTile ct = ychain_tile<T>(a.tile);
+        const int ncs = (a.ph.nx + 4 * ct.NW - 1) / (4 * ct.NW);
+        return ncs * ((a.ph.ny + a.L - 1) / a.L);
+    }
     if (a.window) {
         const YTile yt = ytile<T>(a.tile);
         const int ncs = (a.ph.nx + 4 * yt.NW - 1) / (4 * yt.NW);
@@ -230,6 +347,7 @@ static hipError_t launch_yt(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
 // (imag, norm, outl): the steps use (1, 1, *) and (0, 0, *); the substep calls (*, 0, 0).
 template <typename T, bool IMAG, bool NORM, bool OUTL>
 static hipError_t launch_y_v(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (a.chain) return launch_yc<T, IMAG, NORM, OUTL>(a, st, e0, e1);
     return a.window ? launch_yw<T, IMAG, NORM, OUTL>(a, st, e0, e1) : launch_yt<T, IMAG, NORM, OUTL>(a, st, e0, e1);
 }
 
