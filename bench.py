@@ -1,21 +1,23 @@
 #!/usr/bin/env python
 """Throughput of the split-step Crank-Nicolson spin-1 step on one MI355X.
 
-Headline workload: 512 x 512 real-time run (Dresselhaus gamma = 1, Rabi 0.2,
-Omega = 0.9, c0 = 200, c2 = +5, dx = 0.05, dt = 1e-4) started from the
-imaginary-time state of the same parameters plus seeded complex noise of 1e-3;
-a step is one whole SSCN step (local substep, x sweep, y sweep).  Timed in
-FP64 (the headline value) and in FP32 bulk.  Also timed: 4096 x 4096
-imaginary-time steps (Rashba gamma = 0.75, Omega = 0.95, c0 = 1000, c2 = -20,
-dx = 0.02), the grid whose state (805 MB in FP64) does not fit in the caches,
-which gives the honest HBM roofline fraction.  All inputs are seeded and
-synthetic.
+Headline workload (``value``): the 4096 x 4096 imaginary-time run (Rashba
+gamma = 0.75, Omega = 0.95, c0 = 1000, c2 = -20, Rabi 0, dx = 0.02,
+dt = 0.1 dx^2) from a seeded random-phase Gaussian, in FP64; a step is one
+whole SSCN step (local substep, x sweep, y sweep, renormalisation).  Its
+state (805 MB in FP64) does not fit in the caches, so the roofline fraction
+is an HBM figure.  Beside it: the same grid in FP32 bulk (FP64 reductions),
+with its error against the FP64 oracle; the 128^2 ground-state run (200
+imaginary-time steps, timed in full); the 512^2 real-time run from the
+imaginary-time state of its parameters plus 1e-3 noise; the 256-condensate
+parameter scan (batched FP32 against one-at-a-time FP32 and FP64); and the
+serving trace (Poisson arrivals, 200 per second, 2000 requests).  All inputs
+are seeded and synthetic, resident in device memory before any timed region.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -39,7 +41,9 @@ def bytes_per_complex(prec):
 
 def kernel_roofline(timing, npts, prec):
     """Roofline of the dominant sweep kernel: algorithmic bytes per launch
-    (read + write of the 3 components, 6 s bytes per point) / mean launch time."""
+    (read + write of the 3 components, 6 s bytes per point) / mean launch
+    duration, from event pairs that the kernel dispatches themselves stamp on
+    the solver's stream."""
     per_launch = 6 * bytes_per_complex(prec) * npts
     rows = {}
     for kind in ("x_sweep", "y_sweep"):
@@ -48,21 +52,43 @@ def kernel_roofline(timing, npts, prec):
             avg_s = t["ms"] / t["launches"] / 1e3
             rows[kind] = {"avg_us": avg_s * 1e6, "achieved_GBps": per_launch / avg_s / 1e9,
                           "frac": per_launch / avg_s / HBM_PEAK_BPS, "total_ms": t["ms"]}
+    other = {k: round(v["ms"] / v["launches"] * 1e3, 2) for k, v in timing.items()
+             if k not in rows and v["launches"]}
     dom = max(rows, key=lambda k: rows[k]["total_ms"])
     d = rows[dom]
     return {"bound": "hbm", "kernel": dom, "achieved": round(d["achieved_GBps"], 1), "peak": HBM_PEAK_BPS / 1e9,
             "unit": "GB/s", "frac": round(d["frac"], 4), "traffic": None,
             "bytes_per_launch": per_launch,
-            "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in rows.items()}}
+            "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in rows.items()},
+            "other_kernels_avg_us": other}
 
 
-TILES = {"fp64": [(8, 2), (8, 4), (4, 4), (4, 8)], "fp32": [(8, 4), (4, 8), (4, 4), (8, 8)]}
+XTILES = {"fp64": [(4, 4), (8, 2), (2, 4), (4, 2)], "fp32": [(4, 4), (8, 4), (8, 2), (16, 2)]}
+YCTILES = {"fp64": [(8, 2), (8, 4), (4, 4), (7, 4)], "fp32": [(8, 4), (8, 8), (4, 4), (16, 2)]}
+WTILES = {"fp64": [(8, 2), (8, 4), (4, 4), (4, 8)], "fp32": [(8, 4), (4, 8), (4, 4), (8, 8)]}
 
 
-def tile_args(prec, tile):
-    """Template arguments (points per lane, waves, lines one at a time) of window tile 1..8."""
-    kk, nw = TILES[prec][(tile - 1) & 3]
+def tile_args(table, prec, tile):
+    """Template arguments (points per lane, waves, lines one at a time) of tile 1..8."""
+    kk, nw = table[prec][(tile - 1) & 3]
     return f"{kk}, {nw}, {'true' if (tile - 1) & 4 else 'false'}, "
+
+
+def kernel_prefix(kind, prec, imag, plan):
+    """Name prefix of the kernel a plan launches for one sweep."""
+    T = "double" if prec == "fp64" else "float"
+    im = "true" if imag else "false"
+    if kind == "x_sweep":
+        if plan["x_solver"] == 3:
+            return f"gp::k_x_chain<{T}, {im}, " + tile_args(XTILES, prec, plan["x_tile"])
+        if plan["x_solver"] == 2:
+            return f"gp::k_x_window<{T}, {im}, " + tile_args(WTILES, prec, plan["x_tile"])
+        return f"gp::k_x_scan<{T}, {im}, {plan['x_points_per_thread']}, "
+    if plan["y_solver"] == 3:
+        return f"gp::k_y_chain<{T}, {im}, " + tile_args(YCTILES, prec, plan["y_tile"])
+    if plan["y_solver"] == 2:
+        return f"gp::k_y_thomas<{T}, {im}, "
+    return f"gp::k_y_window<{T}, {im}, " + tile_args(WTILES, prec, plan["y_tile"])
 
 
 def traffic_for(roof, prec, imag, plan, workload):
@@ -70,15 +96,7 @@ def traffic_for(roof, prec, imag, plan, workload):
     summary, or None when there is none for these kernel sources."""
     from paper_2105_10517_amd import profile_summary
     t = profile_summary.read_traffic(os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec}.md"))
-    T = "double" if prec == "fp64" else "float"
-    im = "true" if imag else "false"
-    if roof["kernel"] == "x_sweep":
-        if plan["x_solver"] == 2:
-            prefix = f"gp::k_x_window<{T}, {im}, " + tile_args(prec, plan["x_tile"])
-        else:
-            prefix = f"gp::k_x_scan<{T}, {im}, {plan['x_points_per_thread']}, "
-    else:
-        prefix = f"gp::k_y_window<{T}, {im}, " + tile_args(prec, plan["y_tile"])
+    prefix = kernel_prefix(roof["kernel"], prec, imag, plan)
     for k, v in t.items():
         if k.startswith(prefix):
             return v
@@ -86,7 +104,8 @@ def traffic_for(roof, prec, imag, plan, workload):
 
 
 def time_steps(solver, t, nsteps, imag, torch):
-    st = torch.cuda.current_stream()
+    """Wall time in ms of nsteps on the solver's stream (events on that stream)."""
+    st = solver.stream
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(st)
@@ -103,54 +122,6 @@ def kernel_timing(solver, t, nsteps, imag):
     res = solver.timing_read()
     solver.timing(False)
     return res
-
-
-def c2_initial_state(torch, binding, inputs):
-    """Imaginary-time state of the headline parameters (dt = 0.1 dx^2, stop at
-    |dE|/E < 1e-10 over 100 steps or 20000 steps), plus 1e-3 noise (seed 3)."""
-    p = inputs.config_c2()
-    q = dict(p, dt=0.1 * p["dx"] * p["dx"])
-    psi = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], seed=2, phase_noise=0.1)
-    s = binding.Solver(q, "fp64")
-    t = torch.from_numpy(psi).to("cuda")
-    e_prev, steps = None, 0
-    while steps < 20000:
-        s.step_imag(t, 100)
-        steps += 100
-        e = s.observables(t)["energy"]
-        if e_prev is not None and abs(e - e_prev) < 1e-10 * abs(e):
-            break
-        e_prev = e
-    log(f"[bench] C2 initial state: {steps} imaginary-time steps, E = {e:.10f}")
-    out = inputs.add_noise(t.cpu().numpy(), p["dx"], p["dy"], 1e-3, seed=3)
-    s.close()
-    return p, out
-
-
-def cpu_baseline(p, psi0, seconds):
-    """The oracle on all host threads for about `seconds`, and on one thread
-    for a fifth of that."""
-    import oracle
-    threads = oracle.get_threads()
-
-    def rate(budget):
-        t0 = time.perf_counter()
-        psi = oracle.step(p, psi0, 1, False)
-        t1 = time.perf_counter() - t0
-        n = max(1, int(budget / max(t1, 1e-6)))
-        t0 = time.perf_counter()
-        oracle.step(p, psi, n, False)
-        dt = time.perf_counter() - t0
-        return p["nx"] * p["ny"] * n / dt, n, dt
-
-    v, n, dt = rate(seconds)
-    oracle.set_threads(1)
-    v1, n1, dt1 = rate(seconds / 5)
-    oracle.set_threads(threads)
-    return {"value": v, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": f"{n} real-time FP64 steps of the {p['nx']}x{p['ny']} workload (block-Thomas oracle, "
-                      f"{dt:.1f} s)",
-            "value_1_core": v1, "sample_1_core": f"{n1} steps on one thread ({dt1:.1f} s)"}
 
 
 def copy_rate(torch, nbytes, reps=50):
@@ -174,9 +145,86 @@ def copy_rate(torch, nbytes, reps=50):
     return 2 * nbytes / sec
 
 
+def errors_vs_oracle(np, got, obs, want, o, prec):
+    """FP64: relative L2 on psi; FP32 (and FP64): density error relative to
+    the peak density, relative errors of mu_total and of each mu_m."""
+    rho_g, rho_w = np.abs(got) ** 2, np.abs(want) ** 2
+    out = {"psi_rel_l2": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+           "density_err": float(np.abs(rho_g - rho_w).max() / rho_w.max()),
+           "mu_err": abs(obs["mu_total"] - o["mu_total"]) / abs(o["mu_total"]),
+           "mu_m_err": max(abs(obs["mu"][m] - o["mu"][m]) / abs(o["mu"][m]) for m in range(3) if o["mu"][m] != 0)}
+    return {k: float(f"{v:.3e}") for k, v in out.items()}
+
+
+def gpu_state(torch, np, binding, p, psi0, prec, nsteps, imag, **kw):
+    """psi after nsteps on a fresh solver (with the given launch options), and its observables."""
+    s = binding.Solver(p, prec, **kw)
+    t = torch.from_numpy(psi0).to("cuda").to(s.dtype)
+    (s.step_imag if imag else s.step_real)(t, nsteps)
+    s.sync()
+    obs = s.observables(t)
+    out = t.cpu().numpy().astype(np.complex128)
+    s.close()
+    del t
+    return out, obs
+
+
+def single_solve(torch, binding, p, psi0, prec, imag, steps, warmup, timing_steps, autotune=True):
+    """Steps/s of one condensate: autotuned launch shapes, warm-up, timed steps,
+    then a separate pass with per-kernel timing."""
+    s = binding.Solver(p, prec, autotune=autotune)
+    t = torch.from_numpy(psi0).to("cuda").to(s.dtype)
+    if warmup:
+        (s.step_imag if imag else s.step_real)(t, warmup)
+    ms = time_steps(s, t, steps, imag, torch)
+    tim = kernel_timing(s, t, timing_steps, imag)
+    plan = s.plan(imag)
+    norm = s.observables(t)["norm_total"]
+    s.close()
+    del t
+    torch.cuda.empty_cache()
+    return ms, tim, plan, norm
+
+
+def c2_initial_state(torch, binding, inputs):
+    """Imaginary-time state of the 512^2 real-time parameters (dt = 0.1 dx^2,
+    stop at |dE|/E < 1e-10 over 100 steps or 20000 steps), plus 1e-3 noise (seed 3)."""
+    p = inputs.config_c2()
+    q = dict(p, dt=0.1 * p["dx"] * p["dx"])
+    psi = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], seed=2, phase_noise=0.1)
+    s = binding.Solver(q, "fp64")
+    t = torch.from_numpy(psi).to("cuda")
+    e_prev, steps, e = None, 0, 0.0
+    while steps < 20000:
+        s.step_imag(t, 100)
+        steps += 100
+        e = s.observables(t)["energy"]
+        if e_prev is not None and abs(e - e_prev) < 1e-10 * abs(e):
+            break
+        e_prev = e
+    log(f"[bench] 512^2 initial state: {steps} imaginary-time steps, E = {e:.10f}")
+    out = inputs.add_noise(t.cpu().numpy(), p["dx"], p["dy"], 1e-3, seed=3)
+    s.close()
+    return p, out
+
+
+def oracle_run(p, psi0, nsteps, imag, seconds=None):
+    """The oracle (all host threads): nsteps, or as many as fit `seconds`
+    after a one-step probe.  Returns (state, steps, wall seconds)."""
+    import oracle
+    if seconds is not None:
+        t0 = time.perf_counter()
+        oracle.step(p, psi0, 1, imag)
+        t1 = time.perf_counter() - t0
+        nsteps = max(2, int(round(seconds / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    out = oracle.step(p, psi0, nsteps, imag)
+    return out, nsteps, time.perf_counter() - t0
+
+
 def batch_c4(torch, binding, inputs, nsteps):
-    """256 condensates of the parameter scan (FP32 bulk, imaginary time) in
-    batched launches, against the same solves one at a time in FP64."""
+    """256 condensates of the parameter scan (imaginary time) in batched FP32
+    launches, against the same solves one at a time in FP32 and in FP64."""
     ps = inputs.batch_scan(256, seed=5)
     psi0 = [inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], x0=p["x0"], y0=p["y0"], seed=1000 + k)
             for k, p in enumerate(ps)]
@@ -187,37 +235,50 @@ def batch_c4(torch, binding, inputs, nsteps):
     b.sync()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record()
+    e0.record(b.stream)
     b.step(ts, [nsteps] * len(ps), ["imag"] * len(ps))
-    e1.record()
+    e1.record(b.stream)
     b.sync()
     torch.cuda.synchronize()
     ms_b = e0.elapsed_time(e1)
     info = b.info()
     b.close()
     del ts
-    # the same solves one at a time, FP64
-    t64 = [torch.from_numpy(a).to("cuda") for a in psi0]
-    solvers = [binding.Solver(p, "fp64") for p in ps]
-    for s_, t in zip(solvers, t64):
-        s_.step_imag(t, 5)
-    torch.cuda.synchronize()
-    e0.record()
-    for s_, t in zip(solvers, t64):
-        s_.step_imag(t, nsteps)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_s = e0.elapsed_time(e1)
-    for s_ in solvers:
-        s_.close()
-    del t64
-    torch.cuda.empty_cache()
+
+    def one_at_a_time(prec):
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
+        tt = [torch.from_numpy(a).to(dt).to("cuda") for a in psi0]
+        solvers = [binding.Solver(p, prec) for p in ps]
+        for s_, t in zip(solvers, tt):
+            s_.step_imag(t, 5)
+        st = solvers[0].stream
+        torch.cuda.synchronize()
+        e0.record(st)
+        for s_, t in zip(solvers, tt):
+            s_.step_imag(t, nsteps)
+        e1.record(st)
+        torch.cuda.synchronize()
+        for s_ in solvers:
+            s_.close()
+        del tt
+        torch.cuda.empty_cache()
+        return e0.elapsed_time(e1)
+
+    ms_32 = one_at_a_time("fp32")
+    ms_64 = one_at_a_time("fp64")
+    bps = 96 * pts / (ms_b / 1e3)  # 12 s bytes per point-step, s = 8
     out = {"workload": f"256 condensates, N = 32 k (k ~ U{{4..16}}), {nsteps} imaginary-time steps each",
-           "value_fp32_batched": pts / (ms_b / 1e3), "value_fp64_one_at_a_time": pts / (ms_s / 1e3),
-           "ms_batched": ms_b, "ms_one_at_a_time": ms_s, "unit": UNIT, "grouped": info["grouped"],
-           "individual": info["individual"], "x_points": info["x_points"][0], "y_tile": info["y_tile"][0]}
-    log(f"[bench] C4 batch: FP32 batched {out['value_fp32_batched']:.3e} pt-steps/s vs FP64 one at a time "
-        f"{out['value_fp64_one_at_a_time']:.3e} ({ms_b:.1f} ms vs {ms_s:.1f} ms)")
+           "value_fp32_batched": pts / (ms_b / 1e3), "value_fp32_one_at_a_time": pts / (ms_32 / 1e3),
+           "value_fp64_one_at_a_time": pts / (ms_64 / 1e3),
+           "ms_batched": ms_b, "ms_fp32_one_at_a_time": ms_32, "ms_fp64_one_at_a_time": ms_64, "unit": UNIT,
+           "roofline_batched": {"bound": "hbm", "achieved": round(bps / 1e9, 1), "peak": HBM_PEAK_BPS / 1e9,
+                                "unit": "GB/s", "frac": round(bps / HBM_PEAK_BPS, 4),
+                                "basis": "12 s = 96 B per 3-comp point-step over the whole batched step"},
+           "grouped": info["grouped"], "individual": info["individual"], "x_points": info["x_points"][0],
+           "y_tile": info["y_tile"][0]}
+    log(f"[bench] C4 batch: FP32 batched {out['value_fp32_batched']:.3e} pt-steps/s ({bps / 1e12:.2f} TB/s), "
+        f"FP32 one at a time {out['value_fp32_one_at_a_time']:.3e}, FP64 one at a time "
+        f"{out['value_fp64_one_at_a_time']:.3e} ({ms_b:.1f} / {ms_32:.1f} / {ms_64:.1f} ms)")
     return out
 
 
@@ -238,7 +299,10 @@ def serving_c5(torch, binding, inputs, n, rate):
            "mean_latency_s": st["mean_latency"], "served_rate": st["served_rate"],
            "offered_rate": st["offered_rate"], "wall_s": st["wall_s"], "rounds": st["rounds"],
            "mean_in_flight": st["mean_active"], "max_in_flight": st["max_active"], "unit_rate": UNIT}
-    log(f"[bench] C5 serving: p50 {st['p50_latency']:.3f} s, p99 {st['p99_latency']:.3f} s, served "
+    for k in ("gpu_busy", "admit_ms"):
+        if k in st:
+            out[k] = st[k]
+    log(f"[bench] C5 serving {rate:g}/s x {n}: p50 {st['p50_latency']:.3f} s, p99 {st['p99_latency']:.3f} s, served "
         f"{st['served_rate']:.3e} vs offered {st['offered_rate']:.3e} pt-steps/s, {st['mean_active']:.1f} in flight")
     del reqs
     torch.cuda.empty_cache()
@@ -248,21 +312,26 @@ def serving_c5(torch, binding, inputs, n, rate):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000, help="timed SSCN steps of the headline workload")
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--c3-steps", type=int, default=100, help="timed steps of the 4096^2 grid (0 = skip)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline sample length (0 = skip)")
-    ap.add_argument("--timing-steps", type=int, default=500, help="steps of the per-kernel timing pass")
+    ap.add_argument("--steps", type=int, default=200, help="timed SSCN steps of the 4096^2 headline workload")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--timing-steps", type=int, default=40, help="steps of each per-kernel timing pass")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="oracle sample on the 4096^2 grid (also the FP32/FP64 error check; 0 = skip)")
+    ap.add_argument("--c1", type=int, default=1, help="time the 128^2 200-step ground-state run (0 = skip)")
+    ap.add_argument("--c2-steps", type=int, default=2000, help="timed steps of the 512^2 real-time run (0 = skip)")
+    ap.add_argument("--c2-check-steps", type=int, default=300, help="steps of the 512^2 error check against the oracle")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="imaginary-time steps of the 256-condensate batch (0 = skip)")
-    ap.add_argument("--serve-requests", type=int, default=64, help="requests of the serving trace (0 = skip)")
-    ap.add_argument("--serve-rate", type=float, default=25.0, help="arrival rate of the serving trace (1/s)")
+    ap.add_argument("--serve-requests", type=int, default=2000, help="requests of the serving trace (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=200.0, help="arrival rate of the serving trace (1/s)")
+    ap.add_argument("--serve-sweep", default="", help="extra arrival rates to replay (comma list), 10 s of trace each")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (each condensate runs on "
               f"one device and this build has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2105_10517_amd import binding, inputs
     binding.load()
@@ -271,93 +340,138 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
 
-    p, psi0 = c2_initial_state(torch, binding, inputs)
-    npts = p["nx"] * p["ny"]
-    results = {}
+    # ---- headline: 4096^2 imaginary time, FP64 and FP32 ----
+    q = inputs.config_c3(4096)
+    psi3 = inputs.gaussian(4096, 4096, q["dx"], q["dy"], seed=4, full_phase=True)
+    n3 = 4096 * 4096
+    c3 = {}
     for prec in ("fp64", "fp32"):
-        s = binding.Solver(p, prec, autotune=True)
-        t = torch.from_numpy(psi0).to("cuda").to(s.dtype)
-        s.step_real(t, args.warmup)
-        ms = time_steps(s, t, args.steps, False, torch)
-        norm = s.observables(t)["norm_total"]
-        tim = kernel_timing(s, t, args.timing_steps, False)
-        roof = kernel_roofline(tim, npts, prec)
-        roof["traffic"] = traffic_for(roof, prec, False, s.plan(False), "c2_512")
-        cp = copy_rate(torch, 3 * npts * bytes_per_complex(prec))
+        ms, tim, plan, norm = single_solve(torch, binding, q, psi3, prec, True, args.steps, args.warmup,
+                                           args.timing_steps)
+        roof = kernel_roofline(tim, n3, prec)
+        roof["traffic"] = traffic_for(roof, prec, True, plan, "c3_4096")
+        cp = copy_rate(torch, 3 * n3 * bytes_per_complex(prec), reps=10)
         roof["copy_GBps"] = round(cp / 1e9, 1)
         roof["frac_of_copy"] = round(roof["achieved"] * 1e9 / cp, 4)
-        val = npts * args.steps / (ms / 1e3)
-        step_bytes = 12 * bytes_per_complex(prec) * npts
-        results[prec] = {"value": val, "ms_per_step": ms / args.steps, "roofline": roof,
-                         "step_frac": step_bytes / (ms / args.steps / 1e3) / HBM_PEAK_BPS,
-                         "norm_drift": norm - 1.0, "plan": s.plan(False)}
-        log(f"[bench] 512^2 real {prec}: {val:.3e} pt-steps/s, {ms / args.steps * 1e3:.2f} us/step, "
-            f"dominant {roof['kernel']} {roof['achieved']:.0f} GB/s ({roof['frac'] * 100:.1f}% of HBM peak), "
-            f"norm drift {norm - 1:.2e}")
-        s.close()
-        del t
-        torch.cuda.empty_cache()
+        val = n3 * args.steps / (ms / 1e3)
+        step_bytes = 12 * bytes_per_complex(prec) * n3
+        c3[prec] = {"value": val, "ms_per_step": ms / args.steps, "roofline": roof,
+                    "step_frac": step_bytes / (ms / args.steps / 1e3) / HBM_PEAK_BPS, "plan": plan,
+                    "norm_after": norm}
+        log(f"[bench] 4096^2 imag {prec}: {val:.3e} pt-steps/s, {ms / args.steps:.3f} ms/step, step "
+            f"{c3[prec]['step_frac'] * 100:.1f}% of the 12 s B/pt-step roofline; x {roof['kernels']['x_sweep']['avg_us']:.1f} us, "
+            f"y {roof['kernels']['y_sweep']['avg_us']:.1f} us; dominant {roof['kernel']} {roof['frac'] * 100:.1f}%")
 
-    c3 = {}
-    if args.c3_steps > 0:
-        q = inputs.config_c3(4096)
-        psi3 = inputs.gaussian(4096, 4096, q["dx"], q["dy"], seed=4, full_phase=True)
-        n3 = 4096 * 4096
+    # the oracle on the same grid: CPU baseline sample, and the reference for the error of both precisions
+    cpu = None
+    if args.cpu_seconds > 0:
+        want, n_or, sec = oracle_run(q, psi3, None, True, seconds=args.cpu_seconds)
+        import oracle
+        o = oracle.observables(q, want)
+        cpu = {"value": n3 * n_or / sec, "unit": UNIT, "cores": oracle.get_threads(), "kind": "oracle",
+               "sample": f"{n_or} imaginary-time FP64 steps of the 4096x4096 workload from its initial state "
+                         f"(block-Thomas oracle, {sec:.1f} s)"}
         for prec in ("fp64", "fp32"):
-            s = binding.Solver(q, prec, autotune=True)
-            t = torch.from_numpy(psi3).to("cuda").to(s.dtype)
-            s.step_imag(t, 5)
-            ms = time_steps(s, t, args.c3_steps, True, torch)
-            tim = kernel_timing(s, t, max(10, args.c3_steps // 5), True)
-            roof = kernel_roofline(tim, n3, prec)
-            roof["traffic"] = traffic_for(roof, prec, True, s.plan(True), "c3_4096")
-            cp = copy_rate(torch, 3 * n3 * bytes_per_complex(prec), reps=10)
-            roof["copy_GBps"] = round(cp / 1e9, 1)
-            roof["frac_of_copy"] = round(roof["achieved"] * 1e9 / cp, 4)
-            val = n3 * args.c3_steps / (ms / 1e3)
-            step_bytes = 12 * bytes_per_complex(prec) * n3
-            c3[prec] = {"value": val, "ms_per_step": ms / args.c3_steps, "roofline": roof,
-                        "step_frac": step_bytes / (ms / args.c3_steps / 1e3) / HBM_PEAK_BPS}
-            log(f"[bench] 4096^2 imag {prec}: {val:.3e} pt-steps/s, {ms / args.c3_steps:.3f} ms/step, "
-                f"step {c3[prec]['step_frac'] * 100:.1f}% of the 12 s B/pt-step roofline, dominant "
-                f"{roof['kernel']} {roof['frac'] * 100:.1f}%")
+            got, obs = gpu_state(torch, np, binding, q, psi3, prec, n_or, True, autotune=True)
+            c3[prec]["err_vs_oracle"] = dict(errors_vs_oracle(np, got, obs, want, o, prec), steps=n_or)
+            log(f"[bench] 4096^2 {prec} after {n_or} steps vs oracle: {c3[prec]['err_vs_oracle']}")
+        del want, got
+        log(f"[bench] CPU oracle 4096^2: {cpu['value']:.3e} pt-steps/s on {cpu['cores']} threads")
+    del psi3
+
+    # ---- 128^2 ground state, 200 imaginary-time steps, timed in full ----
+    c1 = None
+    if args.c1:
+        import oracle
+        p1 = inputs.config_c1()
+        psi1 = inputs.gaussian(128, 128, 0.1, 0.1, seed=1, phase_noise=0.1)
+        c1 = {"workload": "128x128, dx=0.1, dt=5e-4, 200 imaginary-time steps, c0=50, c2=-1, Rashba gamma=0.5, "
+                          "Omega=0.5; Gaussian with +-0.1 rad phase noise (seed 1)"}
+        want1, _, sec1 = oracle_run(p1, psi1, 200, True)
+        o1 = oracle.observables(p1, want1)
+        threads = oracle.get_threads()
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        oracle.step(p1, psi1, 40, True)
+        sec_one = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        c1["cpu_baseline"] = {"value": 128 * 128 * 200 / sec1, "unit": UNIT, "cores": threads, "kind": "oracle",
+                              "sample": f"the whole 200-step run ({sec1:.2f} s)",
+                              "value_1_core": 128 * 128 * 40 / sec_one, "sample_1_core": f"40 steps ({sec_one:.2f} s)"}
+        for prec in ("fp64", "fp32"):
+            s = binding.Solver(p1, prec, autotune=True)
+            t = torch.from_numpy(psi1).to("cuda").to(s.dtype)
+            s.step_imag(t, 200)  # warm-up run (then a fresh state)
+            t.copy_(torch.from_numpy(psi1).to(s.dtype))
+            ms = time_steps(s, t, 200, True, torch)
+            obs = s.observables(t)
+            got = t.cpu().numpy().astype(np.complex128)
+            t.copy_(torch.from_numpy(psi1).to(s.dtype))
+            tim = kernel_timing(s, t, 200, True)
+            ktot = sum(v["ms"] for v in tim.values())
+            c1[prec] = {"value": 128 * 128 * 200 / (ms / 1e3), "ms_run": ms, "us_per_step": ms / 200 * 1e3,
+                        "kernel_us_per_step": ktot / 200 * 1e3, "plan": s.plan(True),
+                        "err_vs_oracle": dict(errors_vs_oracle(np, got, obs, want1, o1, prec), steps=200)}
+            log(f"[bench] 128^2 imag {prec}: 200 steps in {ms:.2f} ms ({c1[prec]['value']:.3e} pt-steps/s, "
+                f"{c1[prec]['us_per_step']:.2f} us/step, kernels {c1[prec]['kernel_us_per_step']:.2f} us/step); "
+                f"vs oracle {c1[prec]['err_vs_oracle']}")
             s.close()
-            del t
-            torch.cuda.empty_cache()
-        del psi3
+
+    # ---- 512^2 real time from the imaginary-time state ----
+    c2 = None
+    if args.c2_steps > 0:
+        import oracle
+        p, psi0 = c2_initial_state(torch, binding, inputs)
+        npts = p["nx"] * p["ny"]
+        want2, n2, sec2 = oracle_run(p, psi0, args.c2_check_steps, False)
+        o2 = oracle.observables(p, want2)
+        c2 = {"workload": "512x512 real-time SSCN step, Dresselhaus gamma=1, Rabi=0.2, Omega=0.9, c0=200, c2=+5, "
+                          "dx=0.05, dt=1e-4, from the imaginary-time state + 1e-3 noise; 12.6 MB of FP64 state, "
+                          "resident in the caches (no HBM roofline)",
+              "cpu_baseline": {"value": npts * n2 / sec2, "unit": UNIT, "cores": oracle.get_threads(),
+                               "kind": "oracle", "sample": f"{n2} real-time steps ({sec2:.1f} s)"}}
+        for prec in ("fp64", "fp32"):
+            ms, tim, plan, norm = single_solve(torch, binding, p, psi0, prec, False, args.c2_steps, 200,
+                                               min(500, args.c2_steps))
+            roof = kernel_roofline(tim, npts, prec)
+            got, obs = gpu_state(torch, np, binding, p, psi0, prec, n2, False, autotune=True)
+            c2[prec] = {"value": npts * args.c2_steps / (ms / 1e3), "ms_per_step": ms / args.c2_steps,
+                        "roofline": roof, "norm_drift": norm - 1.0, "plan": plan,
+                        "err_vs_oracle": dict(errors_vs_oracle(np, got, obs, want2, o2, prec), steps=n2)}
+            log(f"[bench] 512^2 real {prec}: {c2[prec]['value']:.3e} pt-steps/s, {ms / args.c2_steps * 1e3:.2f} "
+                f"us/step, norm drift {norm - 1:.2e}, vs oracle after {n2} steps {c2[prec]['err_vs_oracle']}")
 
     c4 = batch_c4(torch, binding, inputs, args.batch_steps) if args.batch_steps > 0 else None
     c5 = serving_c5(torch, binding, inputs, args.serve_requests, args.serve_rate) if args.serve_requests > 0 else None
+    sweep = []
+    for r in [float(x) for x in args.serve_sweep.split(",") if x.strip()]:
+        sweep.append(serving_c5(torch, binding, inputs, max(1, int(round(10 * r))), r))
 
-    cpu = None
-    if args.cpu_seconds > 0:
-        cpu = cpu_baseline(p, psi0, args.cpu_seconds)
-        log(f"[bench] CPU oracle baseline: {cpu['value']:.3e} pt-steps/s on {cpu['cores']} threads, "
-            f"{cpu['value_1_core']:.3e} on one")
-
-    r = results["fp64"]
+    r = c3["fp64"]
     line = {
         "metric": METRIC, "value": r["value"], "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "512x512 real-time SSCN step, Dresselhaus gamma=1, Rabi=0.2, Omega=0.9, c0=200, "
-                               "c2=+5, dx=0.05, dt=1e-4, from the imaginary-time state + 1e-3 noise",
-                   "nx": 512, "ny": 512, "mode": "real", "precision": "fp64"},
+        "config": {"workload": "4096x4096 imaginary-time SSCN step (local substep, x and y Crank-Nicolson sweeps, "
+                               "renormalisation): Rashba gamma=0.75, Omega=0.95, c0=1000, c2=-20, Rabi=0, dx=0.02, "
+                               "dt=4e-5, from a seeded random-phase Gaussian",
+                   "nx": 4096, "ny": 4096, "mode": "imag", "precision": "fp64"},
         "roofline": r["roofline"],
         "step_roofline_frac": round(r["step_frac"], 4),
         "cpu_baseline": cpu,
-        "fp32": {"value": results["fp32"]["value"], "ms_per_step": results["fp32"]["ms_per_step"],
-                 "dtype": "f32 bulk, f64 reductions", "roofline": results["fp32"]["roofline"],
-                 "step_roofline_frac": round(results["fp32"]["step_frac"], 4),
-                 "norm_drift": results["fp32"]["norm_drift"]},
-        "norm_drift_fp64": r["norm_drift"],
-        "c3_4096": {k: {"value": v["value"], "ms_per_step": v["ms_per_step"], "roofline": v["roofline"],
-                        "step_roofline_frac": round(v["step_frac"], 4)} for k, v in c3.items()},
-        "plan": {"x_points_per_thread": r["plan"]["x_points_per_thread"], "y_solver": r["plan"]["y_solver"],
-                 "y_halo": r["plan"]["y_halo"]},
+        "err_vs_oracle_fp64": r.get("err_vs_oracle"),
+        "plan_fp64": r["plan"],
+        "fp32": {"value": c3["fp32"]["value"], "ms_per_step": c3["fp32"]["ms_per_step"],
+                 "dtype": "f32 bulk, f64 reductions", "roofline": c3["fp32"]["roofline"],
+                 "step_roofline_frac": round(c3["fp32"]["step_frac"], 4),
+                 "err_vs_oracle": c3["fp32"].get("err_vs_oracle"), "plan": c3["fp32"]["plan"]},
+        "c1_128": c1,
+        "c2_512": c2,
         "batch_c4": c4,
         "serving_c5": c5,
     }
+    if sweep:
+        line["serving_c5_sweep"] = sweep
     if c5 is not None:
         line["p50_latency_s"] = c5["p50_latency_s"]
         line["p99_latency_s"] = c5["p99_latency_s"]
