@@ -207,6 +207,29 @@ int gp_spin1_step_imag(gp_spin1_t* h, void* psi_dev, int64_t nsteps);
  * GP_EUNSTABLE if the line systems lose diagonal dominance.  Asynchronous. */
 int gp_spin1_step_real(gp_spin1_t* h, void* psi_dev, int64_t nsteps);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): nsteps SSCN steps of
+ * psi_dev (caller-owned, layout as for gp_spin1_create) in imaginary time
+ * (mode 0, renormalised each step) or real time (mode 1), with the launch
+ * plan gp_spin1_create picks without autotuning, computed exactly as by a
+ * handle with the same parameters.  No handle: the line tables, the work wave
+ * function, the norm partials and the scale factors live in a static device
+ * array of GP_STATIC_SCRATCH_BYTES per GPU (held until the process ends; the
+ * grid must fit it: the work wave function takes (3 nx ny + 8320) s bytes,
+ * s = 16 or 8, so up to about 690 thousand points in FP64 and 1.38 million
+ * in FP32).  No device memory is allocated or freed; the tables are built on
+ * the host and copied on hip_stream.  Blocks until the steps are done.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (several host threads, or several streams) race and must not be issued.
+ * Returns GP_EINVAL for invalid parameters, autotune != 0, a NULL psi_dev,
+ * nsteps < 0 or a bad mode; GP_ENOMEM when the grid exceeds the array
+ * (message from gp_spin1_static_last_error); GP_EUNSTABLE and GP_ENONFINITE
+ * as the handle calls. */
+#define GP_STATIC_SCRATCH_BYTES ((size_t)32 << 20)
+int gp_spin1_step_static(const gp_spin1_params* p, void* psi_dev, int64_t nsteps, int32_t mode, void* hip_stream);
+/* Message of the calling thread's last failed gp_spin1_step_static ("" after success). */
+const char* gp_spin1_static_last_error(void);
+
 /* One substep alone (diagnostics and per-kernel parity checks):
  * which = 0 local substep, 1 x sweep, 2 y sweep, 3 renormalise to unit norm;
  * imag != 0 selects the imaginary-time form.  Asynchronous. */

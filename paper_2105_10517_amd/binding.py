@@ -29,7 +29,7 @@ EXPORTS = ("gp_spin1_create", "gp_spin1_destroy", "gp_spin1_step_imag", "gp_spin
            "gp_spin1_strerror", "gp_spin1_last_error",
            "gp_spin1_batch_create", "gp_spin1_batch_set_slot", "gp_spin1_batch_step", "gp_spin1_batch_sync",
            "gp_spin1_batch_observables", "gp_spin1_batch_info_read", "gp_spin1_batch_destroy",
-           "gp_spin1_batch_last_error", "gp_spin1_serve")
+           "gp_spin1_batch_last_error", "gp_spin1_serve", "gp_spin1_step_static", "gp_spin1_static_last_error")
 
 
 class LibraryNotBuilt(RuntimeError):
@@ -148,6 +148,7 @@ def load():
     })
     sig["gp_spin1_serve"] = [ctypes.POINTER(Request), i32, ctypes.POINTER(ServeConfig), vp,
                              ctypes.POINTER(RequestResult), ctypes.POINTER(ServeStats)]
+    sig["gp_spin1_step_static"] = [ctypes.POINTER(Params), vp, i64, i32, vp]
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
@@ -158,6 +159,8 @@ def load():
     lib.gp_spin1_last_error.restype = ctypes.c_char_p
     lib.gp_spin1_batch_last_error.argtypes = [vp]
     lib.gp_spin1_batch_last_error.restype = ctypes.c_char_p
+    lib.gp_spin1_static_last_error.argtypes = []
+    lib.gp_spin1_static_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -326,6 +329,23 @@ class Solver:
 
 
 MODES = {"imag": 0, "real": 1, 0: 0, 1: 1}
+
+
+def step_static(p: dict, psi, nsteps: int, mode, precision: str = "fp64", stream=None):
+    """gp_spin1_step_static: nsteps steps of psi with no device allocation
+    (the library's static scratch array; blocks until done)."""
+    import torch
+    lib = load()
+    dtype = torch.complex128 if precision == "fp64" else torch.complex64
+    ptr = check_psi(psi, dtype, p, device=torch.cuda.current_device())
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    pp = make_params(p, precision)
+    rc = lib.gp_spin1_step_static(ctypes.byref(pp), ctypes.c_void_p(ptr), int(nsteps), MODES[mode],
+                                  ctypes.c_void_p(stream.cuda_stream))
+    if rc != GP_OK:
+        raise GPError(rc, "gp_spin1_step_static: " + lib.gp_spin1_strerror(rc).decode() + ": "
+                      + lib.gp_spin1_static_last_error().decode())
 
 
 class Batch:

@@ -1181,6 +1181,114 @@ int make_handle(const gp_spin1_params* p, hipStream_t st, gp_spin1** out) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Stepping without allocation (gp_spin1_step_static).  The call keeps
+// everything beyond the caller's wave function - the line tables, the work
+// wave function, the norm partials, the scale factors and the non-finite flag
+// - in this array: one copy per GPU, held until the process ends, shared by
+// every such call on that GPU.  On the host the array's name is no device
+// address; its address on each device comes from hipGetSymbolAddress.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GP_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The array's address on the current device (looked up on the first call there).
+int scratch_base(gp_spin1* h, unsigned char** out) {
+    if (h->device < 0 || h->device >= kMaxDevices) return fail(h, GP_EUNSUPPORTED, "device index beyond the static table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[h->device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(h, e, "scratch address");
+        if (!p) return fail(h, GP_EHIP, "scratch address: null");
+        g_scratch_ptr[h->device] = p;
+    }
+    *out = (unsigned char*)g_scratch_ptr[h->device];
+    return GP_OK;
+}
+
+template <typename T>
+int step_static_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
+    const gp_spin1_params& p = h->p;
+    if (p.x_points > 0) {
+        int G, R;
+        if ((p.x_points & (p.x_points - 1)) || p.x_points > 16 || !x_shape(p.nx, p.x_points, G, R))
+            return fail(h, GP_EUNSUPPORTED, "x_points must be 1, 2, 4, 8 or 16 and hold a row in one block");
+    }
+    unsigned char* base = nullptr;
+    int rc = scratch_base(h, &base);
+    if (rc) return rc;
+    Arena a;
+    a.base = base;
+    a.cap = GP_STATIC_SCRATCH_BYTES;
+    a.stream = h->stream;
+    ModeState& ms = h->mode[imag];
+    if ((rc = build_mode<T>(h, ms, imag, &a)) != GP_OK) return rc;
+    int G, R;
+    if (p.x_points > 0 && !ms.xwindow && !x_shape_ok(p.nx, p.x_points, ms.x.Kg, sizeof(T), G, R))
+        return fail(h, GP_EUNSUPPORTED, "x_points too small for the line-start correction of these lines");
+    if (p.x_solver == GP_XSOLVER_WINDOW && !ms.xwindow)
+        return fail(h, GP_EUNSUPPORTED, "x windows asked for, but the decay of the x lines fits no window");
+    const size_t npts = (size_t)p.nx * p.ny;
+    h->psp = psi_stride(p);
+    h->wsp = work_stride(p);
+    h->n_part = std::max<size_t>(3 * max_y_blocks<T>(p, ms), 1024);
+    const size_t work_bytes = (2 * h->wsp + npts) * sizeof(gp::cx<T>);
+    hipError_t e;
+    if (dev_alloc(&a, (void**)&h->d_part, h->n_part * sizeof(double)) != hipSuccess ||
+        dev_alloc(&a, (void**)&h->d_scale, 3 * sizeof(double)) != hipSuccess ||
+        dev_alloc(&a, (void**)&h->d_flag, sizeof(int)) != hipSuccess ||
+        dev_alloc(&a, &h->d_work, work_bytes) != hipSuccess) {
+        char msg[200];
+        std::snprintf(msg, sizeof msg, "grid needs more than the %zu bytes of the static scratch (work wave function alone: %zu)",
+                      (size_t)GP_STATIC_SCRATCH_BYTES, work_bytes);
+        return fail(h, GP_ENOMEM, msg);
+    }
+    // start values (kernels, not memsets: a captured memset node misbehaves on replays)
+    if ((e = gp::launch_set_scale(h->d_scale, 1.0, h->stream)) != hipSuccess) return hip_fail(h, e, "scale reset");
+    if ((e = gp::launch_set_flag(h->d_flag, 0, h->stream)) != hipSuccess) return hip_fail(h, e, "flag reset");
+    if ((rc = steps_t<T>(h, psi, n, imag)) != GP_OK) return rc;
+    int flag = 0;
+    if ((e = hipMemcpyAsync(&flag, h->d_flag, sizeof flag, hipMemcpyDeviceToHost, h->stream)) != hipSuccess)
+        return hip_fail(h, e, "flag read");
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "sync");
+    if (flag) return fail(h, GP_ENONFINITE, "an imaginary-time norm was not finite");
+    return GP_OK;
+}
+
+// Message of the calling thread's last gp_spin1_step_static failure.
+std::string& static_err() {
+    thread_local std::string err;
+    return err;
+}
+
+// One call: a handle on the stack whose device memory is the static array
+// (nothing to free afterwards).
+int step_static(const gp_spin1_params* p, void* psi, int64_t n, int32_t mode, hipStream_t st, std::string* err) {
+    std::string why;
+    int rc = validate(p, why);
+    if (rc) { if (err) *err = why; return rc; }
+    if (p->autotune) { if (err) *err = "autotune needs an allocation: give autotune = 0"; return GP_EINVAL; }
+    if (!psi || n < 0 || (mode != 0 && mode != 1)) { if (err) *err = "psi is NULL, nsteps < 0 or mode not 0/1"; return GP_EINVAL; }
+    gp_spin1 h;
+    h.p = *p;
+    if (std::isnan(h.p.x0)) h.p.x0 = -0.5 * h.p.nx * h.p.dx;
+    if (std::isnan(h.p.y0)) h.p.y0 = -0.5 * h.p.ny * h.p.dy;
+    h.stream = st;
+    if (hipGetDevice(&h.device) != hipSuccess) return GP_EHIP;
+    const bool imag = mode == 0;
+    rc = h.p.precision == GP_FP64 ? step_static_t<double>(&h, psi, n, imag) : step_static_t<float>(&h, psi, n, imag);
+    if (rc && err) *err = h.err;
+    return rc;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // Batches: independent condensates (own grid, couplings, time step and mode)
 // advanced together.  Every sweep is one launch over the rows / column tiles
 // of all condensates that share the batch's launch shape; a condensate whose
@@ -1634,6 +1742,14 @@ int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out
         return make_handle(p, (hipStream_t)hip_stream, out);
     });
 }
+
+int gp_spin1_step_static(const gp_spin1_params* p, void* psi, int64_t nsteps, int32_t mode, void* hip_stream) {
+    std::string& err = static_err();
+    err.clear();
+    return no_throw([&]() -> int { return step_static(p, psi, nsteps, mode, (hipStream_t)hip_stream, &err); }, &err);
+}
+
+const char* gp_spin1_static_last_error(void) { return static_err().c_str(); }
 
 int gp_spin1_destroy(gp_spin1_t* h) {
     if (!h) return GP_EINVAL;
