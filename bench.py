@@ -65,6 +65,7 @@ def kernel_roofline(timing, npts, prec):
 
 XTILES = {"fp64": [(4, 4), (8, 2), (2, 4), (4, 2)], "fp32": [(4, 4), (8, 4), (8, 2), (16, 2)]}
 YCTILES = {"fp64": [(8, 2), (8, 4), (4, 4), (7, 4)], "fp32": [(8, 4), (8, 8), (4, 4), (16, 2)]}
+STACK_K = {"fp64": (8, 6), "fp32": (8, 16)}  # stacked y windows: points per lane of tiles 1..4 (3, 4 one line at a time)
 WTILES = {"fp64": [(8, 2), (8, 4), (4, 4), (4, 8)], "fp32": [(8, 4), (4, 8), (4, 4), (8, 8)]}
 
 
@@ -84,6 +85,9 @@ def kernel_prefix(kind, prec, imag, plan):
         if plan["x_solver"] == 2:
             return f"gp::k_x_window<{T}, {im}, " + tile_args(WTILES, prec, plan["x_tile"])
         return f"gp::k_x_scan<{T}, {im}, {plan['x_points_per_thread']}, "
+    if plan["y_solver"] == 4:
+        kk = STACK_K[prec][(plan["y_tile"] - 1) & 1]
+        return f"gp::k_y_stack<{T}, {im}, {kk}, {'true' if plan['y_tile'] > 2 else 'false'}, "
     if plan["y_solver"] == 3:
         return f"gp::k_y_chain<{T}, {im}, " + tile_args(YCTILES, prec, plan["y_tile"])
     if plan["y_solver"] == 2:

@@ -67,10 +67,12 @@ typedef enum {
     GP_YSOLVER_AUTO = 0,   /* windowed scan when its truncation bound holds, else per-column Thomas */
     GP_YSOLVER_WINDOW = 1, /* windowed partitioned scan over column tiles (2 HBM passes per step) */
     GP_YSOLVER_THOMAS = 2, /* exact per-thread Thomas down whole columns (one thread per column) */
-    GP_YSOLVER_CHAIN = 3   /* windows as GP_YSOLVER_WINDOW, each segment's carry formed from the ceil(h / K)
+    GP_YSOLVER_CHAIN = 3,  /* windows as GP_YSOLVER_WINDOW, each segment's carry formed from the ceil(h / K)
                               segments before and after it instead of a scan of the whole window (their
                               carries are attenuated below the same rounding bound as the window ends);
                               y_tile then names a chain tile */
+    GP_YSOLVER_STACK = 4   /* chain windows with 16 consecutive columns per block and the window's segments
+                              stacked over its waves (carries through shared memory); y_tile 1..4 */
 } gp_ysolver;
 
 /* Choice of the x-sweep line solver. */
@@ -168,7 +170,7 @@ typedef struct {
     int32_t x_points_per_thread; /* K of the x kernel: each thread holds K consecutive points   */
     int32_t x_threads_per_row;   /* threads cooperating on one row                               */
     int32_t x_rows_per_block;
-    int32_t y_solver;            /* GP_YSOLVER_WINDOW, GP_YSOLVER_CHAIN or GP_YSOLVER_THOMAS      */
+    int32_t y_solver;            /* GP_YSOLVER_WINDOW, _CHAIN, _STACK or _THOMAS                  */
     int32_t y_halo;              /* rows read above a y window's output (at least as many below) */
     int32_t y_rows_out;          /* rows written per y window                                    */
     int32_t y_tile;              /* 1..8, the tile shape below (5..8: lines solved one at a time)  */

@@ -17,7 +17,7 @@ LIBPATH = os.path.join(_HERE, "libgp_spin1.so")
 
 GP_OK, GP_EINVAL, GP_EUNSTABLE, GP_ENOMEM, GP_EHIP, GP_ENONFINITE, GP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 GP_FP64, GP_FP32 = 0, 1
-GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS, GP_YSOLVER_CHAIN = 0, 1, 2, 3
+GP_YSOLVER_AUTO, GP_YSOLVER_WINDOW, GP_YSOLVER_THOMAS, GP_YSOLVER_CHAIN, GP_YSOLVER_STACK = 0, 1, 2, 3, 4
 GP_XSOLVER_AUTO, GP_XSOLVER_SCAN, GP_XSOLVER_WINDOW, GP_XSOLVER_CHAIN = 0, 1, 2, 3
 GP_ORDER_AUTO, GP_ORDER_HARDWARE, GP_ORDER_XCD, GP_ORDER_BANDS, GP_ORDER_ROWS = 0, 1, 2, 3, 4
 SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
@@ -172,7 +172,7 @@ def make_params(p: dict, precision: str = "fp64", y_solver: str = "auto", x_poin
     optional gx, gy (trap), split (0 Lie, 1 Strang), fix_m and magnetization)."""
     prec = {"fp64": GP_FP64, "fp32": GP_FP32}[precision]
     ys = {"auto": GP_YSOLVER_AUTO, "window": GP_YSOLVER_WINDOW, "thomas": GP_YSOLVER_THOMAS,
-          "chain": GP_YSOLVER_CHAIN}[y_solver]
+          "chain": GP_YSOLVER_CHAIN, "stack": GP_YSOLVER_STACK}[y_solver]
     return Params(int(p["nx"]), int(p["ny"]), float(p["dx"]), float(p.get("dy", p["dx"])),
                   float(p.get("x0", math.nan)), float(p.get("y0", math.nan)), float(p["dt"]),
                   float(p.get("c0", 0.0)), float(p.get("c2", 0.0)), float(p.get("gamma", 0.0)),

@@ -53,6 +53,19 @@ template <> __host__ __device__ constexpr ChainTile ychain_tile<float>(int t) {
 // Carry lanes of a chain window for a halo of h points: nc = ceil(h / K).
 __host__ __device__ inline int chain_lanes(int h, int K) { return h <= K ? 1 : (h + K - 1) / K; }
 
+// Stacked y windows (k_y_stack): 16 consecutive columns per block, one per
+// lane of a DPP row, and the 16 segments of a window spread over the four
+// waves (4 per wave); carries pass through shared memory.  Tiles: K rows per
+// segment, SEQ as above.
+constexpr int kNumStackTiles = 4;
+template <typename T> __host__ __device__ constexpr ChainTile ystack_tile(int t);
+template <> __host__ __device__ constexpr ChainTile ystack_tile<double>(int t) {
+    return (t & 1) == 0 ? ChainTile{8, 4, t > 1} : ChainTile{6, 4, t > 1};
+}
+template <> __host__ __device__ constexpr ChainTile ystack_tile<float>(int t) {
+    return (t & 1) == 0 ? ChainTile{8, 4, t > 1} : ChainTile{16, 4, t > 1};
+}
+
 // x sweep: K consecutive points per thread; the launch bound of each K.
 constexpr int kNumXK = 5;
 __host__ __device__ constexpr int xk_value(int idx) { return 1 << idx; }  // 1, 2, 4, 8, 16
@@ -166,6 +179,7 @@ template <typename T> struct YLaunch {
     int L, h, tile;
     bool window, imag, norm;
     bool chain = false;  // chain windows (gp_chain.hpp) instead of the scanned windows
+    bool stack = false;  // stacked chain windows (k_y_stack; tile indexes ystack_tile)
     bool outl;  // second half local substep on the way out (Strang)
     int order;  // windows: block order (0 hardware, 1 XCD-contiguous, 2 bands, 3 row bands)
     size_t sp, dp;  // plane strides of src and dst

@@ -50,6 +50,7 @@ struct ModeState {
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
     int xorder = 1, yorder = 0;   // block orders (x windows 0/1, x rows 0/3; y windows 0..3), see gp_kernels.hpp
     bool xchain = false, ychain = false;  // chain windows (gp_chain.hpp) for the x / y sweep
+    bool ystack = false;                  // y chain windows stacked over the waves (yctile indexes ystack_tile)
     int xctile = 0, hcx = 0, Lcx = 0;     // x chain tile, halo points, points written per window
     int yctile = 0, hcy = 0, Lcy = 0;     // y chain tile, halo rows, rows written per window
     gp_spin1_plan plan{};
@@ -351,7 +352,7 @@ struct HostMode {
     bool xwindow = false;
     int hhx = 0, hx = 0, Lx = 0, xtile = 0;
     int xorder = 1, yorder = 0;  // block orders of the windowed sweeps
-    bool xchain = false, ychain = false;
+    bool xchain = false, ychain = false, ystack = false;
     int xctile = 0, hcx = 0, Lcx = 0, yctile = 0, hcy = 0, Lcy = 0;
 };
 
@@ -387,6 +388,13 @@ template <typename T> bool ychain_fits(int nx, int ny, int hh, int Kg, int t, in
     h = std::max(hh, 1);
     L = 16 * ct.K - 2 * h;
     return L > 0 && Kg <= L && (double)nx * ny * sizeof(gp::cx<T>) < 4294967296.0;
+}
+
+template <typename T> bool ystack_fits(int nx, int ny, int hh, int Kg, int t, int& h, int& L) {
+    const gp::ChainTile ct = gp::ystack_tile<T>(t);
+    h = std::max(hh, 1);
+    L = 16 * ct.K - 2 * h;
+    return L > 0 && Kg <= L && gp::chain_lanes(h, ct.K) <= 15 && (double)nx * ny * sizeof(gp::cx<T>) < 4294967296.0;
 }
 
 // Row tile of the y windows as launched.  Under row bands (order 3) each XCD
@@ -446,7 +454,7 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     hm.L = 0;
     hm.ytile = 0;
     if (p.y_solver != GP_YSOLVER_THOMAS) {
-        if (p.y_tile > 0 && p.y_solver != GP_YSOLVER_CHAIN) {
+        if (p.y_tile > 0 && p.y_solver != GP_YSOLVER_CHAIN && p.y_solver != GP_YSOLVER_STACK) {
             hm.ytile = p.y_tile - 1;
             hm.window = tile_window(p.ny, hm.hh, gp::ywindow(gp::ytile<T>(hm.ytile)), hm.h, hm.L);
         } else {
@@ -484,6 +492,13 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
             if (p.y_tile > 0) break;
         }
     }
+    hm.ystack = false;
+    if (p.y_solver == GP_YSOLVER_STACK) {
+        for (int t = p.y_tile > 0 ? p.y_tile - 1 : 0; t < gp::kNumStackTiles && !hm.ychain; ++t) {
+            if (ystack_fits<T>(p.nx, p.ny, hm.hh, hm.y.Kg, t, hm.hcy, hm.Lcy)) { hm.ychain = hm.ystack = true; hm.yctile = t; }
+            if (p.y_tile > 0) break;
+        }
+    }
     // block orders: grouping the x windows by XCD has measured as fast or
     // faster at every size; the y windows gain from it only while the grid is
     // about one wave of blocks (on larger grids the eight separate HBM streams
@@ -511,12 +526,12 @@ void fill_plan(const gp_spin1_params& p, ModeState& ms) {
     out->x_rows_per_block = ms.xR;
     const gp::YTile yt = gp::ytile<T>(ms.ytile);
     if (ms.ychain) {
-        const gp::ChainTile ct = gp::ychain_tile<T>(ms.yctile);
-        out->y_solver = GP_YSOLVER_CHAIN;
+        const gp::ChainTile ct = ms.ystack ? gp::ystack_tile<T>(ms.yctile) : gp::ychain_tile<T>(ms.yctile);
+        out->y_solver = ms.ystack ? GP_YSOLVER_STACK : GP_YSOLVER_CHAIN;
         out->y_halo = ms.hcy;
         out->y_rows_out = ms.Lcy;
         out->y_tile = ms.yctile + 1;
-        out->y_tile_cols = 4 * ct.NW;
+        out->y_tile_cols = ms.ystack ? 16 : 4 * ct.NW;
         out->y_rows_per_thread = ct.K;
     } else {
         out->y_solver = ms.window ? GP_YSOLVER_WINDOW : GP_YSOLVER_THOMAS;
@@ -580,7 +595,7 @@ void copy_plan(const gp_spin1_params& p, const HostMode& hm, ModeState& ms) {
     ms.hhx = hm.hhx; ms.hx = hm.hx; ms.Lx = hm.Lx; ms.xtile = hm.xtile;
     ms.xorder = hm.xorder; ms.yorder = hm.yorder;
     ms.xchain = hm.xchain; ms.xctile = hm.xctile; ms.hcx = hm.hcx; ms.Lcx = hm.Lcx;
-    ms.ychain = hm.ychain; ms.yctile = hm.yctile; ms.hcy = hm.hcy; ms.Lcy = hm.Lcy;
+    ms.ychain = hm.ychain; ms.ystack = hm.ystack; ms.yctile = hm.yctile; ms.hcy = hm.hcy; ms.Lcy = hm.Lcy;
     fill_plan<T>(p, ms);
 }
 
@@ -594,6 +609,11 @@ size_t max_y_blocks(const gp_spin1_params& p, const ModeState& ms) {
         if (!ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, h, L)) continue;
         const gp::ChainTile ct = gp::ychain_tile<T>(t);
         best = std::max(best, (size_t)((p.nx + 4 * ct.NW - 1) / (4 * ct.NW)) * ((p.ny + L - 1) / L));
+    }
+    for (int t = 0; t < gp::kNumStackTiles; ++t) {
+        int h, L;
+        if (!ystack_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, h, L)) continue;
+        best = std::max(best, (size_t)((p.nx + 15) / 16) * ((p.ny + L - 1) / L));
     }
     if (!ms.window) return best;
     for (int t = 0; t < gp::kNumYTiles; ++t) {
@@ -646,7 +666,7 @@ int validate(const gp_spin1_params* p, std::string& why) {
     }
     if (p->eta != 1 && p->eta != -1) { why = "eta must be +1 (Rashba) or -1 (Dresselhaus)"; return GP_EINVAL; }
     if (p->precision != GP_FP64 && p->precision != GP_FP32) { why = "precision must be GP_FP64 or GP_FP32"; return GP_EINVAL; }
-    if (p->y_solver < GP_YSOLVER_AUTO || p->y_solver > GP_YSOLVER_CHAIN) { why = "unknown y_solver"; return GP_EINVAL; }
+    if (p->y_solver < GP_YSOLVER_AUTO || p->y_solver > GP_YSOLVER_STACK) { why = "unknown y_solver"; return GP_EINVAL; }
     const int nmax = 8192;
     if (p->nx > nmax) { why = "nx above the largest row this build holds on chip"; return GP_EUNSUPPORTED; }
     if ((double)p->nx * (double)p->ny * 3.0 > 4.0e9) { why = "grid too large"; return GP_EUNSUPPORTED; }
@@ -838,7 +858,7 @@ int autotune_t(gp_spin1* h) {
             ms.xorder = bestO;
             if (ms.xchain) xchain_fits<T>(ms.hhx, ms.x.Kg, bestT, ms.hcx, ms.Lcx);
         }
-        if (p.y_tile == 0 && ms.window && p.y_solver != GP_YSOLVER_CHAIN) {
+        if (p.y_tile == 0 && ms.window && p.y_solver != GP_YSOLVER_CHAIN && p.y_solver != GP_YSOLVER_STACK) {
             float best = 1e30f;
             int bestT = ms.ytile, bestO = ms.yorder;
             for (int t = 0; t < gp::kNumYTiles && rc == GP_OK; ++t) {
@@ -856,29 +876,39 @@ int autotune_t(gp_spin1* h) {
             tile_window(p.ny, ms.hh, gp::ywindow(gp::ytile<T>(bestT)), ms.h, ms.L);
         }
         // y chain windows: against the choice above (AUTO), or the fastest chain tile (CHAIN)
-        if (rc == GP_OK && p.y_tile == 0 && (p.y_solver == GP_YSOLVER_AUTO || p.y_solver == GP_YSOLVER_CHAIN)) {
+        if (rc == GP_OK && p.y_tile == 0 &&
+            (p.y_solver == GP_YSOLVER_AUTO || p.y_solver == GP_YSOLVER_CHAIN || p.y_solver == GP_YSOLVER_STACK)) {
             float best = 1e30f;
             if (p.y_solver == GP_YSOLVER_AUTO) {
-                ms.ychain = false;
+                ms.ychain = ms.ystack = false;
                 rc = pair(best);
             }
             bool bestC = ms.ychain;
             int bestT = ms.yctile, bestO = ms.yorder;
-            for (int t = 0; t < gp::kNumChainTiles && rc == GP_OK; ++t) {
-                if (!ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, ms.hcy, ms.Lcy)) continue;
-                for (int o = p0; o < std::min(p1, 3) && rc == GP_OK; ++o) {
-                    ms.ychain = true;
-                    ms.yctile = t;
-                    ms.yorder = o;
-                    float tt = 0.f;
-                    rc = pair(tt);
-                    if (rc == GP_OK && tt < best) { best = tt; bestC = true; bestT = t; bestO = o; }
+            bool bestS = ms.ystack;
+            for (int st = 0; st < 2 && rc == GP_OK; ++st) {
+                if ((p.y_solver == GP_YSOLVER_CHAIN && st == 1) || (p.y_solver == GP_YSOLVER_STACK && st == 0)) continue;
+                for (int t = 0; t < (st ? gp::kNumStackTiles : gp::kNumChainTiles) && rc == GP_OK; ++t) {
+                    if (st ? !ystack_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, ms.hcy, ms.Lcy)
+                           : !ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, ms.hcy, ms.Lcy))
+                        continue;
+                    for (int o = p0; o < std::min(p1, 3) && rc == GP_OK; ++o) {
+                        ms.ychain = true;
+                        ms.ystack = st == 1;
+                        ms.yctile = t;
+                        ms.yorder = o;
+                        float tt = 0.f;
+                        rc = pair(tt);
+                        if (rc == GP_OK && tt < best) { best = tt; bestC = true; bestS = st == 1; bestT = t; bestO = o; }
+                    }
                 }
             }
             ms.ychain = bestC;
+            ms.ystack = bestC && bestS;
             ms.yctile = bestT;
             ms.yorder = bestO;
-            if (ms.ychain) ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, bestT, ms.hcy, ms.Lcy);
+            if (ms.ystack) ystack_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, bestT, ms.hcy, ms.Lcy);
+            else if (ms.ychain) ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, bestT, ms.hcy, ms.Lcy);
         }
         if (p.block_order == GP_ORDER_ROWS) ms.xorder = 3;
         // row bands for both sweeps (only as a pair: each sweep then reads what the
@@ -937,7 +967,7 @@ int create_t(gp_spin1* h) {
             return fail(h, GP_EUNSUPPORTED, "x windows asked for, but the decay of the x lines fits no window");
         if (p.x_solver == GP_XSOLVER_CHAIN && !h->mode[m].xchain)
             return fail(h, GP_EUNSUPPORTED, "x chain windows asked for, but the decay of the x lines fits no such tile");
-        if (p.y_solver == GP_YSOLVER_CHAIN && !h->mode[m].ychain)
+        if ((p.y_solver == GP_YSOLVER_CHAIN || p.y_solver == GP_YSOLVER_STACK) && !h->mode[m].ychain)
             return fail(h, GP_EUNSUPPORTED, "y chain windows asked for, but no such tile fits these columns");
     }
     size_t need = 1;
@@ -1009,7 +1039,8 @@ gp::YLaunch<T> ylaunch(gp_spin1* h, const void* src, void* dst, bool imag, bool 
     a.window = ms.window; a.imag = imag; a.norm = norm;
     a.outl = false;
     a.order = ms.yorder;
-    a.chain = ms.ychain;
+    a.chain = ms.ychain && !ms.ystack;
+    a.stack = ms.ystack;
     if (ms.ychain) { a.L = ms.Lcy; a.h = ms.hcy; a.tile = ms.yctile; }
     a.sp = sp;
     a.dp = dp;

@@ -171,6 +171,197 @@ __global__ __launch_bounds__(64 * NW) void k_y_chain(const cx<T>* __restrict__ s
     if (NORM) store_norm_partials(acc, shr, no, blk);
 }
 
+// ---------------------------------------------------------------------------
+// y sweep over stacked chain windows: a block of 4 waves takes 16 consecutive
+// columns (one per lane of a DPP row, so every load and store instruction
+// reads or writes row pieces of 16 columns) and a window of 16 KY rows, its
+// 16 segments spread over the waves (4 per wave, lane = 16 segment + column).
+// The line solves are those of gp_chain.hpp, the carries and the segment-end
+// neighbours passing through shared memory between the phases (each lane's
+// carry from the nc segments before / after it).  Windows start at row
+// rt L - h and write the rows [rt L, rt L + L).
+// ---------------------------------------------------------------------------
+template <typename T> struct StackShm {
+    cx<T> ends[2][3][16][16];  // [first, last point][line][segment][column] (pre-solve values)
+    cx<T> f[3][16][16];        // forward value each segment passes on from a zero carry
+    cx<T> b[3][16][16];        // backward value each segment passes on from a zero carry
+    cx<T> d0[3][16];           // increment at line point 0, per line and column
+};
+
+// Lines q0 .. q0 + NQ - 1 of the window (every thread of the block calls it:
+// barriers inside).  um / up: the neighbours of the segment's first and last
+// point per line.
+template <typename T, int K, bool IMAG, bool EDGE, int NQ>
+__device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& ls, int line0, int nc, int g0, int n,
+                                   int seg, int cl, bool first, int seg0, int k0, StackShm<T>& sh) {
+    using C = cx<T>;
+    C v[NQ][K];
+    ChainLine<T> c[NQ];  // (P, R unused: formed where needed)
+    // right-hand sides times -2 / w, and the forward value passed on from a zero carry
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) {
+        const int q = q0 + qq;
+        c[qq] = chain_line<T, 1>(ls, line0 + q);
+        // segment-end neighbours (pre-solve values; zeros beyond the window)
+        const C um = seg > 0 ? sh.ends[1][q][seg - 1][cl] : zero_c<C>();
+        const C up = seg < 15 ? sh.ends[0][q][seg + 1][cl] : zero_c<C>();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const C l = k == 0 ? um : u[q][k - 1];
+            const C r = k == K - 1 ? up : u[q][k + 1];
+            C t = mul_bm1<T, IMAG>(ls.bm1, u[q][k]);
+            t = cfma(l, c[qq].a, t);
+            t = cfma(r, c[qq].e, t);
+            v[qq][k] = cmul(c[qq].m2, t);
+            if (EDGE && (g0 + k < 0 || g0 + k >= n)) v[qq][k] = zero_c<C>();
+        }
+        C f = v[qq][0];
+#pragma unroll
+        for (int k = 1; k < K; ++k) f = cfma(f, c[qq].nam, v[qq][k]);
+        sh.f[q][seg][cl] = f;
+    }
+    __syncthreads();
+    // carry in from the nc segments before, forward values, backward value passed on
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) {
+        const int q = q0 + qq;
+        const int jm = seg < nc ? seg : nc;
+        const C P = cpow_k<C, K>(c[qq].nam);  // (formed here: shorter live ranges)
+        C x = zero_c<C>();
+        for (int j = jm; j >= 1; --j) x = cfma(x, P, sh.f[q][seg - j][cl]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            x = cfma(x, c[qq].nam, v[qq][k]);
+            if (EDGE && g0 + k >= n) x = zero_c<C>();
+            v[qq][k] = x;
+        }
+        C b = v[qq][K - 1];
+#pragma unroll
+        for (int k = K - 2; k >= 0; --k) b = cfma(b, c[qq].ncp, v[qq][k]);
+        sh.b[q][seg][cl] = b;
+    }
+    __syncthreads();
+    // carry in from the nc segments after, increments
+    C d0[NQ];
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) {
+        const int q = q0 + qq;
+        const int jm = 15 - seg < nc ? 15 - seg : nc;
+        const C R = cpow_k<C, K>(c[qq].ncp);
+        C x = zero_c<C>();
+        for (int j = jm; j >= 1; --j) x = cfma(x, R, sh.b[q][seg + j][cl]);
+        d0[qq] = zero_c<C>();
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            x = cfma(x, c[qq].ncp, v[qq][k]);
+            if (first && seg == seg0 && k == k0) d0[qq] = x;
+            u[q][k] = cadd(u[q][k], x);
+        }
+    }
+    // the increment at line point 0 of each column, for the line-start correction
+    // that the caller applies once every line is solved
+    if (first && seg == seg0)
+#pragma unroll
+        for (int qq = 0; qq < NQ; ++qq) sh.d0[q0 + qq][cl] = d0[qq];
+}
+
+template <typename T, bool IMAG, int KY, bool SEQ, bool NORM, bool OUTL>
+__global__ __launch_bounds__(256, 2) void k_y_stack(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
+                                                 size_t dp, Phys ph, LineSet<T> ls, int L, int h, int nc, int ncs,
+                                                 NormOut no, int nblk, int order) {
+    using C = cx<T>;
+    __shared__ StackShm<T> sh;
+    __shared__ double shr[48];
+    const int blk = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
+    if (blk < 0) return;  // (the whole block)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int cl = lane & 15;                      // column within the block
+    const int seg = (tid >> 6) * 4 + (lane >> 4);  // segment of the window, 0..15
+    const int cs = blk % ncs, rt = blk / ncs;
+    const int i = cs * 16 + cl;
+    const bool col_ok = i < ph.nx;
+    const int nx = ph.nx, ny = ph.ny;
+    const int j0 = rt * L;          // first row written
+    const int s0 = j0 - h;          // first row of the window
+    const int g0 = s0 + seg * KY;   // first row of this lane
+    const bool edge = s0 < 0 || s0 + 16 * KY > ny;  // block-uniform
+    const unsigned col = col_ok ? (unsigned)i : 0u;
+    const unsigned pb = (unsigned)nx * (unsigned)ny * (unsigned)sizeof(C);
+    __amdgpu_buffer_rsrc_t rs[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) rs[m] = plane_rsrc(src + m * sp, pb);
+    C v[3][KY];
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        const bool ok = col_ok && (!edge || (g >= 0 && g < ny));
+        const unsigned o = ((unsigned)(ok ? g : 0) * (unsigned)nx + col) * (unsigned)sizeof(C);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? buf_load<C>(rs[m], o) : zero_c<C>();
+    }
+#pragma unroll
+    for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    // segment-end neighbours of the three lines (zeros beyond the window)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        sh.ends[0][q][seg][cl] = v[q][0];
+        sh.ends[1][q][seg][cl] = v[q][KY - 1];
+    }
+    __syncthreads();
+    const int line0 = (int)col * 3;
+    const bool first = rt == 0;  // the window holds row 0 (at segment h / KY, row h % KY)
+    if (SEQ) {
+        if (!edge) {
+            stack_lines<T, KY, IMAG, false, 1>(v, 0, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+            stack_lines<T, KY, IMAG, false, 1>(v, 1, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+            stack_lines<T, KY, IMAG, false, 1>(v, 2, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+        } else {
+            stack_lines<T, KY, IMAG, true, 1>(v, 0, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+            stack_lines<T, KY, IMAG, true, 1>(v, 1, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+            stack_lines<T, KY, IMAG, true, 1>(v, 2, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+        }
+    } else {
+        if (!edge) stack_lines<T, KY, IMAG, false, 3>(v, 0, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+        else stack_lines<T, KY, IMAG, true, 3>(v, 0, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+    }
+    if (first) {
+        // line-start correction (block-uniform branch)
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; ++q) line_start_fix<T, KY>(v[q], ls, line0 + q, sh.d0[q][cl], g0);
+    }
+#pragma unroll
+    for (int k = 0; k < KY; ++k) from_sx<C, T>(v[0][k], v[1][k], v[2][k]);
+    if (OUTL) {
+        // Strang: the second half local substep, on the way out
+        const T x = (T)(ph.x0 + (int)col * ph.dx);
+#pragma unroll
+        for (int k = 0; k < KY; ++k) {
+            const T y = (T)(ph.y0 + (g0 + k) * ph.dy);
+            local_substep<T, IMAG>(v[0][k], v[1][k], v[2][k], trap_v<T>(ph, x, y), (T)ph.dtl, (T)ph.c0, (T)ph.c2,
+                                   (T)ph.rabi);
+        }
+    }
+    __amdgpu_buffer_rsrc_t rd[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) rd[m] = plane_rsrc(dst + m * dp, pb);
+    const int j1 = min(j0 + L, ny);
+    double acc[3] = {0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < KY; ++k) {
+        const int g = g0 + k;
+        if (col_ok && g >= j0 && g < j1) {
+            const unsigned o = ((unsigned)g * (unsigned)nx + col) * (unsigned)sizeof(C);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                buf_store(v[m][k], rd[m], o);
+                if (NORM) acc[m] += (double)cnorm2(v[m][k]);
+            }
+        }
+    }
+    if (NORM) store_norm_partials(acc, shr, no, blk);
+}
+
 template <typename T, bool IMAG, int KY, int NW, bool SEQ>
 __global__ __launch_bounds__(64 * NW) void k_y_batch(const YSlot<T>* __restrict__ slots, const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
@@ -322,8 +513,37 @@ static hipError_t launch_yc(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
     }
 }
 
+template <typename T, bool IMAG, bool NORM, bool OUTL, int TI>
+static hipError_t launch_ys_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    constexpr ChainTile ct = ystack_tile<T>(TI);
+    // the window (16 KY rows) writes L = 16 KY - 2 h rows; the first window holds the corrected rows;
+    // byte offsets within a plane fit 32 bits; the carries reach at most 15 segments
+    if (a.h < 1 || a.L != 16 * ct.K - 2 * a.h || a.L <= 0 || a.ls.Kg > a.L || chain_lanes(a.h, ct.K) > 15 ||
+        (double)a.ph.nx * a.ph.ny * sizeof(cx<T>) >= 4294967296.0 || a.order == 3)
+        return hipErrorInvalidValue;
+    const int ncs = (a.ph.nx + 15) / 16;
+    const int nrt = (a.ph.ny + a.L - 1) / a.L;
+    const int nblk = ncs * nrt;
+    hipExtLaunchKernelGGL(k_y_stack<T, IMAG, ct.K, ct.SEQ, NORM, OUTL>, dim3(xcd_grid(a.order, ncs, nrt)), dim3(256), 0,
+                          st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.L, a.h, chain_lanes(a.h, ct.K), ncs,
+                          a.no, nblk, a.order);
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG, bool NORM, bool OUTL>
+static hipError_t launch_ys(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    switch (a.tile) {
+        case 0: return launch_ys_t<T, IMAG, NORM, OUTL, 0>(a, st, e0, e1);
+        case 1: return launch_ys_t<T, IMAG, NORM, OUTL, 1>(a, st, e0, e1);
+        case 2: return launch_ys_t<T, IMAG, NORM, OUTL, 2>(a, st, e0, e1);
+        case 3: return launch_ys_t<T, IMAG, NORM, OUTL, 3>(a, st, e0, e1);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 int y_blocks(const YLaunch<T>& a) {
+    if (a.stack) return ((a.ph.nx + 15) / 16) * ((a.ph.ny + a.L - 1) / a.L);
     if (a.chain) {
         const ChainTile ct = ychain_tile<T>(a.tile);
         const int ncs = (a.ph.nx + 4 * ct.NW - 1) / (4 * ct.NW);
@@ -347,6 +567,7 @@ static hipError_t launch_yt(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
 // (imag, norm, outl): the steps use (1, 1, *) and (0, 0, *); the substep calls (*, 0, 0).
 template <typename T, bool IMAG, bool NORM, bool OUTL>
 static hipError_t launch_y_v(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    if (a.stack) return launch_ys<T, IMAG, NORM, OUTL>(a, st, e0, e1);
     if (a.chain) return launch_yc<T, IMAG, NORM, OUTL>(a, st, e0, e1);
     return a.window ? launch_yw<T, IMAG, NORM, OUTL>(a, st, e0, e1) : launch_yt<T, IMAG, NORM, OUTL>(a, st, e0, e1);
 }

@@ -27,7 +27,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--copy-mib", type=int, default=0, help="run a plain copy of this many MiB instead")
     ap.add_argument("--autotune", action="store_true", help="tune the launch shapes first (as bench.py does)")
-    ap.add_argument("--x-solver", default="auto", choices=("auto", "scan", "window"))
+    ap.add_argument("--x-solver", default="auto", choices=("auto", "scan", "window", "chain"))
+    ap.add_argument("--y-solver", default="auto", choices=("auto", "window", "thomas", "chain", "stack"))
     ap.add_argument("--x-tile", type=int, default=0, help="x window tile (1..8, with --x-solver window)")
     ap.add_argument("--x-points", type=int, default=0, help="points per thread of the whole-row x sweep")
     ap.add_argument("--y-tile", type=int, default=0, help="y window tile (1..8)")
@@ -52,7 +53,7 @@ def main():
         p, imag = inputs.config_c3(int(args.workload.split("_")[1])), True
     else:
         raise SystemExit(f"unknown workload {args.workload}")
-    s = binding.Solver(p, args.precision, autotune=args.autotune, x_solver=args.x_solver, x_tile=args.x_tile,
+    s = binding.Solver(p, args.precision, args.y_solver, autotune=args.autotune, x_solver=args.x_solver, x_tile=args.x_tile,
                        x_points=args.x_points, y_tile=args.y_tile, block_order=args.block_order)
     psi = inputs.gaussian(p["nx"], p["ny"], p["dx"], p["dy"], seed=4, full_phase=imag)
     t = torch.from_numpy(psi).to("cuda").to(s.dtype)

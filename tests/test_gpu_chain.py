@@ -76,6 +76,45 @@ def test_every_chain_tile_y(tile):
             s.close()
 
 
+@pytest.mark.parametrize("tile", range(1, 5))
+def test_every_stacked_tile_y(tile):
+    # stacked windows: 16 columns per block (ragged column strips included), segments over the waves
+    for imag in (True, False):
+        for nx, ny in ((9, 3), (37, 90), (21, 700), (50, 1501)):
+            dy = min(12.0 / ny + 0.01, 0.3)
+            p = all_couplings(nx, ny, 0.2, dy=dy, dt=0.4 * dy * dy, eta=1 if ny % 3 else -1)
+            psi = inputs.random_state(nx, ny, seed=90 + tile + ny)
+            s = binding.Solver(p, y_solver="stack", y_tile=tile)
+            pl = s.plan(imag)
+            assert pl["y_solver"] == binding.GP_YSOLVER_STACK and pl["y_tile"] == tile
+            t = dev(psi)
+            s.substep(t, binding.SUB_Y, imag)
+            assert rel(host(t), oracle.sweep_y(p, psi, imag)) < 1e-13, (tile, imag, ny, pl)
+            s.close()
+
+
+@pytest.mark.parametrize("imag", [True, False])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_stacked_full_steps(imag, precision):
+    p = all_couplings(700, 530, 0.06, dy=0.05, dt=0.0015)
+    psi0 = inputs.gaussian(700, 530, 0.06, 0.05, x0=p["x0"], y0=p["y0"], seed=25, center=(-3.0, 0.7))
+    s = binding.Solver(p, precision, x_solver="chain", y_solver="stack")
+    t = dev(psi0, s.dtype)
+    (s.step_imag if imag else s.step_real)(t, 30)
+    s.sync()
+    got = host(t)
+    obs = s.observables(t)
+    s.close()
+    want = oracle.step(p, psi0, 30, imag)
+    if precision == "fp64":
+        assert rel(got, want) < 1e-11
+    else:
+        o = oracle.observables(p, want)
+        rho_g, rho_w = np.abs(got) ** 2, np.abs(want) ** 2
+        assert float(np.abs(rho_g - rho_w).max() / rho_w.max()) < 1e-5
+        assert abs(obs["mu_total"] - o["mu_total"]) / abs(o["mu_total"]) < 1e-6
+
+
 @pytest.mark.parametrize("imag", [True, False])
 def test_chain_wide_halo(imag):
     # slow decay (dt above dx dy): halos of tens of points, several carry lanes
