@@ -77,7 +77,8 @@ typedef enum {
 
 /* Choice of the x-sweep line solver. */
 typedef enum {
-    GP_XSOLVER_AUTO = 0,   /* whole-row partitioned Thomas, or the windows when autotuning finds them faster */
+    GP_XSOLVER_AUTO = 0,   /* whole-row partitioned Thomas, or the windows when autotuning finds them faster;
+                              rows above 4096 points take the chain windows when a chain tile fits       */
     GP_XSOLVER_SCAN = 1,   /* exact partitioned Thomas over whole rows (scans across the row's threads)     */
     GP_XSOLVER_WINDOW = 2, /* truncated overlapping windows along the rows (the y sweep's scheme); refused
                               (GP_EUNSUPPORTED) when the decay bound does not fit any window            */
@@ -194,7 +195,10 @@ typedef struct gp_spin1 gp_spin1_t;
  * the default stream).  Validates p (GP_EINVAL), tabulates the Thomas pivots
  * of every x line (row j, Sigma_y eigenvalue) and y line (column i, Sigma_x
  * eigenvalue) for both propagation modes, and allocates small device tables
- * and reduction scratch.  *out is set only on success. */
+ * and reduction scratch.  GP_EUNSTABLE when the line systems of real time
+ * are not diagonally dominant (then neither propagation can run); parameters
+ * that fail only the imaginary-time bound give a handle whose
+ * gp_spin1_step_imag returns GP_EUNSTABLE.  *out is set only on success. */
 int gp_spin1_create(const gp_spin1_params* p, void* hip_stream, gp_spin1_t** out);
 int gp_spin1_destroy(gp_spin1_t* h);
 

@@ -486,6 +486,19 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
             if (p.x_tile > 0) break;
         }
     }
+    if (p.x_solver == GP_XSOLVER_AUTO && p.x_points == 0 && hm.xK == 16) {
+        // rows longer than 512 threads of eight points: the whole-row solve
+        // would hold sixteen points per thread and spill; the chain windows
+        // take rows of any length (the tile that writes the largest share of
+        // the points it loads)
+        double best = 0.0;
+        for (int t = 0; t < gp::kNumChainTiles; ++t) {
+            int h, L;
+            if (!xchain_fits<T>(hm.hhx, hm.x.Kg, t, h, L)) continue;
+            const double eff = (double)L / (64.0 * gp::xchain_tile<T>(t).K);
+            if (eff > best) { best = eff; hm.xchain = true; hm.xctile = t; hm.hcx = h; hm.Lcx = L; }
+        }
+    }
     if (p.y_solver == GP_YSOLVER_CHAIN) {
         for (int t = p.y_tile > 0 ? p.y_tile - 1 : 0; t < gp::kNumChainTiles && !hm.ychain; ++t) {
             if (ychain_fits<T>(p.nx, p.ny, hm.hh, hm.y.Kg, t, hm.hcy, hm.Lcy)) { hm.ychain = true; hm.yctile = t; }
@@ -970,6 +983,9 @@ int create_t(gp_spin1* h) {
         if ((p.y_solver == GP_YSOLVER_CHAIN || p.y_solver == GP_YSOLVER_STACK) && !h->mode[m].ychain)
             return fail(h, GP_EUNSUPPORTED, "y chain windows asked for, but no such tile fits these columns");
     }
+    // a handle that no propagation can use is refused here; one stable in real
+    // time only is kept, and gp_spin1_step_imag reports the failed bound
+    if (!h->mode[0].stable && !h->mode[1].stable) return fail(h, GP_EUNSTABLE, h->mode[0].why);
     size_t need = 1;
     for (auto& m : h->mode) need = std::max(need, max_y_blocks<T>(p, m));
     const size_t npts = (size_t)p.nx * p.ny;

@@ -85,8 +85,8 @@ def test_decay_matches_closed_form():
 
 def test_stability_checks():
     # imaginary-time Cayley bound (dt/4)(|Omega| L + |gamma|)^2 < 1
-    p = inputs.params(64, 64, 0.1, dt=0.5, omega=0.9, gamma=1.0)
-    assert binding.plan_query(p, True)["stable"] == 0
+    p = inputs.params(64, 64, 0.3, dt=0.05, omega=0.9, gamma=1.0)
+    assert binding.plan_query(p, True)["stable"] == 0 and binding.plan_query(p, False)["stable"] == 1
     # real time with a huge dt and strong rotation loses diagonal dominance
     q = inputs.params(64, 64, 0.1, dt=5.0, omega=5.0)
     assert binding.plan_query(q, False)["stable"] == 0

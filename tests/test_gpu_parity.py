@@ -456,21 +456,41 @@ def test_c3_full_size_steps(precision, n):
 # Error paths (forced from the host; every kernel still exits normally)
 # ---------------------------------------------------------------------------
 def test_unstable_parameters_are_refused():
-    p = inputs.params(64, 64, 0.1, dt=0.5, omega=0.9, gamma=1.0)
+    # the imaginary-time Cayley bound fails, the real-time lines stay diagonally dominant
+    p = inputs.params(64, 64, 0.3, dt=0.05, omega=0.9, gamma=1.0)
+    assert binding.plan_query(p, True)["stable"] == 0 and binding.plan_query(p, False)["stable"] == 1
     s = binding.Solver(p)
-    t = dev(inputs.gaussian(64, 64, 0.1, 0.1, seed=1))
+    t = dev(inputs.gaussian(64, 64, 0.3, 0.3, seed=1))
     with pytest.raises(binding.GPError) as ei:
         s.step_imag(t, 1)
+    assert ei.value.status == binding.GP_EUNSTABLE
+    s.step_real(t, 1)  # real time stays available on this handle
+    s.sync()
+    s.close()
+    # neither propagation stable (real-time lines not diagonally dominant): refused at create
+    q = inputs.params(64, 64, 0.1, dt=5.0, omega=5.0)
+    assert binding.plan_query(q, False)["stable"] == 0 and binding.plan_query(q, True)["stable"] == 0
+    with pytest.raises(binding.GPError) as ei:
+        binding.Solver(q)
     assert ei.value.status == binding.GP_EUNSTABLE
 
 
 @pytest.mark.parametrize("imag", [True, False])
 def test_longest_row_full_steps(imag):
-    # 8192-point rows (the longest the build holds) through whole steps
+    # 8192-point rows (the longest the build holds) through whole steps: by
+    # default the chain windows (the whole-row solve would hold 16 points per
+    # thread), and the whole-row solve when asked for
     p = all_couplings(8192, 12, 0.0015, dy=0.3, dt=2e-5)
     psi0 = inputs.random_state(8192, 12, seed=91, scale=0.4)
-    got, _ = gpu_run(p, psi0, 3, imag)
-    assert rel(got, oracle.step(p, psi0, 3, imag)) < 1e-12
+    want = oracle.step(p, psi0, 3, imag)
+    for xs, solver in (("auto", binding.GP_XSOLVER_CHAIN), ("scan", binding.GP_XSOLVER_SCAN)):
+        s = binding.Solver(p, x_solver=xs)
+        assert s.plan(imag)["x_solver"] == solver
+        t = dev(psi0)
+        (s.step_imag if imag else s.step_real)(t, 3)
+        s.sync()
+        assert rel(host(t), want) < 1e-12, xs
+        s.close()
 
 
 def test_zero_steps_and_invalid_counts():
