@@ -287,7 +287,14 @@ const char* gp_spin1_last_error(const gp_spin1_t* h); /* per-handle message of t
  * one kernel launch per sweep over the rows and column tiles of all of them.
  * Each condensate follows exactly the step of gp_spin1_step_imag /
  * gp_spin1_step_real; results equal those of a single handle created with
- * the batch's x_points and y_tile (gp_spin1_batch_info) bit for bit.
+ * the batch's launch shape (gp_spin1_batch_info: x_solver and x_tile or
+ * x_points, y_solver and y_tile) to the last bit or two.
+ *
+ * Launch shape per propagation mode: chain x windows and stacked chain y
+ * windows when every condensate of that mode that can be grouped (Lie
+ * splitting) leaves x_solver / y_solver at AUTO (or asks for CHAIN / STACK)
+ * and fits one chain tile and one stacked tile (those with the fewest
+ * lane-points over the group); otherwise whole-row scans and scanned windows.
  *
  * gp_spin1_batch_create: p is an array of n parameter sets (1 <= n <= 65536),
  *   one per slot; an entry with nx == 0 leaves its slot empty.  Every entry carries
@@ -300,10 +307,10 @@ const char* gp_spin1_last_error(const gp_spin1_t* h); /* per-handle message of t
  * gp_spin1_batch_step: psi_dev[s] is the device wave function of slot s in
  *   the layout above (complex128 / complex64 by the batch precision);
  *   nsteps[s] >= 0 steps in mode[s] (0 imaginary time, renormalised every
- *   step; 1 real time); active (nullable) masks slots out.  Slots whose
- *   windowed y sweep does not fit the batch tile, that need more than 2^20
- *   blocks in a sweep, or beyond the first 4096 of one mode, run on their
- *   own, on the same stream.  Asynchronous like gp_spin1_step_*; psi_dev arrays may be
+ *   step; 1 real time); active (nullable) masks slots out.  Slots with
+ *   Strang splitting, whose windows do not fit the batch tiles, that need
+ *   more than 2^20 blocks in a sweep, or beyond the first 4096 of one mode,
+ *   run on their own, on the same stream.  Asynchronous like gp_spin1_step_*; psi_dev arrays may be
  *   reused as soon as the call returns.  Calls that overlap on one batch are
  *   not allowed (a batch is not thread-safe).
  * gp_spin1_batch_sync: waits for the stream; GP_ENONFINITE names the slot
@@ -319,6 +326,10 @@ typedef struct {                 /* [0] imaginary-time launches, [1] real-time l
     int32_t individual;  /* condensates that ran on their own plan */
     int32_t phases;      /* groups of steps with a fixed set of condensates */
     int64_t launches;    /* batched sweep and norm launches */
+    int32_t x_solver[2]; /* GP_XSOLVER_CHAIN (chain x windows) or GP_XSOLVER_SCAN (whole-row scans) */
+    int32_t y_solver[2]; /* GP_YSOLVER_STACK (stacked chain windows; y_tile a stacked tile) or
+                            GP_YSOLVER_WINDOW (scanned windows)                                  */
+    int32_t x_tile[2];   /* 1-based chain tile of the batched x sweep (0: whole-row scans)      */
 } gp_spin1_batch_info;
 int gp_spin1_batch_create(const gp_spin1_params* p, int32_t n, void* hip_stream, gp_spin1_batch_t** out);
 int gp_spin1_batch_set_slot(gp_spin1_batch_t* b, int32_t slot, const gp_spin1_params* p);

@@ -86,7 +86,8 @@ class Plan(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("x_points", ctypes.c_int32 * 2), ("x_block", ctypes.c_int32 * 2), ("y_tile", ctypes.c_int32 * 2),
                 ("grouped", ctypes.c_int32), ("individual", ctypes.c_int32), ("phases", ctypes.c_int32),
-                ("launches", ctypes.c_int64)]
+                ("launches", ctypes.c_int64), ("x_solver", ctypes.c_int32 * 2), ("y_solver", ctypes.c_int32 * 2),
+                ("x_tile", ctypes.c_int32 * 2)]
 
 
 class Request(ctypes.Structure):
@@ -351,12 +352,15 @@ def step_static(p: dict, psi, nsteps: int, mode, precision: str = "fp64", stream
 class Batch:
     """Independent condensates advanced together (one launch per sweep over
     all of them).  ``params`` holds one parameter mapping per slot, or None
-    for an empty slot; every slot has the batch precision."""
+    for an empty slot; every slot has the batch precision and the solver
+    requests x_solver / y_solver ("auto": chain shapes when the group fits
+    them; "scan" / "window": the whole-row scans and scanned windows)."""
 
-    def __init__(self, params, precision: str = "fp64", stream=None):
+    def __init__(self, params, precision: str = "fp64", stream=None, x_solver: str = "auto", y_solver: str = "auto"):
         import torch
         self._lib = load()
         self.precision = precision
+        self.x_solver, self.y_solver = x_solver, y_solver
         self.n = len(params)
         self.dtype = torch.complex128 if precision == "fp64" else torch.complex64
         if stream is None:
@@ -375,7 +379,7 @@ class Batch:
             q = Params()
             q.precision = {"fp64": GP_FP64, "fp32": GP_FP32}[self.precision]
             return q
-        return make_params(p, self.precision)
+        return make_params(p, self.precision, self.y_solver, x_solver=self.x_solver)
 
     def _check(self, rc, what):
         if rc != GP_OK:
@@ -424,7 +428,7 @@ class Batch:
         out = {}
         for k, _ in BatchInfo._fields_:
             v = getattr(b, k)
-            out[k] = list(v) if k in ("x_points", "x_block", "y_tile") else v
+            out[k] = list(v) if k in ("x_points", "x_block", "y_tile", "x_solver", "y_solver", "x_tile") else v
         return out
 
     def close(self):

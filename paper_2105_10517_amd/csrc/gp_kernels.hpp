@@ -212,6 +212,28 @@ template <typename T> struct YSlot {
     size_t sp, dp;
 };
 
+// Batched chain windows (x) and stacked chain windows (y): per condensate,
+// the windows of its own plan (halo h, carry lanes nc, points written L).
+template <typename T> struct XCSlot {
+    const cx<T>* src;
+    cx<T>* dst;
+    Phys ph;
+    LineSet<T> ls;
+    const double* scale;
+    int h, nc, L, nwin;  // nwin windows per row
+    size_t sp, dp;
+};
+
+template <typename T> struct YSSlot {
+    const cx<T>* src;
+    cx<T>* dst;
+    Phys ph;
+    LineSet<T> ls;
+    double* partials;
+    int L, h, nc, ncs;  // ncs strips of 16 columns
+    size_t sp, dp;
+};
+
 struct NSlot {
     const double* partials;
     int n;
@@ -261,13 +283,19 @@ hipError_t launch_obs_finalize(const double* partials, int nblk, double* out, hi
 
 // Batched forms: the x sweep (local substep fused; imaginary time also applies
 // each condensate's pending scale) and the windowed y sweep (imaginary time
-// stores norm partials) over the map's blocks; per-condensate norm totals,
-// scale resets and final scaling.
+// stores norm partials) over the map's blocks, as whole-row scans and scanned
+// windows or as chain x windows and stacked chain y windows (tile: the chain
+// and stacked tile indices); per-condensate norm totals, scale resets and
+// final scaling.
 template <typename T>
 hipError_t launch_x_batch(const XSlot<T>* slots, const unsigned* map, int nblk, int K, int block, bool imag,
                           hipStream_t st);
 template <typename T>
 hipError_t launch_y_batch(const YSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st);
+template <typename T>
+hipError_t launch_xc_batch(const XCSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st);
+template <typename T>
+hipError_t launch_ys_batch(const YSSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st);
 hipError_t launch_set_scale_batch(const NSlot* slots, int n, double v, hipStream_t st);
 hipError_t launch_norm_finalize_batch(const NSlot* slots, int n, hipStream_t st);
 template <typename T>

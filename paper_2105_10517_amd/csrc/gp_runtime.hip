@@ -490,11 +490,13 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
         // rows longer than 512 threads of eight points: the whole-row solve
         // would hold sixteen points per thread and spill; the chain windows
         // take rows of any length (the tile that writes the largest share of
-        // the points it loads)
+        // the points it loads; sixteen points per lane spill with the local
+        // substep fused)
         double best = 0.0;
-        for (int t = 0; t < gp::kNumChainTiles; ++t) {
+        for (int i = 0; i < gp::kNumChainTiles; ++i) {
+            const int t = (i + 4) % gp::kNumChainTiles;  // (one line at a time first: fewer registers)
             int h, L;
-            if (!xchain_fits<T>(hm.hhx, hm.x.Kg, t, h, L)) continue;
+            if (gp::xchain_tile<T>(t).K > 8 || !xchain_fits<T>(hm.hhx, hm.x.Kg, t, h, L)) continue;
             const double eff = (double)L / (64.0 * gp::xchain_tile<T>(t).K);
             if (eff > best) { best = eff; hm.xchain = true; hm.xctile = t; hm.hcx = h; hm.Lcx = L; }
         }
@@ -1389,7 +1391,55 @@ size_t stage_put(std::vector<unsigned char>& img, const std::vector<V>& v) {
 // from the widest row, the y tile that the most condensates can window.
 struct BatchShape {
     int K = 2, block = 64, tile = 0;
+    bool chain = false;     // chain x windows and stacked chain y windows
+    int xtile = 0, ytile = 0;  // their tiles
 };
+
+// The chain shapes of a group, when every condensate of it that can be
+// grouped (Lie splitting) leaves both solvers to the library or asks for
+// these, and fits one x chain tile and one stacked y tile: the tiles with the
+// fewest lane-points over the group.
+template <typename T>
+bool batch_chain_shape(const std::vector<gp_spin1*>& hs, bool imag, BatchShape& bs) {
+    std::vector<gp_spin1*> g;
+    for (gp_spin1* h : hs) {
+        if (h->p.split != GP_SPLIT_LIE) continue;
+        if (h->p.x_solver != GP_XSOLVER_AUTO && h->p.x_solver != GP_XSOLVER_CHAIN) return false;
+        if (h->p.y_solver != GP_YSOLVER_AUTO && h->p.y_solver != GP_YSOLVER_STACK) return false;
+        g.push_back(h);
+    }
+    if (g.empty()) return false;
+    double bx = -1.0, by = -1.0;
+    for (int i = 0; i < gp::kNumChainTiles; ++i) {
+        const int t = (i + 4) % gp::kNumChainTiles;  // (one line at a time first: fewer registers)
+        if (gp::xchain_tile<T>(t).K > 8) continue;   // (spills with the local substep fused)
+        double cost = 0.0;
+        bool all = true;
+        for (gp_spin1* h : g) {
+            const ModeState& ms = h->mode[imag];
+            int hh, L;
+            if (!xchain_fits<T>(ms.hhx, ms.x.Kg, t, hh, L)) { all = false; break; }
+            cost += (double)((h->p.nx + L - 1) / L) * h->p.ny * 64.0 * gp::xchain_tile<T>(t).K;
+        }
+        if (all && (bx < 0 || cost < bx)) { bx = cost; bs.xtile = t; }
+    }
+    for (int t = 0; t < gp::kNumStackTiles; ++t) {
+        double cost = 0.0;
+        bool all = true;
+        for (gp_spin1* h : g) {
+            const ModeState& ms = h->mode[imag];
+            int hh, L;
+            if (!ystack_fits<T>(h->p.nx, h->p.ny, ms.hh, ms.y.Kg, t, hh, L)) { all = false; break; }
+            cost += (double)((h->p.nx + 15) / 16) * ((h->p.ny + L - 1) / L) * 256.0 * gp::ystack_tile<T>(t).K;
+        }
+        if (all && (by < 0 || cost < by)) { by = cost; bs.ytile = t; }
+    }
+    if (bx < 0 || by < 0) return false;
+    bs.chain = true;
+    bs.K = gp::xchain_tile<T>(bs.xtile).K;
+    bs.block = 64 * gp::xchain_tile<T>(bs.xtile).NW;
+    return true;
+}
 
 template <typename T>
 BatchShape batch_shape(const std::vector<gp_spin1*>& hs, bool imag) {
@@ -1415,6 +1465,59 @@ BatchShape batch_shape(const std::vector<gp_spin1*>& hs, bool imag) {
         if (cnt > best) { best = cnt; bs.tile = t; }
     }
     return bs;
+}
+
+// Descriptors and block maps of the chain-shaped group for one phase (the
+// condensates with steps left after `done`), appended to the staging image.
+template <typename T>
+void chain_tables(gp_spin1_batch* b, const std::vector<int>& grouped, void* const* psi, const int64_t* nsteps,
+                  int64_t done, bool imag, const BatchShape& bs, std::vector<unsigned char>& img, size_t& o_xs,
+                  size_t& o_ys, size_t& o_ns, size_t& o_ss, size_t& o_xm, size_t& o_ym, size_t& o_sm, int& nslot,
+                  int& xblk, int& yblk, int& sblk) {
+    using C = gp::cx<T>;
+    std::vector<gp::XCSlot<T>> xs;
+    std::vector<gp::YSSlot<T>> ys;
+    std::vector<gp::NSlot> ns;
+    std::vector<gp::SSlot<T>> ss;
+    std::vector<unsigned> xm, ym, sm;
+    const gp::ChainTile xt = gp::xchain_tile<T>(bs.xtile);
+    const gp::ChainTile yt = gp::ystack_tile<T>(bs.ytile);
+    for (int s : grouped) {
+        if (nsteps[s] <= done) continue;
+        gp_spin1* h = b->slot[s];
+        const ModeState& ms = h->mode[imag];
+        const unsigned id = (unsigned)xs.size();
+        int hx, Lx, hy, Ly;
+        xchain_fits<T>(ms.hhx, ms.x.Kg, bs.xtile, hx, Lx);
+        ystack_fits<T>(h->p.nx, h->p.ny, ms.hh, ms.y.Kg, bs.ytile, hy, Ly);
+        const int nwin = (h->p.nx + Lx - 1) / Lx;
+        const int xb = (int)(((int64_t)nwin * h->p.ny + xt.NW - 1) / xt.NW);
+        const int ncs = (h->p.nx + 15) / 16;
+        const int nyb = ncs * ((h->p.ny + Ly - 1) / Ly);
+        const size_t n3 = (size_t)3 * h->p.nx * h->p.ny;
+        const int nsb = (int)((n3 + gp::kScaleChunk - 1) / gp::kScaleChunk);
+        xs.push_back(gp::XCSlot<T>{(const C*)psi[s], (C*)h->d_work, phys(h->p), lineset<T>(ms.x), h->d_scale, hx,
+                                   gp::chain_lanes(hx, xt.K), Lx, nwin, h->psp, h->wsp});
+        ys.push_back(gp::YSSlot<T>{(const C*)h->d_work, (C*)psi[s], phys(h->p), lineset<T>(ms.y), h->d_part, Ly, hy,
+                                   gp::chain_lanes(hy, yt.K), ncs, h->wsp, h->psp});
+        ns.push_back(gp::NSlot{h->d_part, nyb, h->p.dx * h->p.dy, h->d_scale, h->d_flag, norm_rule(h->p)});
+        ss.push_back(gp::SSlot<T>{(C*)psi[s], n3 / 3, h->psp, h->d_scale});
+        for (int k = 0; k < xb; ++k) xm.push_back((id << gp::kMapShift) | (unsigned)k);
+        for (int k = 0; k < nyb; ++k) ym.push_back((id << gp::kMapShift) | (unsigned)k);
+        for (int k = 0; k < nsb; ++k) sm.push_back((id << gp::kMapShift) | (unsigned)k);
+    }
+    nslot = (int)xs.size();
+    if (!nslot) return;
+    xblk = (int)xm.size();
+    yblk = (int)ym.size();
+    sblk = (int)sm.size();
+    o_xs = stage_put(img, xs);
+    o_ys = stage_put(img, ys);
+    o_ns = stage_put(img, ns);
+    o_ss = stage_put(img, ss);
+    o_xm = stage_put(img, xm);
+    o_ym = stage_put(img, ym);
+    o_sm = stage_put(img, sm);
 }
 
 template <typename T>
@@ -1444,7 +1547,7 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
         for (int s : act)
             if ((mode[s] == 0) == (im == 1)) hs.push_back(b->slot[s]);
         if (hs.empty()) continue;
-        shape[im] = batch_shape<T>(hs, im == 1);
+        if (!batch_chain_shape<T>(hs, im == 1, shape[im])) shape[im] = batch_shape<T>(hs, im == 1);
     }
     int64_t maxn = 0;
     for (int s : act) {
@@ -1453,18 +1556,34 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
         const ModeState& ms = h->mode[im];
         int hh, L, G, R;
         // Strang slots need the y sweep's output substep, which the batched kernel does not carry
-        bool ok = h->p.split == GP_SPLIT_LIE && ms.window && tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
-                  x_shape_ok(h->p.nx, shape[im].K, ms.x.Kg, sizeof(T), G, R) && G <= shape[im].block;
-        if (ok) {
-            // every block of a grouped condensate is named by a map entry with
-            // kMapShift bits of block index: larger condensates run alone
-            const gp::YTile yt = gp::ytile<T>(shape[im].tile);
-            const int64_t rb = std::max(1, std::min(8, shape[im].block / G));
-            const int64_t xb = (h->p.ny + rb - 1) / rb;
-            const int64_t yb = (int64_t)((h->p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((h->p.ny + L - 1) / L);
-            const int64_t sb = ((int64_t)3 * h->p.nx * h->p.ny + gp::kScaleChunk - 1) / gp::kScaleChunk;
-            const int64_t lim = (int64_t)gp::kMapMask + 1;
-            ok = xb <= lim && yb <= lim && sb <= lim;
+        bool ok;
+        if (shape[im].chain) {
+            const gp::ChainTile xt = gp::xchain_tile<T>(shape[im].xtile);
+            int hx, Lx;
+            ok = h->p.split == GP_SPLIT_LIE && xchain_fits<T>(ms.hhx, ms.x.Kg, shape[im].xtile, hx, Lx) &&
+                 ystack_fits<T>(h->p.nx, h->p.ny, ms.hh, ms.y.Kg, shape[im].ytile, hh, L);
+            if (ok) {
+                const int64_t xb = ((int64_t)((h->p.nx + Lx - 1) / Lx) * h->p.ny + xt.NW - 1) / xt.NW;
+                const int64_t yb = (int64_t)((h->p.nx + 15) / 16) * ((h->p.ny + L - 1) / L);
+                const int64_t sb = ((int64_t)3 * h->p.nx * h->p.ny + gp::kScaleChunk - 1) / gp::kScaleChunk;
+                const int64_t lim = (int64_t)gp::kMapMask + 1;
+                ok = xb <= lim && yb <= lim && sb <= lim;
+            }
+        } else {
+            ok = h->p.split == GP_SPLIT_LIE && ms.window &&
+                 tile_window(h->p.ny, ms.hh, gp::ywindow(gp::ytile<T>(shape[im].tile)), hh, L) &&
+                 x_shape_ok(h->p.nx, shape[im].K, ms.x.Kg, sizeof(T), G, R) && G <= shape[im].block;
+            if (ok) {
+                // every block of a grouped condensate is named by a map entry with
+                // kMapShift bits of block index: larger condensates run alone
+                const gp::YTile yt = gp::ytile<T>(shape[im].tile);
+                const int64_t rb = std::max(1, std::min(8, shape[im].block / G));
+                const int64_t xb = (h->p.ny + rb - 1) / rb;
+                const int64_t yb = (int64_t)((h->p.nx + 4 * yt.NW - 1) / (4 * yt.NW)) * ((h->p.ny + L - 1) / L);
+                const int64_t sb = ((int64_t)3 * h->p.nx * h->p.ny + gp::kScaleChunk - 1) / gp::kScaleChunk;
+                const int64_t lim = (int64_t)gp::kMapMask + 1;
+                ok = xb <= lim && yb <= lim && sb <= lim;
+            }
         }
         // and the map names at most kMaxBatchSlots condensates per launch
         if (ok && (int)grouped[im].size() >= gp::kMaxBatchSlots) ok = false;
@@ -1484,7 +1603,10 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
         if (grouped[im].empty()) continue;
         b->info.x_points[md] = shape[im].K;
         b->info.x_block[md] = shape[im].block;
-        b->info.y_tile[md] = shape[im].tile + 1;
+        b->info.y_tile[md] = (shape[im].chain ? shape[im].ytile : shape[im].tile) + 1;
+        b->info.x_solver[md] = shape[im].chain ? GP_XSOLVER_CHAIN : GP_XSOLVER_SCAN;
+        b->info.y_solver[md] = shape[im].chain ? GP_YSOLVER_STACK : GP_YSOLVER_WINDOW;
+        b->info.x_tile[md] = shape[im].chain ? shape[im].xtile + 1 : 0;
     }
     // phases: the grouped condensates still running share each launch
     int64_t done = 0;
@@ -1501,6 +1623,12 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
             int nslot = 0, xblk = 0, yblk = 0, sblk = 0;
         } tb[2];
         for (int im = 0; im < 2; ++im) {
+            if (shape[im].chain) {
+                chain_tables<T>(b, grouped[im], psi, nsteps, done, im == 1, shape[im], img, tb[im].xs, tb[im].ys,
+                                tb[im].ns, tb[im].ss, tb[im].xm, tb[im].ym, tb[im].sm, tb[im].nslot, tb[im].xblk,
+                                tb[im].yblk, tb[im].sblk);
+                continue;
+            }
             std::vector<gp::XSlot<T>> xs;
             std::vector<gp::YSlot<T>> ys;
             std::vector<gp::NSlot> ns;
@@ -1580,12 +1708,21 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
             for (int im = 1; im >= 0; --im) {
                 if (!tb[im].nslot) continue;
                 const GroupTables& g = tb[im];
-                if ((e = gp::launch_x_batch<T>((const gp::XSlot<T>*)at(g.xs), (const unsigned*)at(g.xm), g.xblk,
-                                               shape[im].K, shape[im].block, im == 1, st)) != hipSuccess)
-                    return bhip(b, e, "batch x sweep");
-                if ((e = gp::launch_y_batch<T>((const gp::YSlot<T>*)at(g.ys), (const unsigned*)at(g.ym), g.yblk,
-                                               shape[im].tile, im == 1, st)) != hipSuccess)
-                    return bhip(b, e, "batch y sweep");
+                if (shape[im].chain) {
+                    if ((e = gp::launch_xc_batch<T>((const gp::XCSlot<T>*)at(g.xs), (const unsigned*)at(g.xm), g.xblk,
+                                                    shape[im].xtile, im == 1, st)) != hipSuccess)
+                        return bhip(b, e, "batch x sweep");
+                    if ((e = gp::launch_ys_batch<T>((const gp::YSSlot<T>*)at(g.ys), (const unsigned*)at(g.ym), g.yblk,
+                                                    shape[im].ytile, im == 1, st)) != hipSuccess)
+                        return bhip(b, e, "batch y sweep");
+                } else {
+                    if ((e = gp::launch_x_batch<T>((const gp::XSlot<T>*)at(g.xs), (const unsigned*)at(g.xm), g.xblk,
+                                                   shape[im].K, shape[im].block, im == 1, st)) != hipSuccess)
+                        return bhip(b, e, "batch x sweep");
+                    if ((e = gp::launch_y_batch<T>((const gp::YSlot<T>*)at(g.ys), (const unsigned*)at(g.ym), g.yblk,
+                                                   shape[im].tile, im == 1, st)) != hipSuccess)
+                        return bhip(b, e, "batch y sweep");
+                }
                 if (im == 1 && (e = gp::launch_norm_finalize_batch((const gp::NSlot*)at(g.ns), g.nslot, st)) != hipSuccess)
                     return bhip(b, e, "batch norm");
                 b->info.launches += im == 1 ? 3 : 2;

@@ -280,16 +280,14 @@ __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ 
 // point h).  Waves are independent (no shared memory, no barrier): wave w of
 // logical block lb takes window lb NW + w of the row-major window list.
 // ---------------------------------------------------------------------------
-template <typename T, bool IMAG, int K, int NW, bool SEQ, bool LOCAL, bool SCALE>
-__global__ __launch_bounds__(64 * NW) void k_x_chain(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
-                                                     size_t sp, size_t dp, Phys ph, LineSet<T> ls,
-                                                     const double* __restrict__ scale, int h, int nc, int L, int nwin,
-                                                     int nblk, int order) {
+// One wave's window: wave gw of the sweep takes window gw mod nwin of row
+// gw / nwin.
+template <typename T, bool IMAG, int K, bool SEQ, bool LOCAL, bool SCALE>
+__device__ __attribute__((always_inline)) inline void x_chain_wave(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp,
+                                    const Phys& ph, const LineSet<T>& ls, const double* __restrict__ scale, int h,
+                                    int nc, int L, int nwin, int gw) {
     using C = cx<T>;
-    const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, nblk, 1);
-    if (lb < 0) return;
     const int lane = threadIdx.x & 63;
-    const int gw = lb * NW + (int)(threadIdx.x >> 6);
     const int nx = ph.nx;
     if (gw >= nwin * ph.ny) return;  // whole waves
     const int j = gw / nwin, cs = gw - j * nwin;
@@ -343,6 +341,29 @@ __global__ __launch_bounds__(64 * NW) void k_x_chain(const cx<T>* __restrict__ s
         if (g0 + k >= i0 && g0 + k < i1)
 #pragma unroll
             for (int m = 0; m < 3; ++m) rowq[m * dp + g0 + k] = v[m][k];
+}
+
+template <typename T, bool IMAG, int K, int NW, bool SEQ, bool LOCAL, bool SCALE>
+__global__ __launch_bounds__(64 * NW) void k_x_chain(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                     size_t sp, size_t dp, Phys ph, LineSet<T> ls,
+                                                     const double* __restrict__ scale, int h, int nc, int L, int nwin,
+                                                     int nblk, int order) {
+    const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, nblk, 1);
+    if (lb < 0) return;
+    x_chain_wave<T, IMAG, K, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, h, nc, L, nwin,
+                                                lb * NW + (int)(threadIdx.x >> 6));
+}
+
+// Many condensates in one launch: map entry b names the condensate and its
+// block, NW waves of that condensate's windows (local substep and pending
+// scale fused as in the single sweep).
+template <typename T, bool IMAG, int K, int NW, bool SEQ>
+__global__ __launch_bounds__(64 * NW) void k_x_chain_batch(const XCSlot<T>* __restrict__ slots,
+                                                           const unsigned* __restrict__ map) {
+    const unsigned e = map[blockIdx.x];
+    const XCSlot<T>& s = slots[e >> kMapShift];
+    x_chain_wave<T, IMAG, K, SEQ, true, IMAG>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.scale, s.h, s.nc, s.L, s.nwin,
+                                              (int)(e & kMapMask) * NW + (int)(threadIdx.x >> 6));
 }
 
 template <typename T, bool IMAG, int K, bool LOCAL, bool SCALE, int LB>
@@ -513,6 +534,36 @@ static hipError_t launch_x_batch_t(const XSlot<T>* slots, const unsigned* map, i
     return hipGetLastError();
 }
 
+template <typename T, bool IMAG, int TI>
+static hipError_t launch_xc_batch_t(const XCSlot<T>* slots, const unsigned* map, int nblk, hipStream_t st) {
+    constexpr ChainTile ct = xchain_tile<T>(TI);
+    hipExtLaunchKernelGGL(k_x_chain_batch<T, IMAG, ct.K, ct.NW, ct.SEQ>, dim3(nblk), dim3(64 * ct.NW), 0, st, nullptr,
+                          nullptr, 0, slots, map);
+    return hipGetLastError();
+}
+
+template <typename T, bool IMAG>
+static hipError_t launch_xc_batch_i(const XCSlot<T>* slots, const unsigned* map, int nblk, int tile, hipStream_t st) {
+    if (nblk <= 0) return hipErrorInvalidValue;
+    switch (tile) {
+        case 0: return launch_xc_batch_t<T, IMAG, 0>(slots, map, nblk, st);
+        case 1: return launch_xc_batch_t<T, IMAG, 1>(slots, map, nblk, st);
+        case 2: return launch_xc_batch_t<T, IMAG, 2>(slots, map, nblk, st);
+        case 3: return launch_xc_batch_t<T, IMAG, 3>(slots, map, nblk, st);
+        case 4: return launch_xc_batch_t<T, IMAG, 4>(slots, map, nblk, st);
+        case 5: return launch_xc_batch_t<T, IMAG, 5>(slots, map, nblk, st);
+        case 6: return launch_xc_batch_t<T, IMAG, 6>(slots, map, nblk, st);
+        case 7: return launch_xc_batch_t<T, IMAG, 7>(slots, map, nblk, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t launch_xc_batch(const XCSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st) {
+    return imag ? launch_xc_batch_i<T, true>(slots, map, nblk, tile, st)
+                : launch_xc_batch_i<T, false>(slots, map, nblk, tile, st);
+}
+
 template <typename T>
 hipError_t launch_x_batch(const XSlot<T>* slots, const unsigned* map, int nblk, int K, int block, bool imag,
                           hipStream_t st) {
@@ -524,5 +575,7 @@ template hipError_t launch_x<double>(const XLaunch<double>&, hipStream_t, hipEve
 template hipError_t launch_x<float>(const XLaunch<float>&, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_x_batch<double>(const XSlot<double>*, const unsigned*, int, int, int, bool, hipStream_t);
 template hipError_t launch_x_batch<float>(const XSlot<float>*, const unsigned*, int, int, int, bool, hipStream_t);
+template hipError_t launch_xc_batch<double>(const XCSlot<double>*, const unsigned*, int, int, bool, hipStream_t);
+template hipError_t launch_xc_batch<float>(const XCSlot<float>*, const unsigned*, int, int, bool, hipStream_t);
 
 }  // namespace gp

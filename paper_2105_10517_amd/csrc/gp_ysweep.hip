@@ -265,15 +265,13 @@ __device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& l
         for (int qq = 0; qq < NQ; ++qq) sh.d0[q0 + qq][cl] = d0[qq];
 }
 
+// One block's window: logical block blk takes column strip blk mod ncs of row
+// tile blk / ncs.
 template <typename T, bool IMAG, int KY, bool SEQ, bool NORM, bool OUTL>
-__global__ __launch_bounds__(256, 2) void k_y_stack(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
-                                                 size_t dp, Phys ph, LineSet<T> ls, int L, int h, int nc, int ncs,
-                                                 NormOut no, int nblk, int order) {
+__device__ __attribute__((always_inline)) inline void y_stack_block(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp,
+                                     const Phys& ph, const LineSet<T>& ls, int L, int h, int nc, int ncs, NormOut no,
+                                     int blk, StackShm<T>& sh, double* shr) {
     using C = cx<T>;
-    __shared__ StackShm<T> sh;
-    __shared__ double shr[48];
-    const int blk = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
-    if (blk < 0) return;  // (the whole block)
     const int tid = threadIdx.x, lane = tid & 63;
     const int cl = lane & 15;                      // column within the block
     const int seg = (tid >> 6) * 4 + (lane >> 4);  // segment of the window, 0..15
@@ -360,6 +358,30 @@ __global__ __launch_bounds__(256, 2) void k_y_stack(const cx<T>* __restrict__ sr
         }
     }
     if (NORM) store_norm_partials(acc, shr, no, blk);
+}
+
+template <typename T, bool IMAG, int KY, bool SEQ, bool NORM, bool OUTL>
+__global__ __launch_bounds__(256, 2) void k_y_stack(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
+                                                 size_t dp, Phys ph, LineSet<T> ls, int L, int h, int nc, int ncs,
+                                                 NormOut no, int nblk, int order) {
+    __shared__ StackShm<T> sh;
+    __shared__ double shr[48];
+    const int blk = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
+    if (blk < 0) return;  // (the whole block)
+    y_stack_block<T, IMAG, KY, SEQ, NORM, OUTL>(src, dst, sp, dp, ph, ls, L, h, nc, ncs, no, blk, sh, shr);
+}
+
+// Many condensates in one launch: map entry b names the condensate and its
+// window (imaginary time stores each condensate's norm partials).
+template <typename T, bool IMAG, int KY, bool SEQ>
+__global__ __launch_bounds__(256, 2) void k_y_stack_batch(const YSSlot<T>* __restrict__ slots,
+                                                       const unsigned* __restrict__ map) {
+    __shared__ StackShm<T> sh;
+    __shared__ double shr[48];
+    const unsigned e = map[blockIdx.x];
+    const YSSlot<T>& s = slots[e >> kMapShift];
+    y_stack_block<T, IMAG, KY, SEQ, IMAG, false>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.L, s.h, s.nc, s.ncs,
+                                                 NormOut{s.partials}, (int)(e & kMapMask), sh, shr);
 }
 
 template <typename T, bool IMAG, int KY, int NW, bool SEQ>
@@ -606,6 +628,26 @@ static hipError_t launch_y_batch_i(const YSlot<T>* slots, const unsigned* map, i
     }
 }
 
+template <typename T, bool IMAG, int TI>
+static hipError_t launch_ys_batch_t(const YSSlot<T>* slots, const unsigned* map, int nblk, hipStream_t st) {
+    constexpr ChainTile ct = ystack_tile<T>(TI);
+    hipExtLaunchKernelGGL(k_y_stack_batch<T, IMAG, ct.K, ct.SEQ>, dim3(nblk), dim3(256), 0, st, nullptr, nullptr, 0,
+                          slots, map);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ys_batch(const YSSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st) {
+    if (nblk <= 0) return hipErrorInvalidValue;
+    switch (tile) {
+        case 0: return imag ? launch_ys_batch_t<T, true, 0>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 0>(slots, map, nblk, st);
+        case 1: return imag ? launch_ys_batch_t<T, true, 1>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 1>(slots, map, nblk, st);
+        case 2: return imag ? launch_ys_batch_t<T, true, 2>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 2>(slots, map, nblk, st);
+        case 3: return imag ? launch_ys_batch_t<T, true, 3>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 3>(slots, map, nblk, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_y_batch(const YSlot<T>* slots, const unsigned* map, int nblk, int tile, bool imag, hipStream_t st) {
     return imag ? launch_y_batch_i<T, true>(slots, map, nblk, tile, st) : launch_y_batch_i<T, false>(slots, map, nblk, tile, st);
@@ -617,5 +659,7 @@ template int y_blocks<double>(const YLaunch<double>&);
 template int y_blocks<float>(const YLaunch<float>&);
 template hipError_t launch_y_batch<double>(const YSlot<double>*, const unsigned*, int, int, bool, hipStream_t);
 template hipError_t launch_y_batch<float>(const YSlot<float>*, const unsigned*, int, int, bool, hipStream_t);
+template hipError_t launch_ys_batch<double>(const YSSlot<double>*, const unsigned*, int, int, bool, hipStream_t);
+template hipError_t launch_ys_batch<float>(const YSSlot<float>*, const unsigned*, int, int, bool, hipStream_t);
 
 }  // namespace gp

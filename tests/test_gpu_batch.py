@@ -7,6 +7,10 @@ batched and single kernels are separate instantiations of one source, and
 the compiler may contract a product and a sum into an FMA in one and not the
 other, a last-bit difference).  Tolerance: relative L2 1e-12 (FP64) and 2e-6
 (FP32) after up to 30 steps.  Against the oracle: the FP64 parity bar.
+
+Both batched shapes are covered: chain x windows with stacked chain y windows
+(the default when the group fits them) and whole-row scans with scanned y
+windows (asked for per slot, or when a slot does not fit the chain tiles).
 """
 import math
 
@@ -51,7 +55,12 @@ def same(got, want, precision):
 def alone(p, psi0, n, mode, precision, info, dtype):
     """The same condensate on a single handle with the batch's launch shape."""
     md = 0 if mode == "imag" else 1
-    s = binding.Solver(p, precision, x_points=info["x_points"][md], y_tile=info["y_tile"][md])
+    if info["x_solver"][md] == binding.GP_XSOLVER_CHAIN:
+        assert info["y_solver"][md] == binding.GP_YSOLVER_STACK
+        s = binding.Solver(p, precision, x_solver="chain", x_tile=info["x_tile"][md], y_solver="stack",
+                           y_tile=info["y_tile"][md])
+    else:
+        s = binding.Solver(p, precision, x_points=info["x_points"][md], y_tile=info["y_tile"][md])
     t = dev(psi0, dtype)
     (s.step_imag if mode == "imag" else s.step_real)(t, n)
     s.sync()
@@ -60,12 +69,17 @@ def alone(p, psi0, n, mode, precision, info, dtype):
     return out
 
 
+SHAPES = {"chain": dict(), "scan": dict(x_solver="scan", y_solver="window")}
+SHAPE_SOLVER = {"chain": binding.GP_XSOLVER_CHAIN, "scan": binding.GP_XSOLVER_SCAN}
+
+
+@pytest.mark.parametrize("shape", ["chain", "scan"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_equals_single_handles(precision):
+def test_batch_equals_single_handles(precision, shape):
     ps = mixed_slots()
     modes = ["imag", "real", "imag", "real", "imag"]
     nsteps = [30, 12, 7, 30, 19]  # several phases
-    b = binding.Batch(ps, precision)
+    b = binding.Batch(ps, precision, **SHAPES[shape])
     psi0 = [initial(p, 10 + k) for k, p in enumerate(ps)]
     ts = [dev(a, b.dtype) for a in psi0]
     b.step(ts, nsteps, modes)
@@ -73,6 +87,7 @@ def test_batch_equals_single_handles(precision):
     info = b.info()
     assert info["grouped"] == len(ps) and info["individual"] == 0
     assert info["phases"] == len(set(nsteps))
+    assert info["x_solver"] == [SHAPE_SOLVER[shape]] * 2, info
     for k, p in enumerate(ps):
         want = alone(p, psi0[k], nsteps[k], modes[k], precision, info, b.dtype)
         got = ts[k].cpu()
@@ -81,11 +96,12 @@ def test_batch_equals_single_handles(precision):
     b.close()
 
 
-def test_batch_matches_oracle():
+@pytest.mark.parametrize("shape", ["chain", "scan"])
+def test_batch_matches_oracle(shape):
     ps = mixed_slots()[:4]
     modes = ["imag", "real", "real", "imag"]
     nsteps = [25, 25, 10, 40]
-    b = binding.Batch(ps, "fp64")
+    b = binding.Batch(ps, "fp64", **SHAPES[shape])
     psi0 = [initial(p, 20 + k) for k, p in enumerate(ps)]
     ts = [dev(a, torch.complex128) for a in psi0]
     b.step(ts, nsteps, modes)
@@ -144,6 +160,8 @@ def test_slot_outside_the_batch_tile_runs_alone():
     b.sync()
     info = b.info()
     assert info["individual"] == 1 and info["grouped"] == 1
+    # (the tall grid fits no stacked tile either: the group takes the scanned shapes)
+    assert info["x_solver"][0] == binding.GP_XSOLVER_SCAN
     s = binding.Solver(tall, "fp64")
     t = dev(psi[1], torch.complex128)
     s.step_imag(t, 6)
@@ -223,7 +241,7 @@ def test_condensate_beyond_the_block_map_runs_alone():
     assert ny > (1 << 20)
     if binding.plan_query(huge, True)["y_solver"] != binding.GP_YSOLVER_WINDOW:
         pytest.skip("the tall grid does not window here")
-    b = binding.Batch([small, short], "fp32")
+    b = binding.Batch([small, short], "fp32", **SHAPES["scan"])
     b.step([dev(initial(small, 71), torch.complex64), dev(initial(short, 72), torch.complex64)], [2, 2], ["imag", "imag"])
     b.sync()
     assert b.info()["grouped"] == 2
@@ -238,13 +256,13 @@ def test_condensate_beyond_the_block_map_runs_alone():
     for m, w in enumerate((0.25, 0.5, 0.25)):
         psi[m, j, :] = np.sqrt(w) * g * np.exp(1j * rng.uniform(-np.pi, np.pi, g.shape))
     psi /= np.sqrt((np.abs(psi.astype(np.complex128)) ** 2).sum() * 0.01)
-    b = binding.Batch([small, huge], "fp32")
+    b = binding.Batch([small, huge], "fp32", **SHAPES["scan"])
     ts = [dev(initial(small, 71), torch.complex64), torch.from_numpy(psi).cuda()]
     b.step(ts, [3, 3], ["imag", "imag"])
     b.sync()
     info = b.info()
     assert info["individual"] == 1 and info["grouped"] == 1
-    s = binding.Solver(huge, "fp32")
+    s = binding.Solver(huge, "fp32", x_solver="scan", y_solver="window")
     t = torch.from_numpy(psi).cuda()
     s.step_imag(t, 3)
     s.sync()
