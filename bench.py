@@ -307,7 +307,8 @@ def serving_c5(torch, binding, inputs, n, rate):
         if k in st:
             out[k] = st[k]
     log(f"[bench] C5 serving {rate:g}/s x {n}: p50 {st['p50_latency']:.3f} s, p99 {st['p99_latency']:.3f} s, served "
-        f"{st['served_rate']:.3e} vs offered {st['offered_rate']:.3e} pt-steps/s, {st['mean_active']:.1f} in flight")
+        f"{st['served_rate']:.3e} vs offered {st['offered_rate']:.3e} pt-steps/s, {st['mean_active']:.1f} in flight, "
+        f"GPU busy {st.get('gpu_busy', 0.0):.3f}, admission {st.get('admit_ms', 0.0):.0f} ms")
     del reqs
     torch.cuda.empty_cache()
     return out

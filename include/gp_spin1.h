@@ -351,7 +351,13 @@ const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b);
  * 64 KiB of scratch, s = 16 or 8); each round advances every admitted
  * condensate together by the steps left to the nearest completion (at most
  * chunk_steps), so requests join and leave between rounds.  A request's
- * latency runs from its arrival to the end of the round that completes it.
+ * latency runs from its arrival to the end of the round that completes it
+ * (read from an event recorded after that round).  The rounds run on a stream
+ * of the loop's own (non-blocking, default priority; it starts after the
+ * work queued on hip_stream, which resumes after the last round), up to two
+ * at a time: while the GPU runs one round the host admits arrivals (building
+ * their tables) and enqueues the next; the tables of finished requests are
+ * released while the GPU idles or at the end.
  *
  * req[n]: sorted by arrival (seconds after the start of the trace, scaled by
  *   time_scale; 0 replays every request as arriving at once); p as for
@@ -363,7 +369,7 @@ const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b);
  *   latency percentiles (p50, p99; linear interpolation), rounds and mean /
  *   maximum condensates in flight.
  * Blocks until every request is done.  Allocates the slot tables as requests
- * are admitted and frees them as they complete.  GP_EINVAL for unsorted or
+ * are admitted and frees them after they complete.  GP_EINVAL for unsorted or
  * malformed requests or a request larger than the budget; errors of the
  * batch calls otherwise (message on stderr). */
 typedef struct {
@@ -387,6 +393,8 @@ typedef struct {
     double p50_latency, p99_latency, mean_latency, max_latency;
     int32_t completed, max_active, rounds;
     double mean_active;
+    double gpu_busy;          /* fraction of the wall time the GPU spent in rounds */
+    double admit_ms;          /* host time spent admitting requests (tables, uploads) */
 } gp_spin1_serve_stats;
 int gp_spin1_serve(const gp_spin1_request* req, int32_t n, const gp_spin1_serve_config* cfg, void* hip_stream,
                    gp_spin1_request_result* out, gp_spin1_serve_stats* stats);

@@ -109,7 +109,8 @@ class ServeStats(ctypes.Structure):
                 ("offered_rate", ctypes.c_double), ("p50_latency", ctypes.c_double),
                 ("p99_latency", ctypes.c_double), ("mean_latency", ctypes.c_double),
                 ("max_latency", ctypes.c_double), ("completed", ctypes.c_int32), ("max_active", ctypes.c_int32),
-                ("rounds", ctypes.c_int32), ("mean_active", ctypes.c_double)]
+                ("rounds", ctypes.c_int32), ("mean_active", ctypes.c_double), ("gpu_busy", ctypes.c_double),
+                ("admit_ms", ctypes.c_double)]
 
 
 _lib = None

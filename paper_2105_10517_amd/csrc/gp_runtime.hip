@@ -1746,8 +1746,17 @@ int batch_step_t(gp_spin1_batch* b, void* const* psi, const int64_t* nsteps, con
 // and the device-memory budget allows; every round advances all admitted
 // condensates together by the steps left to the nearest completion (at most
 // chunk_steps), so requests join and leave between rounds (continuous
-// batching).  Latency runs from arrival to the end of the round that
-// completes the request.
+// batching).
+//
+// The host keeps up to two rounds in flight on a stream of its own (one that
+// does not wait for the null stream, so the table uploads of an admission run
+// beside the rounds): while the GPU runs round r, the host admits arrivals
+// and enqueues round r + 1.  The condensates that a round completes are known
+// when it is enqueued (the step counts are), so their slots take new
+// requests for the next round at once; their tables are released only when
+// the GPU is idle (freeing device memory waits for the whole device) or at
+// the end.  A request's completion time is read from the event recorded after
+// its last round, and its latency runs from its arrival to that time.
 // ---------------------------------------------------------------------------
 // Device bytes a condensate holds while admitted: its wave function, the
 // work copy and the per-line tables (pivots + coefficients, both directions).
@@ -1762,6 +1771,45 @@ size_t request_bytes(const gp_spin1_params& p) {
 double seconds_since(const std::chrono::steady_clock::time_point& t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
+
+// A round in flight: its events and the requests it completes.
+struct Round {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    std::vector<int> finishing;   // request indices
+    std::vector<gp_spin1*> dead;  // their slot handles (released later)
+    double bytes = 0.0;           // their budget charge
+};
+
+// Everything the serving loop owns (released on every exit path).
+struct ServeState {
+    hipStream_t sst = nullptr;
+    gp_spin1_batch* b = nullptr;
+    std::vector<hipEvent_t> events;  // pool
+    std::vector<Round> flight;       // rounds in flight, oldest first
+    std::vector<gp_spin1*> graveyard;
+    hipEvent_t origin = nullptr;
+    ~ServeState() {
+        if (sst) (void)hipStreamSynchronize(sst);
+        for (Round& r : flight) {
+            for (gp_spin1* h : r.dead) graveyard.push_back(h);
+            if (r.e0) events.push_back(r.e0);
+            if (r.e1) events.push_back(r.e1);
+        }
+        for (gp_spin1* h : graveyard) destroy_all(h);
+        if (b) (void)gp_spin1_batch_destroy(b);
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (origin) (void)hipEventDestroy(origin);
+        if (sst) (void)hipStreamDestroy(sst);
+    }
+    hipError_t event(hipEvent_t* e) {
+        if (!events.empty()) {
+            *e = events.back();
+            events.pop_back();
+            return hipSuccess;
+        }
+        return hipEventCreate(e);
+    }
+};
 
 int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& cfg, hipStream_t st,
               gp_spin1_request_result* out, gp_spin1_serve_stats* stats, std::string& err) {
@@ -1778,12 +1826,37 @@ int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& c
             return GP_EINVAL;
         }
     }
+    ServeState S;
+    hipError_t e;
+    auto hfail = [&](hipError_t x, const char* where) {
+        err = std::string("serve: ") + where + ": " + hipGetErrorString(x);
+        return GP_EHIP;
+    };
+    if ((e = hipStreamCreateWithFlags(&S.sst, hipStreamNonBlocking)) != hipSuccess) return hfail(e, "stream");
+    // the rounds start after the caller's work on st (the wave functions' uploads)
+    if ((e = S.event(&S.origin)) != hipSuccess) return hfail(e, "event");
+    if ((e = hipEventRecord(S.origin, st)) != hipSuccess) return hfail(e, "event");
+    if ((e = hipStreamWaitEvent(S.sst, S.origin, 0)) != hipSuccess) return hfail(e, "event");
+    if ((e = hipEventSynchronize(S.origin)) != hipSuccess) return hfail(e, "event");
     const int ns = cfg.max_slots;
     std::vector<gp_spin1_params> empty(ns);
-    for (auto& e : empty) { std::memset(&e, 0, sizeof e); e.precision = prec; }
-    gp_spin1_batch* b = nullptr;
-    int rc = gp_spin1_batch_create(empty.data(), ns, (void*)st, &b);
+    for (auto& x : empty) { std::memset(&x, 0, sizeof x); x.precision = prec; }
+    int rc = gp_spin1_batch_create(empty.data(), ns, (void*)S.sst, &S.b);
     if (rc) { err = "batch create failed"; return rc; }
+    gp_spin1_batch* b = S.b;
+    // the clock starts just before the origin event, which the idle stream
+    // passes at once (so a GPU time after the origin never runs ahead of the
+    // host clock: a request admitted after the host saw a round end starts
+    // no earlier than that round's end)
+    const auto t0 = std::chrono::steady_clock::now();
+    if ((e = hipEventRecord(S.origin, S.sst)) != hipSuccess) return hfail(e, "event");
+    if ((e = hipEventSynchronize(S.origin)) != hipSuccess) return hfail(e, "event");
+    auto arrival = [&](int k) { return req[k].arrival * cfg.time_scale; };
+    auto gpu_time = [&](hipEvent_t ev) {  // seconds after the origin, on the GPU's clock
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, S.origin, ev);
+        return 1e-3 * ms;
+    };
     std::vector<int> who(ns, -1);
     std::vector<int64_t> left(ns, 0);
     std::vector<void*> psi(ns, nullptr);
@@ -1792,20 +1865,51 @@ int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& c
     std::vector<uint8_t> on(ns, 0);
     std::vector<double> lat;
     lat.reserve(n);
-    double in_use = 0.0, active_sum = 0.0, pts = 0.0;
+    std::vector<Round>& flight = S.flight;
+    double in_use = 0.0, dead_bytes = 0.0, active_sum = 0.0, pts = 0.0, busy = 0.0, admit_s = 0.0;
     int next = 0, done = 0, active = 0, max_active = 0, rounds = 0;
-    const auto t0 = std::chrono::steady_clock::now();
-    auto arrival = [&](int k) { return req[k].arrival * cfg.time_scale; };
+    const double dead_cap = std::max(1e9, 0.25 * cfg.hbm_budget_bytes);
+    // retire the oldest round (waits for it)
+    auto retire = [&]() -> int {
+        Round& r = flight.front();
+        if ((e = hipEventSynchronize(r.e1)) != hipSuccess) return hfail(e, "round");
+        const double fin = gpu_time(r.e1);
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) busy += 1e-3 * ms;
+        for (int k : r.finishing) {
+            out[k].finish = fin;
+            lat.push_back(fin - arrival(k));
+            ++done;
+        }
+        in_use -= r.bytes;
+        for (gp_spin1* h : r.dead) S.graveyard.push_back(h);
+        S.events.push_back(r.e0);
+        S.events.push_back(r.e1);
+        flight.erase(flight.begin());
+        return GP_OK;
+    };
+    // release the tables of finished requests (only when nothing is in flight)
+    auto bury = [&]() {
+        for (gp_spin1* h : S.graveyard) destroy_all(h);
+        S.graveyard.clear();
+        dead_bytes = 0.0;
+    };
     while (done < n) {
-        double now = seconds_since(t0);
+        // rounds that have ended
+        while (!flight.empty() && hipEventQuery(flight.front().e1) == hipSuccess)
+            if ((rc = retire())) return rc;
         // admission, first come first served
+        const auto ta = std::chrono::steady_clock::now();
+        double now = seconds_since(t0);
         for (int sl = 0; sl < ns && next < n; ++sl) {
             if (who[sl] >= 0) continue;
             if (arrival(next) > now) break;
             const double need = (double)request_bytes(req[next].p);
             if (in_use + need > cfg.hbm_budget_bytes) break;
-            rc = gp_spin1_batch_set_slot(b, sl, &req[next].p);
-            if (rc) { err = "request " + std::to_string(next) + ": " + b->err; break; }
+            gp_spin1* h = nullptr;
+            rc = make_handle(&req[next].p, S.sst, &h);
+            if (rc) { err = "request " + std::to_string(next) + ": invalid or unsupported parameters"; return rc; }
+            b->slot[sl] = h;
             who[sl] = next;
             left[sl] = req[next].nsteps;
             psi[sl] = req[next].psi_dev;
@@ -1815,15 +1919,31 @@ int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& c
             ++active;
             ++next;
         }
-        if (rc) break;
+        admit_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - ta).count();
         if (active == 0) {
-            // idle until the next arrival
+            if (!flight.empty()) {
+                if ((rc = retire())) return rc;
+                continue;
+            }
+            // idle until the next arrival: a good time to release tables
+            bury();
             if (next < n) {
                 const double wait = arrival(next) - seconds_since(t0);
                 if (wait > 0) std::this_thread::sleep_for(std::chrono::duration<double>(wait));
             }
             continue;
         }
+        if (flight.size() >= 2) {
+            if ((rc = retire())) return rc;
+            continue;
+        }
+        if (dead_bytes > dead_cap) {
+            // too much held for finished requests: drain and release
+            while (!flight.empty())
+                if ((rc = retire())) return rc;
+            bury();
+        }
+        // enqueue the next round
         max_active = std::max(max_active, active);
         int64_t c = cfg.chunk_steps > 0 ? cfg.chunk_steps : INT64_MAX;
         for (int sl = 0; sl < ns; ++sl)
@@ -1832,11 +1952,13 @@ int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& c
             on[sl] = who[sl] >= 0;
             nst[sl] = on[sl] ? c : 0;
         }
+        flight.emplace_back();
+        Round& r = flight.back();
+        if ((e = S.event(&r.e0)) != hipSuccess || (e = S.event(&r.e1)) != hipSuccess) return hfail(e, "event");
+        if ((e = hipEventRecord(r.e0, S.sst)) != hipSuccess) return hfail(e, "event");
         rc = gp_spin1_batch_step(b, psi.data(), nst.data(), md.data(), on.data());
-        if (rc) { err = b->err; break; }
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) { err = std::string("serve: ") + hipGetErrorString(e); rc = GP_EHIP; break; }
-        now = seconds_since(t0);
+        if (rc) { err = b->err; return rc; }
+        if ((e = hipEventRecord(r.e1, S.sst)) != hipSuccess) return hfail(e, "event");
         ++rounds;
         active_sum += active;
         for (int sl = 0; sl < ns; ++sl) {
@@ -1845,21 +1967,25 @@ int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& c
             pts += (double)c * req[k].p.nx * req[k].p.ny;
             left[sl] -= c;
             if (left[sl] > 0) continue;
-            out[k].finish = now;
-            lat.push_back(now - arrival(k));
-            in_use -= (double)request_bytes(req[k].p);
+            // done with this round: the slot takes a new request for the next one
+            r.finishing.push_back(k);
+            r.dead.push_back(b->slot[sl]);
+            r.bytes += (double)request_bytes(req[k].p);
+            dead_bytes += (double)request_bytes(req[k].p);
+            b->slot[sl] = nullptr;
             who[sl] = -1;
             --active;
-            ++done;
-            rc = gp_spin1_batch_set_slot(b, sl, nullptr);
-            if (rc) { err = b->err; break; }
         }
-        if (rc) break;
     }
-    if (rc == GP_OK) rc = gp_spin1_batch_sync(b);
+    while (!flight.empty())
+        if ((rc = retire())) return rc;
+    // (the batch's own stream is idle now)
+    rc = gp_spin1_batch_sync(b);
+    if (rc) { err = b->err; return rc; }
+    // the caller's stream continues after the rounds
+    if ((e = hipEventRecord(S.origin, S.sst)) != hipSuccess || (e = hipStreamWaitEvent(st, S.origin, 0)) != hipSuccess)
+        return hfail(e, "event");
     const double wall = seconds_since(t0);
-    (void)gp_spin1_batch_destroy(b);
-    if (rc) return rc;
     std::sort(lat.begin(), lat.end());
     auto pct = [&](double q) {
         if (lat.empty()) return 0.0;
@@ -1886,6 +2012,8 @@ int serve_run(const gp_spin1_request* req, int n, const gp_spin1_serve_config& c
     stats->max_active = max_active;
     stats->rounds = rounds;
     stats->mean_active = rounds ? active_sum / rounds : 0.0;
+    stats->gpu_busy = wall > 0 ? busy / wall : 0.0;
+    stats->admit_ms = 1e3 * admit_s;
     return GP_OK;
 }
 

@@ -62,6 +62,7 @@ def test_served_states_equal_solo_runs(precision):
     assert st["completed"] == len(reqs)
     assert 1 <= st["max_active"] <= 4
     assert st["rounds"] >= 1 and st["p99_latency"] >= st["p50_latency"] > 0
+    assert 0.0 < st["gpu_busy"] <= 1.0 and st["admit_ms"] >= 0.0
     for k, r in enumerate(reqs):
         start, finish = res[k]
         assert 0 <= start < finish
