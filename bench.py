@@ -65,7 +65,9 @@ def kernel_roofline(timing, npts, prec):
 
 XTILES = {"fp64": [(4, 4), (8, 2), (2, 4), (4, 2)], "fp32": [(4, 4), (8, 4), (8, 2), (16, 2)]}
 YCTILES = {"fp64": [(8, 2), (8, 4), (4, 4), (7, 4)], "fp32": [(8, 4), (8, 8), (4, 4), (16, 2)]}
-STACK_K = {"fp64": (8, 6), "fp32": (8, 16)}  # stacked y windows: points per lane of tiles 1..4 (3, 4 one line at a time)
+# stacked y windows: (rows per lane, segments, one line at a time) of tiles 1..6
+STACK = {"fp64": [(8, 16, False), (6, 16, False), (8, 16, True), (6, 16, True), (8, 32, True), (6, 32, True)],
+         "fp32": [(8, 16, False), (16, 16, False), (8, 16, True), (16, 16, True), (8, 32, True), (16, 32, True)]}
 WTILES = {"fp64": [(8, 2), (8, 4), (4, 4), (4, 8)], "fp32": [(8, 4), (4, 8), (4, 4), (8, 8)]}
 
 
@@ -86,8 +88,8 @@ def kernel_prefix(kind, prec, imag, plan):
             return f"gp::k_x_window<{T}, {im}, " + tile_args(WTILES, prec, plan["x_tile"])
         return f"gp::k_x_scan<{T}, {im}, {plan['x_points_per_thread']}, "
     if plan["y_solver"] == 4:
-        kk = STACK_K[prec][(plan["y_tile"] - 1) & 1]
-        return f"gp::k_y_stack<{T}, {im}, {kk}, {'true' if plan['y_tile'] > 2 else 'false'}, "
+        kk, ns, seq = STACK[prec][plan["y_tile"] - 1]
+        return f"gp::k_y_stack<{T}, {im}, {kk}, {ns}, {'true' if seq else 'false'}, "
     if plan["y_solver"] == 3:
         return f"gp::k_y_chain<{T}, {im}, " + tile_args(YCTILES, prec, plan["y_tile"])
     if plan["y_solver"] == 2:

@@ -72,7 +72,8 @@ typedef enum {
                               carries are attenuated below the same rounding bound as the window ends);
                               y_tile then names a chain tile */
     GP_YSOLVER_STACK = 4   /* chain windows with 16 consecutive columns per block and the window's segments
-                              stacked over its waves (carries through shared memory); y_tile 1..4 */
+                              stacked over its waves (carries through shared memory); y_tile 1..4 with
+                              16 segments per window, 5..6 with 32                                      */
 } gp_ysolver;
 
 /* Choice of the x-sweep line solver. */
@@ -175,8 +176,9 @@ typedef struct {
     int32_t y_halo;              /* rows read above a y window's output (at least as many below) */
     int32_t y_rows_out;          /* rows written per y window                                    */
     int32_t y_tile;              /* 1..8, the tile shape below (5..8: lines solved one at a time)  */
-    int32_t y_tile_cols;         /* columns per y block (4 per wave)                              */
-    int32_t y_segments;          /* segments per column and window (16: one DPP row of lanes)     */
+    int32_t y_tile_cols;         /* columns per y block (4 per wave; 16 for stacked windows)      */
+    int32_t y_segments;          /* segments per column and window (16: one DPP row of lanes;
+                                    stacked windows 16 or 32)                                     */
     int32_t y_rows_per_thread;   /* a window spans y_segments * y_rows_per_thread rows            */
     int32_t pivots_x, pivots_y;  /* tabulated Thomas pivots per line before the constant limit  */
     double decay_x, decay_y;     /* largest |a m| or |c'| of the converged pivots per direction  */

@@ -54,16 +54,18 @@ template <> __host__ __device__ constexpr ChainTile ychain_tile<float>(int t) {
 __host__ __device__ inline int chain_lanes(int h, int K) { return h <= K ? 1 : (h + K - 1) / K; }
 
 // Stacked y windows (k_y_stack): 16 consecutive columns per block, one per
-// lane of a DPP row, and the 16 segments of a window spread over the four
+// lane of a DPP row, and the 4 NW segments of a window spread over the NW
 // waves (4 per wave); carries pass through shared memory.  Tiles: K rows per
-// segment, SEQ as above.
-constexpr int kNumStackTiles = 4;
+// segment, NW waves, SEQ as above; tiles 0-3 have 16 segments (windows of
+// 16 K rows), tiles 4-5 32 segments (twice the rows per halo, one line at a
+// time to keep the shared memory small).
+constexpr int kNumStackTiles = 6;
 template <typename T> __host__ __device__ constexpr ChainTile ystack_tile(int t);
 template <> __host__ __device__ constexpr ChainTile ystack_tile<double>(int t) {
-    return (t & 1) == 0 ? ChainTile{8, 4, t > 1} : ChainTile{6, 4, t > 1};
+    return t >= 4 ? ChainTile{t == 4 ? 8 : 6, 8, true} : (t & 1) == 0 ? ChainTile{8, 4, t > 1} : ChainTile{6, 4, t > 1};
 }
 template <> __host__ __device__ constexpr ChainTile ystack_tile<float>(int t) {
-    return (t & 1) == 0 ? ChainTile{8, 4, t > 1} : ChainTile{16, 4, t > 1};
+    return t >= 4 ? ChainTile{t == 4 ? 8 : 16, 8, true} : (t & 1) == 0 ? ChainTile{8, 4, t > 1} : ChainTile{16, 4, t > 1};
 }
 
 // x sweep: K consecutive points per thread; the launch bound of each K.

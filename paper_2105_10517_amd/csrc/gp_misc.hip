@@ -73,23 +73,25 @@ __device__ inline void finalize_norms(const double* __restrict__ partials, int n
 __global__ __launch_bounds__(1024) void k_norm_finalize(const double* __restrict__ partials, int n, double dxdy,
                                                        NormRule rule, double* __restrict__ scale, int* __restrict__ flag) {
     __shared__ double shr[48];
-    constexpr int U = 4;
+    // U independent loads per component in flight per thread (guarded, not a
+    // tail loop: a 4096^2 grid's ten thousand partials take two rounds)
+    constexpr int U = 8;
     const int nt = blockDim.x;
     double a[U][3];
 #pragma unroll
     for (int u = 0; u < U; ++u) a[u][0] = a[u][1] = a[u][2] = 0.0;
-    int k = threadIdx.x;
-    for (; k + (U - 1) * nt < n; k += U * nt)
+    for (int k0 = threadIdx.x; k0 < n; k0 += U * nt)
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + u * nt;
+            if (k < n)
 #pragma unroll
-            for (int m = 0; m < 3; ++m) a[u][m] += partials[3 * (k + u * nt) + m];
-    for (; k < n; k += nt)
-#pragma unroll
-        for (int m = 0; m < 3; ++m) a[0][m] += partials[3 * k + m];
+                for (int m = 0; m < 3; ++m) a[u][m] += partials[3 * k + m];
+        }
     double acc[3];
 #pragma unroll
-    for (int m = 0; m < 3; ++m) acc[m] = (a[0][m] + a[1][m]) + (a[2][m] + a[3][m]);
+    for (int m = 0; m < 3; ++m)
+        acc[m] = ((a[0][m] + a[1][m]) + (a[2][m] + a[3][m])) + ((a[4][m] + a[5][m]) + (a[6][m] + a[7][m]));
     block_sum3(acc, shr);
     if (threadIdx.x == 0) {
         const double N[3] = {acc[0] * dxdy, acc[1] * dxdy, acc[2] * dxdy};

@@ -392,9 +392,10 @@ template <typename T> bool ychain_fits(int nx, int ny, int hh, int Kg, int t, in
 
 template <typename T> bool ystack_fits(int nx, int ny, int hh, int Kg, int t, int& h, int& L) {
     const gp::ChainTile ct = gp::ystack_tile<T>(t);
+    const int ns = 4 * ct.NW;  // segments per window
     h = std::max(hh, 1);
-    L = 16 * ct.K - 2 * h;
-    return L > 0 && Kg <= L && gp::chain_lanes(h, ct.K) <= 15 && (double)nx * ny * sizeof(gp::cx<T>) < 4294967296.0;
+    L = ns * ct.K - 2 * h;
+    return L > 0 && Kg <= L && gp::chain_lanes(h, ct.K) <= ns - 1 && (double)nx * ny * sizeof(gp::cx<T>) < 4294967296.0;
 }
 
 // Row tile of the y windows as launched.  Under row bands (order 3) each XCD
@@ -555,7 +556,7 @@ void fill_plan(const gp_spin1_params& p, ModeState& ms) {
         out->y_tile_cols = 4 * yt.NW;
         out->y_rows_per_thread = yt.KY;
     }
-    out->y_segments = 16;
+    out->y_segments = ms.ystack ? 4 * gp::ystack_tile<T>(ms.yctile).NW : 16;
     out->pivots_x = ms.x.K;
     out->pivots_y = ms.y.K;
     out->decay_x = ms.x.decay;
@@ -1430,7 +1431,8 @@ bool batch_chain_shape(const std::vector<gp_spin1*>& hs, bool imag, BatchShape& 
             const ModeState& ms = h->mode[imag];
             int hh, L;
             if (!ystack_fits<T>(h->p.nx, h->p.ny, ms.hh, ms.y.Kg, t, hh, L)) { all = false; break; }
-            cost += (double)((h->p.nx + 15) / 16) * ((h->p.ny + L - 1) / L) * 256.0 * gp::ystack_tile<T>(t).K;
+            cost += (double)((h->p.nx + 15) / 16) * ((h->p.ny + L - 1) / L) * 64.0 * gp::ystack_tile<T>(t).NW *
+                    gp::ystack_tile<T>(t).K;
         }
         if (all && (by < 0 || cost < by)) { by = cost; bs.ytile = t; }
     }

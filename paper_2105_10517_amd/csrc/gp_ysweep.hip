@@ -172,29 +172,37 @@ __global__ __launch_bounds__(64 * NW) void k_y_chain(const cx<T>* __restrict__ s
 }
 
 // ---------------------------------------------------------------------------
-// y sweep over stacked chain windows: a block of 4 waves takes 16 consecutive
-// columns (one per lane of a DPP row, so every load and store instruction
-// reads or writes row pieces of 16 columns) and a window of 16 KY rows, its
-// 16 segments spread over the waves (4 per wave, lane = 16 segment + column).
-// The line solves are those of gp_chain.hpp, the carries and the segment-end
-// neighbours passing through shared memory between the phases (each lane's
-// carry from the nc segments before / after it).  Windows start at row
-// rt L - h and write the rows [rt L, rt L + L).
+// y sweep over stacked chain windows: a block of NS / 4 waves takes 16
+// consecutive columns (one per lane of a DPP row, so every load and store
+// instruction reads or writes row pieces of 16 columns) and a window of NS KY
+// rows, its NS segments (16 or 32) spread over the waves (4 per wave, lane =
+// 16 segment + column).  The line solves are those of gp_chain.hpp, the
+// carries and the segment-end neighbours passing through shared memory
+// between the phases (each lane's carry from the nc segments before / after
+// it).  Windows start at row rt L - h and write the rows [rt L, rt L + L).
 // ---------------------------------------------------------------------------
-template <typename T> struct StackShm {
-    cx<T> ends[2][3][16][16];  // [first, last point][line][segment][column] (pre-solve values)
-    cx<T> f[3][16][16];        // forward value each segment passes on from a zero carry
-    cx<T> b[3][16][16];        // backward value each segment passes on from a zero carry
-    cx<T> d0[3][16];           // increment at line point 0, per line and column
+// Shared memory of NQ lines at a time (3: the lines interleaved; 1: one after
+// another, the buffers reused line by line).
+template <typename T, int NS, int NQ> struct StackShm {
+    cx<T> ends[2][NQ][NS][16];  // [first, last point][line][segment][column] (pre-solve values)
+    cx<T> f[NQ][NS][16];        // forward value each segment passes on from a zero carry
+    cx<T> b[NQ][NS][16];        // backward value each segment passes on from a zero carry
+    cx<T> d0[3][16];            // increment at line point 0, per line and column
 };
 
 // Lines q0 .. q0 + NQ - 1 of the window (every thread of the block calls it:
-// barriers inside).  um / up: the neighbours of the segment's first and last
-// point per line.
-template <typename T, int K, bool IMAG, bool EDGE, int NQ>
+// barriers inside).  Their segment-end values go to shared memory first (the
+// previous group's last reads of it lie two barriers back).
+template <typename T, int K, bool IMAG, bool EDGE, int NQ, int NS>
 __device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& ls, int line0, int nc, int g0, int n,
-                                   int seg, int cl, bool first, int seg0, int k0, StackShm<T>& sh) {
+                                   int seg, int cl, bool first, int seg0, int k0, StackShm<T, NS, NQ>& sh) {
     using C = cx<T>;
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) {
+        sh.ends[0][qq][seg][cl] = u[q0 + qq][0];
+        sh.ends[1][qq][seg][cl] = u[q0 + qq][K - 1];
+    }
+    __syncthreads();
     C v[NQ][K];
     ChainLine<T> c[NQ];  // (P, R unused: formed where needed)
     // right-hand sides times -2 / w, and the forward value passed on from a zero carry
@@ -203,8 +211,8 @@ __device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& l
         const int q = q0 + qq;
         c[qq] = chain_line<T, 1>(ls, line0 + q);
         // segment-end neighbours (pre-solve values; zeros beyond the window)
-        const C um = seg > 0 ? sh.ends[1][q][seg - 1][cl] : zero_c<C>();
-        const C up = seg < 15 ? sh.ends[0][q][seg + 1][cl] : zero_c<C>();
+        const C um = seg > 0 ? sh.ends[1][qq][seg - 1][cl] : zero_c<C>();
+        const C up = seg < NS - 1 ? sh.ends[0][qq][seg + 1][cl] : zero_c<C>();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const C l = k == 0 ? um : u[q][k - 1];
@@ -218,17 +226,16 @@ __device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& l
         C f = v[qq][0];
 #pragma unroll
         for (int k = 1; k < K; ++k) f = cfma(f, c[qq].nam, v[qq][k]);
-        sh.f[q][seg][cl] = f;
+        sh.f[qq][seg][cl] = f;
     }
     __syncthreads();
     // carry in from the nc segments before, forward values, backward value passed on
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq) {
-        const int q = q0 + qq;
         const int jm = seg < nc ? seg : nc;
         const C P = cpow_k<C, K>(c[qq].nam);  // (formed here: shorter live ranges)
         C x = zero_c<C>();
-        for (int j = jm; j >= 1; --j) x = cfma(x, P, sh.f[q][seg - j][cl]);
+        for (int j = jm; j >= 1; --j) x = cfma(x, P, sh.f[qq][seg - j][cl]);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             x = cfma(x, c[qq].nam, v[qq][k]);
@@ -238,7 +245,7 @@ __device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& l
         C b = v[qq][K - 1];
 #pragma unroll
         for (int k = K - 2; k >= 0; --k) b = cfma(b, c[qq].ncp, v[qq][k]);
-        sh.b[q][seg][cl] = b;
+        sh.b[qq][seg][cl] = b;
     }
     __syncthreads();
     // carry in from the nc segments after, increments
@@ -246,10 +253,10 @@ __device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& l
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq) {
         const int q = q0 + qq;
-        const int jm = 15 - seg < nc ? 15 - seg : nc;
+        const int jm = NS - 1 - seg < nc ? NS - 1 - seg : nc;
         const C R = cpow_k<C, K>(c[qq].ncp);
         C x = zero_c<C>();
-        for (int j = jm; j >= 1; --j) x = cfma(x, R, sh.b[q][seg + j][cl]);
+        for (int j = jm; j >= 1; --j) x = cfma(x, R, sh.b[qq][seg + j][cl]);
         d0[qq] = zero_c<C>();
 #pragma unroll
         for (int k = K - 1; k >= 0; --k) {
@@ -267,14 +274,14 @@ __device__ inline void stack_lines(cx<T> (&u)[3][K], int q0, const LineSet<T>& l
 
 // One block's window: logical block blk takes column strip blk mod ncs of row
 // tile blk / ncs.
-template <typename T, bool IMAG, int KY, bool SEQ, bool NORM, bool OUTL>
+template <typename T, bool IMAG, int KY, int NS, bool SEQ, bool NORM, bool OUTL>
 __device__ __attribute__((always_inline)) inline void y_stack_block(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp,
                                      const Phys& ph, const LineSet<T>& ls, int L, int h, int nc, int ncs, NormOut no,
-                                     int blk, StackShm<T>& sh, double* shr) {
+                                     int blk, StackShm<T, NS, SEQ ? 1 : 3>& sh, double* shr) {
     using C = cx<T>;
     const int tid = threadIdx.x, lane = tid & 63;
     const int cl = lane & 15;                      // column within the block
-    const int seg = (tid >> 6) * 4 + (lane >> 4);  // segment of the window, 0..15
+    const int seg = (tid >> 6) * 4 + (lane >> 4);  // segment of the window, 0 .. NS - 1
     const int cs = blk % ncs, rt = blk / ncs;
     const int i = cs * 16 + cl;
     const bool col_ok = i < ph.nx;
@@ -282,7 +289,7 @@ __device__ __attribute__((always_inline)) inline void y_stack_block(const cx<T>*
     const int j0 = rt * L;          // first row written
     const int s0 = j0 - h;          // first row of the window
     const int g0 = s0 + seg * KY;   // first row of this lane
-    const bool edge = s0 < 0 || s0 + 16 * KY > ny;  // block-uniform
+    const bool edge = s0 < 0 || s0 + NS * KY > ny;  // block-uniform
     const unsigned col = col_ok ? (unsigned)i : 0u;
     const unsigned pb = (unsigned)nx * (unsigned)ny * (unsigned)sizeof(C);
     __amdgpu_buffer_rsrc_t rs[3];
@@ -299,28 +306,21 @@ __device__ __attribute__((always_inline)) inline void y_stack_block(const cx<T>*
     }
 #pragma unroll
     for (int k = 0; k < KY; ++k) to_sx<C, T>(v[0][k], v[1][k], v[2][k]);
-    // segment-end neighbours of the three lines (zeros beyond the window)
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-        sh.ends[0][q][seg][cl] = v[q][0];
-        sh.ends[1][q][seg][cl] = v[q][KY - 1];
-    }
-    __syncthreads();
     const int line0 = (int)col * 3;
     const bool first = rt == 0;  // the window holds row 0 (at segment h / KY, row h % KY)
-    if (SEQ) {
+    if constexpr (SEQ) {
         if (!edge) {
-            stack_lines<T, KY, IMAG, false, 1>(v, 0, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
-            stack_lines<T, KY, IMAG, false, 1>(v, 1, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
-            stack_lines<T, KY, IMAG, false, 1>(v, 2, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+            stack_lines<T, KY, IMAG, false, 1, NS>(v, 0, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+            stack_lines<T, KY, IMAG, false, 1, NS>(v, 1, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+            stack_lines<T, KY, IMAG, false, 1, NS>(v, 2, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
         } else {
-            stack_lines<T, KY, IMAG, true, 1>(v, 0, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
-            stack_lines<T, KY, IMAG, true, 1>(v, 1, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
-            stack_lines<T, KY, IMAG, true, 1>(v, 2, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+            stack_lines<T, KY, IMAG, true, 1, NS>(v, 0, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+            stack_lines<T, KY, IMAG, true, 1, NS>(v, 1, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+            stack_lines<T, KY, IMAG, true, 1, NS>(v, 2, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
         }
     } else {
-        if (!edge) stack_lines<T, KY, IMAG, false, 3>(v, 0, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
-        else stack_lines<T, KY, IMAG, true, 3>(v, 0, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
+        if (!edge) stack_lines<T, KY, IMAG, false, 3, NS>(v, 0, ls, line0, nc, g0, ny, seg, cl, false, 0, 0, sh);
+        else stack_lines<T, KY, IMAG, true, 3, NS>(v, 0, ls, line0, nc, g0, ny, seg, cl, first, h / KY, h % KY, sh);
     }
     if (first) {
         // line-start correction (block-uniform branch)
@@ -360,28 +360,29 @@ __device__ __attribute__((always_inline)) inline void y_stack_block(const cx<T>*
     if (NORM) store_norm_partials(acc, shr, no, blk);
 }
 
-template <typename T, bool IMAG, int KY, bool SEQ, bool NORM, bool OUTL>
-__global__ __launch_bounds__(256, 2) void k_y_stack(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp,
-                                                 size_t dp, Phys ph, LineSet<T> ls, int L, int h, int nc, int ncs,
-                                                 NormOut no, int nblk, int order) {
-    __shared__ StackShm<T> sh;
+// (16 NS threads; launch bound: 8 waves per CU, i.e. 256 registers per lane)
+template <typename T, bool IMAG, int KY, int NS, bool SEQ, bool NORM, bool OUTL>
+__global__ __launch_bounds__(16 * NS, 32 / NS) void k_y_stack(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
+                                                             size_t sp, size_t dp, Phys ph, LineSet<T> ls, int L, int h,
+                                                             int nc, int ncs, NormOut no, int nblk, int order) {
+    __shared__ StackShm<T, NS, SEQ ? 1 : 3> sh;
     __shared__ double shr[48];
     const int blk = order_logical(order, (int)blockIdx.x, ncs, nblk / ncs);
     if (blk < 0) return;  // (the whole block)
-    y_stack_block<T, IMAG, KY, SEQ, NORM, OUTL>(src, dst, sp, dp, ph, ls, L, h, nc, ncs, no, blk, sh, shr);
+    y_stack_block<T, IMAG, KY, NS, SEQ, NORM, OUTL>(src, dst, sp, dp, ph, ls, L, h, nc, ncs, no, blk, sh, shr);
 }
 
 // Many condensates in one launch: map entry b names the condensate and its
 // window (imaginary time stores each condensate's norm partials).
-template <typename T, bool IMAG, int KY, bool SEQ>
-__global__ __launch_bounds__(256, 2) void k_y_stack_batch(const YSSlot<T>* __restrict__ slots,
-                                                       const unsigned* __restrict__ map) {
-    __shared__ StackShm<T> sh;
+template <typename T, bool IMAG, int KY, int NS, bool SEQ>
+__global__ __launch_bounds__(16 * NS, 32 / NS) void k_y_stack_batch(const YSSlot<T>* __restrict__ slots,
+                                                                   const unsigned* __restrict__ map) {
+    __shared__ StackShm<T, NS, SEQ ? 1 : 3> sh;
     __shared__ double shr[48];
     const unsigned e = map[blockIdx.x];
     const YSSlot<T>& s = slots[e >> kMapShift];
-    y_stack_block<T, IMAG, KY, SEQ, IMAG, false>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.L, s.h, s.nc, s.ncs,
-                                                 NormOut{s.partials}, (int)(e & kMapMask), sh, shr);
+    y_stack_block<T, IMAG, KY, NS, SEQ, IMAG, false>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.L, s.h, s.nc, s.ncs,
+                                                     NormOut{s.partials}, (int)(e & kMapMask), sh, shr);
 }
 
 template <typename T, bool IMAG, int KY, int NW, bool SEQ>
@@ -538,17 +539,18 @@ static hipError_t launch_yc(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
 template <typename T, bool IMAG, bool NORM, bool OUTL, int TI>
 static hipError_t launch_ys_t(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     constexpr ChainTile ct = ystack_tile<T>(TI);
-    // the window (16 KY rows) writes L = 16 KY - 2 h rows; the first window holds the corrected rows;
-    // byte offsets within a plane fit 32 bits; the carries reach at most 15 segments
-    if (a.h < 1 || a.L != 16 * ct.K - 2 * a.h || a.L <= 0 || a.ls.Kg > a.L || chain_lanes(a.h, ct.K) > 15 ||
+    constexpr int NS = 4 * ct.NW;  // segments per window
+    // the window (NS KY rows) writes L = NS KY - 2 h rows; the first window holds the corrected rows;
+    // byte offsets within a plane fit 32 bits; the carries reach at most NS - 1 segments
+    if (a.h < 1 || a.L != NS * ct.K - 2 * a.h || a.L <= 0 || a.ls.Kg > a.L || chain_lanes(a.h, ct.K) > NS - 1 ||
         (double)a.ph.nx * a.ph.ny * sizeof(cx<T>) >= 4294967296.0 || a.order == 3)
         return hipErrorInvalidValue;
     const int ncs = (a.ph.nx + 15) / 16;
     const int nrt = (a.ph.ny + a.L - 1) / a.L;
     const int nblk = ncs * nrt;
-    hipExtLaunchKernelGGL(k_y_stack<T, IMAG, ct.K, ct.SEQ, NORM, OUTL>, dim3(xcd_grid(a.order, ncs, nrt)), dim3(256), 0,
-                          st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.L, a.h, chain_lanes(a.h, ct.K), ncs,
-                          a.no, nblk, a.order);
+    hipExtLaunchKernelGGL(k_y_stack<T, IMAG, ct.K, NS, ct.SEQ, NORM, OUTL>, dim3(xcd_grid(a.order, ncs, nrt)),
+                          dim3(16 * NS), 0, st, e0, e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.L, a.h,
+                          chain_lanes(a.h, ct.K), ncs, a.no, nblk, a.order);
     return hipGetLastError();
 }
 
@@ -559,13 +561,15 @@ static hipError_t launch_ys(const YLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
         case 1: return launch_ys_t<T, IMAG, NORM, OUTL, 1>(a, st, e0, e1);
         case 2: return launch_ys_t<T, IMAG, NORM, OUTL, 2>(a, st, e0, e1);
         case 3: return launch_ys_t<T, IMAG, NORM, OUTL, 3>(a, st, e0, e1);
+        case 4: return launch_ys_t<T, IMAG, NORM, OUTL, 4>(a, st, e0, e1);
+        case 5: return launch_ys_t<T, IMAG, NORM, OUTL, 5>(a, st, e0, e1);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
 int y_blocks(const YLaunch<T>& a) {
-    if (a.stack) return ((a.ph.nx + 15) / 16) * ((a.ph.ny + a.L - 1) / a.L);
+    if (a.stack) return ((a.ph.nx + 15) / 16) * ((a.ph.ny + a.L - 1) / a.L);  // (any segment count)
     if (a.chain) {
         const ChainTile ct = ychain_tile<T>(a.tile);
         const int ncs = (a.ph.nx + 4 * ct.NW - 1) / (4 * ct.NW);
@@ -631,8 +635,8 @@ static hipError_t launch_y_batch_i(const YSlot<T>* slots, const unsigned* map, i
 template <typename T, bool IMAG, int TI>
 static hipError_t launch_ys_batch_t(const YSSlot<T>* slots, const unsigned* map, int nblk, hipStream_t st) {
     constexpr ChainTile ct = ystack_tile<T>(TI);
-    hipExtLaunchKernelGGL(k_y_stack_batch<T, IMAG, ct.K, ct.SEQ>, dim3(nblk), dim3(256), 0, st, nullptr, nullptr, 0,
-                          slots, map);
+    hipExtLaunchKernelGGL(k_y_stack_batch<T, IMAG, ct.K, 4 * ct.NW, ct.SEQ>, dim3(nblk), dim3(64 * ct.NW), 0, st,
+                          nullptr, nullptr, 0, slots, map);
     return hipGetLastError();
 }
 
@@ -644,6 +648,8 @@ hipError_t launch_ys_batch(const YSSlot<T>* slots, const unsigned* map, int nblk
         case 1: return imag ? launch_ys_batch_t<T, true, 1>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 1>(slots, map, nblk, st);
         case 2: return imag ? launch_ys_batch_t<T, true, 2>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 2>(slots, map, nblk, st);
         case 3: return imag ? launch_ys_batch_t<T, true, 3>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 3>(slots, map, nblk, st);
+        case 4: return imag ? launch_ys_batch_t<T, true, 4>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 4>(slots, map, nblk, st);
+        case 5: return imag ? launch_ys_batch_t<T, true, 5>(slots, map, nblk, st) : launch_ys_batch_t<T, false, 5>(slots, map, nblk, st);
         default: return hipErrorInvalidValue;
     }
 }

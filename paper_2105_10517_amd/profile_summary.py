@@ -3,6 +3,8 @@
     python3 paper_2105_10517_amd/profile_summary.py stats RUN_DIR [--last N] --command "..." --out profiles/NAME.md
     python3 paper_2105_10517_amd/profile_summary.py traffic --fetch DIR --write DIR --copy-fetch DIR \
         --copy-write DIR --copy-mib 512 --command "..." --out profiles/NAME.md
+    python3 paper_2105_10517_amd/profile_summary.py counters DIR [DIR ...] [--match RE] [--last N] \
+        --command "..." --out profiles/NAME.md
 
 ``stats`` condenses ``*_kernel_stats.csv`` of a ``--kernel-trace --stats``
 run (calls, mean / min / max duration per kernel).  ``traffic`` turns
@@ -10,7 +12,8 @@ run (calls, mean / min / max duration per kernel).  ``traffic`` turns
 launch of every SSCN kernel, scaled by what the same counters read for a
 plain device copy of known size, and records a hash of the kernel sources so
 that a reader (``bench.py``) can tell whether the numbers still describe the
-kernels it runs.
+kernels it runs.  ``counters`` tabulates other ``--pmc`` passes (SQ, TA, TCP,
+TCC groups) per kernel, with per-wave instruction counts and a few ratios.
 """
 import argparse
 import csv
@@ -66,17 +69,17 @@ def counters(d: str, counter: str, last: int = 0) -> dict:
 
 
 def last_means(d: str, last: int) -> dict:
-    """Per kernel, from the kernel trace: its most frequent launch shape (grid
-    size; one workload's timed steps, as tuning candidates and other workloads
-    launch other shapes), that shape's dispatch count, and the mean duration in
-    us of its last `last` dispatches."""
+    """Per kernel, from the kernel trace: the launch shape (grid size) that
+    took the most time in total (one workload's timed steps: tuning candidates
+    and other, smaller workloads launch other shapes), that shape's dispatch
+    count, and the mean duration in us of its last `last` dispatches."""
     acc = {}
     for row in csv.DictReader(open(find(d, "kernel_trace.csv"))):
         acc.setdefault(short(row["Kernel_Name"]), {}).setdefault(int(row["Grid_Size_X"]), []).append(
             (int(row["Dispatch_Id"]), int(row["End_Timestamp"]) - int(row["Start_Timestamp"])))
     out = {}
     for k, shapes in acc.items():
-        grid, v = max(shapes.items(), key=lambda kv: len(kv[1]))
+        grid, v = max(shapes.items(), key=lambda kv: sum(x for _, x in kv[1]))
         t = [x for _, x in sorted(v)][-last:]
         out[k] = (grid, len(v), sum(t) / len(t) / 1e3)
     return out
@@ -88,9 +91,9 @@ def cmd_stats(a):
     lines = [f"# Kernel durations: {a.title}", "", "Command:", "", "```", a.command, "```", "",
              f"Kernel sources: `{kernel_source_hash()}`", ""]
     if a.last:
-        lines += [f"Last columns: each kernel's most frequent launch shape (grid size in work-items), its "
-                  f"dispatches, and their mean over the last {a.last} (one workload's timed steps; tuning "
-                  f"candidates and other workloads launch other shapes).", ""]
+        lines += [f"Last columns: each kernel's launch shape (grid size in work-items) with the largest total "
+                  f"time, its dispatches, and their mean over the last {a.last} (one workload's timed steps; "
+                  f"tuning candidates and other workloads launch other shapes).", ""]
     lines += ["| kernel | calls | mean us | min us | max us | share |" + (
               f" main grid | its calls | its last {a.last} mean us |" if a.last else ""),
               "|---|---:|---:|---:|---:|---:|" + ("---:|---:|---:|" if a.last else "")]
@@ -137,6 +140,70 @@ def cmd_traffic(a):
     open(a.out, "w").write("\n".join(lines) + "\n")
 
 
+def all_counters(d: str, last: int = 0) -> dict:
+    """kernel -> counter -> mean value per dispatch (over the last `last`
+    dispatches of each kernel when last > 0)."""
+    acc = {}
+    for row in csv.DictReader(open(find(d, "counter_collection.csv"))):
+        k = short(row["Kernel_Name"])
+        c = acc.setdefault(k, {}).setdefault(row["Counter_Name"], {})
+        did = int(row["Dispatch_Id"])
+        c[did] = c.get(did, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for k, cs in acc.items():
+        out[k] = {}
+        for c, v in cs.items():
+            vals = [v[i] for i in sorted(v)]
+            if last > 0:
+                vals = vals[-last:]
+            out[k][c] = sum(vals) / len(vals)
+    return out
+
+
+# Ratios worth reading off the counters (name, numerator, denominator).
+DERIVED = (
+    ("VALU instr / wave", "SQ_INSTS_VALU", "SQ_WAVES"),
+    ("FP64 FMA / wave", "SQ_INSTS_VALU_FMA_F64", "SQ_WAVES"),
+    ("FP64 MUL / wave", "SQ_INSTS_VALU_MUL_F64", "SQ_WAVES"),
+    ("FP64 ADD / wave", "SQ_INSTS_VALU_ADD_F64", "SQ_WAVES"),
+    ("FP32 FMA / wave", "SQ_INSTS_VALU_FMA_F32", "SQ_WAVES"),
+    ("SALU instr / wave", "SQ_INSTS_SALU", "SQ_WAVES"),
+    ("LDS instr / wave", "SQ_INSTS_LDS", "SQ_WAVES"),
+    ("vector loads / wave", "SQ_INSTS_VMEM_RD", "SQ_WAVES"),
+    ("vector stores / wave", "SQ_INSTS_VMEM_WR", "SQ_WAVES"),
+    ("wave cycles / busy cycle", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"),
+    ("waiting / issuing (any instr)", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_ANY"),
+    ("VALU share of issue", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_ANY"),
+    ("L2 hit rate", "TCC_HIT_sum", ("TCC_HIT_sum", "TCC_MISS_sum")),
+)
+
+
+def cmd_counters(a):
+    merged = {}
+    for d in a.runs:
+        for k, cs in all_counters(d, a.last).items():
+            merged.setdefault(k, {}).update(cs)
+    keep = [k for k in sorted(merged) if any(re.search(m, k) for m in a.match)] if a.match else sorted(merged)
+    names = sorted({c for k in keep for c in merged[k]})
+    lines = [f"# Counters per dispatch: {a.title}", "", "Commands (one counter group per pass):", "", "```",
+             a.command, "```", "", f"Kernel sources: `{kernel_source_hash()}`", "",
+             "Mean value per dispatch" + (f" over each kernel's last {a.last} dispatches" if a.last else "")
+             + ", summed over the hardware instances of each counter.", ""]
+    lines += ["| ratio | " + " | ".join(f"`{k}`" for k in keep) + " |", "|---|" + "---:|" * len(keep)]
+    for label, num, den in DERIVED:
+        row = []
+        for k in keep:
+            c = merged[k]
+            dv = sum(c.get(x, 0.0) for x in den) if isinstance(den, tuple) else c.get(den, 0.0)
+            row.append(f"{c[num] / dv:.3g}" if num in c and dv else "")
+        if any(row):
+            lines.append(f"| {label} | " + " | ".join(row) + " |")
+    lines += ["", "| counter | " + " | ".join(f"`{k}`" for k in keep) + " |", "|---|" + "---:|" * len(keep)]
+    for c in names:
+        lines.append(f"| {c} | " + " | ".join(f"{merged[k][c]:.4g}" if c in merged[k] else "" for k in keep) + " |")
+    open(a.out, "w").write("\n".join(lines) + "\n")
+
+
 def read_traffic(path: str) -> dict:
     """Kernel -> traffic bytes per launch from a summary written by ``traffic``,
     or {} when the kernel sources have changed since."""
@@ -173,8 +240,15 @@ def main():
     t.add_argument("--command", required=True)
     t.add_argument("--title", default="")
     t.add_argument("--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("runs", nargs="+", help="rocprofv3 --pmc output directories (one counter group each)")
+    c.add_argument("--match", action="append", default=[], help="keep kernels whose name matches (regex; repeatable)")
+    c.add_argument("--last", type=int, default=0, help="use each kernel's last N dispatches only")
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="")
+    c.add_argument("--out", required=True)
     a = ap.parse_args()
-    {"stats": cmd_stats, "traffic": cmd_traffic}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "counters": cmd_counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

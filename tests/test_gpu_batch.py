@@ -148,9 +148,10 @@ def test_set_slot_admits_a_new_condensate():
 
 def test_slot_outside_the_batch_tile_runs_alone():
     # a tall grid with slow decay in y (large dt / dy^2) needs a bigger window
-    # than the tile chosen for the rest; it runs on its own plan
+    # than any tile (scanned or stacked); it runs on its own plan
     small = inputs.params(48, 48, 0.3, dt=0.009, c0=20.0, c2=-1.0, gamma=0.4, eta=1, rabi=0.1, omega=0.3)
-    tall = inputs.params(40, 700, 0.2, dy=0.05, dt=0.02, c0=20.0, c2=-1.0, gamma=0.4, eta=1, rabi=0.1, omega=0.3)
+    tall = inputs.params(40, 700, 0.2, dy=0.05, dt=0.05, c0=20.0, c2=-1.0, gamma=0.4, eta=1, rabi=0.1, omega=0.3)
+    assert binding.plan_query(tall, True)["stable"] == 1
     if binding.plan_query(tall, True)["y_solver"] == binding.GP_YSOLVER_WINDOW:
         pytest.skip("the tall grid windows with every tile here")
     b = binding.Batch([small, tall], "fp64")

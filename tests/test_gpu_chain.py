@@ -76,9 +76,9 @@ def test_every_chain_tile_y(tile):
             s.close()
 
 
-@pytest.mark.parametrize("tile", range(1, 5))
+@pytest.mark.parametrize("tile", range(1, 7))
 def test_every_stacked_tile_y(tile):
-    # stacked windows: 16 columns per block (ragged column strips included), segments over the waves
+    # stacked windows: 16 columns per block (ragged column strips included), 16 or 32 segments over the waves
     for imag in (True, False):
         for nx, ny in ((9, 3), (37, 90), (21, 700), (50, 1501)):
             dy = min(12.0 / ny + 0.01, 0.3)
