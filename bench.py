@@ -416,11 +416,28 @@ def main():
             t.copy_(torch.from_numpy(psi1).to(s.dtype))
             tim = kernel_timing(s, t, 200, True)
             ktot = sum(v["ms"] for v in tim.values())
+            # the same 200 steps replayed from a captured HIP graph (captured by the first call)
+            t.copy_(torch.from_numpy(psi1).to(s.dtype))
+            s.step_graph(t, 200, True)
+            s.sync()
+            t.copy_(torch.from_numpy(psi1).to(s.dtype))
+            torch.cuda.synchronize()
+            g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            g0.record(s.stream)
+            s.step_graph(t, 200, True)
+            g1.record(s.stream)
+            torch.cuda.synchronize()
+            s.sync()
+            ms_graph = g0.elapsed_time(g1)
+            same = bool(np.array_equal(t.cpu().numpy().astype(np.complex128), got))
             c1[prec] = {"value": 128 * 128 * 200 / (ms / 1e3), "ms_run": ms, "us_per_step": ms / 200 * 1e3,
                         "kernel_us_per_step": ktot / 200 * 1e3, "plan": s.plan(True),
+                        "graph": {"value": 128 * 128 * 200 / (ms_graph / 1e3), "ms_run": ms_graph,
+                                  "us_per_step": ms_graph / 200 * 1e3, "equals_eager": same},
                         "err_vs_oracle": dict(errors_vs_oracle(np, got, obs, want1, o1, prec), steps=200)}
             log(f"[bench] 128^2 imag {prec}: 200 steps in {ms:.2f} ms ({c1[prec]['value']:.3e} pt-steps/s, "
-                f"{c1[prec]['us_per_step']:.2f} us/step, kernels {c1[prec]['kernel_us_per_step']:.2f} us/step); "
+                f"{c1[prec]['us_per_step']:.2f} us/step, kernels {c1[prec]['kernel_us_per_step']:.2f} us/step; "
+                f"HIP graph {ms_graph:.2f} ms, {c1[prec]['graph']['us_per_step']:.2f} us/step, equal {same}); "
                 f"vs oracle {c1[prec]['err_vs_oracle']}")
             s.close()
 

@@ -215,6 +215,20 @@ int gp_spin1_step_imag(gp_spin1_t* h, void* psi_dev, int64_t nsteps);
  * GP_EUNSTABLE if the line systems lose diagonal dominance.  Asynchronous. */
 int gp_spin1_step_real(gp_spin1_t* h, void* psi_dev, int64_t nsteps);
 
+/* nsteps steps in mode 0 (imaginary time, as gp_spin1_step_imag) or 1 (real
+ * time, as gp_spin1_step_real), replayed from a HIP graph: the launch
+ * sequence of nsteps steps on psi_dev is captured once (on a stream of the
+ * handle's own; it holds kernels only) and kept per (psi_dev, nsteps, mode),
+ * up to 8 per handle (the oldest is dropped, after a wait for the stream);
+ * every call then launches the graph on the handle's stream.  Results equal
+ * those of gp_spin1_step_imag / step_real bit for bit.  For runs of many
+ * short steps, where the host's launch cost could leave the GPU idle.
+ * Per-kernel timing (gp_spin1_timing_enable) does not see
+ * the kernels of a graph.  The captured sequence holds psi_dev's address: a
+ * graph must not outlive the wave function it was captured on (free it with
+ * the handle, or call with other arguments).  Asynchronous. */
+int gp_spin1_step_graph(gp_spin1_t* h, void* psi_dev, int64_t nsteps, int32_t mode);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): nsteps SSCN steps of
  * psi_dev (caller-owned, layout as for gp_spin1_create) in imaginary time

@@ -23,7 +23,7 @@ GP_ORDER_AUTO, GP_ORDER_HARDWARE, GP_ORDER_XCD, GP_ORDER_BANDS, GP_ORDER_ROWS = 
 SUB_LOCAL, SUB_X, SUB_Y, SUB_NORMALIZE = 0, 1, 2, 3
 
 # Every entry point the header declares (checked by the CPU test suite).
-EXPORTS = ("gp_spin1_create", "gp_spin1_destroy", "gp_spin1_step_imag", "gp_spin1_step_real",
+EXPORTS = ("gp_spin1_create", "gp_spin1_destroy", "gp_spin1_step_imag", "gp_spin1_step_real", "gp_spin1_step_graph",
            "gp_spin1_substep", "gp_spin1_observables", "gp_spin1_sync", "gp_spin1_get_plan",
            "gp_spin1_plan_query", "gp_spin1_timing_enable", "gp_spin1_timing_read",
            "gp_spin1_strerror", "gp_spin1_last_error",
@@ -130,6 +130,7 @@ def load():
         "gp_spin1_destroy": [vp],
         "gp_spin1_step_imag": [vp, vp, i64],
         "gp_spin1_step_real": [vp, vp, i64],
+        "gp_spin1_step_graph": [vp, vp, i64, i32],
         "gp_spin1_substep": [vp, vp, i32, i32],
         "gp_spin1_observables": [vp, vp, ctypes.POINTER(Obs), vp],
         "gp_spin1_sync": [vp],
@@ -280,6 +281,12 @@ class Solver:
 
     def step_real(self, psi, nsteps: int):
         self._check(self._lib.gp_spin1_step_real(self._h, self._psi(psi), int(nsteps)), "step_real")
+
+    def step_graph(self, psi, nsteps: int, imag: bool):
+        """nsteps steps replayed from a captured HIP graph (captured on the
+        first call with these arguments)."""
+        self._check(self._lib.gp_spin1_step_graph(self._h, self._psi(psi), int(nsteps), 0 if imag else 1),
+                    "step_graph")
 
     def substep(self, psi, which: int, imag: bool):
         self._check(self._lib.gp_spin1_substep(self._h, self._psi(psi), int(which), int(bool(imag))), "substep")

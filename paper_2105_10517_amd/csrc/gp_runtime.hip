@@ -78,6 +78,16 @@ struct gp_spin1 {
     size_t ev_next = 0;
     int64_t t_launches[4] = {0, 0, 0, 0};
     double t_ms[4] = {0, 0, 0, 0};
+    // step sequences captured as HIP graphs (gp_spin1_step_graph), newest last
+    struct Graph {
+        void* psi;
+        int64_t n;
+        bool imag;
+        hipGraph_t g;
+        hipGraphExec_t x;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t cap_stream = nullptr;  // the stream the captures are recorded on
     std::string err;
 };
 
@@ -651,6 +661,12 @@ void free_dir(DirTable& d) {
 }
 
 void destroy_all(gp_spin1* h) {
+    if (!h->graphs.empty()) (void)hipStreamSynchronize(h->stream);
+    for (auto& g : h->graphs) {
+        (void)hipGraphExecDestroy(g.x);
+        (void)hipGraphDestroy(g.g);
+    }
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     for (auto& m : h->mode) { free_dir(m.x); free_dir(m.y); }
     if (h->d_scale) (void)hipFree(h->d_scale);
     if (h->d_flag) (void)hipFree(h->d_flag);
@@ -1140,6 +1156,59 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
         if ((e = timed(h, 3, [&](hipEvent_t a, hipEvent_t b) { return gp::launch_scale<T>((gp::cx<T>*)psi, npts, h->psp, h->d_scale, st, a, b); })) != hipSuccess)
             return hip_fail(h, e, "scale launch");
     }
+    return GP_OK;
+}
+
+// The launch sequence of n steps on psi, captured once as a HIP graph (on a
+// stream of the handle's own, with per-kernel timing off: event records would
+// become graph nodes) and replayed on the handle's stream.  The sequence holds
+// kernels only (scale and flag resets are one-thread kernels, no memset
+// nodes).  Up to kMaxGraphs captures are kept per handle, the oldest dropped.
+constexpr size_t kMaxGraphs = 8;
+
+template <typename T>
+int graph_steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
+    const ModeState& ms = h->mode[imag];
+    if (!ms.stable) return fail(h, GP_EUNSTABLE, ms.why);
+    if (n == 0) return GP_OK;
+    hipError_t e;
+    size_t k = 0;
+    while (k < h->graphs.size() && !(h->graphs[k].psi == psi && h->graphs[k].n == n && h->graphs[k].imag == imag)) ++k;
+    if (k == h->graphs.size()) {
+        if (!h->cap_stream && (e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(h, e, "capture stream");
+        const hipStream_t st = h->stream;
+        const bool timing = h->timing;
+        if ((e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(h, e, "begin capture");
+        h->stream = h->cap_stream;
+        h->timing = false;
+        const int rc = steps_t<T>(h, psi, n, imag);
+        h->stream = st;
+        h->timing = timing;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(h->cap_stream, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(h, e, "end capture");
+        hipGraphExec_t x = nullptr;
+        if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(h, e, "graph instantiate");
+        }
+        if (h->graphs.size() == kMaxGraphs) {
+            // (the oldest may still run on the stream)
+            if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_fail(h, e, "graph eviction");
+            (void)hipGraphExecDestroy(h->graphs.front().x);
+            (void)hipGraphDestroy(h->graphs.front().g);
+            h->graphs.erase(h->graphs.begin());
+        }
+        h->graphs.push_back(gp_spin1::Graph{psi, n, imag, g, x});
+        k = h->graphs.size() - 1;
+    }
+    if ((e = hipGraphLaunch(h->graphs[k].x, h->stream)) != hipSuccess) return hip_fail(h, e, "graph launch");
     return GP_OK;
 }
 
@@ -2084,6 +2153,16 @@ int gp_spin1_step_real(gp_spin1_t* h, void* psi, int64_t nsteps) {
         if (!h) return GP_EINVAL;
         if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
         return h->p.precision == GP_FP64 ? steps_t<double>(h, psi, nsteps, false) : steps_t<float>(h, psi, nsteps, false);
+    }, h ? &h->err : nullptr);
+}
+
+int gp_spin1_step_graph(gp_spin1_t* h, void* psi, int64_t nsteps, int32_t mode) {
+    return no_throw([&]() -> int {
+        if (!h) return GP_EINVAL;
+        if (!psi || nsteps < 0) return fail(h, GP_EINVAL, "psi is NULL or nsteps < 0");
+        if (mode != 0 && mode != 1) return fail(h, GP_EINVAL, "mode must be 0 (imaginary time) or 1 (real time)");
+        return h->p.precision == GP_FP64 ? graph_steps_t<double>(h, psi, nsteps, mode == 0)
+                                         : graph_steps_t<float>(h, psi, nsteps, mode == 0);
     }, h ? &h->err : nullptr);
 }
 
