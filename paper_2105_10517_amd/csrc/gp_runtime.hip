@@ -500,17 +500,26 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     if (p.x_solver == GP_XSOLVER_AUTO && p.x_points == 0 && hm.xK == 16) {
         // rows longer than 512 threads of eight points: the whole-row solve
         // would hold sixteen points per thread and spill; the chain windows
-        // take rows of any length (the tile that writes the largest share of
-        // the points it loads; sixteen points per lane spill with the local
-        // substep fused)
+        // take rows of any length.  Four points per lane (the fastest tiles
+        // on long rows, 4096^2), one line at a time first; where no such
+        // tile fits, the tile that writes the largest share of the points it
+        // loads (sixteen points per lane spill with the local substep fused)
+        for (int i = 0; i < gp::kNumChainTiles && !hm.xchain; ++i) {
+            const int t = gp::kNumChainTiles - 1 - i;  // (one line at a time first: fewer registers)
+            if (gp::xchain_tile<T>(t).K == 4 && xchain_fits<T>(hm.hhx, hm.x.Kg, t, hm.hcx, hm.Lcx)) {
+                hm.xchain = true;
+                hm.xctile = t;
+            }
+        }
         double best = 0.0;
-        for (int i = 0; i < gp::kNumChainTiles; ++i) {
-            const int t = (i + 4) % gp::kNumChainTiles;  // (one line at a time first: fewer registers)
+        for (int i = 0; i < gp::kNumChainTiles && !hm.xchain; ++i) {
+            const int t = (i + 4) % gp::kNumChainTiles;
             int h, L;
             if (gp::xchain_tile<T>(t).K > 8 || !xchain_fits<T>(hm.hhx, hm.x.Kg, t, h, L)) continue;
             const double eff = (double)L / (64.0 * gp::xchain_tile<T>(t).K);
-            if (eff > best) { best = eff; hm.xchain = true; hm.xctile = t; hm.hcx = h; hm.Lcx = L; }
+            if (eff > best) { best = eff; hm.xctile = t; hm.hcx = h; hm.Lcx = L; }
         }
+        if (best > 0.0) hm.xchain = true;
     }
     if (p.y_solver == GP_YSOLVER_CHAIN) {
         for (int t = p.y_tile > 0 ? p.y_tile - 1 : 0; t < gp::kNumChainTiles && !hm.ychain; ++t) {
