@@ -64,7 +64,9 @@ typedef enum { GP_FP64 = 0, GP_FP32 = 1 } gp_precision; /* FP32: bulk in FP32, r
 
 /* Choice of the y-sweep line solver. */
 typedef enum {
-    GP_YSOLVER_AUTO = 0,   /* windowed scan when its truncation bound holds, else per-column Thomas */
+    GP_YSOLVER_AUTO = 0,   /* grids of 1024^2 points and up: stacked chain windows when a tile fits;
+                              otherwise the windowed scan when its truncation bound holds, else
+                              per-column Thomas (autotuning may choose any of them)                */
     GP_YSOLVER_WINDOW = 1, /* windowed partitioned scan over column tiles (2 HBM passes per step) */
     GP_YSOLVER_THOMAS = 2, /* exact per-thread Thomas down whole columns (one thread per column) */
     GP_YSOLVER_CHAIN = 3,  /* windows as GP_YSOLVER_WINDOW, each segment's carry formed from the ceil(h / K)
@@ -79,7 +81,8 @@ typedef enum {
 /* Choice of the x-sweep line solver. */
 typedef enum {
     GP_XSOLVER_AUTO = 0,   /* whole-row partitioned Thomas, or the windows when autotuning finds them faster;
-                              rows above 4096 points take the chain windows when a chain tile fits       */
+                              grids of 1024^2 points and up, and rows above 4096 points, take the chain
+                              windows (four points per lane) when a chain tile fits                      */
     GP_XSOLVER_SCAN = 1,   /* exact partitioned Thomas over whole rows (scans across the row's threads)     */
     GP_XSOLVER_WINDOW = 2, /* truncated overlapping windows along the rows (the y sweep's scheme); refused
                               (GP_EUNSUPPORTED) when the decay bound does not fit any window            */

@@ -497,11 +497,13 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
             if (p.x_tile > 0) break;
         }
     }
-    if (p.x_solver == GP_XSOLVER_AUTO && p.x_points == 0 && hm.xK == 16) {
+    const bool large = (double)p.nx * p.ny >= 1048576.0;  // 1024^2 points and up
+    if (p.x_solver == GP_XSOLVER_AUTO && p.x_points == 0 && (hm.xK == 16 || large)) {
         // rows longer than 512 threads of eight points: the whole-row solve
         // would hold sixteen points per thread and spill; the chain windows
-        // take rows of any length.  Four points per lane (the fastest tiles
-        // on long rows, 4096^2), one line at a time first; where no such
+        // take rows of any length, and on large grids they are the faster
+        // sweep (4096^2 FP64: 366 against 777 us).  Four points per lane
+        // (the fastest tiles there), one line at a time first; where no such
         // tile fits, the tile that writes the largest share of the points it
         // loads (sixteen points per lane spill with the local substep fused)
         for (int i = 0; i < gp::kNumChainTiles && !hm.xchain; ++i) {
@@ -528,6 +530,12 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
         }
     }
     hm.ystack = false;
+    if (p.y_solver == GP_YSOLVER_AUTO && p.y_tile == 0 && large) {
+        // large grids: the stacked chain windows (4096^2 FP64: 362 against
+        // 480 us for the scanned windows), the first tile that fits
+        for (int t = 0; t < gp::kNumStackTiles && !hm.ychain; ++t)
+            if (ystack_fits<T>(p.nx, p.ny, hm.hh, hm.y.Kg, t, hm.hcy, hm.Lcy)) { hm.ychain = hm.ystack = true; hm.yctile = t; }
+    }
     if (p.y_solver == GP_YSOLVER_STACK) {
         for (int t = p.y_tile > 0 ? p.y_tile - 1 : 0; t < gp::kNumStackTiles && !hm.ychain; ++t) {
             if (ystack_fits<T>(p.nx, p.ny, hm.hh, hm.y.Kg, t, hm.hcy, hm.Lcy)) { hm.ychain = hm.ystack = true; hm.yctile = t; }

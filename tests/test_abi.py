@@ -64,9 +64,15 @@ def test_plan_of_the_workloads():
     assert c2["decay_y"] ** c2["y_halo"] < 2.0 ** -60
     assert c2["y_rows_out"] == c2["y_segments"] * c2["y_rows_per_thread"] - 2 * c2["y_halo"]
     for prec in ("fp64", "fp32"):
+        # large grids: chain x windows of four points per lane and stacked y windows by default
         c3 = binding.plan_query(inputs.config_c3(4096), True, prec)
-        assert c3["stable"] == 1 and c3["y_solver"] == binding.GP_YSOLVER_WINDOW
-        assert c3["x_points_per_thread"] * c3["x_threads_per_row"] >= 4096
+        assert c3["stable"] == 1 and c3["y_solver"] == binding.GP_YSOLVER_STACK and c3["y_segments"] == 16
+        assert c3["x_solver"] == binding.GP_XSOLVER_CHAIN and c3["x_points_per_thread"] == 4
+        assert c3["x_points_out"] == 64 * 4 - 2 * c3["x_halo"] and c3["decay_x"] ** c3["x_halo"] < 2.0 ** -32
+        # and the scanned windows / whole rows when asked for
+        w = binding.plan_query(inputs.config_c3(4096), True, prec, y_solver="window", x_solver="scan")
+        assert w["y_solver"] == binding.GP_YSOLVER_WINDOW and w["x_solver"] == binding.GP_XSOLVER_SCAN
+        assert w["x_points_per_thread"] * w["x_threads_per_row"] >= 4096
     th = binding.plan_query(inputs.config_c2(), False, y_solver="thomas")
     assert th["y_solver"] == binding.GP_YSOLVER_THOMAS
 
@@ -127,9 +133,11 @@ def test_block_orders_of_the_windowed_sweeps():
     small = binding.plan_query(inputs.config_c2(), False, x_solver="window")
     assert small["x_solver"] == binding.GP_XSOLVER_WINDOW and small["x_block_order"] == 1
     assert small["y_block_order"] == 1
-    big = binding.plan_query(inputs.config_c3(4096), True)
+    big = binding.plan_query(inputs.config_c3(4096), True, y_solver="window", x_solver="scan")
     assert big["y_solver"] == binding.GP_YSOLVER_WINDOW and big["y_block_order"] == 0
     assert big["x_block_order"] == 0  # whole-row x sweep: no windows to order
+    chain = binding.plan_query(inputs.config_c3(4096), True)  # chain x and stacked y windows
+    assert chain["x_block_order"] == 1 and chain["y_block_order"] == 0
     for order, wx, wy in (("hardware", 0, 0), ("xcd", 1, 1), ("bands", 1, 2), ("rows", 3, 3)):
         for p, imag in ((inputs.config_c2(), False), (inputs.config_c3(4096), True)):
             pl = binding.plan_query(p, imag, x_solver="window", block_order=order)
