@@ -281,7 +281,11 @@ def batch_c4(torch, binding, inputs, nsteps):
                                 "unit": "GB/s", "frac": round(bps / HBM_PEAK_BPS, 4),
                                 "basis": "12 s = 96 B per 3-comp point-step over the whole batched step"},
            "grouped": info["grouped"], "individual": info["individual"], "x_points": info["x_points"][0],
-           "y_tile": info["y_tile"][0]}
+           "y_tile": info["y_tile"][0],
+           "shape": {"x": {1: "whole-row scans", 3: "chain windows"}.get(info["x_solver"][0], info["x_solver"][0]),
+                     "x_tile": info["x_tile"][0],
+                     "y": {1: "scanned windows", 4: "stacked chain windows"}.get(info["y_solver"][0],
+                                                                                 info["y_solver"][0])}}
     log(f"[bench] C4 batch: FP32 batched {out['value_fp32_batched']:.3e} pt-steps/s ({bps / 1e12:.2f} TB/s), "
         f"FP32 one at a time {out['value_fp32_one_at_a_time']:.3e}, FP64 one at a time "
         f"{out['value_fp64_one_at_a_time']:.3e} ({ms_b:.1f} / {ms_32:.1f} / {ms_64:.1f} ms)")
