@@ -69,7 +69,7 @@ typedef enum {
                               per-column Thomas (autotuning may choose any of them)                */
     GP_YSOLVER_WINDOW = 1, /* windowed partitioned scan over column tiles (2 HBM passes per step) */
     GP_YSOLVER_THOMAS = 2, /* exact per-thread Thomas down whole columns (one thread per column) */
-    GP_YSOLVER_CHAIN = 3,  /* windows as GP_YSOLVER_WINDOW, each segment's carry formed from the ceil(h / K)
+    GP_YSOLVER_CHAIN = 3,  /* windows as GP_YSOLVER_WINDOW, each segment's carry formed from the ceil((h - 1) / K)
                               segments before and after it instead of a scan of the whole window (their
                               carries are attenuated below the same rounding bound as the window ends);
                               y_tile then names a chain tile */
@@ -86,7 +86,7 @@ typedef enum {
     GP_XSOLVER_SCAN = 1,   /* exact partitioned Thomas over whole rows (scans across the row's threads)     */
     GP_XSOLVER_WINDOW = 2, /* truncated overlapping windows along the rows (the y sweep's scheme); refused
                               (GP_EUNSUPPORTED) when the decay bound does not fit any window            */
-    GP_XSOLVER_CHAIN = 3   /* windows of one row segment per wave (64 K points) with carries over ceil(h / K)
+    GP_XSOLVER_CHAIN = 3   /* windows of one row segment per wave (64 K points) with carries over ceil((h - 1) / K)
                               lanes (as GP_YSOLVER_CHAIN); x_tile then names a chain tile               */
 } gp_xsolver;
 

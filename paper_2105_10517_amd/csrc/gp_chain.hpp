@@ -8,10 +8,11 @@
 // inside the window composes every lane's transfer map with all the maps
 // before it (a scan).  But with the converged pivots a lane passes on
 // P = (-a m)^K times the carry it receives (forward; R = (-e m)^K backward),
-// so the lanes more than nc = ceil(h / K) lanes away reach a point only
-// through nc whole lanes, i.e. through at least h points: below the rounding
-// level, like the carries the window ends drop.  The carry entering lane l is
-// therefore formed from the nc lanes before it,
+// so a lane more than nc = ceil((h - 1) / K) lanes away reaches a point only
+// through nc whole lanes and at least one point of the receiving lane, i.e.
+// through at least h points: below the rounding level, like the carries the
+// window ends drop.  The carry entering lane l is therefore formed from the
+// nc lanes before it,
 //     c_in(l) = sum_{j=1..nc} P^{j-1} e(l - j),
 // e(k) the value lane k passes on from a zero carry: nc shifts of one lane,
 // each after a multiply-add (no scan, no shared memory), and every point at

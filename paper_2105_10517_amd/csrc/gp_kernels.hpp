@@ -50,8 +50,10 @@ template <> __host__ __device__ constexpr ChainTile ychain_tile<float>(int t) {
                         : (t & 3) == 2 ? ChainTile{4, 4, t > 3} : ChainTile{16, 2, t > 3};
 }
 
-// Carry lanes of a chain window for a halo of h points: nc = ceil(h / K).
-__host__ __device__ inline int chain_lanes(int h, int K) { return h <= K ? 1 : (h + K - 1) / K; }
+// Carry lanes of a chain window for a halo of h points: nc = ceil((h - 1) / K),
+// at least 1.  A carry from a lane farther away crosses nc whole lanes and at
+// least one point of the receiving lane, nc K + 1 >= h points.
+__host__ __device__ inline int chain_lanes(int h, int K) { return h <= K + 1 ? 1 : (h - 1 + K - 1) / K; }
 
 // Stacked y windows (k_y_stack): 16 consecutive columns per block, one per
 // lane of a DPP row, and the 4 NW segments of a window spread over the NW

@@ -1,5 +1,5 @@
 """Chain windows (GP_XSOLVER_CHAIN, GP_YSOLVER_CHAIN): the windowed sweeps
-with each lane's carry formed from the ceil(h / K) lanes before and after it.
+with each lane's carry formed from the ceil((h - 1) / K) lanes before and after it.
 Every point a window writes lies at least h from both window ends, so the
 result equals the exact line solve to the rounding level: the FP64 parity
 bars are those of the scanned windows (1e-13 for a substep, 1e-11 after tens
