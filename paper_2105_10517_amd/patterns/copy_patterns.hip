@@ -133,6 +133,33 @@ __global__ __launch_bounds__(256) void k_ystack(const C* __restrict__ s, C* __re
         for (int m = 0; m < 3; ++m) d[m * PL + (size_t)(g0 + k) * NX + i] = v[m][k];
 }
 
+// The stacked pattern with the windows of the 4096^2 FP64 y sweep: windows
+// of 16 K rows starting at rt L - h, every row read, the middle L rows
+// written (the halo rows are read twice, by neighbouring windows).
+template <int K>
+__global__ __launch_bounds__(256) void k_ystack_halo(const C* __restrict__ s, C* __restrict__ d, int h, int L) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    constexpr int ncs = NX / 16;
+    const int rt = blockIdx.x / ncs, cs = blockIdx.x % ncs;
+    const int i = cs * 16 + (lane & 15);
+    const int j0 = rt * L, g0 = j0 - h + (w * 4 + (lane >> 4)) * K;
+    C v[3][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int g = g0 + k;
+        const bool ok = g >= 0 && g < NY;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][k] = ok ? s[m * PL + (size_t)(ok ? g : 0) * NX + i] : C{0, 0};
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int g = g0 + k;
+        if (g >= j0 && g < j0 + L && g < NY)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) d[m * PL + (size_t)g * NX + i] = v[m][k];
+    }
+}
+
 template <typename F>
 float timeit(F f, int reps = 20) {
     hipEvent_t a, b;
@@ -173,6 +200,8 @@ int main() {
     rep("y 4-col K8 NW2", timeit([&] { k_y4col<8, 2><<<(NX / 8) * (NY / 128), 128>>>(s, d); }));
     rep("y 4-col K8 NW4", timeit([&] { k_y4col<8, 4><<<(NX / 16) * (NY / 128), 256>>>(s, d); }));
     rep("y stack K8", timeit([&] { k_ystack<8><<<(NX / 16) * (NY / 128), 256>>>(s, d); }));
+    // h = 13, L = 102: the FP64 windows (41 row tiles)
+    rep("y stack K8 halo 13", timeit([&] { k_ystack_halo<8><<<(NX / 16) * ((NY + 101) / 102), 256>>>(s, d, 13, 102); }));
     CK(hipGetLastError());
     CK(hipDeviceSynchronize());
     CK(hipFree(s));
