@@ -489,7 +489,8 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
                 if (tile_window(p.nx, hm.hhx, gp::ywindow(gp::ytile<T>(t)), hm.hx, hm.Lx)) { hm.xwindow = true; hm.xtile = t; }
         }
     }
-    // chain windows: only when asked for (autotuning may also choose them)
+    // chain windows: when asked for, and by default on large grids and long
+    // rows (below); autotuning may also choose them
     hm.xchain = hm.ychain = false;
     if (p.x_solver == GP_XSOLVER_CHAIN) {
         for (int t = p.x_tile > 0 ? p.x_tile - 1 : 0; t < gp::kNumChainTiles && !hm.xchain; ++t) {
