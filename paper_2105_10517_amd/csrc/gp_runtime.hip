@@ -178,7 +178,8 @@ void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
         d.W[l] = wl;
         zd w = d.b;
         int k = 0;
-        while (k < n - 1 && std::abs(w - wl) > tol * std::abs(wl)) {
+        const double wl2 = tol * tol * std::norm(wl);  // (squared moduli: no square roots in the loops)
+        while (k < n - 1 && std::norm(w - wl) > wl2) {
             w = d.b - a * e / w;
             ++k;
         }
@@ -190,30 +191,38 @@ void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
     // (Thomas with the limit pivots throughout), kept while |g_k| is above
     // the rounding level of T relative to |g_0| (the same bound as the halo)
     const double tolg = sizeof(T) == 8 ? std::ldexp(1.0, -60) : std::ldexp(1.0, -32);
-    std::vector<std::vector<zd>> gl(lines);
+    // (every line's g in one buffer: no allocation per line)
+    std::vector<zd> y, gall;
+    std::vector<size_t> goff(lines + 1, 0);
     int Kg = 1;
     for (int l = 0; l < lines; ++l) {
         const zd w = d.W[l], m = 1.0 / w, am = d.A[l] * m, cp = d.E[l] * m;
         // y = L^{-1} e0 decays geometrically; past the point where it is far
         // below the rounding level it is taken as zero (exact for short lines)
-        std::vector<zd> y(1, m);
-        while ((int)y.size() < n && std::abs(y.back()) > 1e-27 * std::abs(m)) y.push_back(-am * y.back());
+        y.assign(1, m);
+        const double ycut = 1e-54 * std::norm(m);
+        while ((int)y.size() < n && std::norm(y.back()) > ycut) y.push_back(-am * y.back());
         const int M = (int)y.size();
-        std::vector<zd> g(M);
+        const size_t off = gall.size();
+        gall.resize(off + M);
+        zd* g = gall.data() + off;
         g[M - 1] = y[M - 1];
         for (int k = M - 2; k >= 0; --k) g[k] = y[k] - cp * g[k + 1];
         int kg = M;
-        while (kg > 1 && std::abs(g[kg - 1]) < tolg * std::abs(g[0])) --kg;
+        const double gcut = tolg * tolg * std::norm(g[0]);
+        while (kg > 1 && std::norm(g[kg - 1]) < gcut) --kg;
         Kg = std::max(Kg, kg);
-        gl[l] = std::move(g);
+        goff[l + 1] = off + M;
     }
     d.Kg = Kg;
     d.G.assign((size_t)lines * Kg, zd());
     d.GC.assign(lines, zd());
     for (int l = 0; l < lines; ++l) {
-        for (int k = 0; k < Kg && k < (int)gl[l].size(); ++k) d.G[(size_t)l * Kg + k] = gl[l][k];
+        const zd* g = gall.data() + goff[l];
+        const int M = (int)(goff[l + 1] - goff[l]);
+        for (int k = 0; k < Kg && k < M; ++k) d.G[(size_t)l * Kg + k] = g[k];
         const zd bw = d.b - d.W[l];
-        d.GC[l] = bw / (1.0 + bw * gl[l][0]);
+        d.GC[l] = bw / (1.0 + bw * g[0]);
     }
 }
 
