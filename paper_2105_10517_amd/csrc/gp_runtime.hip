@@ -15,12 +15,15 @@
 #include <stdexcept>
 #include <string>
 #include <thread>
+#include <exception>
 #include <vector>
 
 #include "gp_kernels.hpp"
 #include "gp_spin1.h"
 
 using zd = std::complex<double>;
+// |z|^2 from the parts (the library's std::norm goes through |z|, a hypot)
+inline double nrm(zd z) { return z.real() * z.real() + z.imag() * z.imag(); }
 
 namespace {
 
@@ -178,8 +181,8 @@ void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
         d.W[l] = wl;
         zd w = d.b;
         int k = 0;
-        const double wl2 = tol * tol * std::norm(wl);  // (squared moduli: no square roots in the loops)
-        while (k < n - 1 && std::norm(w - wl) > wl2) {
+        const double wl2 = tol * tol * nrm(wl);  // (squared moduli: no square roots in the loops)
+        while (k < n - 1 && nrm(w - wl) > wl2) {
             w = d.b - a * e / w;
             ++k;
         }
@@ -200,8 +203,8 @@ void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
         // y = L^{-1} e0 decays geometrically; past the point where it is far
         // below the rounding level it is taken as zero (exact for short lines)
         y.assign(1, m);
-        const double ycut = 1e-54 * std::norm(m);
-        while ((int)y.size() < n && std::norm(y.back()) > ycut) y.push_back(-am * y.back());
+        const double ycut = 1e-54 * nrm(m);
+        while ((int)y.size() < n && nrm(y.back()) > ycut) y.push_back(-am * y.back());
         const int M = (int)y.size();
         const size_t off = gall.size();
         gall.resize(off + M);
@@ -209,8 +212,8 @@ void host_dir(HostDir& d, int n, int nother, zd alpha, double step, F coef) {
         g[M - 1] = y[M - 1];
         for (int k = M - 2; k >= 0; --k) g[k] = y[k] - cp * g[k + 1];
         int kg = M;
-        const double gcut = tolg * tolg * std::norm(g[0]);
-        while (kg > 1 && std::norm(g[kg - 1]) < gcut) --kg;
+        const double gcut = tolg * tolg * nrm(g[0]);
+        while (kg > 1 && nrm(g[kg - 1]) < gcut) --kg;
         Kg = std::max(Kg, kg);
         goff[l + 1] = off + M;
     }
@@ -438,14 +441,32 @@ void band_tile(int ny, int order, int W, int h, int L, int& hb, int& Lb) {
 template <typename T>
 void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
     const zd alpha = imag ? zd(0.5 * p.dt, 0.0) : zd(0.0, 0.5 * p.dt);
-    host_dir<T>(hm.x, p.nx, p.ny, alpha, p.dx, [&](int l) {
-        const double y = p.y0 + (l / 3) * p.dy;
-        return zd(0.0, -(p.omega * y - p.gamma * kNu[l % 3]));  // c = -i (Omega y - gamma nu)
-    });
-    host_dir<T>(hm.y, p.ny, p.nx, alpha, p.dy, [&](int l) {
-        const double x = p.x0 + (l / 3) * p.dx;
-        return zd(0.0, p.omega * x - p.eta * p.gamma * kNu[l % 3]);  // c = i (Omega x - eta gamma mu)
-    });
+    auto xdir = [&] {
+        host_dir<T>(hm.x, p.nx, p.ny, alpha, p.dx, [&](int l) {
+            const double y = p.y0 + (l / 3) * p.dy;
+            return zd(0.0, -(p.omega * y - p.gamma * kNu[l % 3]));  // c = -i (Omega y - gamma nu)
+        });
+    };
+    auto ydir = [&] {
+        host_dir<T>(hm.y, p.ny, p.nx, alpha, p.dy, [&](int l) {
+            const double x = p.x0 + (l / 3) * p.dx;
+            return zd(0.0, p.omega * x - p.eta * p.gamma * kNu[l % 3]);  // c = i (Omega x - eta gamma mu)
+        });
+    };
+    if ((long)p.nx + p.ny < 1024) {
+        xdir();
+        ydir();
+    } else {
+        // large grids: the y tables on a second thread (an exception there is
+        // passed on after the join)
+        std::exception_ptr err;
+        std::thread ty([&] {
+            try { ydir(); } catch (...) { err = std::current_exception(); }
+        });
+        try { xdir(); } catch (...) { ty.join(); throw; }
+        ty.join();
+        if (err) std::rethrow_exception(err);
+    }
     hm.stable = true;
     hm.why.clear();
     if (!hm.x.dominant || !hm.y.dominant) {
