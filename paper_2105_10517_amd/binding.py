@@ -123,6 +123,10 @@ def load():
         return _lib
     if not os.path.exists(LIBPATH):
         raise LibraryNotBuilt(f"{LIBPATH} is missing: run `python -m paper_2105_10517_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has loaded
+    # (the wave functions are torch allocations; loading the library first
+    # can leave two runtimes in the process, and the library's calls fail)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIBPATH)
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     sig = {
