@@ -7,7 +7,8 @@ dt = 0.1 dx^2) from a seeded random-phase Gaussian, in FP64; a step is one
 whole SSCN step (local substep, x sweep, y sweep, renormalisation).  Its
 state (805 MB in FP64) does not fit in the caches, so the roofline fraction
 is an HBM figure.  Beside it: the same grid in FP32 bulk (FP64 reductions),
-with its error against the FP64 oracle; the 128^2 ground-state run (200
+with its error against the FP64 oracle; the same parameters on 2048^2; the
+128^2 ground-state run (200
 imaginary-time steps, timed in full); the 512^2 real-time run from the
 imaginary-time state of its parameters plus 1e-3 noise; the 256-condensate
 parameter scan (batched FP32 against one-at-a-time FP32 and FP64); and the
@@ -390,6 +391,23 @@ def main():
         log(f"[bench] CPU oracle 4096^2: {cpu['value']:.3e} pt-steps/s on {cpu['cores']} threads")
     del psi3
 
+    # ---- 2048^2, the large-grid run's other size (same parameters), timed like the headline ----
+    c3b = {"workload": "2048x2048 imaginary-time steps, the 4096^2 parameters (dx=0.02)"}
+    q2 = inputs.config_c3(2048)
+    psi2 = inputs.gaussian(2048, 2048, q2["dx"], q2["dy"], seed=4, full_phase=True)
+    for prec in ("fp64", "fp32"):
+        ms, tim, plan, norm = single_solve(torch, binding, q2, psi2, prec, True, args.steps, args.warmup,
+                                           args.timing_steps)
+        n2 = 2048 * 2048
+        c3b[prec] = {"value": n2 * args.steps / (ms / 1e3), "ms_per_step": ms / args.steps,
+                     "step_frac": 12 * bytes_per_complex(prec) * n2 / (ms / args.steps / 1e3) / HBM_PEAK_BPS,
+                     "kernels_us": {k: round(v["ms"] / v["launches"] * 1e3, 2) for k, v in tim.items() if v["launches"]},
+                     "plan": {k: plan[k] for k in ("x_solver", "x_tile", "y_solver", "y_tile")}}
+        log(f"[bench] 2048^2 imag {prec}: {c3b[prec]['value']:.3e} pt-steps/s, {ms / args.steps:.3f} ms/step, "
+            f"step {100 * c3b[prec]['step_frac']:.1f}% of the 12 s B/pt-step roofline")
+    del psi2
+    torch.cuda.empty_cache()
+
     # ---- 128^2 ground state, 200 imaginary-time steps, timed in full ----
     c1 = None
     if args.c1:
@@ -493,6 +511,7 @@ def main():
                  "dtype": "f32 bulk, f64 reductions", "roofline": c3["fp32"]["roofline"],
                  "step_roofline_frac": round(c3["fp32"]["step_frac"], 4),
                  "err_vs_oracle": c3["fp32"].get("err_vs_oracle"), "plan": c3["fp32"]["plan"]},
+        "c3_2048": c3b,
         "c1_128": c1,
         "c2_512": c2,
         "batch_c4": c4,
