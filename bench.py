@@ -340,7 +340,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (each condensate runs on "
-              f"one device and this build has no multi-GPU path)", file=sys.stderr)
+              f"one device and the library has no multi-GPU path)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

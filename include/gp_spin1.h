@@ -57,7 +57,7 @@ typedef enum {
     GP_ENOMEM = -3,        /* a device or host allocation failed */
     GP_EHIP = -4,          /* a HIP runtime call failed; gp_spin1_last_error has the message */
     GP_ENONFINITE = -5,    /* a NaN or Inf was met in a norm or an observable */
-    GP_EUNSUPPORTED = -6   /* a size or option this build does not handle */
+    GP_EUNSUPPORTED = -6   /* a size or option the library does not handle  */
 } gp_status;
 
 typedef enum { GP_FP64 = 0, GP_FP32 = 1 } gp_precision; /* FP32: bulk in FP32, reductions in FP64 */

@@ -748,7 +748,7 @@ int validate(const gp_spin1_params* p, std::string& why) {
     if (p->precision != GP_FP64 && p->precision != GP_FP32) { why = "precision must be GP_FP64 or GP_FP32"; return GP_EINVAL; }
     if (p->y_solver < GP_YSOLVER_AUTO || p->y_solver > GP_YSOLVER_STACK) { why = "unknown y_solver"; return GP_EINVAL; }
     const int nmax = 8192;
-    if (p->nx > nmax) { why = "nx above the largest row this build holds on chip"; return GP_EUNSUPPORTED; }
+    if (p->nx > nmax) { why = "nx above the longest row the library handles (8192)"; return GP_EUNSUPPORTED; }
     if ((double)p->nx * (double)p->ny * 3.0 > 4.0e9) { why = "grid too large"; return GP_EUNSUPPORTED; }
     if (!finite(p->trap_gx) || !finite(p->trap_gy) || p->trap_gx < 0 || p->trap_gy < 0) {
         why = "trap_gx, trap_gy must be finite and >= 0 (0 selects 1)";

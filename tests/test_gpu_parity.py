@@ -477,7 +477,7 @@ def test_unstable_parameters_are_refused():
 
 @pytest.mark.parametrize("imag", [True, False])
 def test_longest_row_full_steps(imag):
-    # 8192-point rows (the longest the build holds) through whole steps: by
+    # 8192-point rows (the longest the library handles) through whole steps: by
     # default the chain windows (the whole-row solve would hold 16 points per
     # thread), and the whole-row solve when asked for
     p = all_couplings(8192, 12, 0.0015, dy=0.3, dt=2e-5)
