@@ -234,3 +234,39 @@ def test_chain_full_size_4096(precision):
         rho_g, rho_w = np.abs(got) ** 2, np.abs(want) ** 2
         assert float(np.abs(rho_g - rho_w).max() / rho_w.max()) < 1e-5
         assert abs(obs["mu_total"] - o["mu_total"]) / abs(o["mu_total"]) < 1e-6
+
+
+def test_seeded_random_plans_match_oracle():
+    # seeded random grids (ragged sizes, rectangular cells), couplings, time
+    # steps and chain / stacked tiles, in both propagation modes, against the
+    # oracle; cases whose decay fits no chosen tile are drawn again
+    rng = np.random.default_rng(2024)
+    done = 0
+    while done < 16:
+        nx, ny = int(rng.integers(3, 260)), int(rng.integers(3, 260))
+        dx, dy = float(rng.uniform(0.04, 0.3)), float(rng.uniform(0.04, 0.3))
+        dt = float(rng.uniform(0.05, 1.0)) * min(dx, dy) ** 2
+        p = inputs.params(nx, ny, dx, dy=dy, dt=dt, c0=float(rng.uniform(0, 200)), c2=float(rng.uniform(-10, 10)),
+                          gamma=float(rng.uniform(0, 1)), eta=int(rng.choice([-1, 1])),
+                          rabi=float(rng.uniform(0, 0.5)), omega=float(rng.uniform(0, 0.9)))
+        imag = bool(rng.integers(0, 2))
+        kw = dict(x_solver="chain", x_tile=int(rng.integers(1, 9)), y_solver=str(rng.choice(["chain", "stack"])))
+        kw["y_tile"] = int(rng.integers(1, 9 if kw["y_solver"] == "chain" else 7))
+        pl = binding.plan_query(p, imag, **kw)
+        if (not pl["stable"] or pl["x_solver"] != binding.GP_XSOLVER_CHAIN
+                or pl["y_solver"] not in (binding.GP_YSOLVER_CHAIN, binding.GP_YSOLVER_STACK)):
+            continue
+        # the amplitude keeps the nonlinear phase of one step near 0.3 rad
+        # (the workloads turn through far less): in real time each local
+        # substep multiplies a difference in rounding by about that phase
+        # times the mean density, in both implementations alike
+        g = dt * (p["c0"] + abs(p["c2"]))
+        psi0 = inputs.random_state(nx, ny, seed=500 + done, scale=min(1.0, (0.05 / max(g, 1e-30)) ** 0.5))
+        s = binding.Solver(p, "fp64", **kw)
+        t = dev(psi0)
+        (s.step_imag if imag else s.step_real)(t, 3)
+        got = host(t)
+        s.close()
+        want = oracle.step(p, psi0, 3, imag)
+        assert rel(got, want) < 1e-12, (nx, ny, dx, dy, dt, imag, kw, pl)
+        done += 1
