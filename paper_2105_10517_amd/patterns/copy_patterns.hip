@@ -14,6 +14,12 @@
 //   x lds K     the same segment loaded coalesced (lane l: points l + 64 k),
 //               every load issued first, transposed through shared memory to
 //               the blocked layout and back, stored coalesced
+//   x swz K4    the same, through a shared-memory region per wave (no block
+//               barrier), slots rotated within 16-element chunks so that the
+//               blocked reads and writes are free of bank conflicts; "in" stores
+//               the blocked layout directly, "in+out" transposes back first
+//   x pf K4     the blocked pattern from a fixed grid of waves, each looping
+//               over segments and loading the next before storing the current
 //   y 4-col K   4 columns per wave, 16 segments of K rows per column (one DPP
 //               row of lanes each): the scanned and chain y windows
 //   y stack K   16 consecutive columns per block, one per lane of a DPP row,
@@ -95,6 +101,103 @@ __global__ __launch_bounds__(64 * NW) void k_xlds(const C* __restrict__ s, C* __
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int m = 0; m < 3; ++m) d[m * PL + base + lane + 64 * k] = t[m][k];
+}
+
+// Shared-memory slot of point p of a 256-point segment: a rotation within each
+// chunk of 16 by the chunk index.  Lanes l and l + 16 j of a blocked access
+// (points 4 l + k) then fall on different 16-byte bank groups.
+__device__ inline int swz(int p) { return (p & ~15) | ((p + (p >> 4)) & 15); }
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int NW, bool OUT>
+__global__ __launch_bounds__(64 * NW) void k_xswz(const C* __restrict__ s, C* __restrict__ d) {
+    __shared__ C sh[NW][3][256];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int gw = blockIdx.x * NW + w;  // grid covers the segments exactly
+    constexpr int nseg = NX / 256;
+    const size_t base = (size_t)(gw / nseg) * NX + (gw % nseg) * 256;
+    C t[3][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) t[m][k] = s[m * PL + base + 64 * k + lane];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sh[w][m][swz(64 * k + lane)] = t[m][k];
+    wave_sync();
+    C v[3][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m][k] = sh[w][m][swz(4 * lane + k)];
+    if (!OUT) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) d[m * PL + base + 4 * lane + k] = v[m][k];
+        return;
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) sh[w][m][swz(4 * lane + k)] = v[m][k];
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) d[m * PL + base + 64 * k + lane] = sh[w][m][swz(64 * k + lane)];
+}
+
+// Blocked K = 4 from nw resident waves: wave w copies segments w, w + nw, ...,
+// the next segment's loads issued before the current segment's stores.
+__device__ inline size_t xpf_base(int gw, int lane) {
+    constexpr int nseg = NX / 256;
+    return (size_t)(gw / nseg) * NX + (gw % nseg) * 256 + lane * 4;
+}
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_xpf(const C* __restrict__ s, C* __restrict__ d, int nw) {
+    constexpr int total = NY * (NX / 256);
+    const int lane = threadIdx.x & 63;
+    int gw = blockIdx.x * NW + (threadIdx.x >> 6);
+    if (gw >= total) return;
+    C a[3][4], b[3][4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) a[m][k] = s[m * PL + xpf_base(gw, lane) + k];
+    for (;;) {
+        const int g1 = gw + nw;
+        if (g1 < total) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) b[m][k] = s[m * PL + xpf_base(g1, lane) + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) d[m * PL + xpf_base(gw, lane) + k] = a[m][k];
+        if (g1 >= total) return;
+        const int g2 = g1 + nw;
+        if (g2 < total) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) a[m][k] = s[m * PL + xpf_base(g2, lane) + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) d[m * PL + xpf_base(g1, lane) + k] = b[m][k];
+        if (g2 >= total) return;
+        gw = g2;
+    }
 }
 
 template <int K, int NW>
@@ -197,6 +300,14 @@ int main() {
     rep("x blocked K8", timeit([&] { k_xblocked<8, 2><<<npts / 512 / 2, 128>>>(s, d); }));
     rep("x lds K4", timeit([&] { k_xlds<4, 2><<<npts / 256 / 2, 128>>>(s, d); }));
     rep("x lds K8", timeit([&] { k_xlds<8, 1><<<npts / 512, 64>>>(s, d); }));
+    rep("x swz K4 in NW4", timeit([&] { k_xswz<4, false><<<npts / 256 / 4, 256>>>(s, d); }));
+    rep("x swz K4 in+out NW4", timeit([&] { k_xswz<4, true><<<npts / 256 / 4, 256>>>(s, d); }));
+    for (int wps : {2, 3, 4}) {
+        const int nw = 256 * 4 * wps;  // resident waves: wps per SIMD
+        char name[40];
+        std::snprintf(name, sizeof name, "x pf K4 %d waves/SIMD", wps);
+        rep(name, timeit([&] { k_xpf<2><<<nw / 2, 128>>>(s, d, nw); }));
+    }
     rep("y 4-col K8 NW2", timeit([&] { k_y4col<8, 2><<<(NX / 8) * (NY / 128), 128>>>(s, d); }));
     rep("y 4-col K8 NW4", timeit([&] { k_y4col<8, 4><<<(NX / 16) * (NY / 128), 256>>>(s, d); }));
     rep("y stack K8", timeit([&] { k_ystack<8><<<(NX / 16) * (NY / 128), 256>>>(s, d); }));
