@@ -375,8 +375,11 @@ const char* gp_spin1_batch_last_error(const gp_spin1_batch_t* b);
  * of the loop's own (non-blocking, default priority; it starts after the
  * work queued on hip_stream, which resumes after the last round), up to two
  * at a time: while the GPU runs one round the host admits arrivals (building
- * their tables) and enqueues the next; the tables of finished requests are
- * released while the GPU idles or at the end.
+ * their tables) and enqueues the next.  A finished request's tables and work
+ * copy leave the budget with its round but stay allocated until they are
+ * released (freeing waits for the device): while the GPU idles, at the end,
+ * or once such held memory exceeds max(1 GB, a quarter of the budget), after
+ * the rounds in flight have drained.
  *
  * req[n]: sorted by arrival (seconds after the start of the trace, scaled by
  *   time_scale; 0 replays every request as arriving at once); p as for
