@@ -533,10 +533,23 @@ void host_mode(const gp_spin1_params& p, bool imag, HostMode& hm) {
         // rows longer than 512 threads of eight points: the whole-row solve
         // would hold sixteen points per thread and spill; the chain windows
         // take rows of any length, and on large grids they are the faster
-        // sweep (4096^2 FP64: 366 against 777 us).  Four points per lane
-        // (the fastest tiles there), one line at a time first; where no such
-        // tile fits, the tile that writes the largest share of the points it
-        // loads (sixteen points per lane spill with the local substep fused)
+        // sweep (4096^2 FP64: 316 against 777 us).  FP64: two points per
+        // lane, one line at a time, while the window writes at least 3/4 of
+        // the points it loads (4096^2: 316-320 against 371-385 us for four
+        // points per lane).  Then four points per lane (the fastest FP32
+        // tiles), one line at a time first; where no such tile fits, the tile
+        // that writes the largest share of the points it loads (sixteen
+        // points per lane spill with the local substep fused)
+        if (sizeof(T) == 8) {
+            constexpr int t2 = 6;  // {K = 2, 4 waves, one line at a time}
+            int h2, L2;
+            if (xchain_fits<T>(hm.hhx, hm.x.Kg, t2, h2, L2) && 4 * L2 >= 3 * 64 * gp::xchain_tile<T>(t2).K) {
+                hm.xchain = true;
+                hm.xctile = t2;
+                hm.hcx = h2;
+                hm.Lcx = L2;
+            }
+        }
         for (int i = 0; i < gp::kNumChainTiles && !hm.xchain; ++i) {
             const int t = gp::kNumChainTiles - 1 - i;  // (one line at a time first: fewer registers)
             if (gp::xchain_tile<T>(t).K == 4 && xchain_fits<T>(hm.hhx, hm.x.Kg, t, hm.hcx, hm.Lcx)) {
