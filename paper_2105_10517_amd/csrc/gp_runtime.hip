@@ -979,13 +979,18 @@ int autotune_t(gp_spin1* h) {
             bool bestC = ms.ychain;
             int bestT = ms.yctile, bestO = ms.yorder;
             bool bestS = ms.ystack;
+            // large grids: the hardware order only, unless one is asked for (there
+            // the eight XCDs' separate streams through HBM cost more than the shared
+            // halos save; short autotuning pairs have measured otherwise, 4096^2 FP32:
+            // bands chosen, 198 against 190 us over a run)
+            const int pe = p.block_order == GP_ORDER_AUTO && (double)p.nx * p.ny >= 1048576.0 ? 1 : std::min(p1, 3);
             for (int st = 0; st < 2 && rc == GP_OK; ++st) {
                 if ((p.y_solver == GP_YSOLVER_CHAIN && st == 1) || (p.y_solver == GP_YSOLVER_STACK && st == 0)) continue;
                 for (int t = 0; t < (st ? gp::kNumStackTiles : gp::kNumChainTiles) && rc == GP_OK; ++t) {
                     if (st ? !ystack_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, ms.hcy, ms.Lcy)
                            : !ychain_fits<T>(p.nx, p.ny, ms.hh, ms.y.Kg, t, ms.hcy, ms.Lcy))
                         continue;
-                    for (int o = p0; o < std::min(p1, 3) && rc == GP_OK; ++o) {
+                    for (int o = p0; o < pe && rc == GP_OK; ++o) {
                         ms.ychain = true;
                         ms.ystack = st == 1;
                         ms.yctile = t;
