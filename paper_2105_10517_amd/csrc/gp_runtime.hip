@@ -1203,11 +1203,13 @@ int steps_t(gp_spin1* h, void* psi, int64_t n, bool imag) {
     hipError_t e;
     if (imag && (e = gp::launch_set_scale(h->d_scale, 1.0, st)) != hipSuccess) return hip_fail(h, e, "set_scale");
     // Imaginary time: the y sweep leaves per-block norm partials.  Where they are
-    // few, every block of the next x sweep sums them itself (no launch in
-    // between); otherwise one block sums them into the scale factors.  The last
-    // step's partials always go through that block (for the final scaling).
+    // few, every block (whole rows) or wave (chain windows, total norm one) of
+    // the next x sweep sums them itself (no launch in between); otherwise one
+    // block sums them into the scale factors.  The last step's partials always go through that
+    // block (for the final scaling).
     gp::XLaunch<T> xn = xa;
-    const bool fold = imag && !xa.window && !xa.chain && 3 * nyb <= 8 * xa.G * xa.R;
+    const bool fold = imag && !xa.window &&
+                      (xa.chain ? !rule.fix_m && 3 * nyb <= 8 * 64 : 3 * nyb <= 8 * xa.G * xa.R);
     if (fold) xn.nin = gp::NormIn{h->d_part, nyb, dxdy, rule, h->d_flag};
     for (int64_t s = 0; s < n; ++s) {
         const gp::XLaunch<T>& x = s > 0 ? xn : xa;

@@ -409,6 +409,16 @@ __device__ inline void store_norm_partials(double (&acc)[3], double* sh, NormOut
         for (int m = 0; m < 3; ++m) no.partials[3 * blk + m] = acc[m];
 }
 
+// The total-norm branch of norm_scales alone (the same arithmetic), for
+// kernels that must not hold the fixed-magnetisation branch's registers.
+__device__ inline bool norm_scale_total(const double (&N)[3], double* s) {
+    const double t = N[0] + N[1] + N[2];
+    const double f = 1.0 / sqrt(t);
+    const bool ok = isfinite(f) && f > 0.0;
+    s[0] = s[1] = s[2] = ok ? f : 1.0;
+    return ok;
+}
+
 // Scale factors of the three components from their norms N[m] (dx dy sum
 // |psi_m|^2).  Total norm one: s_m = 1 / sqrt(N_{+1} + N_0 + N_{-1}).  Fixed
 // magnetisation mag: the s_m that give total norm one, N_{+1} - N_{-1} = mag

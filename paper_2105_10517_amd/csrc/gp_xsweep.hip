@@ -271,6 +271,13 @@ __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ 
     x_window<T, IMAG, KX, NW, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, L, h, cs, rt, rlo, rhi);
 }
 
+// A double that is the same in every lane, moved to scalar registers.
+__device__ inline double wave_uniform(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)b), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // ---------------------------------------------------------------------------
 // x sweep over chain windows (gp_chain.hpp): one row segment of W = 64 K
 // points per wave, K consecutive points per lane, carries over nc lanes; the
@@ -284,8 +291,8 @@ __global__ __launch_bounds__(64 * NW) void k_x_window(const cx<T>* __restrict__ 
 // gw / nwin.
 template <typename T, bool IMAG, int K, bool SEQ, bool LOCAL, bool SCALE>
 __device__ __attribute__((always_inline)) inline void x_chain_wave(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst, size_t sp, size_t dp,
-                                    const Phys& ph, const LineSet<T>& ls, const double* __restrict__ scale, int h,
-                                    int nc, int L, int nwin, int gw) {
+                                    const Phys& ph, const LineSet<T>& ls, const double* __restrict__ scale,
+                                    const NormIn& nin, int h, int nc, int L, int nwin, int gw) {
     using C = cx<T>;
     const int lane = threadIdx.x & 63;
     const int nx = ph.nx;
@@ -303,6 +310,34 @@ __device__ __attribute__((always_inline)) inline void x_chain_wave(const cx<T>* 
     const int g0 = s0 + lane * K;    // first point of this lane
     const C* rowp = src + (size_t)j * nx;
     const bool edge = s0 < 0 || s0 + 64 * K > nx;  // wave-uniform
+    // the pending scale factors, formed before the loads and held in scalar
+    // registers (the same in every lane)
+    double sc[3] = {1.0, 1.0, 1.0};
+    int bad = 0;  // a non-finite norm total (flagged at the end: a store here would
+                  // keep the later loads of the line tables off the scalar path)
+    if (SCALE) {
+        if (nin.partials != nullptr) {
+            // from the previous y sweep's few partials (total norm one; the host
+            // folds no other rule here), summed by every wave in the same order:
+            // lane sums, then an xor butterfly (commutative at each stage, so
+            // every lane holds the same total)
+            double acc[3] = {0, 0, 0};
+            for (int k = lane; k < nin.n; k += 64)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) acc[m] += nin.partials[3 * k + m];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) acc[m] += __shfl_xor(acc[m], o, 64);
+            const double N[3] = {acc[0] * nin.dxdy, acc[1] * nin.dxdy, acc[2] * nin.dxdy};
+            bad = __builtin_amdgcn_readfirstlane(norm_scale_total(N, sc) ? 0 : 1);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sc[m] = wave_uniform(sc[m]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sc[m] = scale[m];
+        }
+    }
     C v[3][K];
     if (!edge) {
 #pragma unroll
@@ -321,9 +356,9 @@ __device__ __attribute__((always_inline)) inline void x_chain_wave(const cx<T>* 
     if (SCALE) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const T sc = (T)scale[m];
+            const T f = (T)sc[m];
 #pragma unroll
-            for (int k = 0; k < K; ++k) v[m][k] = cscale(v[m][k], sc);
+            for (int k = 0; k < K; ++k) v[m][k] = cscale(v[m][k], f);
         }
     }
     if (LOCAL) {
@@ -348,16 +383,17 @@ __device__ __attribute__((always_inline)) inline void x_chain_wave(const cx<T>* 
         if (g0 + k >= i0 && g0 + k < i1)
 #pragma unroll
             for (int m = 0; m < 3; ++m) rowq[m * dp + g0 + k] = v[m][k];
+    if (bad) *nin.flag = 1;  // (the same value from every lane)
 }
 
 template <typename T, bool IMAG, int K, int NW, bool SEQ, bool LOCAL, bool SCALE>
 __global__ __launch_bounds__(64 * NW) void k_x_chain(const cx<T>* __restrict__ src, cx<T>* __restrict__ dst,
                                                      size_t sp, size_t dp, Phys ph, LineSet<T> ls,
-                                                     const double* __restrict__ scale, int h, int nc, int L, int nwin,
-                                                     int nblk, int order) {
+                                                     const double* __restrict__ scale, NormIn nin, int h, int nc, int L,
+                                                     int nwin, int nblk, int order) {
     const int lb = order_logical(order ? 1 : 0, (int)blockIdx.x, nblk, 1);
     if (lb < 0) return;
-    x_chain_wave<T, IMAG, K, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, h, nc, L, nwin,
+    x_chain_wave<T, IMAG, K, SEQ, LOCAL, SCALE>(src, dst, sp, dp, ph, ls, scale, nin, h, nc, L, nwin,
                                                 lb * NW + (int)(threadIdx.x >> 6));
 }
 
@@ -369,7 +405,8 @@ __global__ __launch_bounds__(64 * NW) void k_x_chain_batch(const XCSlot<T>* __re
                                                            const unsigned* __restrict__ map) {
     const unsigned e = map[blockIdx.x];
     const XCSlot<T>& s = slots[e >> kMapShift];
-    x_chain_wave<T, IMAG, K, SEQ, true, IMAG>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.scale, s.h, s.nc, s.L, s.nwin,
+    x_chain_wave<T, IMAG, K, SEQ, true, IMAG>(s.src, s.dst, s.sp, s.dp, s.ph, s.ls, s.scale,
+                                              NormIn{nullptr, 0, 0.0, NormRule{0, 0.0}, nullptr}, s.h, s.nc, s.L, s.nwin,
                                               (int)(e & kMapMask) * NW + (int)(threadIdx.x >> 6));
 }
 
@@ -483,8 +520,8 @@ static hipError_t launch_xc_t(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0
     const int nblk = (int)((nwav + ct.NW - 1) / ct.NW);
     const int grid = a.order ? xcd_blocks(nblk) : nblk;
     hipExtLaunchKernelGGL(k_x_chain<T, IMAG, ct.K, ct.NW, ct.SEQ, LOCAL, SCALE>, dim3(grid), dim3(64 * ct.NW), 0, st, e0,
-                          e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.h, chain_lanes(a.h, ct.K), a.L, nwin,
-                          nblk, a.order);
+                          e1, 0, a.src, a.dst, a.sp, a.dp, a.ph, a.ls, a.scale, a.nin, a.h, chain_lanes(a.h, ct.K), a.L,
+                          nwin, nblk, a.order);
     return hipGetLastError();
 }
 
@@ -506,8 +543,10 @@ static hipError_t launch_xc(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, 
 template <typename T>
 hipError_t launch_x(const XLaunch<T>& a, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
     if (a.chain) {
-        // (the scale factors come from `scale`)
-        if (a.nin.partials != nullptr) return hipErrorInvalidValue;
+        // (the scale factors come from `scale`, or from a few norm partials
+        // under the total-norm rule, summed by every wave)
+        if (a.nin.partials != nullptr && (!a.imag || !a.local || a.nin.rule.fix_m || 3 * a.nin.n > 8 * 64))
+            return hipErrorInvalidValue;
         if (a.imag) return a.local ? launch_xc<T, true, true, true>(a, st, e0, e1) : launch_xc<T, true, false, false>(a, st, e0, e1);
         return a.local ? launch_xc<T, false, true, false>(a, st, e0, e1) : launch_xc<T, false, false, false>(a, st, e0, e1);
     }
