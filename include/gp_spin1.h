@@ -82,7 +82,8 @@ typedef enum {
 typedef enum {
     GP_XSOLVER_AUTO = 0,   /* whole-row partitioned Thomas, or the windows when autotuning finds them faster;
                               grids of 1024^2 points and up, and rows above 4096 points, take the chain
-                              windows (four points per lane) when a chain tile fits                      */
+                              windows when a chain tile fits (FP64: two points per lane while a window
+                              writes at least 3/4 of what it loads, else four; FP32: four)               */
     GP_XSOLVER_SCAN = 1,   /* exact partitioned Thomas over whole rows (scans across the row's threads)     */
     GP_XSOLVER_WINDOW = 2, /* truncated overlapping windows along the rows (the y sweep's scheme); refused
                               (GP_EUNSUPPORTED) when the decay bound does not fit any window            */
